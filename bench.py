@@ -1,0 +1,209 @@
+"""Benchmark of the shallow-water step on one MI355X.
+
+Workload: the 10,000,000-triangle water drop (jittered split-square mesh of a 10 km x 5 km box,
+sloping bed with 64 Gaussian bumps, Manning n ~ U(0.015, 0.06), Gaussian hump of water at the
+centre, walls, Morton-ordered cells).  A "step" is one explicit step of the whole path:
+reconstruction + HLLC on every cell's three edges, update, friction and the CFL dt reduction.
+
+Prints one JSON line: cell-updates/s of the FP64 step (the paper's precision) as `value`, the
+FP32 step under `variants`, the HBM roofline of the step kernel from its algorithmic bytes, and
+the CPU oracle timed on this host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0     # MI355X HBM3E, public specification
+STEP_KERNEL = "step_kernel"
+
+
+def algorithmic_bytes(n_cells: int, n_nodes: int, word: int) -> int:
+    """Compulsory HBM bytes of one step: every array read or written once.
+
+    Per cell: U in (3 words), U out (3), bed (1), roughness (1), three neighbour ids and three
+    node ids (int32); per node: two double coordinates."""
+    return n_cells * (8 * word + 24) + n_nodes * 16
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1807_00672_amd", "csrc", "swe_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(dtype: str, n_cells: int):
+    """HBM bytes per launch of the step kernel from committed counter runs, if they were taken
+    on the current kernel source for this workload; else None."""
+    p = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_sha") != kernel_source_hash() or d.get("n_cells") != n_cells:
+        return None
+    return d.get("bytes_per_launch", {}).get(dtype)
+
+
+def time_gpu(solver, steps, warmup, stream):
+    import torch
+    solver.run(warmup, sync=True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+        solver.run(steps, sync=False, stream=stream)
+        ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    rc, st = solver.stats(stream=stream)
+    return ms, rc, st
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Plain device copy: achieved GB/s (read + write) as a measured ceiling for context."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def cpu_baseline(case, budget_s=12.0, threads=None):
+    """The oracle, as it is, on this host: a bounded number of steps of the same workload."""
+    import oracle
+    if threads:
+        oracle.set_threads(threads)
+    nth = oracle.threads()
+    t0 = time.perf_counter()
+    mesh = oracle.Mesh(case.xy, case.tri, case.edge_tag)
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rc, *_ = oracle.run_case(case, steps=1, mesh=mesh)
+    one = time.perf_counter() - t0
+    steps = int(max(1, min(50, budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    rc, *_ = oracle.run_case(case, steps=steps, mesh=mesh)
+    el = time.perf_counter() - t0
+    assert rc == 0, rc
+    return {"value": case.n_cells * steps / el, "unit": "cell-updates/s", "cores": nth,
+            "kind": "oracle",
+            "sample": f"{case.n_cells} cells, {steps} steps from the initial state "
+                      f"({el:.1f} s on {nth} OpenMP threads; mesh build {build_s:.1f} s untimed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", default="full", choices=["full", "small"],
+                    help="small: the same recipe at 1e5 cells (quick checks)")
+    ap.add_argument("--dtypes", default="f64,f32")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--probe", choices=["copy"], default=None,
+                    help="copy: run only a plain 2 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_1807_00672_amd as swe
+    swe.require_gpu()
+
+    if args.probe == "copy":
+        gbps = copy_bandwidth()
+        print(json.dumps({"probe": "copy", "bytes_per_copy": 2 << 30, "GBps": gbps}), flush=True)
+        return
+
+    t_gen = time.perf_counter()
+    case = gen.config(3) if args.size == "full" else gen.water_drop(nx=250, ny=200,
+                                                                    lx=2000.0, ly=1600.0)
+    t_gen = time.perf_counter() - t_gen
+    t_mesh = time.perf_counter()
+    mesh = swe.Mesh(case.xy, case.tri, morton=True)
+    t_mesh = time.perf_counter() - t_mesh
+    print(f"# {case.name}: {case.n_cells} cells, {case.n_nodes} nodes; generate {t_gen:.1f} s, "
+          f"mesh build {t_mesh:.1f} s", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.Stream()
+    results = {}
+    for dt in args.dtypes.split(","):
+        solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt)
+        ms, rc, st = time_gpu(solver, args.steps, args.warmup, stream)
+        if rc != swe.SWE_OK or st["steps"] != args.warmup + args.steps:
+            raise RuntimeError(f"{dt}: run failed rc={rc} stats={st}")
+        word = 8 if dt == "f64" else 4
+        per_step_s = ms * 1e-3 / args.steps
+        alg = algorithmic_bytes(case.n_cells, case.n_nodes, word)
+        results[dt] = {
+            "value": case.n_cells * args.steps / (ms * 1e-3),
+            "ms_per_step": ms / args.steps,
+            "alg_bytes_per_step": alg,
+            "achieved_GBps": alg / per_step_s / 1e9,
+            "traffic": load_traffic(dt, case.n_cells),
+            "t_end_state": st["t"],
+        }
+        print(f"# {dt}: {ms / args.steps:.4f} ms/step, {results[dt]['value'] / 1e9:.2f} G "
+              f"cell-updates/s, {results[dt]['achieved_GBps']:.0f} GB/s algorithmic",
+              file=sys.stderr, flush=True)
+        del solver
+        torch.cuda.empty_cache()
+
+    copy_gbps = copy_bandwidth()
+    main_dt = "f64" if "f64" in results else next(iter(results))
+    r = results[main_dt]
+    line = {
+        "metric": "cell-updates/s at 10M triangles (FP64 step; FP32 under variants)",
+        "value": r["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_dt,
+        "data": "synthetic",
+        "config": {"workload": f"water drop, {case.n_cells} triangles, jittered split-square "
+                               f"mesh 10 km x 5 km, Morton order, walls",
+                   "n_cells": case.n_cells, "n_nodes": case.n_nodes, "parallelism": "none"},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBPS,
+                     "traffic": r["traffic"], "kernel": STEP_KERNEL,
+                     "alg_bytes_per_launch": r["alg_bytes_per_step"]},
+        "variants": {k: {kk: vv for kk, vv in v.items() if kk != "t_end_state"}
+                     for k, v in results.items()},
+        "copy_GBps_measured": copy_gbps,
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * swe.h -- C ABI of libswe.so, one explicit step of the cell-centred HLLC finite-volume
+ * shallow-water solver of Zaoui, "A GPU-enabled finite volume solver for large shallow water
+ * simulations" (EDF R&D, 2016), written for AMD MI355X (gfx950).
+ *
+ * Problem (section 2.1, eq. 1): U = (h, hu, hv) on a triangle mesh (section 2.2) over a bed z
+ * with Manning roughness n and gravity g, advanced by explicit Euler steps (eq. 4) whose dt
+ * follows the CFL condition with a Courant number (0.7 in the paper).  Fluxes are HLLC with a
+ * hydrostatic reconstruction of the bed; friction is semi-implicit (section 2.2).  The host
+ * loops over time and the device does the work, with no per-step transfers (section 2.3).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns an int32 status (SWE_OK or a negative code) and never aborts or
+ *    throws; swe_last_error() gives a message for the calling thread's last failure.
+ *  - Host pointers are read during the call only.  Device pointers are owned by the caller
+ *    (the library allocates no device memory in the step path) and must stay valid until the
+ *    work queued on the stream has finished.
+ *  - Per-cell device arrays are in MESH order: the cell order chosen by swe_mesh_create
+ *    (Morton order of the centroids with SWE_MORTON).  SWE_ARR_PERM maps mesh order to input
+ *    order.
+ *  - `stream` is a hipStream_t (NULL: the null stream).  swe_state_init, swe_step and swe_run
+ *    (with out == NULL) only queue work; swe_read_stats and swe_run (with out != NULL)
+ *    synchronise the stream.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define SWE_OK 0
+#define SWE_EINVAL (-1)        /* null pointer, bad size or parameter */
+#define SWE_EMESH (-2)         /* degenerate triangle, edge shared by > 2 cells, bad index */
+#define SWE_EDEVICE (-3)       /* a HIP runtime call failed */
+#define SWE_ENONFINITE (-4)    /* the state stopped being finite */
+#define SWE_EDRY (-5)          /* no wet cell: the CFL time step is undefined */
+#define SWE_EUNSUPPORTED (-6)  /* valid request this build cannot serve */
+
+/* ------------------------------------------------------------------ constants */
+#define SWE_F64 0              /* state, bed and roughness in double */
+#define SWE_F32 1              /* state, bed and roughness in float (coordinates stay double) */
+#define SWE_MORTON 1u          /* swe_mesh_create flag: renumber cells along a Morton curve */
+#define SWE_MAX_INFLOW 16      /* inflow segments per mesh */
+#define SWE_CTRL_BYTES 512     /* size of the device control block of a state */
+#define SWE_WALL (-1)          /* boundary code of a reflective wall (section 3) */
+
+typedef struct swe_mesh swe_mesh;   /* host-side mesh object, owned by the library */
+
+typedef struct swe_mesh_info {
+    int64_t n_cells;           /* T: triangles (finite volumes) */
+    int64_t n_nodes;           /* V */
+    int64_t n_edges;           /* E: interfaces */
+    int64_t n_boundary_edges;  /* B = 2E - 3T */
+    int64_t n_inflow_edges;
+    int32_t n_inflow_segments; /* largest inflow tag used */
+    uint32_t flags;            /* flags given to swe_mesh_create */
+    double min_area, max_area, total_area, min_inradius;
+    double bbox[4];            /* xmin, ymin, xmax, ymax */
+} swe_mesh_info;
+
+/* Arrays swe_mesh_export copies out (sizes in elements). */
+enum swe_mesh_array {
+    SWE_ARR_PERM = 0,      /* int32[T]: input index of mesh cell i */
+    SWE_ARR_NBR = 1,       /* int32[3T], structure of arrays: [k*T + i] = neighbour (mesh
+                              order) across local edge k of cell i, or a boundary code:
+                              SWE_WALL, or -1 - s for inflow segment s >= 1 */
+    SWE_ARR_C2N = 2,       /* int32[3T], [k*T + i] = node k of cell i (mesh node order);
+                              counter-clockwise, local edge k runs from node k to node k+1 */
+    SWE_ARR_XY = 3,        /* double[2V]: (x, y) of mesh node j at [2j], [2j+1] */
+    SWE_ARR_NODE_PERM = 4  /* int32[V]: input index of mesh node j */
+};
+
+/* Device view of a mesh: the arrays of swe_mesh_export copied to device memory. */
+typedef struct swe_dev_mesh {
+    int64_t n_cells, n_nodes;
+    const int32_t *nbr;    /* device, as SWE_ARR_NBR */
+    const int32_t *c2n;    /* device, as SWE_ARR_C2N */
+    const double *xy;      /* device, as SWE_ARR_XY, 16-byte aligned */
+} swe_dev_mesh;
+
+/* Physical and numerical parameters (section 2.1-2.2). */
+typedef struct swe_params {
+    double g;              /* gravity, > 0 */
+    double courant;        /* CFL number, in (0, 1]; the paper uses 0.7 */
+    double h_dry;          /* dry threshold (m), >= 0: velocities are zero at or below it */
+    int32_t dtype;         /* SWE_F64 or SWE_F32 */
+    int32_t n_inflow;      /* number of inflow segments, <= SWE_MAX_INFLOW */
+    const double *inflow_q;/* host, n_inflow unit discharges (m^2/s) entering, >= 0 */
+} swe_params;
+
+/* Device state of one simulation.  All pointers device, element type given by dtype. */
+typedef struct swe_state {
+    void *h[2], *hu[2], *hv[2];  /* two buffers of T values each; buffer `cur` holds U^n */
+    const void *z;               /* bed elevation, T values */
+    const void *n;               /* Manning coefficient, T values, >= 0 */
+    void *ctrl;                  /* SWE_CTRL_BYTES, 16-byte aligned: time, dt, counters */
+    void *work;                  /* swe_workspace_bytes(T) bytes, 256-byte aligned */
+    int32_t cur;                 /* host: buffer holding the current state */
+    int32_t reserved;
+} swe_state;
+
+/* Counters of a state since swe_state_init. */
+typedef struct swe_run_stats {
+    int64_t steps;         /* steps taken */
+    int64_t clamps;        /* negative depths set to zero */
+    double t;              /* current time */
+    double dt_next;        /* dt of the next step */
+    double dt_min, dt_max, dt_sum;   /* over the steps taken */
+    int32_t status;        /* SWE_OK, SWE_ENONFINITE or SWE_EDRY */
+    int32_t done;          /* t_end reached or an error stopped the state */
+    int32_t cur;           /* buffer holding the current state */
+    int32_t reserved;
+} swe_run_stats;
+
+/* ------------------------------------------------------------------ mesh (host only) */
+
+/*
+ * Build a mesh from a raw triangle list (section 2.2: the domain is divided into triangles;
+ * section 2.3: fluxes live on the interfaces).  xy: host double[2*nv] node coordinates;
+ * tri: host int32[3*nt] node ids, either orientation (clockwise triangles are reordered
+ * (v0, v2, v1)); edge_tag: host int32[3*nt] or NULL (all walls): for a boundary edge k of
+ * triangle t (nodes k, k+1 of the input triangle), 0 = wall, s >= 1 = inflow segment s.
+ * flags: SWE_MORTON or 0 (keep the input order).  On success *out owns a new mesh.
+ * Errors: SWE_EINVAL (null pointer, nv < 3, nt < 1, sizes beyond int32, non-finite
+ * coordinates, tag out of range), SWE_EMESH (repeated or out-of-range node, zero-area
+ * triangle, edge shared by more than two triangles or twice in the same direction).
+ */
+int32_t swe_mesh_create(const double *xy, int64_t nv, const int32_t *tri, int64_t nt,
+                        const int32_t *edge_tag, uint32_t flags, swe_mesh **out);
+
+/* Counts and geometry summary of a mesh.  Errors: SWE_EINVAL. */
+int32_t swe_mesh_info_get(const swe_mesh *mesh, swe_mesh_info *out);
+
+/* Copy array `which` (enum swe_mesh_array) into host memory dst of dst_bytes bytes.
+ * Errors: SWE_EINVAL (unknown array, null pointer, dst_bytes too small). */
+int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t dst_bytes);
+
+/* Free a mesh (NULL is ignored). */
+void swe_mesh_destroy(swe_mesh *mesh);
+
+/* Bytes of the device workspace a state of n_cells cells needs.  Errors: SWE_EINVAL. */
+int32_t swe_workspace_bytes(int64_t n_cells, int64_t *bytes);
+
+/* ------------------------------------------------------------------ stepping (device) */
+
+/*
+ * Start a state at time t0: computes the first CFL dt from U in buffer state->cur (section
+ * 2.2, Courant number params->courant) and clears the counters.  t_end > 0 makes every later
+ * step stop at t_end exactly (the step that would pass it is shortened); t_end <= 0: no end.
+ * Queues work only.  Errors: SWE_EINVAL (bad parameter, pointer or size), SWE_EDEVICE.  A
+ * state without a wet cell is reported later, by swe_read_stats, as SWE_EDRY.
+ */
+int32_t swe_state_init(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                       swe_state *s, double t0, double t_end, void *stream);
+
+/*
+ * One explicit Euler step (eq. 4) of the dt held in the control block: hydrostatic
+ * reconstruction and HLLC flux on each cell's three edges, bed correction, update, negative
+ * depths clamped, semi-implicit Manning friction, then the CFL dt of the next step reduced
+ * over all cells.  Reads buffer s->cur, writes the other one and flips s->cur.  Once the state
+ * is done (t_end reached, or an error) the step changes nothing and s->cur is kept.  Queues
+ * work only.  Errors: SWE_EINVAL, SWE_EDEVICE.
+ */
+int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                 swe_state *s, void *stream);
+
+/*
+ * n_steps steps (the host time loop of section 2.3) with no host round trip between them.
+ * dt_seq: NULL (CFL dt) or a device array of n_steps doubles replayed as the steps' dt (the
+ * t_end clip still applies).  out: NULL to only queue the work, or a stats record: then the
+ * stream is synchronised, *out filled, and s->cur set to the buffer holding the result; the
+ * return value is then also the state's status (SWE_ENONFINITE, SWE_EDRY).
+ * Errors: SWE_EINVAL, SWE_EDEVICE, and with out != NULL the state's status.
+ */
+int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                swe_state *s, int64_t n_steps, const double *dt_seq, swe_run_stats *out,
+                void *stream);
+
+/* Synchronise the stream and read the state's counters; sets s->cur.  Returns the state's
+ * status (SWE_OK, SWE_ENONFINITE, SWE_EDRY) or SWE_EINVAL / SWE_EDEVICE. */
+int32_t swe_read_stats(swe_state *s, swe_run_stats *out, void *stream);
+
+/* Message of the calling thread's last failure ("" if none).  Valid until the next call. */
+const char *swe_last_error(void);
+
+/* ------------------------------------------------------------------ test hook */
+
+/*
+ * Evaluate the device interface flux on n independent edges, exactly as the step does for a
+ * cell facing a neighbour (section 2.2: hydrostatic reconstruction, then HLLC).  Device
+ * arrays of n elements of the dtype: left and right states (h, hu, hv, z) and a unit normal
+ * (nx, ny) pointing from left to right; outputs f (3n: mass, x- and y-momentum flux per unit
+ * length, at [3i..3i+2]) and the left bed correction p (n).  right_h == NULL evaluates a
+ * reflective wall instead of a neighbour.  Queues work only.  Errors: SWE_EINVAL, SWE_EDEVICE.
+ */
+int32_t swe_flux_eval(int32_t dtype, int64_t n, double g, double h_dry, const void *hl,
+                      const void *hul, const void *hvl, const void *zl, const void *hr,
+                      const void *hur, const void *hvr, const void *zr, const void *nx,
+                      const void *ny, void *f, void *p, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWE_H */

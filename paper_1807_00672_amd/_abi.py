@@ -1,0 +1,194 @@
+"""ctypes binding of libswe.so with the C ABI's names (include/swe.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of the library.
+A missing or unloadable library raises at import; there is no other implementation to fall
+back to.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library then shares)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswe.so")
+
+SWE_OK = 0
+SWE_EINVAL = -1
+SWE_EMESH = -2
+SWE_EDEVICE = -3
+SWE_ENONFINITE = -4
+SWE_EDRY = -5
+SWE_EUNSUPPORTED = -6
+
+SWE_F64 = 0
+SWE_F32 = 1
+SWE_MORTON = 1
+SWE_MAX_INFLOW = 16
+SWE_CTRL_BYTES = 512
+SWE_WALL = -1
+
+SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM = range(5)
+
+_NAMES = {0: "SWE_OK", -1: "SWE_EINVAL", -2: "SWE_EMESH", -3: "SWE_EDEVICE",
+          -4: "SWE_ENONFINITE", -5: "SWE_EDRY", -6: "SWE_EUNSUPPORTED"}
+
+
+class SweError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class swe_mesh_info(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("n_edges", C.c_int64),
+                ("n_boundary_edges", C.c_int64), ("n_inflow_edges", C.c_int64),
+                ("n_inflow_segments", C.c_int32), ("flags", C.c_uint32),
+                ("min_area", C.c_double), ("max_area", C.c_double),
+                ("total_area", C.c_double), ("min_inradius", C.c_double),
+                ("bbox", C.c_double * 4)]
+
+
+class swe_dev_mesh(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("nbr", C.c_void_p),
+                ("c2n", C.c_void_p), ("xy", C.c_void_p)]
+
+
+class swe_params(C.Structure):
+    _fields_ = [("g", C.c_double), ("courant", C.c_double), ("h_dry", C.c_double),
+                ("dtype", C.c_int32), ("n_inflow", C.c_int32),
+                ("inflow_q", C.POINTER(C.c_double))]
+
+
+class swe_state(C.Structure):
+    _fields_ = [("h", C.c_void_p * 2), ("hu", C.c_void_p * 2), ("hv", C.c_void_p * 2),
+                ("z", C.c_void_p), ("n", C.c_void_p), ("ctrl", C.c_void_p), ("work", C.c_void_p),
+                ("cur", C.c_int32), ("reserved", C.c_int32)]
+
+
+class swe_run_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("clamps", C.c_int64), ("t", C.c_double),
+                ("dt_next", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double),
+                ("dt_sum", C.c_double), ("status", C.c_int32), ("done", C.c_int32),
+                ("cur", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+EXPORTS = [
+    "swe_mesh_create", "swe_mesh_info_get", "swe_mesh_export", "swe_mesh_destroy",
+    "swe_workspace_bytes", "swe_state_init", "swe_step", "swe_run", "swe_read_stats",
+    "swe_last_error", "swe_flux_eval",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "(hipcc for gfx950); there is no fallback implementation")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.swe_mesh_create.argtypes = [vp, i64, vp, i64, vp, C.c_uint32, C.POINTER(vp)]
+    L.swe_mesh_info_get.argtypes = [vp, C.POINTER(swe_mesh_info)]
+    L.swe_mesh_export.argtypes = [vp, i32, vp, i64]
+    L.swe_mesh_destroy.argtypes = [vp]
+    L.swe_mesh_destroy.restype = None
+    L.swe_workspace_bytes.argtypes = [i64, C.POINTER(i64)]
+    L.swe_state_init.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
+                                 C.POINTER(swe_state), dbl, dbl, vp]
+    L.swe_step.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
+                           C.POINTER(swe_state), vp]
+    L.swe_run.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
+                          C.POINTER(swe_state), i64, vp, C.POINTER(swe_run_stats), vp]
+    L.swe_read_stats.argtypes = [C.POINTER(swe_state), C.POINTER(swe_run_stats), vp]
+    L.swe_last_error.argtypes = []
+    L.swe_last_error.restype = C.c_char_p
+    L.swe_flux_eval.argtypes = [i32, i64, dbl, dbl] + [vp] * 12 + [vp]
+    for name in EXPORTS:
+        if name not in ("swe_mesh_destroy", "swe_last_error"):
+            getattr(L, name).restype = i32
+    return L
+
+
+lib = _load()
+
+
+def swe_last_error() -> str:
+    return lib.swe_last_error().decode()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != SWE_OK:
+        raise SweError(rc, where, swe_last_error())
+    return rc
+
+
+def _np_ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data)
+
+
+def swe_mesh_create(xy, tri, edge_tag=None, flags: int = SWE_MORTON) -> C.c_void_p:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    tag = None if edge_tag is None else np.ascontiguousarray(edge_tag, np.int32).reshape(-1, 3)
+    out = C.c_void_p()
+    _check(lib.swe_mesh_create(_np_ptr(xy), xy.shape[0], _np_ptr(tri), tri.shape[0],
+                               None if tag is None else _np_ptr(tag), flags, C.byref(out)),
+           "swe_mesh_create")
+    return out
+
+
+def swe_mesh_info_get(mesh) -> swe_mesh_info:
+    info = swe_mesh_info()
+    _check(lib.swe_mesh_info_get(mesh, C.byref(info)), "swe_mesh_info_get")
+    return info
+
+
+def swe_mesh_export(mesh, which: int, n: int, dtype) -> np.ndarray:
+    out = np.empty(n, dtype=dtype)
+    _check(lib.swe_mesh_export(mesh, which, _np_ptr(out), out.nbytes), "swe_mesh_export")
+    return out
+
+
+def swe_mesh_destroy(mesh) -> None:
+    lib.swe_mesh_destroy(mesh)
+
+
+def swe_workspace_bytes(n_cells: int) -> int:
+    b = C.c_int64()
+    _check(lib.swe_workspace_bytes(n_cells, C.byref(b)), "swe_workspace_bytes")
+    return int(b.value)
+
+
+def swe_state_init(mesh, dm, params, state, t0=0.0, t_end=0.0, stream=None) -> None:
+    _check(lib.swe_state_init(mesh, C.byref(dm), C.byref(params), C.byref(state), t0, t_end,
+                              stream), "swe_state_init")
+
+
+def swe_step(mesh, dm, params, state, stream=None) -> None:
+    _check(lib.swe_step(mesh, C.byref(dm), C.byref(params), C.byref(state), stream), "swe_step")
+
+
+def swe_run(mesh, dm, params, state, n_steps: int, dt_seq=None, stats=None, stream=None) -> int:
+    """Queue n_steps steps; with a stats record, synchronise and return the state's status."""
+    rc = lib.swe_run(mesh, C.byref(dm), C.byref(params), C.byref(state), n_steps, dt_seq,
+                     None if stats is None else C.byref(stats), stream)
+    if rc in (SWE_EINVAL, SWE_EDEVICE, SWE_EMESH, SWE_EUNSUPPORTED):
+        _check(rc, "swe_run")
+    return rc
+
+
+def swe_read_stats(state, stats, stream=None) -> int:
+    rc = lib.swe_read_stats(C.byref(state), C.byref(stats), stream)
+    if rc in (SWE_EINVAL, SWE_EDEVICE):
+        _check(rc, "swe_read_stats")
+    return rc
+
+
+def swe_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny, f, p,
+                  stream=None) -> None:
+    _check(lib.swe_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny, f,
+                             p, stream), "swe_flux_eval")

@@ -1,0 +1,198 @@
+// C ABI of libswe: argument checks, launch sequencing and counters.  Device memory and streams
+// belong to the caller; nothing here allocates device memory.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "swe_internal.h"
+
+namespace swe {
+
+namespace {
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int32_t check_hip(int err, const char *where)
+{
+    if (err == hipSuccess) return SWE_OK;
+    return fail(SWE_EDEVICE, std::string(where) + ": " +
+                                 hipGetErrorString(static_cast<hipError_t>(err)));
+}
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int32_t check_params(const swe_params *p, const char *where)
+{
+    if (!p) return fail(SWE_EINVAL, std::string(where) + ": null params");
+    if (!(p->g > 0.0) || !isfinite(p->g)) return fail(SWE_EINVAL, std::string(where) + ": g must be > 0");
+    if (!(p->courant > 0.0) || !(p->courant <= 1.0))
+        return fail(SWE_EINVAL, std::string(where) + ": courant must be in (0, 1]");
+    if (!(p->h_dry >= 0.0) || !isfinite(p->h_dry))
+        return fail(SWE_EINVAL, std::string(where) + ": h_dry must be >= 0");
+    if (p->dtype != SWE_F64 && p->dtype != SWE_F32)
+        return fail(SWE_EINVAL, std::string(where) + ": dtype must be SWE_F64 or SWE_F32");
+    if (p->n_inflow < 0 || p->n_inflow > SWE_MAX_INFLOW)
+        return fail(SWE_EINVAL, std::string(where) + ": n_inflow out of range");
+    if (p->n_inflow > 0 && !p->inflow_q)
+        return fail(SWE_EINVAL, std::string(where) + ": null inflow_q");
+    for (int k = 0; k < p->n_inflow; ++k)
+        if (!(p->inflow_q[k] >= 0.0) || !isfinite(p->inflow_q[k]))
+            return fail(SWE_EINVAL, std::string(where) + ": inflow_q must be finite and >= 0");
+    return SWE_OK;
+}
+
+int32_t check_call(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                   const swe_state *s, const char *where)
+{
+    const std::string w(where);
+    if (!mesh || !dm || !s) return fail(SWE_EINVAL, w + ": null mesh, device mesh or state");
+    if (int32_t rc = check_params(p, where)) return rc;
+    if (dm->n_cells != mesh->info.n_cells || dm->n_nodes != mesh->info.n_nodes)
+        return fail(SWE_EINVAL, w + ": device mesh sizes differ from the mesh");
+    if (!dm->nbr || !dm->c2n || !dm->xy) return fail(SWE_EINVAL, w + ": null device mesh array");
+    if (!aligned(dm->xy, 16)) return fail(SWE_EINVAL, w + ": xy must be 16-byte aligned");
+    if (mesh->info.n_inflow_segments > p->n_inflow)
+        return fail(SWE_EINVAL, w + ": mesh has inflow segment " +
+                                    std::to_string(mesh->info.n_inflow_segments) +
+                                    " but params give " + std::to_string(p->n_inflow));
+    for (int b = 0; b < 2; ++b)
+        if (!s->h[b] || !s->hu[b] || !s->hv[b]) return fail(SWE_EINVAL, w + ": null state buffer");
+    if (!s->z || !s->n || !s->ctrl || !s->work) return fail(SWE_EINVAL, w + ": null z, n, ctrl or work");
+    if (!aligned(s->ctrl, 16)) return fail(SWE_EINVAL, w + ": ctrl must be 16-byte aligned");
+    if (!aligned(s->work, 256)) return fail(SWE_EINVAL, w + ": work must be 256-byte aligned");
+    if (s->cur != 0 && s->cur != 1) return fail(SWE_EINVAL, w + ": cur must be 0 or 1");
+    return SWE_OK;
+}
+
+StepConfig make_config(const swe_mesh *mesh, const swe_params *p)
+{
+    StepConfig c;
+    memset(&c, 0, sizeof(c));
+    c.n_cells = mesh->info.n_cells;
+    c.g = p->g;
+    c.courant = p->courant;
+    c.h_dry = p->h_dry;
+    c.n_inflow = p->n_inflow;
+    for (int k = 0; k < p->n_inflow; ++k) c.inflow_q[k] = p->inflow_q[k];
+    return c;
+}
+
+int32_t status_code(int32_t bits)
+{
+    if (bits & (kStatusNonFinite | kStatusBadDt)) return SWE_ENONFINITE;
+    if (bits & kStatusDry) return SWE_EDRY;
+    return SWE_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace swe
+
+using namespace swe;
+
+extern "C" {
+
+const char *swe_last_error(void) { return g_last_error.c_str(); }
+
+int32_t swe_workspace_bytes(int64_t n_cells, int64_t *bytes)
+{
+    if (!bytes || n_cells < 1) return fail(SWE_EINVAL, "swe_workspace_bytes: bad argument");
+    *bytes = workspace_bytes(n_cells);
+    return SWE_OK;
+}
+
+int32_t swe_state_init(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                       swe_state *s, double t0, double t_end, void *stream)
+{
+    if (int32_t rc = check_call(mesh, dm, p, s, "swe_state_init")) return rc;
+    if (!isfinite(t0) || !isfinite(t_end)) return fail(SWE_EINVAL, "swe_state_init: t0 and t_end must be finite");
+    const StepConfig cfg = make_config(mesh, p);
+    return check_hip(launch_init(p->dtype, *dm, cfg, *s, t0, t_end, stream), "swe_state_init");
+}
+
+int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                 swe_state *s, void *stream)
+{
+    if (int32_t rc = check_call(mesh, dm, p, s, "swe_step")) return rc;
+    const StepConfig cfg = make_config(mesh, p);
+    if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, nullptr, 0, stream),
+                               "swe_step"))
+        return rc;
+    s->cur ^= 1;
+    return SWE_OK;
+}
+
+int32_t swe_read_stats(swe_state *s, swe_run_stats *out, void *stream)
+{
+    if (!s || !out || !s->ctrl) return fail(SWE_EINVAL, "swe_read_stats: null argument");
+    Ctrl c;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (int32_t rc = check_hip(hipMemcpyAsync(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st),
+                               "swe_read_stats"))
+        return rc;
+    if (int32_t rc = check_hip(hipStreamSynchronize(st), "swe_read_stats")) return rc;
+    memset(out, 0, sizeof(*out));
+    out->steps = c.steps;
+    out->clamps = c.clamps;
+    out->t = c.t;
+    out->dt_next = c.dt;
+    out->dt_min = c.dt_min;
+    out->dt_max = c.dt_max;
+    out->dt_sum = c.dt_sum;
+    out->status = status_code(c.status);
+    out->done = c.done;
+    out->cur = static_cast<int32_t>((c.cur0 + c.steps) & 1);
+    s->cur = out->cur;
+    if (out->status != SWE_OK)
+        g_last_error = out->status == SWE_EDRY ? "state has no wet cell: dt undefined"
+                                               : "state or dt stopped being finite";
+    return out->status;
+}
+
+int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                swe_state *s, int64_t n_steps, const double *dt_seq, swe_run_stats *out,
+                void *stream)
+{
+    if (int32_t rc = check_call(mesh, dm, p, s, "swe_run")) return rc;
+    if (n_steps < 0) return fail(SWE_EINVAL, "swe_run: n_steps < 0");
+    if (dt_seq && n_steps < 1) return fail(SWE_EINVAL, "swe_run: dt_seq needs n_steps >= 1");
+    const StepConfig cfg = make_config(mesh, p);
+    if (int32_t rc = check_hip(launch_run_begin(*s, dt_seq, stream), "swe_run")) return rc;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_steps,
+                                               stream),
+                                   "swe_run"))
+            return rc;
+        s->cur ^= 1;
+    }
+    if (!out) return SWE_OK;
+    return swe_read_stats(s, out, stream);
+}
+
+int32_t swe_flux_eval(int32_t dtype, int64_t n, double g, double h_dry, const void *hl,
+                      const void *hul, const void *hvl, const void *zl, const void *hr,
+                      const void *hur, const void *hvr, const void *zr, const void *nx,
+                      const void *ny, void *f, void *p, void *stream)
+{
+    if (dtype != SWE_F64 && dtype != SWE_F32) return fail(SWE_EINVAL, "swe_flux_eval: bad dtype");
+    if (n < 0) return fail(SWE_EINVAL, "swe_flux_eval: n < 0");
+    if (n == 0) return SWE_OK;
+    if (!hl || !hul || !hvl || !zl || !nx || !ny || !f || !p)
+        return fail(SWE_EINVAL, "swe_flux_eval: null argument");
+    if (hr && (!hur || !hvr || !zr)) return fail(SWE_EINVAL, "swe_flux_eval: partial right state");
+    if (!(g > 0.0) || !(h_dry >= 0.0)) return fail(SWE_EINVAL, "swe_flux_eval: bad g or h_dry");
+    return check_hip(launch_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx,
+                                      ny, f, p, stream),
+                     "swe_flux_eval");
+}
+
+}  // extern "C"

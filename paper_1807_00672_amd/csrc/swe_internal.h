@@ -1,0 +1,90 @@
+// Internal declarations shared by the mesh builder, the C ABI and the HIP kernels of libswe.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "swe.h"
+
+namespace swe {
+
+// Device control block of a state (SWE_CTRL_BYTES bytes, written by the kernels only).
+struct Ctrl {
+    double t;          // time of the current state
+    double dt;         // dt of the next step
+    double t_end;      // stop time, <= 0: none
+    double dt_min, dt_max, dt_sum;
+    int64_t steps;     // steps taken since swe_state_init
+    int64_t run_step;  // steps taken by the current swe_run (index into dt_seq)
+    int64_t clamps;    // negative depths clamped to zero
+    int32_t status;    // kStatus* bits
+    int32_t done;      // 1: steps change nothing (t_end reached or error)
+    int32_t last;      // 1: the next step ends at t_end exactly
+    int32_t cur0;      // buffer holding the state at swe_state_init
+};
+static_assert(sizeof(Ctrl) <= SWE_CTRL_BYTES, "control block too large");
+
+enum : int32_t { kStatusNonFinite = 1, kStatusDry = 2, kStatusBadDt = 4 };
+
+constexpr int kBlock = 256;          // cells per workgroup of the step kernel
+
+// Per-block partial results of a step, laid out in the workspace.
+struct Partials {
+    double *dt;        // [nblocks] min over the block's cells of r / (|u| + c)
+    int32_t *clamps;   // [nblocks]
+    int32_t *flags;    // [nblocks] kStatus* bits
+};
+
+inline int64_t n_blocks(int64_t n_cells) { return (n_cells + kBlock - 1) / kBlock; }
+
+inline Partials partials_of(void *work, int64_t n_cells)
+{
+    const int64_t nb = n_blocks(n_cells);
+    char *p = static_cast<char *>(work);
+    Partials r;
+    r.dt = reinterpret_cast<double *>(p);
+    r.clamps = reinterpret_cast<int32_t *>(p + ((nb * 8 + 255) / 256) * 256);
+    r.flags = r.clamps + ((nb + 63) / 64) * 64;
+    return r;
+}
+
+inline int64_t workspace_bytes(int64_t n_cells)
+{
+    const int64_t nb = n_blocks(n_cells);
+    return ((nb * 8 + 255) / 256) * 256 + 2 * ((nb + 63) / 64) * 64 * 4 + 256;
+}
+
+// Everything a launch needs besides the state: plain values, passed by value to kernels.
+struct StepConfig {
+    int64_t n_cells;
+    double g, courant, h_dry;
+    int32_t n_inflow;
+    double inflow_q[SWE_MAX_INFLOW];
+};
+
+// Launchers (swe_kernels.hip).  All queue work on `stream` and return a hipError_t as int.
+int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
+                double t0, double t_end, void *stream);
+int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
+                int cur, const double *dt_seq, int64_t n_seq, void *stream);
+int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);
+int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *hl,
+                     const void *hul, const void *hvl, const void *zl, const void *hr,
+                     const void *hur, const void *hvr, const void *zr, const void *nx,
+                     const void *ny, void *f, void *p, void *stream);
+
+void set_error(const std::string &msg);
+
+}  // namespace swe
+
+// The host-side mesh object behind the opaque swe_mesh handle.
+struct swe_mesh {
+    swe_mesh_info info;
+    std::vector<int32_t> perm;       // mesh cell -> input cell
+    std::vector<int32_t> nbr;        // [3][T]
+    std::vector<int32_t> c2n;        // [3][T]
+    std::vector<double> xy;          // [V][2]
+    std::vector<int32_t> node_perm;  // mesh node -> input node
+};

@@ -1,0 +1,562 @@
+// HIP kernels of libswe for gfx950: the fused per-cell step, the dt reduction pass, the
+// initial-dt pass and the flux test hook.
+//
+// One work-item per cell (cells in Morton order).  Each cell gathers its three neighbours,
+// evaluates the three interface fluxes itself (section 2.2: HLLC with hydrostatic
+// reconstruction), accumulates them in local-edge order, applies the explicit Euler update of
+// eq. 4, clamps negative depths, applies semi-implicit Manning friction and finally computes
+// its CFL bound for the next step.  An interior edge is thus evaluated by both of its cells;
+// the flux is written so that the two evaluations are exact negatives of each other, which
+// keeps mass conservation exact up to the rounding of the cell sums, with no atomics.
+//
+// Every product and sum is rounded on its own (the library is built with contraction off),
+// in the order written here.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "swe_internal.h"
+
+namespace swe {
+namespace {
+
+constexpr double kInf = __builtin_huge_val();
+
+// ------------------------------------------------------------------------ flux pieces
+
+// Velocity of a cell: zero at or below the dry threshold.
+template <typename R>
+__device__ __forceinline__ R velocity(R h, R hq, R h_dry)
+{
+    return h > h_dry ? hq / h : R(0);
+}
+
+// HLLC flux in the edge frame (section 2.2, ref. [6]).  Reconstructed depths (already zero
+// when dry), normal (q) and tangential (w) velocities of both sides; outputs the mass,
+// normal-momentum and tangential-momentum flux.  Two-rarefaction wave speeds with the dry-bed
+// speeds; mass and normal momentum from the HLL average; tangential momentum carried by the
+// mass flux with the tangential velocity upwind of the contact speed S*.
+template <typename R>
+__device__ __forceinline__ void hllc_normal(R g, R hl, R ql, R wl, R hr, R qr, R wr, R &fh,
+                                            R &fq, R &fw)
+{
+    if (hl == R(0) && hr == R(0)) {
+        fh = R(0); fq = R(0); fw = R(0);
+        return;
+    }
+    const R cl = sqrt(g * hl), cr = sqrt(g * hr);
+    R sl, sr;
+    if (hl == R(0)) {
+        sl = qr - R(2) * cr;
+        sr = qr + cr;
+    } else if (hr == R(0)) {
+        sl = ql - cl;
+        sr = ql + R(2) * cl;
+    } else {
+        const R us = (ql + qr) / R(2) + (cl - cr);
+        const R cs = (cl + cr) / R(2) + (ql - qr) / R(4);
+        sl = fmin(ql - cl, us - cs);
+        sr = fmax(qr + cr, us + cs);
+    }
+    const R fhl = hl * ql, fql = hl * ql * ql + R(0.5) * g * hl * hl;
+    const R fhr = hr * qr, fqr = hr * qr * qr + R(0.5) * g * hr * hr;
+    if (sl >= R(0)) {
+        fh = fhl; fq = fql; fw = fh * wl;
+    } else if (sr <= R(0)) {
+        fh = fhr; fq = fqr; fw = fh * wr;
+    } else {
+        const R den = sr - sl;
+        fh = ((sr * fhl - sl * fhr) + sl * sr * (hr - hl)) / den;
+        fq = ((sr * fql - sl * fqr) + sl * sr * (hr * qr - hl * ql)) / den;
+        const R sstar = (sl * hr * (qr - sr) - sr * hl * (ql - sl)) /
+                        (hr * (qr - sr) - hl * (ql - sl));
+        const R wup = sstar > R(0) ? wl : (sstar < R(0) ? wr : (wl + wr) / R(2));
+        fw = fh * wup;
+    }
+}
+
+// Flux through an interior edge seen from cell "l" with the hydrostatic reconstruction of
+// the bed (z* = max, h* = max(0, h - (z* - z)), velocities kept) and l's bed correction
+// p = g/2 (h^2 - h*^2).  (fx, fy) are the momentum fluxes in (x, y).
+template <typename R>
+__device__ __forceinline__ void interface_flux(R g, R hd, R hl, R ul, R vl, R zl, R hr, R hur,
+                                               R hvr, R zr, R nx, R ny, R &fh, R &fx, R &fy,
+                                               R &p)
+{
+    const R zs = fmax(zl, zr);
+    R hsl = fmax(R(0), hl - (zs - zl));
+    R hsr = fmax(R(0), hr - (zs - zr));
+    if (hsl <= hd) hsl = R(0);
+    if (hsr <= hd) hsr = R(0);
+    const R ur = velocity(hr, hur, hd), vr = velocity(hr, hvr, hd);
+    const R ql = ul * nx + vl * ny, wl = vl * nx - ul * ny;
+    const R qr = ur * nx + vr * ny, wr = vr * nx - ur * ny;
+    R fq, fw;
+    hllc_normal(g, hsl, ql, wl, hsr, qr, wr, fh, fq, fw);
+    fx = fq * nx - fw * ny;
+    fy = fq * ny + fw * nx;
+    p = R(0.5) * g * (hl * hl - hsl * hsl);
+}
+
+// Reflective wall (section 3): mirror ghost built in the edge frame (q -> -q, w kept), so the
+// mass flux is exactly zero.
+template <typename R>
+__device__ __forceinline__ void wall_flux(R g, R hd, R h, R u, R v, R nx, R ny, R &fh, R &fx,
+                                          R &fy, R &p)
+{
+    const R q = u * nx + v * ny, w = v * nx - u * ny;
+    const R hs = h > hd ? h : R(0);
+    R fq, fw;
+    hllc_normal(g, hs, q, w, hs, -q, w, fh, fq, fw);
+    fx = fq * nx - fw * ny;
+    fy = fq * ny + fw * nx;
+    p = R(0.5) * g * (h * h - hs * hs);
+}
+
+// Inflow segment: discharge q_in per unit length enters through the edge; boundary depth
+// h_b = max(h, (q_in^2/g)^(1/3)).  Returns the boundary wave speed q_in/h_b + sqrt(g h_b).
+template <typename R>
+__device__ __forceinline__ R inflow_flux(R g, R q_in, R h, R nx, R ny, R &fh, R &fx, R &fy)
+{
+    const R hc = cbrt(q_in * q_in / g);
+    const R hb = fmax(h, hc);
+    const R mom = q_in * q_in / hb + R(0.5) * g * hb * hb;
+    fh = -q_in;
+    fx = mom * nx;
+    fy = mom * ny;
+    return q_in / hb + sqrt(g * hb);
+}
+
+template <typename R>
+__device__ __forceinline__ R inflow_speed(R g, R q_in, R h)
+{
+    const R hc = cbrt(q_in * q_in / g);
+    const R hb = fmax(h, hc);
+    return q_in / hb + sqrt(g * hb);
+}
+
+// ------------------------------------------------------------------------ geometry
+
+// Local edge k of a counter-clockwise triangle runs from node k to node k+1; its outward
+// unit normal is (dy, -dx) / l (section 2.2, eq. 3, Fig. 1).  Coordinates are double for both
+// precisions; the edge vector is rounded to R after the subtraction.
+template <typename R>
+struct CellGeom {
+    R nx[3], ny[3], l[3];
+    R area, inradius;
+};
+
+template <typename R>
+__device__ __forceinline__ void cell_geometry(const double2 *__restrict__ xy, int32_t n0,
+                                              int32_t n1, int32_t n2, CellGeom<R> &gm)
+{
+    const double2 p0 = xy[n0], p1 = xy[n1], p2 = xy[n2];
+    const double ex[3] = {p1.x - p0.x, p2.x - p1.x, p0.x - p2.x};
+    const double ey[3] = {p1.y - p0.y, p2.y - p1.y, p0.y - p2.y};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const R dx = static_cast<R>(ex[k]), dy = static_cast<R>(ey[k]);
+        const R l = sqrt(dx * dx + dy * dy);
+        gm.nx[k] = dy / l;
+        gm.ny[k] = -dx / l;
+        gm.l[k] = l;
+    }
+    gm.area = static_cast<R>(0.5 * (ex[0] * ey[1] - ey[0] * ex[1]));
+    gm.inradius = R(2) * gm.area / (gm.l[0] + gm.l[1] + gm.l[2]);
+}
+
+// ------------------------------------------------------------------------ reductions
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_or(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide (kBlock work-items) min / sum / or; thread 0 writes the block's partials.
+__device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
+                                               const Partials &part)
+{
+    __shared__ double s_dt[kBlock / 64];
+    __shared__ int s_cl[kBlock / 64], s_fl[kBlock / 64];
+    dtc = wave_min(dtc);
+    clamp = wave_sum(clamp);
+    flag = wave_or(flag);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_dt[wv] = dtc;
+        s_cl[wv] = clamp;
+        s_fl[wv] = flag;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            dtc = fmin(dtc, s_dt[w]);
+            clamp += s_cl[w];
+            flag |= s_fl[w];
+        }
+        part.dt[blockIdx.x] = dtc;
+        part.clamps[blockIdx.x] = clamp;
+        part.flags[blockIdx.x] = flag;
+    }
+}
+
+// CFL bound r / (|u| + sqrt(g h)) of a cell (inflow edges add their boundary speed);
+// +inf for a dry cell without inflow.
+template <typename R>
+__device__ __forceinline__ R cell_dt(R g, R hd, R h, R hu, R hv, R inradius, const int32_t *nb,
+                                     const StepConfig &cfg)
+{
+    R s = R(0);
+    if (h > hd) {
+        const R u = hu / h, v = hv / h;
+        s = sqrt(u * u + v * v) + sqrt(g * h);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (nb[k] < SWE_WALL) {
+            const R sb = inflow_speed(g, static_cast<R>(cfg.inflow_q[-2 - nb[k]]), h);
+            if (sb > s) s = sb;
+        }
+    return s > R(0) ? inradius / s : static_cast<R>(kInf);
+}
+
+// ------------------------------------------------------------------------ kernels
+
+template <typename R>
+struct StepArgs {
+    const int32_t *__restrict__ nbr;
+    const int32_t *__restrict__ c2n;
+    const double2 *__restrict__ xy;
+    const R *__restrict__ z;
+    const R *__restrict__ n;
+    const R *__restrict__ h;
+    const R *__restrict__ hu;
+    const R *__restrict__ hv;
+    R *__restrict__ ho;
+    R *__restrict__ huo;
+    R *__restrict__ hvo;
+    const Ctrl *ctrl;
+    Partials part;
+};
+
+// One explicit step for every cell (eq. 4 with the source treatments of section 2.2).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<R> a, StepConfig cfg)
+{
+    if (a.ctrl->done) return;   // uniform over the grid: the state has stopped
+    const int64_t T = cfg.n_cells;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
+    const R dt = static_cast<R>(a.ctrl->dt);
+    R dtc = static_cast<R>(kInf);
+    int clamp = 0, flag = 0;
+    if (i < T) {
+        CellGeom<R> gm;
+        cell_geometry<R>(a.xy, a.c2n[i], a.c2n[T + i], a.c2n[2 * T + i], gm);
+        const R h = a.h[i], hu = a.hu[i], hv = a.hv[i], z = a.z[i];
+        const R u = velocity(h, hu, hd), v = velocity(h, hv, hd);
+        int32_t nb[3];
+        R acc0 = R(0), acc1 = R(0), acc2 = R(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            nb[k] = a.nbr[k * T + i];
+            const int32_t j = nb[k];
+            R fh, fx, fy, p;
+            if (j >= 0) {
+                interface_flux<R>(g, hd, h, u, v, z, a.h[j], a.hu[j], a.hv[j], a.z[j], gm.nx[k],
+                                  gm.ny[k], fh, fx, fy, p);
+            } else if (j == SWE_WALL) {
+                wall_flux<R>(g, hd, h, u, v, gm.nx[k], gm.ny[k], fh, fx, fy, p);
+            } else {
+                inflow_flux<R>(g, static_cast<R>(cfg.inflow_q[-2 - j]), h, gm.nx[k], gm.ny[k],
+                               fh, fx, fy);
+                p = R(0);
+            }
+            const R c0 = gm.l[k] * fh;
+            const R c1 = gm.l[k] * (fx + p * gm.nx[k]);
+            const R c2 = gm.l[k] * (fy + p * gm.ny[k]);
+            if (k == 0) {
+                acc0 = c0; acc1 = c1; acc2 = c2;
+            } else {
+                acc0 = acc0 + c0; acc1 = acc1 + c1; acc2 = acc2 + c2;
+            }
+        }
+        // explicit Euler update, positivity clamp, semi-implicit friction
+        const R r = dt / gm.area;
+        R hs = h - r * acc0;
+        const R hus = hu - r * acc1;
+        const R hvs = hv - r * acc2;
+        if (hs < R(0)) {
+            clamp = 1;
+            hs = R(0);
+        }
+        R hun, hvn;
+        if (hs > hd) {
+            const R nm = a.n[i];
+            const R mag = sqrt(hus * hus + hvs * hvs);
+            const R d = R(1) + dt * g * nm * nm * mag / (hs * hs * cbrt(hs));
+            hun = hus / d;
+            hvn = hvs / d;
+        } else {
+            hun = R(0);
+            hvn = R(0);
+        }
+        a.ho[i] = hs;
+        a.huo[i] = hun;
+        a.hvo[i] = hvn;
+        if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
+        dtc = cell_dt<R>(g, hd, hs, hun, hvn, gm.inradius, nb, cfg);
+    }
+    block_partials(static_cast<double>(dtc), clamp, flag, a.part);
+}
+
+// CFL bounds of the initial state.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig cfg)
+{
+    const int64_t T = cfg.n_cells;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
+    R dtc = static_cast<R>(kInf);
+    int flag = 0;
+    if (i < T) {
+        CellGeom<R> gm;
+        cell_geometry<R>(a.xy, a.c2n[i], a.c2n[T + i], a.c2n[2 * T + i], gm);
+        const int32_t nb[3] = {a.nbr[i], a.nbr[T + i], a.nbr[2 * T + i]};
+        const R h = a.h[i], hu = a.hu[i], hv = a.hv[i];
+        if (!isfinite(h) || !isfinite(hu) || !isfinite(hv)) flag = kStatusNonFinite;
+        dtc = cell_dt<R>(g, hd, h, hu, hv, gm.inradius, nb, cfg);
+    }
+    block_partials(static_cast<double>(dtc), 0, flag, a.part);
+}
+
+constexpr int kPassThreads = 1024;
+
+// Reduce the per-block partials into the control block: account for the step just taken
+// (mode 1) or start the state (mode 0), then set the next step's dt (CFL, replayed, or cut
+// at t_end).
+__global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl, Partials part,
+                                                               int64_t nb, double courant,
+                                                               const double *dt_seq,
+                                                               int64_t n_seq, int mode,
+                                                               double t0, double t_end,
+                                                               int cur0)
+{
+    __shared__ double s_dt[kPassThreads / 64];
+    __shared__ long long s_cl[kPassThreads / 64];
+    __shared__ int s_fl[kPassThreads / 64];
+    if (mode == 1 && ctrl->done) return;
+    double m = kInf;
+    long long cl = 0;
+    int fl = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += kPassThreads) {
+        m = fmin(m, part.dt[b]);
+        cl += part.clamps[b];
+        fl |= part.flags[b];
+    }
+    m = wave_min(m);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cl += __shfl_xor(cl, off, 64);
+    fl = wave_or(fl);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_dt[wv] = m;
+        s_cl[wv] = cl;
+        s_fl[wv] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < kPassThreads / 64; ++w) {
+        m = fmin(m, s_dt[w]);
+        cl += s_cl[w];
+        fl |= s_fl[w];
+    }
+    Ctrl c = *ctrl;
+    if (mode == 0) {
+        c.t = t0;
+        c.dt = 0.0;
+        c.t_end = t_end;
+        c.dt_min = 0.0; c.dt_max = 0.0; c.dt_sum = 0.0;
+        c.steps = 0; c.run_step = 0; c.clamps = 0;
+        c.status = 0; c.done = 0; c.last = 0;
+        c.cur0 = cur0;
+        if (t_end > 0.0 && t0 >= t_end) c.done = 1;
+    } else {
+        c.t = c.last ? c.t_end : c.t + c.dt;
+        c.dt_min = c.steps == 0 ? c.dt : fmin(c.dt_min, c.dt);
+        c.dt_max = c.steps == 0 ? c.dt : fmax(c.dt_max, c.dt);
+        c.dt_sum = c.dt_sum + c.dt;
+        c.steps += 1;
+        c.run_step += 1;
+        c.clamps += cl;
+        if (c.last) c.done = 1;
+    }
+    if (fl & kStatusNonFinite) {
+        c.status |= kStatusNonFinite;
+        c.done = 1;
+    }
+    if (!c.done) {
+        double dt = courant * m;
+        if (dt_seq) dt = c.run_step < n_seq ? dt_seq[c.run_step] : c.dt;
+        c.last = 0;
+        if (!(dt < kInf)) {
+            c.status |= kStatusDry;
+            c.done = 1;
+        } else if (!(dt > 0.0)) {
+            c.status |= kStatusBadDt;
+            c.done = 1;
+        } else {
+            if (c.t_end > 0.0 && dt >= c.t_end - c.t) {
+                dt = c.t_end - c.t;
+                c.last = 1;
+            }
+            c.dt = dt;
+        }
+    }
+    *ctrl = c;
+}
+
+// Start a run: restart the dt_seq index and, when replaying, take dt_seq[0] (cut at t_end).
+__global__ void run_begin_kernel(Ctrl *ctrl, const double *dt_seq)
+{
+    if (threadIdx.x != 0) return;
+    Ctrl c = *ctrl;
+    c.run_step = 0;
+    if (dt_seq && !c.done) {
+        double dt = dt_seq[0];
+        c.last = 0;
+        if (!(dt > 0.0) || !(dt < kInf)) {
+            c.status |= kStatusBadDt;
+            c.done = 1;
+        } else {
+            if (c.t_end > 0.0 && dt >= c.t_end - c.t) {
+                dt = c.t_end - c.t;
+                c.last = 1;
+            }
+            c.dt = dt;
+        }
+    }
+    *ctrl = c;
+}
+
+// Test hook: interface or wall fluxes on independent edges.
+template <typename R>
+__global__ void flux_eval_kernel(int64_t n, R g, R hd, const R *hl, const R *hul, const R *hvl,
+                                 const R *zl, const R *hr, const R *hur, const R *hvr,
+                                 const R *zr, const R *nx, const R *ny, R *f, R *p)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const R h = hl[i];
+    const R u = velocity(h, hul[i], hd), v = velocity(h, hvl[i], hd);
+    R fh, fx, fy, pp;
+    if (hr)
+        interface_flux<R>(g, hd, h, u, v, zl[i], hr[i], hur[i], hvr[i], zr[i], nx[i], ny[i], fh,
+                          fx, fy, pp);
+    else
+        wall_flux<R>(g, hd, h, u, v, nx[i], ny[i], fh, fx, fy, pp);
+    f[3 * i] = fh;
+    f[3 * i + 1] = fx;
+    f[3 * i + 2] = fy;
+    p[i] = pp;
+}
+
+template <typename R>
+StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
+{
+    StepArgs<R> a;
+    a.nbr = dm.nbr;
+    a.c2n = dm.c2n;
+    a.xy = reinterpret_cast<const double2 *>(dm.xy);
+    a.z = static_cast<const R *>(s.z);
+    a.n = static_cast<const R *>(s.n);
+    a.h = static_cast<const R *>(s.h[cur]);
+    a.hu = static_cast<const R *>(s.hu[cur]);
+    a.hv = static_cast<const R *>(s.hv[cur]);
+    a.ho = static_cast<R *>(s.h[1 - cur]);
+    a.huo = static_cast<R *>(s.hu[1 - cur]);
+    a.hvo = static_cast<R *>(s.hv[1 - cur]);
+    a.ctrl = static_cast<const Ctrl *>(s.ctrl);
+    a.part = partials_of(s.work, dm.n_cells);
+    return a;
+}
+
+}  // namespace
+
+int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
+                double t0, double t_end, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nb = n_blocks(cfg.n_cells);
+    if (dtype == SWE_F64)
+        init_kernel<double><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<double>(dm, s, s.cur), cfg);
+    else
+        init_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<float>(dm, s, s.cur), cfg);
+    dt_pass_kernel<<<1, kPassThreads, 0, st>>>(static_cast<Ctrl *>(s.ctrl),
+                                               partials_of(s.work, cfg.n_cells), nb, cfg.courant,
+                                               nullptr, 0, 0, t0, t_end, s.cur);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
+                int cur, const double *dt_seq, int64_t n_seq, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nb = n_blocks(cfg.n_cells);
+    if (dtype == SWE_F64)
+        step_kernel<double><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<double>(dm, s, cur), cfg);
+    else
+        step_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<float>(dm, s, cur), cfg);
+    dt_pass_kernel<<<1, kPassThreads, 0, st>>>(static_cast<Ctrl *>(s.ctrl),
+                                               partials_of(s.work, cfg.n_cells), nb, cfg.courant,
+                                               dt_seq, n_seq, 1, 0.0, 0.0, 0);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream)
+{
+    run_begin_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(static_cast<Ctrl *>(s.ctrl),
+                                                                      dt_seq);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *hl,
+                     const void *hul, const void *hvl, const void *zl, const void *hr,
+                     const void *hur, const void *hvr, const void *zr, const void *nx,
+                     const void *ny, void *f, void *p, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nb = (n + 255) / 256;
+    if (dtype == SWE_F64) {
+        using R = double;
+        flux_eval_kernel<R><<<dim3(nb), dim3(256), 0, st>>>(
+            n, g, h_dry, (const R *)hl, (const R *)hul, (const R *)hvl, (const R *)zl,
+            (const R *)hr, (const R *)hur, (const R *)hvr, (const R *)zr, (const R *)nx,
+            (const R *)ny, (R *)f, (R *)p);
+    } else {
+        using R = float;
+        flux_eval_kernel<R><<<dim3(nb), dim3(256), 0, st>>>(
+            n, (R)g, (R)h_dry, (const R *)hl, (const R *)hul, (const R *)hvl, (const R *)zl,
+            (const R *)hr, (const R *)hur, (const R *)hvr, (const R *)zr, (const R *)nx,
+            (const R *)ny, (R *)f, (R *)p);
+    }
+    return static_cast<int>(hipGetLastError());
+}
+
+}  // namespace swe

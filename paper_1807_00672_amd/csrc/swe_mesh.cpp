@@ -1,0 +1,315 @@
+// Host-side mesh builder of libswe: orientation, interface matching, boundary codes, Morton
+// renumbering of cells and first-touch renumbering of nodes.
+//
+// The paper's domain is a set of triangles (section 2.2, eq. 3) and its flux loop runs over
+// interfaces (section 2.3).  The step kernels instead gather per cell, so the builder turns
+// the triangle list into per-cell neighbour lists in an order that keeps neighbours close in
+// memory.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "swe_internal.h"
+
+namespace {
+
+struct Fail {
+    int32_t code;
+    std::string msg;
+};
+
+inline uint32_t spread_bits(uint32_t v)  // 16 bits -> even bit positions of 32
+{
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Stable LSD radix sort of (key, index) by a 32-bit key, two 16-bit passes.
+void radix_sort_by_key(std::vector<uint32_t> &key, std::vector<int32_t> &idx)
+{
+    const size_t n = key.size();
+    std::vector<uint32_t> k2(n);
+    std::vector<int32_t> i2(n);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int sh = 16 * pass;
+        std::vector<size_t> cnt(65537, 0);
+        for (size_t i = 0; i < n; ++i) ++cnt[((key[i] >> sh) & 0xffffu) + 1];
+        for (size_t b = 1; b <= 65536; ++b) cnt[b] += cnt[b - 1];
+        for (size_t i = 0; i < n; ++i) {
+            const size_t d = cnt[(key[i] >> sh) & 0xffffu]++;
+            k2[d] = key[i];
+            i2[d] = idx[i];
+        }
+        key.swap(k2);
+        idx.swap(i2);
+    }
+}
+
+void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_t nt,
+           const int32_t *tags, uint32_t flags)
+{
+    if (!xy || !tri) throw Fail{SWE_EINVAL, "null xy or tri"};
+    if (nv < 3 || nt < 1) throw Fail{SWE_EINVAL, "need at least 3 nodes and 1 triangle"};
+    if (nv > INT32_MAX / 2 || nt > INT32_MAX / 3)
+        throw Fail{SWE_EINVAL, "mesh too large for int32 indices"};
+    if (flags & ~SWE_MORTON) throw Fail{SWE_EINVAL, "unknown flags"};
+    for (int64_t j = 0; j < 2 * nv; ++j)
+        if (!isfinite(xy[j])) throw Fail{SWE_EINVAL, "non-finite node coordinate"};
+
+    const int64_t T = nt;
+    // 1. counter-clockwise triangles, local order kept; clockwise ones become (v0, v2, v1)
+    std::vector<int32_t> cn(3 * T), ct(3 * T, 0);
+    int32_t max_tag = 0;
+    for (int64_t c = 0; c < T; ++c) {
+        int32_t v0 = tri[3 * c], v1 = tri[3 * c + 1], v2 = tri[3 * c + 2];
+        if (v0 < 0 || v1 < 0 || v2 < 0 || v0 >= nv || v1 >= nv || v2 >= nv)
+            throw Fail{SWE_EMESH, "triangle " + std::to_string(c) + " has a node out of range"};
+        if (v0 == v1 || v1 == v2 || v0 == v2)
+            throw Fail{SWE_EMESH, "triangle " + std::to_string(c) + " repeats a node"};
+        const double e0x = xy[2 * v1] - xy[2 * v0], e0y = xy[2 * v1 + 1] - xy[2 * v0 + 1];
+        const double e1x = xy[2 * v2] - xy[2 * v1], e1y = xy[2 * v2 + 1] - xy[2 * v1 + 1];
+        const double cr = e0x * e1y - e0y * e1x;
+        if (!(cr != 0.0)) throw Fail{SWE_EMESH, "triangle " + std::to_string(c) + " has zero area"};
+        int32_t t0 = 0, t1 = 0, t2 = 0;
+        if (tags) {
+            t0 = tags[3 * c]; t1 = tags[3 * c + 1]; t2 = tags[3 * c + 2];
+            if (t0 < 0 || t1 < 0 || t2 < 0 || t0 > SWE_MAX_INFLOW || t1 > SWE_MAX_INFLOW ||
+                t2 > SWE_MAX_INFLOW)
+                throw Fail{SWE_EINVAL, "edge tag out of range [0, SWE_MAX_INFLOW]"};
+        }
+        if (cr < 0.0) {
+            std::swap(v1, v2);
+            std::swap(t0, t2);
+        }
+        cn[3 * c] = v0; cn[3 * c + 1] = v1; cn[3 * c + 2] = v2;
+        ct[3 * c] = t0; ct[3 * c + 1] = t1; ct[3 * c + 2] = t2;
+    }
+
+    // 2. match half-edges: bucket by their smaller node (counting sort), pair within buckets
+    std::vector<int64_t> start(nv + 1, 0);
+    for (int64_t h = 0; h < 3 * T; ++h) {
+        const int32_t a = cn[h], b = cn[(h / 3) * 3 + (h % 3 + 1) % 3];
+        ++start[std::min(a, b) + 1];
+    }
+    for (int64_t j = 0; j < nv; ++j) start[j + 1] += start[j];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    std::vector<int32_t> bucket(3 * T);
+    for (int64_t h = 0; h < 3 * T; ++h) {
+        const int32_t a = cn[h], b = cn[(h / 3) * 3 + (h % 3 + 1) % 3];
+        bucket[fill[std::min(a, b)]++] = static_cast<int32_t>(h);
+    }
+    std::vector<int32_t> nb_old(3 * T, SWE_WALL);
+    int64_t ne = 0, nbnd = 0, ninflow = 0;
+    for (int64_t lo = 0; lo < nv; ++lo) {
+        const int64_t s0 = start[lo], s1 = start[lo + 1];
+        for (int64_t x = s0; x < s1; ++x) {
+            const int32_t h = bucket[x];
+            if (h < 0) continue;  // already paired
+            const int32_t c = h / 3, k = h % 3;
+            const int32_t a = cn[h], b = cn[3 * c + (k + 1) % 3];
+            const int32_t hi = std::max(a, b);
+            int32_t mate = -1;
+            for (int64_t y = x + 1; y < s1; ++y) {
+                const int32_t g = bucket[y];
+                if (g < 0) continue;
+                const int32_t cg = g / 3, kg = g % 3;
+                const int32_t ag = cn[g], bg = cn[3 * cg + (kg + 1) % 3];
+                if (std::max(ag, bg) != hi) continue;
+                if (mate >= 0)
+                    throw Fail{SWE_EMESH, "edge (" + std::to_string(a) + "," + std::to_string(b) +
+                                              ") is shared by more than two triangles"};
+                if (ag == a)
+                    throw Fail{SWE_EMESH, "triangles " + std::to_string(c) + " and " +
+                                              std::to_string(cg) + " overlap along an edge"};
+                mate = static_cast<int32_t>(y);
+            }
+            ++ne;
+            if (mate >= 0) {
+                const int32_t g = bucket[mate];
+                nb_old[h] = g / 3;
+                nb_old[g] = c;
+                bucket[mate] = -1;
+            } else {
+                ++nbnd;
+                const int32_t tg = ct[h];
+                nb_old[h] = tg > 0 ? -1 - tg : SWE_WALL;
+                if (tg > 0) {
+                    ++ninflow;
+                    max_tag = std::max(max_tag, tg);
+                }
+            }
+            bucket[x] = -1;
+        }
+    }
+
+    // 3. geometry summary and centroids
+    swe_mesh_info &inf = m.info;
+    memset(&inf, 0, sizeof(inf));
+    inf.n_cells = T;
+    inf.n_nodes = nv;
+    inf.n_edges = ne;
+    inf.n_boundary_edges = nbnd;
+    inf.n_inflow_edges = ninflow;
+    inf.n_inflow_segments = max_tag;
+    inf.flags = flags;
+    inf.min_area = INFINITY;
+    inf.min_inradius = INFINITY;
+    inf.bbox[0] = inf.bbox[1] = INFINITY;
+    inf.bbox[2] = inf.bbox[3] = -INFINITY;
+    for (int64_t j = 0; j < nv; ++j) {
+        inf.bbox[0] = std::min(inf.bbox[0], xy[2 * j]);
+        inf.bbox[1] = std::min(inf.bbox[1], xy[2 * j + 1]);
+        inf.bbox[2] = std::max(inf.bbox[2], xy[2 * j]);
+        inf.bbox[3] = std::max(inf.bbox[3], xy[2 * j + 1]);
+    }
+    std::vector<uint32_t> key(T);
+    const double sx = inf.bbox[2] > inf.bbox[0] ? 65535.0 / (inf.bbox[2] - inf.bbox[0]) : 0.0;
+    const double sy = inf.bbox[3] > inf.bbox[1] ? 65535.0 / (inf.bbox[3] - inf.bbox[1]) : 0.0;
+    for (int64_t c = 0; c < T; ++c) {
+        const int32_t *v = &cn[3 * c];
+        double per = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double dx = xy[2 * v[(k + 1) % 3]] - xy[2 * v[k]];
+            const double dy = xy[2 * v[(k + 1) % 3] + 1] - xy[2 * v[k] + 1];
+            per += sqrt(dx * dx + dy * dy);
+        }
+        const double e0x = xy[2 * v[1]] - xy[2 * v[0]], e0y = xy[2 * v[1] + 1] - xy[2 * v[0] + 1];
+        const double e1x = xy[2 * v[2]] - xy[2 * v[1]], e1y = xy[2 * v[2] + 1] - xy[2 * v[1] + 1];
+        const double a = 0.5 * (e0x * e1y - e0y * e1x);
+        inf.min_area = std::min(inf.min_area, a);
+        inf.max_area = std::max(inf.max_area, a);
+        inf.total_area += a;
+        inf.min_inradius = std::min(inf.min_inradius, 2.0 * a / per);
+        const double cx = (xy[2 * v[0]] + xy[2 * v[1]] + xy[2 * v[2]]) / 3.0;
+        const double cy = (xy[2 * v[0] + 1] + xy[2 * v[1] + 1] + xy[2 * v[2] + 1]) / 3.0;
+        const uint32_t qx = static_cast<uint32_t>(std::min(65535.0, std::max(0.0, (cx - inf.bbox[0]) * sx)));
+        const uint32_t qy = static_cast<uint32_t>(std::min(65535.0, std::max(0.0, (cy - inf.bbox[1]) * sy)));
+        key[c] = spread_bits(qx) | (spread_bits(qy) << 1);
+    }
+
+    // 4. cell order: Morton key, ties by input index (stable sort of increasing indices)
+    m.perm.resize(T);
+    for (int64_t c = 0; c < T; ++c) m.perm[c] = static_cast<int32_t>(c);
+    if (flags & SWE_MORTON) radix_sort_by_key(key, m.perm);
+    std::vector<int32_t> inv(T);
+    for (int64_t i = 0; i < T; ++i) inv[m.perm[i]] = static_cast<int32_t>(i);
+
+    // 5. nodes in order of first use by the renumbered cells; unused nodes last
+    std::vector<int32_t> node_new(nv, -1);
+    m.node_perm.clear();
+    m.node_perm.reserve(nv);
+    for (int64_t i = 0; i < T; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const int32_t v = cn[3 * m.perm[i] + k];
+            if (node_new[v] < 0) {
+                node_new[v] = static_cast<int32_t>(m.node_perm.size());
+                m.node_perm.push_back(v);
+            }
+        }
+    for (int64_t j = 0; j < nv; ++j)
+        if (node_new[j] < 0) {
+            node_new[j] = static_cast<int32_t>(m.node_perm.size());
+            m.node_perm.push_back(static_cast<int32_t>(j));
+        }
+
+    // 6. structure-of-arrays neighbour and node lists in mesh order
+    m.nbr.resize(3 * T);
+    m.c2n.resize(3 * T);
+    for (int64_t i = 0; i < T; ++i) {
+        const int32_t c = m.perm[i];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t o = nb_old[3 * c + k];
+            m.nbr[k * T + i] = o >= 0 ? inv[o] : o;
+            m.c2n[k * T + i] = node_new[cn[3 * c + k]];
+        }
+    }
+    m.xy.resize(2 * nv);
+    for (int64_t j = 0; j < nv; ++j) {
+        m.xy[2 * j] = xy[2 * m.node_perm[j]];
+        m.xy[2 * j + 1] = xy[2 * m.node_perm[j] + 1];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t swe_mesh_create(const double *xy, int64_t nv, const int32_t *tri, int64_t nt,
+                        const int32_t *edge_tag, uint32_t flags, swe_mesh **out)
+{
+    if (!out) {
+        swe::set_error("swe_mesh_create: null out");
+        return SWE_EINVAL;
+    }
+    *out = nullptr;
+    swe_mesh *m = nullptr;
+    try {
+        m = new swe_mesh();
+        build(*m, xy, nv, tri, nt, edge_tag, flags);
+    } catch (const Fail &f) {
+        delete m;
+        swe::set_error("swe_mesh_create: " + f.msg);
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        delete m;
+        swe::set_error("swe_mesh_create: out of host memory");
+        return SWE_EINVAL;
+    } catch (...) {
+        delete m;
+        swe::set_error("swe_mesh_create: unexpected failure");
+        return SWE_EINVAL;
+    }
+    *out = m;
+    return SWE_OK;
+}
+
+int32_t swe_mesh_info_get(const swe_mesh *mesh, swe_mesh_info *out)
+{
+    if (!mesh || !out) {
+        swe::set_error("swe_mesh_info_get: null argument");
+        return SWE_EINVAL;
+    }
+    *out = mesh->info;
+    return SWE_OK;
+}
+
+int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t dst_bytes)
+{
+    if (!mesh || !dst) {
+        swe::set_error("swe_mesh_export: null argument");
+        return SWE_EINVAL;
+    }
+    const void *src = nullptr;
+    int64_t bytes = 0;
+    switch (which) {
+    case SWE_ARR_PERM: src = mesh->perm.data(); bytes = 4 * (int64_t)mesh->perm.size(); break;
+    case SWE_ARR_NBR: src = mesh->nbr.data(); bytes = 4 * (int64_t)mesh->nbr.size(); break;
+    case SWE_ARR_C2N: src = mesh->c2n.data(); bytes = 4 * (int64_t)mesh->c2n.size(); break;
+    case SWE_ARR_XY: src = mesh->xy.data(); bytes = 8 * (int64_t)mesh->xy.size(); break;
+    case SWE_ARR_NODE_PERM:
+        src = mesh->node_perm.data(); bytes = 4 * (int64_t)mesh->node_perm.size(); break;
+    default:
+        swe::set_error("swe_mesh_export: unknown array " + std::to_string(which));
+        return SWE_EINVAL;
+    }
+    if (dst_bytes < bytes) {
+        swe::set_error("swe_mesh_export: destination holds " + std::to_string(dst_bytes) +
+                       " bytes, array needs " + std::to_string(bytes));
+        return SWE_EINVAL;
+    }
+    memcpy(dst, src, static_cast<size_t>(bytes));
+    return SWE_OK;
+}
+
+void swe_mesh_destroy(swe_mesh *mesh) { delete mesh; }
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+"""Mesh and Solver: torch-owned device memory around the libswe C ABI.
+
+torch provides device memory and the stream; the library's kernels do all the work.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """A triangle mesh built by swe_mesh_create, with its arrays copied to the device.
+
+    xy: [V, 2] node coordinates; tri: [T, 3] node ids (either orientation); edge_tag: optional
+    [T, 3] boundary tags (0 wall, s >= 1 inflow segment s) of input edge (k, k+1).
+    """
+
+    def __init__(self, xy, tri, edge_tag=None, morton: bool = True, device="cuda"):
+        self.handle = A.swe_mesh_create(xy, tri, edge_tag, A.SWE_MORTON if morton else 0)
+        self.info = A.swe_mesh_info_get(self.handle)
+        t, v = int(self.info.n_cells), int(self.info.n_nodes)
+        self.n_cells, self.n_nodes = t, v
+        self.perm = A.swe_mesh_export(self.handle, A.SWE_ARR_PERM, t, np.int32)
+        self.nbr = A.swe_mesh_export(self.handle, A.SWE_ARR_NBR, 3 * t, np.int32)
+        self.c2n = A.swe_mesh_export(self.handle, A.SWE_ARR_C2N, 3 * t, np.int32)
+        self.xy = A.swe_mesh_export(self.handle, A.SWE_ARR_XY, 2 * v, np.float64)
+        self.node_perm = A.swe_mesh_export(self.handle, A.SWE_ARR_NODE_PERM, v, np.int32)
+        self.device = None
+        if device is not None:
+            self.to(device)
+
+    def to(self, device="cuda"):
+        d = torch.device(device)
+        if d.type == "cuda" and d.index is None:
+            d = torch.device("cuda", torch.cuda.current_device())
+        self.device = d
+        self.d_nbr = torch.from_numpy(self.nbr).to(self.device)
+        self.d_c2n = torch.from_numpy(self.c2n).to(self.device)
+        self.d_xy = torch.from_numpy(self.xy).to(self.device)
+        self.dev = A.swe_dev_mesh(self.n_cells, self.n_nodes, _ptr(self.d_nbr), _ptr(self.d_c2n),
+                                  _ptr(self.d_xy))
+        return self
+
+    def to_mesh_order(self, a):
+        return np.asarray(a)[self.perm]
+
+    def to_input_order(self, a):
+        a = np.asarray(a)
+        out = np.empty_like(a)
+        out[self.perm] = a
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and A is not None and A.lib is not None:
+            A.swe_mesh_destroy(h)
+            self.handle = None
+
+
+class Solver:
+    """One simulation state on the device: U = (h, hu, hv) ping-pong buffers, bed, roughness,
+    the control block (time, dt, counters) and the reduction workspace."""
+
+    def __init__(self, mesh: Mesh, z, n, h, hu, hv, dtype: str = "f64", g=9.81, courant=0.7,
+                 h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None):
+        if mesh.device is None:
+            raise ValueError("mesh has no device arrays")
+        self.mesh = mesh
+        self.dtype = {"f64": A.SWE_F64, "f32": A.SWE_F32}[dtype]
+        self.tdtype = torch.float64 if self.dtype == A.SWE_F64 else torch.float32
+        dev = mesh.device
+        self._q = np.ascontiguousarray(inflow_q if inflow_q is not None else [], np.float64)
+        self.params = A.swe_params(g, courant, h_dry, self.dtype, self._q.size,
+                                   self._q.ctypes.data_as(C.POINTER(C.c_double)))
+        t = mesh.n_cells
+
+        def field(a):
+            return torch.from_numpy(mesh.to_mesh_order(np.asarray(a, np.float64))).to(
+                device=dev, dtype=self.tdtype).contiguous()
+
+        self.z, self.n = field(z), field(n)
+        self.h = [field(h), torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.hu = [field(hu), torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.hv = [field(hv), torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.ctrl = torch.zeros(A.SWE_CTRL_BYTES // 8, dtype=torch.float64, device=dev)
+        self.work = torch.zeros(A.swe_workspace_bytes(t), dtype=torch.uint8, device=dev)
+        self.state = A.swe_state(
+            (C.c_void_p * 2)(self.h[0].data_ptr(), self.h[1].data_ptr()),
+            (C.c_void_p * 2)(self.hu[0].data_ptr(), self.hu[1].data_ptr()),
+            (C.c_void_p * 2)(self.hv[0].data_ptr(), self.hv[1].data_ptr()),
+            _ptr(self.z), _ptr(self.n), _ptr(self.ctrl), _ptr(self.work), 0, 0)
+        self.init(t0, t_end, stream)
+
+    def init(self, t0=0.0, t_end=0.0, stream=None):
+        A.swe_state_init(self.mesh.handle, self.mesh.dev, self.params, self.state, t0, t_end,
+                         _stream_handle(stream))
+
+    def step(self, stream=None):
+        A.swe_step(self.mesh.handle, self.mesh.dev, self.params, self.state, _stream_handle(stream))
+
+    def run(self, n_steps: int, dt_seq: torch.Tensor | None = None, sync: bool = True,
+            stream=None):
+        """Queue n_steps steps; with sync, wait and return (status code, stats dict)."""
+        seq = None
+        if dt_seq is not None:
+            if dt_seq.dtype != torch.float64 or dt_seq.device != self.mesh.device:
+                raise ValueError("dt_seq must be a float64 tensor on the mesh device")
+            seq = _ptr(dt_seq.contiguous())
+        st = A.swe_run_stats() if sync else None
+        rc = A.swe_run(self.mesh.handle, self.mesh.dev, self.params, self.state, n_steps, seq,
+                       st, _stream_handle(stream))
+        return (rc, st.as_dict()) if sync else None
+
+    def stats(self, stream=None):
+        st = A.swe_run_stats()
+        rc = A.swe_read_stats(self.state, st, _stream_handle(stream))
+        return rc, st.as_dict()
+
+    @property
+    def cur(self) -> int:
+        return int(self.state.cur)
+
+    def device_state(self):
+        """The current (h, hu, hv) device tensors, mesh order."""
+        c = self.cur
+        return self.h[c], self.hu[c], self.hv[c]
+
+    def numpy_state(self):
+        """The current state as float64 numpy arrays in input order (synchronises)."""
+        self.stats()
+        return tuple(self.mesh.to_input_order(t.double().cpu().numpy())
+                     for t in self.device_state())

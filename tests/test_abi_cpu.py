@@ -1,0 +1,150 @@
+"""Host-side checks of libswe that need no GPU: the library loads, exports every function
+include/swe.h declares, and its mesh builder agrees with the oracle's independent
+connectivity (section 2.2 triangles; section 2.3 interfaces)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+swe = pytest.importorskip("paper_1807_00672_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swe.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swe_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert "swe_run" in names and "swe_mesh_create" in names and len(names) >= 11
+    for n in names:
+        assert hasattr(swe.lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", swe.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (swe_\w+)", out))
+    assert set(names) <= exported
+    assert set(names) == set(swe.EXPORTS)
+
+
+def test_library_embeds_gfx950_code():
+    with open(swe.LIB_PATH, "rb") as f:
+        blob = f.read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("morton", [True, False])
+def test_mesh_builder_agrees_with_oracle_connectivity(k, morton):
+    c = gen.small(k)
+    m = swe.Mesh(c.xy, c.tri, morton=morton, device=None)
+    om = oracle.Mesh(c.xy, c.tri)
+    info = m.info
+    assert (info.n_cells, info.n_nodes, info.n_edges, info.n_boundary_edges) == (
+        om.n_cells, om.n_nodes, om.n_edges, om.n_boundary)
+    assert info.n_nodes - info.n_edges + info.n_cells == 1
+    assert 2 * info.n_edges == 3 * info.n_cells + info.n_boundary_edges
+    t = m.n_cells
+    perm = m.perm
+    assert np.array_equal(np.sort(perm), np.arange(t))            # bijection
+    if not morton:
+        assert np.array_equal(perm, np.arange(t))
+    ocn, onb, oarea, _ = om.arrays()
+    # nodes: same counter-clockwise local order per cell, through both renumberings
+    c2n = m.c2n.reshape(3, t).T
+    assert np.array_equal(m.node_perm[c2n], ocn[perm])
+    xy = m.xy.reshape(-1, 2)
+    assert np.array_equal(xy, c.xy[m.node_perm])
+    # neighbours: same cells across the same local edges, boundary codes kept
+    nbr = m.nbr.reshape(3, t).T
+    inner = nbr >= 0
+    mapped = np.where(inner, perm[np.where(inner, nbr, 0)], nbr)
+    assert np.array_equal(mapped, onb[perm])
+    assert info.total_area == pytest.approx(oarea.sum(), rel=1e-13)
+
+
+def test_morton_order_brings_neighbours_closer():
+    """Rows of 800 triangles: in input order a 256-cell tile holds a third of a row, so the
+    neighbours above and below fall outside it; Morton tiles are compact."""
+    c = gen.wetdry(nx=400, ny=200, steps=1)
+    far, same = {}, {}
+    for morton in (False, True):
+        m = swe.Mesh(c.xy, c.tri, morton=morton, device=None)
+        t = m.n_cells
+        nbr = m.nbr.reshape(3, t).T
+        i = np.repeat(np.arange(t)[:, None], 3, 1)
+        ok = nbr >= 0
+        far[morton] = np.percentile(np.abs(nbr[ok] - i[ok]), 90)
+        same[morton] = (nbr[ok] // 256 == i[ok] // 256).mean()
+    assert far[True] < far[False] / 8
+    assert same[True] > 0.85 > 0.7 > same[False]
+
+
+def test_clockwise_input_and_edge_tags_are_reoriented():
+    c = gen.ensemble_scenario(3)
+    tri = c.tri.copy()
+    tag = c.edge_tag.copy()
+    flip = np.arange(len(tri)) % 3 == 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]        # clockwise: edges become (e2^-1, e1^-1, e0^-1)
+    tag[flip] = tag[flip][:, [2, 1, 0]]
+    a = swe.Mesh(c.xy, c.tri, c.edge_tag, device=None)
+    b = swe.Mesh(c.xy, tri, tag, device=None)
+    assert np.array_equal(a.nbr, b.nbr) and np.array_equal(a.c2n, b.c2n)
+    assert a.info.n_inflow_edges == (c.edge_tag > 0).sum() == b.info.n_inflow_edges
+    assert a.info.n_inflow_segments == 1
+    assert (a.nbr == -2).sum() == a.info.n_inflow_edges
+
+
+def test_bad_meshes_are_rejected_with_codes():
+    xy = np.array([[0, 0], [1, 0], [0, 1], [1, 1], [2, 2]], float)
+    ok = np.array([[0, 1, 2], [1, 3, 2]], np.int32)
+    swe.Mesh(xy, ok, device=None)
+    cases = {
+        "node out of range": (np.array([[0, 1, 7]]), swe.SWE_EMESH),
+        "repeated node": (np.array([[0, 1, 1]]), swe.SWE_EMESH),
+        "zero area": (np.array([[0, 3, 4]]), swe.SWE_EMESH),
+        "edge shared three times": (np.array([[0, 1, 2], [1, 3, 2], [1, 4, 2]]), swe.SWE_EMESH),
+        "overlapping triangles": (np.array([[0, 1, 2], [0, 1, 3]]), swe.SWE_EMESH),
+    }
+    for name, (tri, code) in cases.items():
+        with pytest.raises(swe.SweError) as e:
+            swe.swe_mesh_create(xy, tri)
+        assert e.value.code == code, name
+        assert swe.swe_last_error()
+    with pytest.raises(swe.SweError) as e:
+        swe.swe_mesh_create(xy, np.zeros((0, 3), np.int32))
+    assert e.value.code == swe.SWE_EINVAL
+    bad = xy.copy()
+    bad[4, 0] = np.nan
+    with pytest.raises(swe.SweError) as e:
+        swe.swe_mesh_create(bad, ok)
+    assert e.value.code == swe.SWE_EINVAL
+    out = C.c_void_p()
+    assert swe.lib.swe_mesh_create(None, 5, None, 2, None, 0, C.byref(out)) == swe.SWE_EINVAL
+    with pytest.raises(swe.SweError) as e:
+        swe.swe_mesh_create(xy, ok, edge_tag=np.full((2, 3), 99))
+    assert e.value.code == swe.SWE_EINVAL
+
+
+def test_step_calls_reject_bad_arguments_without_touching_a_device():
+    c = gen.small(1)
+    m = swe.Mesh(c.xy, c.tri, device=None)
+    dm = swe.swe_dev_mesh(m.n_cells, m.n_nodes, None, None, None)
+    p = swe.swe_params(9.81, 0.7, 1e-6, swe.SWE_F64, 0, None)
+    s = swe.swe_state()
+    for bad in (swe.swe_params(0.0, 0.7, 1e-6, 0, 0, None), swe.swe_params(9.81, 1.5, 1e-6, 0, 0, None),
+                swe.swe_params(9.81, 0.7, -1.0, 0, 0, None), swe.swe_params(9.81, 0.7, 1e-6, 7, 0, None)):
+        assert swe.lib.swe_step(m.handle, C.byref(dm), C.byref(bad), C.byref(s), None) == swe.SWE_EINVAL
+    assert swe.lib.swe_step(m.handle, C.byref(dm), C.byref(p), C.byref(s), None) == swe.SWE_EINVAL
+    assert "null" in swe.swe_last_error()
+    assert swe.lib.swe_run(None, None, None, None, 1, None, None, None) == swe.SWE_EINVAL
+    assert swe.swe_workspace_bytes(10000) >= 40 * 16

@@ -1,0 +1,216 @@
+"""HIP path against the FP64 oracle, element by element, on seeded inputs.
+
+The oracle follows section 2 of the paper (eq. 4 over the three edges of each triangle, HLLC
+with hydrostatic reconstruction, semi-implicit friction, CFL with Courant 0.7).  Tolerances:
+FP64 1e-12 relative per field; FP32 1e-5 relative to max h, wet/dry masks identical outside a
+band of 1e-5 max h around the dry threshold; step counts identical.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from parity import TOL_F32, TOL_F64, errors, mask_mismatch, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand_edges(rng, n, dry_frac=0.2):
+    h = rng.uniform(0.0, 3.0, n)
+    h[rng.random(n) < dry_frac] = 0.0
+    h[rng.random(n) < 0.05] = 0.5e-6
+    return h, rng.uniform(-6, 6, n) * h, rng.uniform(-6, 6, n) * h
+
+
+@pytest.mark.parametrize("wall", [False, True])
+def test_flux_matches_oracle_bitwise_in_fp64(gpu, wall):
+    import torch
+    rng = np.random.default_rng(11)
+    n = 1 << 20
+    hl, hul, hvl = _rand_edges(rng, n)
+    hr, hur, hvr = _rand_edges(rng, n)
+    zl = rng.uniform(-1, 1, n)
+    zr = np.where(rng.random(n) < 0.3, zl, rng.uniform(-1, 1, n))
+    th = rng.uniform(0, 2 * math.pi, n)
+    nx, ny = np.cos(th), np.sin(th)
+    if wall:
+        f_o, p_o = oracle.wall(hl, hul, hvl, nx, ny)
+    else:
+        f_o, p_o, _ = oracle.interface(hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny)
+    d = {k: torch.from_numpy(v).cuda() for k, v in dict(hl=hl, hul=hul, hvl=hvl, zl=zl, hr=hr,
+                                                        hur=hur, hvr=hvr, zr=zr, nx=nx,
+                                                        ny=ny).items()}
+    f = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    p = torch.empty(n, dtype=torch.float64, device="cuda")
+    P = lambda t: t.data_ptr()
+    gpu.swe_flux_eval(gpu.SWE_F64, n, 9.81, 1e-6, P(d["hl"]), P(d["hul"]), P(d["hvl"]),
+                      P(d["zl"]), None if wall else P(d["hr"]), None if wall else P(d["hur"]),
+                      None if wall else P(d["hvr"]), None if wall else P(d["zr"]), P(d["nx"]),
+                      P(d["ny"]), P(f), P(p))
+    torch.cuda.synchronize()
+    f_g = f.cpu().numpy().reshape(n, 3)
+    assert np.array_equal(f_g, f_o)
+    assert np.array_equal(p.cpu().numpy(), p_o)
+
+
+def test_flux_fp32_is_close(gpu):
+    import torch
+    rng = np.random.default_rng(12)
+    n = 1 << 18
+    hl, hul, hvl = _rand_edges(rng, n)
+    hr, hur, hvr = _rand_edges(rng, n)
+    zl = rng.uniform(-1, 1, n)
+    zr = rng.uniform(-1, 1, n)
+    th = rng.uniform(0, 2 * math.pi, n)
+    nx, ny = np.cos(th), np.sin(th)
+    f_o, p_o, _ = oracle.interface(hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny)
+    args = [torch.from_numpy(v.astype(np.float32)).cuda()
+            for v in (hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny)]
+    f = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+    p = torch.empty(n, dtype=torch.float32, device="cuda")
+    gpu.swe_flux_eval(gpu.SWE_F32, n, 9.81, 1e-6, *[a.data_ptr() for a in args], f.data_ptr(),
+                      p.data_ptr())
+    torch.cuda.synchronize()
+    f_g = f.cpu().numpy().reshape(n, 3).astype(np.float64)
+    # inputs were rounded to float: compare against the oracle on the rounded inputs
+    r = [a.cpu().numpy().astype(np.float64) for a in args]
+    f_r, p_r, _ = oracle.interface(*r)
+    scale = 1.0 + np.abs(f_r).max(axis=1)
+    # cells at the dry threshold may legitimately switch branch in float
+    ok = (np.abs(r[0] - 1e-6) > 1e-8) & (np.abs(r[4] - 1e-6) > 1e-8)
+    assert (np.abs(f_g - f_r).max(axis=1)[ok] / scale[ok]).max() < 5e-5
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fp64_parity_small_configs(gpu, k):
+    case = gen.small(k)
+    rc_o, *ora, dts, st_o = run_oracle(case)
+    rc_g, st_g, *g = run_gpu(case, "f64")
+    assert rc_o == 0 and rc_g == 0
+    assert st_g["steps"] == st_o["steps"] == case.steps
+    e = errors(case, g, ora)
+    print(f"config {k} small fp64: errors {e}, exact h {np.mean(g[0] == ora[0]):.4f}, "
+          f"t gpu {st_g['t']!r} oracle {st_o['t']!r}")
+    assert max(e) <= TOL_F64
+    assert st_g["t"] == pytest.approx(st_o["t"], rel=TOL_F64)
+    assert mask_mismatch(case, g[0], ora[0])[0] == 0
+    assert st_g["clamps"] == st_o["clamps"]
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_fp32_parity_small_configs(gpu, k):
+    case = gen.small(k)
+    rc_o, *ora, dts, st_o = run_oracle(case)
+    rc_g, st_g, *g = run_gpu(case, "f32")
+    assert rc_o == 0 and rc_g == 0 and st_g["steps"] == st_o["steps"]
+    hmax = np.abs(ora[0]).max()
+    e_h = np.abs(g[0] - ora[0]).max() / hmax
+    e = errors(case, g, ora)
+    mism, exempt = mask_mismatch(case, g[0], ora[0], band=TOL_F32 * hmax)
+    print(f"config {k} small fp32: errors {e}, mask mismatches {mism}, exempt {exempt}")
+    assert e_h <= TOL_F32
+    assert max(e[1:]) <= 10 * TOL_F32
+    assert mism == 0
+
+
+def test_morton_order_does_not_change_results(gpu):
+    case = gen.small(2)
+    a = run_gpu(case, "f64", steps=100, morton=True)
+    b = run_gpu(case, "f64", steps=100, morton=False)
+    for x, y in zip(a[2:], b[2:]):
+        assert np.array_equal(x, y)
+
+
+def test_runs_are_bitwise_repeatable_and_stepwise_equal(gpu):
+    import paper_1807_00672_amd as swe
+    case = gen.small(3)
+    a = run_gpu(case, "f64", steps=60)
+    b = run_gpu(case, "f64", steps=60)
+    for x, y in zip(a[2:], b[2:]):
+        assert np.array_equal(x, y)
+    m = swe.Mesh(case.xy, case.tri)
+    s = swe.Solver(m, case.z, case.n, case.h, case.hu, case.hv)
+    for _ in range(60):
+        s.step()
+    for x, y in zip(s.numpy_state(), a[2:]):
+        assert np.array_equal(x, y)
+
+
+def test_t_end_gives_the_oracle_step_count(gpu):
+    case = gen.config(1)
+    rc_o, *ora, dts, st_o = run_oracle(case, steps=100000, t_end=0.5)
+    rc_g, st_g, *g = run_gpu(case, "f64", steps=1000, t_end=0.5)
+    assert rc_o == 0 and rc_g == 0
+    assert st_g["steps"] == st_o["steps"] and st_g["t"] == 0.5 and st_g["done"] == 1
+    assert max(errors(case, g, ora)) <= TOL_F64
+
+
+def test_replayed_dt_sequence(gpu):
+    case = gen.small(2)
+    seq = np.full(80, 0.05)
+    seq[::7] = 0.08
+    rc_o, *ora, dts, st_o = run_oracle(case, steps=80, dt_seq=seq)
+    rc_g, st_g, *g = run_gpu(case, "f64", steps=80, dt_seq=seq)
+    assert rc_o == 0 and rc_g == 0 and st_g["steps"] == 80
+    assert st_g["dt_sum"] == pytest.approx(seq.sum(), rel=1e-15)
+    assert max(errors(case, g, ora)) <= TOL_F64
+
+
+def test_inflow_scenario_matches_oracle(gpu):
+    case = gen.ensemble_scenario(3)
+    rc_o, *ora, dts, st_o = run_oracle(case, steps=300)
+    rc_g, st_g, *g = run_gpu(case, "f64", steps=300)
+    assert rc_o == 0 and rc_g == 0
+    assert max(errors(case, g, ora)) <= TOL_F64
+
+
+def test_lake_at_rest_and_mass_on_gpu(gpu):
+    case = gen.lake_at_rest()
+    rc, st, h, hu, hv = run_gpu(case, "f64")
+    assert rc == 0 and st["steps"] == case.steps
+    hmax = case.h.max()
+    assert np.abs(h - case.h).max() <= 1e-12 * hmax
+    om = oracle.Mesh(case.xy, case.tri)
+    area = om.arrays()[2]
+    c1 = gen.small(2)
+    rc, st, h2, *_ = run_gpu(c1, "f64")
+    area2 = oracle.Mesh(c1.xy, c1.tri).arrays()[2]
+    m0, m1 = np.dot(c1.h, area2), np.dot(h2, area2)
+    assert abs(m1 - m0) / m0 <= 1e-12
+
+
+def test_tiny_meshes(gpu):
+    xy = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], float)
+    one = gen.Case("one", xy[:3], np.array([[0, 1, 2]], np.int32), np.zeros(1), np.full(1, 0.03),
+                   np.full(1, 0.7), np.zeros(1), np.zeros(1), 20)
+    rc, st, h, hu, hv = run_gpu(one, "f64")
+    assert rc == 0 and st["steps"] == 20
+    assert abs(h[0] - 0.7) <= 1e-15 and abs(hu[0]) <= 1e-14 and abs(hv[0]) <= 1e-14
+    two = gen.Case("two", xy, np.array([[0, 1, 2], [1, 3, 2]], np.int32), np.array([0.0, 0.1]),
+                   np.full(2, 0.02), np.array([1.0, 0.2]), np.array([0.3, 0.0]),
+                   np.array([0.0, -0.1]), 15)
+    rc_o, *ora, _, st_o = run_oracle(two)
+    rc_g, st_g, *g = run_gpu(two, "f64")
+    assert rc_o == rc_g == 0
+    assert max(errors(two, g, ora)) <= TOL_F64
+
+
+def test_dry_and_nonfinite_states_are_reported(gpu):
+    import paper_1807_00672_amd as swe
+    case = gen.small(1)
+    z = np.zeros(case.n_cells)
+    dry = gen.Case("dry", case.xy, case.tri, z, z, z, z, z, 5)
+    rc, st, *_ = run_gpu(dry, "f64")
+    assert rc == swe.SWE_EDRY and st["steps"] == 0
+    h = case.h.copy()
+    h[1234] = np.nan
+    bad = gen.Case("nan", case.xy, case.tri, z, z, h, z, z, 5)
+    rc, st, *_ = run_gpu(bad, "f64")
+    assert rc == swe.SWE_ENONFINITE
+    h = case.h.copy()
+    h[4321] = np.inf
+    bad = gen.Case("inf", case.xy, case.tri, z, z, h, z, z, 5)
+    rc, st, *_ = run_gpu(bad, "f32")
+    assert rc == swe.SWE_ENONFINITE
