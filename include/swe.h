@@ -48,6 +48,12 @@ extern "C" {
 #define SWE_MAX_INFLOW 16      /* inflow segments per mesh */
 #define SWE_CTRL_BYTES 512     /* size of the device control block of a state */
 #define SWE_WALL (-1)          /* boundary code of a reflective wall (section 3) */
+#define SWE_AUTO 0             /* variant: tiled when the device mesh has tile arrays and the
+                                  tile's LDS fits the device, else per-cell */
+#define SWE_CELL 1             /* variant: one work-item per cell gathering its neighbours */
+#define SWE_TILED 2            /* variant: tile-staged states, each tile interface once */
+#define SWE_TILE 256           /* cells per tile: consecutive mesh-order cells stepped by one
+                                  workgroup, which stages them and their neighbours in LDS */
 
 typedef struct swe_mesh swe_mesh;   /* host-side mesh object, owned by the library */
 
@@ -61,6 +67,11 @@ typedef struct swe_mesh_info {
     uint32_t flags;            /* flags given to swe_mesh_create */
     double min_area, max_area, total_area, min_inradius;
     double bbox[4];            /* xmin, ymin, xmax, ymax */
+    int64_t n_tiles;           /* ceil(T / SWE_TILE) */
+    int64_t n_halo;            /* total halo entries over all tiles */
+    int64_t n_tile_edges;      /* total edge-list entries over all tiles */
+    int32_t max_halo;          /* largest halo of a tile */
+    int32_t max_tile_edges;    /* longest edge list of a tile */
 } swe_mesh_info;
 
 /* Arrays swe_mesh_export copies out (sizes in elements). */
@@ -72,7 +83,16 @@ enum swe_mesh_array {
     SWE_ARR_C2N = 2,       /* int32[3T], [k*T + i] = node k of cell i (mesh node order);
                               counter-clockwise, local edge k runs from node k to node k+1 */
     SWE_ARR_XY = 3,        /* double[2V]: (x, y) of mesh node j at [2j], [2j+1] */
-    SWE_ARR_NODE_PERM = 4  /* int32[V]: input index of mesh node j */
+    SWE_ARR_NODE_PERM = 4, /* int32[V]: input index of mesh node j */
+    SWE_ARR_HALO_OFF = 5,  /* int32[n_tiles+1]: tile t's halo is HALO[off[t] .. off[t+1]) */
+    SWE_ARR_HALO = 6,      /* int32[n_halo]: cells outside a tile that neighbour it, ascending */
+    SWE_ARR_EDGE_OFF = 7,  /* int32[n_tiles+1]: tile t's edges are EDGES[off[t] .. off[t+1]) */
+    SWE_ARR_EDGES = 8,     /* uint32[n_tile_edges]: one per interface a tile evaluates:
+                              bits 0-7 owning cell a (tile-local), bits 8-9 a's local edge k,
+                              bits 16-31 int16 b: tile-local cell (< SWE_TILE), halo slot
+                              SWE_TILE + j, or a boundary code (SWE_WALL, -1 - s) */
+    SWE_ARR_SLOT = 9       /* uint16[3T], [k*T + i]: entry of cell i's local edge k in its
+                              tile's edge list; bit 15 set when i is the edge's side b */
 };
 
 /* Device view of a mesh: the arrays of swe_mesh_export copied to device memory. */
@@ -81,6 +101,11 @@ typedef struct swe_dev_mesh {
     const int32_t *nbr;    /* device, as SWE_ARR_NBR */
     const int32_t *c2n;    /* device, as SWE_ARR_C2N */
     const double *xy;      /* device, as SWE_ARR_XY, 16-byte aligned */
+    const int32_t *halo_off;   /* device, as SWE_ARR_HALO_OFF */
+    const int32_t *halo;       /* device, as SWE_ARR_HALO */
+    const int32_t *edge_off;   /* device, as SWE_ARR_EDGE_OFF */
+    const uint32_t *edges;     /* device, as SWE_ARR_EDGES */
+    const uint16_t *slot;      /* device, as SWE_ARR_SLOT */
 } swe_dev_mesh;
 
 /* Physical and numerical parameters (section 2.1-2.2). */
@@ -91,6 +116,8 @@ typedef struct swe_params {
     int32_t dtype;         /* SWE_F64 or SWE_F32 */
     int32_t n_inflow;      /* number of inflow segments, <= SWE_MAX_INFLOW */
     const double *inflow_q;/* host, n_inflow unit discharges (m^2/s) entering, >= 0 */
+    int32_t variant;       /* step kernel: SWE_AUTO, SWE_CELL or SWE_TILED (same results) */
+    int32_t reserved;
 } swe_params;
 
 /* Device state of one simulation.  All pointers device, element type given by dtype. */

@@ -4,8 +4,9 @@ include/swe.h, with torch providing device memory and streams.
 """
 from ._abi import (  # noqa: F401
     EXPORTS, LIB_PATH, SWE_ARR_C2N, SWE_ARR_NBR, SWE_ARR_NODE_PERM, SWE_ARR_PERM, SWE_ARR_XY,
-    SWE_CTRL_BYTES, SWE_EDEVICE, SWE_EDRY, SWE_EINVAL, SWE_EMESH, SWE_ENONFINITE,
-    SWE_EUNSUPPORTED, SWE_F32, SWE_F64, SWE_MAX_INFLOW, SWE_MORTON, SWE_OK, SWE_WALL, SweError,
+    SWE_AUTO, SWE_CELL, SWE_CTRL_BYTES, SWE_EDEVICE, SWE_EDRY, SWE_EINVAL, SWE_EMESH, SWE_ENONFINITE,
+    SWE_EUNSUPPORTED, SWE_F32, SWE_F64, SWE_MAX_INFLOW, SWE_MORTON, SWE_OK, SWE_TILE, SWE_TILED,
+    SWE_WALL, SweError,
     lib, swe_dev_mesh, swe_flux_eval, swe_last_error, swe_mesh_create, swe_mesh_destroy,
     swe_mesh_export, swe_mesh_info, swe_mesh_info_get, swe_params, swe_read_stats, swe_run,
     swe_run_stats, swe_state, swe_state_init, swe_step, swe_workspace_bytes)

@@ -30,7 +30,11 @@ SWE_MAX_INFLOW = 16
 SWE_CTRL_BYTES = 512
 SWE_WALL = -1
 
-SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM = range(5)
+SWE_AUTO, SWE_CELL, SWE_TILED = 0, 1, 2
+SWE_TILE = 256
+
+(SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,
+ SWE_ARR_HALO, SWE_ARR_EDGE_OFF, SWE_ARR_EDGES, SWE_ARR_SLOT) = range(10)
 
 _NAMES = {0: "SWE_OK", -1: "SWE_EINVAL", -2: "SWE_EMESH", -3: "SWE_EDEVICE",
           -4: "SWE_ENONFINITE", -5: "SWE_EDRY", -6: "SWE_EUNSUPPORTED"}
@@ -48,18 +52,23 @@ class swe_mesh_info(C.Structure):
                 ("n_inflow_segments", C.c_int32), ("flags", C.c_uint32),
                 ("min_area", C.c_double), ("max_area", C.c_double),
                 ("total_area", C.c_double), ("min_inradius", C.c_double),
-                ("bbox", C.c_double * 4)]
+                ("bbox", C.c_double * 4), ("n_tiles", C.c_int64), ("n_halo", C.c_int64),
+                ("n_tile_edges", C.c_int64), ("max_halo", C.c_int32),
+                ("max_tile_edges", C.c_int32)]
 
 
 class swe_dev_mesh(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("nbr", C.c_void_p),
-                ("c2n", C.c_void_p), ("xy", C.c_void_p)]
+                ("c2n", C.c_void_p), ("xy", C.c_void_p), ("halo_off", C.c_void_p),
+                ("halo", C.c_void_p), ("edge_off", C.c_void_p), ("edges", C.c_void_p),
+                ("slot", C.c_void_p)]
 
 
 class swe_params(C.Structure):
     _fields_ = [("g", C.c_double), ("courant", C.c_double), ("h_dry", C.c_double),
                 ("dtype", C.c_int32), ("n_inflow", C.c_int32),
-                ("inflow_q", C.POINTER(C.c_double))]
+                ("inflow_q", C.POINTER(C.c_double)), ("variant", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class swe_state(C.Structure):

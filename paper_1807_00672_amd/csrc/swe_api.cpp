@@ -84,6 +84,143 @@ StepConfig make_config(const swe_mesh *mesh, const swe_params *p)
     return c;
 }
 
+// Largest dynamic LDS of a workgroup on the current device, and whether the tiled kernels
+// have been allowed to use more than the default 64 KiB there.
+struct DeviceLds {
+    int limit = -1;
+    size_t prepared = 0;
+};
+DeviceLds g_lds[64];
+
+// Pick the step kernel: the tiled one when asked for or possible, else the per-cell one.
+int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                       const TileLayout **out, const char *where)
+{
+    *out = nullptr;
+    const std::string w(where);
+    if (p->variant == SWE_CELL) return SWE_OK;
+    if (p->variant != SWE_AUTO && p->variant != SWE_TILED)
+        return fail(SWE_EINVAL, w + ": unknown variant");
+    const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot;
+    if (!have) {
+        if (p->variant == SWE_TILED) return fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
+        return SWE_OK;
+    }
+    int dev = 0;
+    if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;
+    if (dev < 0 || dev >= 64) return fail(SWE_EUNSUPPORTED, w + ": device index beyond 63");
+    DeviceLds &d = g_lds[dev];
+    if (d.limit < 0) {
+        int lim = 0;
+        if (int32_t rc = check_hip(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), where))
+            return rc;
+        d.limit = lim;
+    }
+    const size_t need = tile_lds_bytes_for(p->dtype, mesh->tiles);
+    if (need > static_cast<size_t>(d.limit)) {
+        if (p->variant == SWE_TILED)
+            return fail(SWE_EUNSUPPORTED, w + ": tile needs " + std::to_string(need) +
+                                              " bytes of LDS, device allows " + std::to_string(d.limit));
+        return SWE_OK;
+    }
+    if (need > 65536 && d.prepared < need) {
+        if (int32_t rc = check_hip(prepare_tile_kernels(static_cast<size_t>(d.limit)), where)) return rc;
+        d.prepared = static_cast<size_t>(d.limit);
+    }
+    *out = &mesh->tiles;
+    return SWE_OK;
+}
+
+// Two steps (even and odd buffer) captured once as a graph and replayed by swe_run; the
+// launch arguments it bakes in form its key.
+struct GraphKey {
+    swe_dev_mesh dm;
+    double g, courant, h_dry;
+    int32_t dtype, variant, n_inflow, cur;
+    double q[SWE_MAX_INFLOW];
+    void *h[2], *hu[2], *hv[2];
+    const void *z, *n;
+    void *ctrl, *work;
+    const double *dt_seq;
+    int64_t n_seq;
+    const void *tl;
+    int device;
+};
+
+struct GraphCache {
+    GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphCache()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+hipStream_t g_capture[64] = {};
+
+GraphKey make_key(const swe_dev_mesh *dm, const swe_params *p, const swe_state *s,
+                  const double *dt_seq, int64_t n_seq, const TileLayout *tl, int dev)
+{
+    GraphKey k;
+    memset(&k, 0, sizeof(k));
+    k.dm = *dm;
+    k.g = p->g; k.courant = p->courant; k.h_dry = p->h_dry;
+    k.dtype = p->dtype; k.variant = p->variant; k.n_inflow = p->n_inflow; k.cur = s->cur;
+    for (int i = 0; i < p->n_inflow; ++i) k.q[i] = p->inflow_q[i];
+    for (int b = 0; b < 2; ++b) { k.h[b] = s->h[b]; k.hu[b] = s->hu[b]; k.hv[b] = s->hv[b]; }
+    k.z = s->z; k.n = s->n; k.ctrl = s->ctrl; k.work = s->work;
+    k.dt_seq = dt_seq;
+    k.n_seq = dt_seq ? n_seq : 0;
+    k.tl = tl;
+    k.device = dev;
+    return k;
+}
+
+// The executable two-step graph for these arguments, captured on a library-owned stream
+// (nullptr if graphs are unavailable: the caller then launches step by step).
+hipGraphExec_t two_step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                              const StepConfig &cfg, const swe_state *s, const double *dt_seq,
+                              int64_t n_seq, const TileLayout *tl)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    const GraphKey key = make_key(dm, p, s, dt_seq, n_seq, tl, dev);
+    swe_mesh *m = const_cast<swe_mesh *>(mesh);
+    GraphCache *gc = static_cast<GraphCache *>(m->graph);
+    if (gc && memcmp(&gc->key, &key, sizeof(key)) == 0) return gc->exec;
+    delete gc;
+    m->graph = nullptr;
+    if (!g_capture[dev] && hipStreamCreateWithFlags(&g_capture[dev], hipStreamNonBlocking) != hipSuccess) {
+        g_capture[dev] = nullptr;
+        return nullptr;
+    }
+    hipStream_t cs = g_capture[dev];
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    int e0 = launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_seq, cs, tl);
+    int e1 = launch_step(p->dtype, *dm, cfg, *s, 1 - s->cur, dt_seq, n_seq, cs, tl);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (e0 != hipSuccess || e1 != hipSuccess || ee != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    gc = new GraphCache();
+    gc->key = key;
+    gc->graph = graph;
+    gc->exec = exec;
+    m->graph = gc;
+    return exec;
+}
+
 int32_t status_code(int32_t bits)
 {
     if (bits & (kStatusNonFinite | kStatusBadDt)) return SWE_ENONFINITE;
@@ -96,6 +233,8 @@ int32_t status_code(int32_t bits)
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 }  // namespace swe
+
+swe_mesh::~swe_mesh() { delete static_cast<swe::GraphCache *>(graph); }
 
 using namespace swe;
 
@@ -124,7 +263,9 @@ int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
 {
     if (int32_t rc = check_call(mesh, dm, p, s, "swe_step")) return rc;
     const StepConfig cfg = make_config(mesh, p);
-    if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, nullptr, 0, stream),
+    const TileLayout *tl = nullptr;
+    if (int32_t rc = choose_variant(mesh, dm, p, &tl, "swe_step")) return rc;
+    if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, nullptr, 0, stream, tl),
                                "swe_step"))
         return rc;
     s->cur ^= 1;
@@ -166,10 +307,21 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
     if (n_steps < 0) return fail(SWE_EINVAL, "swe_run: n_steps < 0");
     if (dt_seq && n_steps < 1) return fail(SWE_EINVAL, "swe_run: dt_seq needs n_steps >= 1");
     const StepConfig cfg = make_config(mesh, p);
+    const TileLayout *tl = nullptr;
+    if (int32_t rc = choose_variant(mesh, dm, p, &tl, "swe_run")) return rc;
     if (int32_t rc = check_hip(launch_run_begin(*s, dt_seq, stream), "swe_run")) return rc;
-    for (int64_t k = 0; k < n_steps; ++k) {
+    int64_t k = 0;
+    if (n_steps >= 4) {
+        if (hipGraphExec_t ex = two_step_graph(mesh, dm, p, cfg, s, dt_seq, n_steps, tl)) {
+            for (; k + 2 <= n_steps; k += 2)
+                if (int32_t rc = check_hip(hipGraphLaunch(ex, static_cast<hipStream_t>(stream)),
+                                           "swe_run"))
+                    return rc;
+        }
+    }
+    for (; k < n_steps; ++k) {
         if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_steps,
-                                               stream),
+                                               stream, tl),
                                    "swe_run"))
             return rc;
         s->cur ^= 1;

@@ -28,7 +28,7 @@ static_assert(sizeof(Ctrl) <= SWE_CTRL_BYTES, "control block too large");
 
 enum : int32_t { kStatusNonFinite = 1, kStatusDry = 2, kStatusBadDt = 4 };
 
-constexpr int kBlock = 256;          // cells per workgroup of the step kernel
+constexpr int kBlock = SWE_TILE;     // cells per workgroup of the step kernels
 
 // Per-block partial results of a step, laid out in the workspace.
 struct Partials {
@@ -64,11 +64,20 @@ struct StepConfig {
     double inflow_q[SWE_MAX_INFLOW];
 };
 
+// Tile sizes of a mesh that the tiled step needs at launch.
+struct TileLayout {
+    int64_t n_tiles;
+    int32_t max_halo, max_edges;
+};
+
 // Launchers (swe_kernels.hip).  All queue work on `stream` and return a hipError_t as int.
 int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 double t0, double t_end, void *stream);
+// tl == nullptr: the per-cell kernel; else the tiled kernel (its LDS must fit, see below).
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                int cur, const double *dt_seq, int64_t n_seq, void *stream);
+                int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl);
+size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);
+int prepare_tile_kernels(size_t max_lds);   // allow dynamic LDS up to max_lds bytes
 int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);
 int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *hl,
                      const void *hul, const void *hvl, const void *zl, const void *hr,
@@ -87,4 +96,12 @@ struct swe_mesh {
     std::vector<int32_t> c2n;        // [3][T]
     std::vector<double> xy;          // [V][2]
     std::vector<int32_t> node_perm;  // mesh node -> input node
+    std::vector<int32_t> halo_off;   // [n_tiles + 1]
+    std::vector<int32_t> halo;       // cells neighbouring a tile from outside, per tile
+    std::vector<int32_t> edge_off;   // [n_tiles + 1]
+    std::vector<uint32_t> edges;     // packed edge-list entries, per tile
+    std::vector<uint16_t> slot;      // [3][T]
+    swe::TileLayout tiles;           // sizes the tiled step needs at launch
+    void *graph = nullptr;           // cached two-step graph of swe_run (swe_api.cpp)
+    ~swe_mesh();
 };

@@ -74,27 +74,38 @@ __device__ __forceinline__ void hllc_normal(R g, R hl, R ql, R wl, R hr, R qr, R
     }
 }
 
-// Flux through an interior edge seen from cell "l" with the hydrostatic reconstruction of
-// the bed (z* = max, h* = max(0, h - (z* - z)), velocities kept) and l's bed correction
-// p = g/2 (h^2 - h*^2).  (fx, fy) are the momentum fluxes in (x, y).
+// Flux through an interior edge from side a to side b (unit normal (nx, ny) out of a) with the
+// hydrostatic reconstruction of the bed (z* = max, h* = max(0, h - (z* - z)), velocities
+// kept) and both side terms p = g/2 (h^2 - h*^2).  (fx, fy) are the momentum fluxes in (x, y).
 template <typename R>
-__device__ __forceinline__ void interface_flux(R g, R hd, R hl, R ul, R vl, R zl, R hr, R hur,
-                                               R hvr, R zr, R nx, R ny, R &fh, R &fx, R &fy,
-                                               R &p)
+__device__ __forceinline__ void interface_flux_uv(R g, R hd, R hl, R ul, R vl, R zl, R hr, R ur,
+                                                  R vr, R zr, R nx, R ny, R &fh, R &fx, R &fy,
+                                                  R &pl, R &pr)
 {
     const R zs = fmax(zl, zr);
     R hsl = fmax(R(0), hl - (zs - zl));
     R hsr = fmax(R(0), hr - (zs - zr));
     if (hsl <= hd) hsl = R(0);
     if (hsr <= hd) hsr = R(0);
-    const R ur = velocity(hr, hur, hd), vr = velocity(hr, hvr, hd);
     const R ql = ul * nx + vl * ny, wl = vl * nx - ul * ny;
     const R qr = ur * nx + vr * ny, wr = vr * nx - ur * ny;
     R fq, fw;
     hllc_normal(g, hsl, ql, wl, hsr, qr, wr, fh, fq, fw);
     fx = fq * nx - fw * ny;
     fy = fq * ny + fw * nx;
-    p = R(0.5) * g * (hl * hl - hsl * hsl);
+    pl = R(0.5) * g * (hl * hl - hsl * hsl);
+    pr = R(0.5) * g * (hr * hr - hsr * hsr);
+}
+
+// The same seen from cell l with the right state in conserved variables.
+template <typename R>
+__device__ __forceinline__ void interface_flux(R g, R hd, R hl, R ul, R vl, R zl, R hr, R hur,
+                                               R hvr, R zr, R nx, R ny, R &fh, R &fx, R &fy,
+                                               R &p)
+{
+    R pr;
+    interface_flux_uv(g, hd, hl, ul, vl, zl, hr, velocity(hr, hur, hd), velocity(hr, hvr, hd),
+                      zr, nx, ny, fh, fx, fy, p, pr);
 }
 
 // Reflective wall (section 3): mirror ghost built in the edge frame (q -> -q, w kept), so the
@@ -188,9 +199,9 @@ __device__ __forceinline__ int wave_or(int v)
     return v;
 }
 
-// Block-wide (kBlock work-items) min / sum / or; thread 0 writes the block's partials.
-__device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
-                                               const Partials &part)
+// Block-wide (kBlock work-items) min / sum / or; thread 0 writes them as partials[slot].
+__device__ __forceinline__ void block_partials_at(double dtc, int clamp, int flag,
+                                                  const Partials &part, int slot)
 {
     __shared__ double s_dt[kBlock / 64];
     __shared__ int s_cl[kBlock / 64], s_fl[kBlock / 64];
@@ -210,10 +221,16 @@ __device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
             clamp += s_cl[w];
             flag |= s_fl[w];
         }
-        part.dt[blockIdx.x] = dtc;
-        part.clamps[blockIdx.x] = clamp;
-        part.flags[blockIdx.x] = flag;
+        part.dt[slot] = dtc;
+        part.clamps[slot] = clamp;
+        part.flags[slot] = flag;
     }
+}
+
+__device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
+                                               const Partials &part)
+{
+    block_partials_at(dtc, clamp, flag, part, blockIdx.x);
 }
 
 // CFL bound r / (|u| + sqrt(g h)) of a cell (inflow edges add their boundary speed);
@@ -326,6 +343,187 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<R> a, StepConfig 
     block_partials(static_cast<double>(dtc), clamp, flag, a.part);
 }
 
+// ------------------------------------------------------------------------ tiled step
+
+template <typename R>
+struct TileArgs {
+    StepArgs<R> s;
+    const int32_t *__restrict__ halo_off;
+    const int32_t *__restrict__ halo;
+    const int32_t *__restrict__ edge_off;
+    const uint32_t *__restrict__ edges;
+    const uint16_t *__restrict__ slot;
+    int32_t n_tiles, max_halo, max_edges, pad;
+};
+
+// LDS bytes of the tiled step: tile + halo states (h, u, v, z), the tile's node ids and
+// seven values per edge-list entry (both sides' contributions and the length).
+inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
+{
+    return 4 * word * static_cast<size_t>(kBlock + max_halo) + 3 * 4 * kBlock +
+           7 * word * static_cast<size_t>(max_edges);
+}
+
+// Workgroups are handed to the eight XCDs in turn; give each XCD a contiguous run of tiles
+// so that a tile's halo was recently read into the same XCD's L2 by its neighbour tiles.
+__device__ __forceinline__ int xcd_tile(int b, int n_tiles)
+{
+    const int per = (n_tiles + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
+// One explicit step, tiled.  Phase 1 stages the tile's cells and its halo in LDS as
+// (h, u, v, z), each velocity computed once.  Phase 2 evaluates every interface of the edge
+// list once (section 2.3's interface loop, restricted to the tile) and stores each side's
+// contribution l (F + p n) to eq. 3, computed exactly as the per-cell form computes it.
+// Phase 3 sums each cell's three contributions in local-edge order and applies the update of
+// eq. 4, the clamp, the friction and the next CFL bound, as the per-cell kernel does.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg)
+{
+    const StepArgs<R> &a = ta.s;
+    if (a.ctrl->done) return;
+    const int tile = xcd_tile(blockIdx.x, ta.n_tiles);
+    if (tile >= ta.n_tiles) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ns = kBlock + ta.max_halo;
+    R *s_h = reinterpret_cast<R *>(smem);
+    R *s_u = s_h + ns;
+    R *s_v = s_u + ns;
+    R *s_z = s_v + ns;
+    int32_t *s_c2n = reinterpret_cast<int32_t *>(s_z + ns);
+    R *e_a0 = reinterpret_cast<R *>(s_c2n + 3 * kBlock);
+    R *e_a1 = e_a0 + ta.max_edges;
+    R *e_a2 = e_a1 + ta.max_edges;
+    R *e_b0 = e_a2 + ta.max_edges;
+    R *e_b1 = e_b0 + ta.max_edges;
+    R *e_b2 = e_b1 + ta.max_edges;
+    R *e_l = e_b2 + ta.max_edges;
+
+    const int64_t T = cfg.n_cells;
+    const int64_t s0 = static_cast<int64_t>(tile) * kBlock;
+    const int tid = threadIdx.x;
+    const int64_t i = s0 + tid;
+    const bool mine = i < T;
+    const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
+    const R dt = static_cast<R>(a.ctrl->dt);
+
+    // phase 1: own cell and halo into LDS
+    R h = R(0), hu = R(0), hv = R(0);
+    int32_t n0 = 0, n1 = 0, n2 = 0;
+    if (mine) {
+        h = a.h[i]; hu = a.hu[i]; hv = a.hv[i];
+        s_h[tid] = h;
+        s_u[tid] = velocity(h, hu, hd);
+        s_v[tid] = velocity(h, hv, hd);
+        s_z[tid] = a.z[i];
+        n0 = a.c2n[i]; n1 = a.c2n[T + i]; n2 = a.c2n[2 * T + i];
+        s_c2n[tid] = n0; s_c2n[kBlock + tid] = n1; s_c2n[2 * kBlock + tid] = n2;
+    }
+    const int hb = ta.halo_off[tile], he = ta.halo_off[tile + 1];
+    for (int j = hb + tid; j < he; j += kBlock) {
+        const int32_t c = ta.halo[j];
+        const R hh = a.h[c];
+        const int q = kBlock + (j - hb);
+        s_h[q] = hh;
+        s_u[q] = velocity(hh, a.hu[c], hd);
+        s_v[q] = velocity(hh, a.hv[c], hd);
+        s_z[q] = a.z[c];
+    }
+    __syncthreads();
+
+    // phase 2: the tile's interfaces, each once
+    const int eb = ta.edge_off[tile], ee = ta.edge_off[tile + 1];
+    for (int e = eb + tid; e < ee; e += kBlock) {
+        const uint32_t w = ta.edges[e];
+        const int ca = static_cast<int>(w & 0xffu);
+        const int k = static_cast<int>((w >> 8) & 3u);
+        const int cb = static_cast<int16_t>(w >> 16);
+        const double2 p0 = a.xy[s_c2n[k * kBlock + ca]];
+        const double2 p1 = a.xy[s_c2n[(k == 2 ? 0 : k + 1) * kBlock + ca]];
+        const R dx = static_cast<R>(p1.x - p0.x), dy = static_cast<R>(p1.y - p0.y);
+        const R l = sqrt(dx * dx + dy * dy);
+        const R nx = dy / l, ny = -dx / l;
+        const R ha = s_h[ca], ua = s_u[ca], va = s_v[ca];
+        R fh, fx, fy, pa, pb;
+        const int q = e - eb;
+        if (cb >= 0) {
+            interface_flux_uv<R>(g, hd, ha, ua, va, s_z[ca], s_h[cb], s_u[cb], s_v[cb], s_z[cb],
+                                 nx, ny, fh, fx, fy, pa, pb);
+            if (cb < kBlock) {
+                e_b0[q] = l * (-fh);
+                e_b1[q] = l * (-fx + pb * (-nx));
+                e_b2[q] = l * (-fy + pb * (-ny));
+            }
+        } else if (cb == SWE_WALL) {
+            wall_flux<R>(g, hd, ha, ua, va, nx, ny, fh, fx, fy, pa);
+        } else {
+            inflow_flux<R>(g, static_cast<R>(cfg.inflow_q[-2 - cb]), ha, nx, ny, fh, fx, fy);
+            pa = R(0);
+        }
+        e_a0[q] = l * fh;
+        e_a1[q] = l * (fx + pa * nx);
+        e_a2[q] = l * (fy + pa * ny);
+        e_l[q] = l;
+    }
+    __syncthreads();
+
+    // phase 3: per-cell sum, update, clamp, friction, next CFL bound
+    R dtc = static_cast<R>(kInf);
+    int clamp = 0, flag = 0;
+    if (mine) {
+        R acc0 = R(0), acc1 = R(0), acc2 = R(0), l[3];
+        int32_t nb[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t sl = ta.slot[k * T + i];
+            const int q = static_cast<int>(sl & 0x7fffu);
+            const bool side_b = (sl & 0x8000u) != 0;
+            const R c0 = side_b ? e_b0[q] : e_a0[q];
+            const R c1 = side_b ? e_b1[q] : e_a1[q];
+            const R c2 = side_b ? e_b2[q] : e_a2[q];
+            l[k] = e_l[q];
+            nb[k] = 0;
+            if (cfg.n_inflow > 0 && !side_b) nb[k] = static_cast<int16_t>(ta.edges[eb + q] >> 16);
+            if (k == 0) {
+                acc0 = c0; acc1 = c1; acc2 = c2;
+            } else {
+                acc0 = acc0 + c0; acc1 = acc1 + c1; acc2 = acc2 + c2;
+            }
+        }
+        const double2 p0 = a.xy[n0], p1 = a.xy[n1], p2 = a.xy[n2];
+        const double e0x = p1.x - p0.x, e0y = p1.y - p0.y;
+        const double e1x = p2.x - p1.x, e1y = p2.y - p1.y;
+        const R area = static_cast<R>(0.5 * (e0x * e1y - e0y * e1x));
+        const R inradius = R(2) * area / (l[0] + l[1] + l[2]);
+        const R r = dt / area;
+        R hs = h - r * acc0;
+        const R hus = hu - r * acc1;
+        const R hvs = hv - r * acc2;
+        if (hs < R(0)) {
+            clamp = 1;
+            hs = R(0);
+        }
+        R hun, hvn;
+        if (hs > hd) {
+            const R nm = a.n[i];
+            const R mag = sqrt(hus * hus + hvs * hvs);
+            const R d = R(1) + dt * g * nm * nm * mag / (hs * hs * cbrt(hs));
+            hun = hus / d;
+            hvn = hvs / d;
+        } else {
+            hun = R(0);
+            hvn = R(0);
+        }
+        a.ho[i] = hs;
+        a.huo[i] = hun;
+        a.hvo[i] = hvn;
+        if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
+        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg);
+    }
+    block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
+}
+
 // CFL bounds of the initial state.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig cfg)
@@ -365,10 +563,26 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl, Parti
     double m = kInf;
     long long cl = 0;
     int fl = 0;
-    for (int64_t b = threadIdx.x; b < nb; b += kPassThreads) {
-        m = fmin(m, part.dt[b]);
-        cl += part.clamps[b];
-        fl |= part.flags[b];
+    // kUnroll independent loads per work-item in flight: the partials are few, so latency,
+    // not bandwidth, bounds this loop
+    constexpr int kUnroll = 16;
+    for (int64_t b0 = threadIdx.x; b0 < nb; b0 += kPassThreads * kUnroll) {
+        double v[kUnroll];
+        int c[kUnroll], f[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t b = b0 + static_cast<int64_t>(u) * kPassThreads;
+            const bool in = b < nb;
+            v[u] = in ? part.dt[b] : kInf;
+            c[u] = in ? part.clamps[b] : 0;
+            f[u] = in ? part.flags[b] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            m = fmin(m, v[u]);
+            cl += c[u];
+            fl |= f[u];
+        }
     }
     m = wave_min(m);
 #pragma unroll
@@ -497,6 +711,24 @@ StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
     return a;
 }
 
+template <typename R>
+TileArgs<R> make_tile_args(const swe_dev_mesh &dm, const swe_state &s, int cur,
+                           const TileLayout &tl)
+{
+    TileArgs<R> t;
+    t.s = make_args<R>(dm, s, cur);
+    t.halo_off = dm.halo_off;
+    t.halo = dm.halo;
+    t.edge_off = dm.edge_off;
+    t.edges = dm.edges;
+    t.slot = dm.slot;
+    t.n_tiles = static_cast<int32_t>(tl.n_tiles);
+    t.max_halo = tl.max_halo;
+    t.max_edges = tl.max_edges;
+    t.pad = 0;
+    return t;
+}
+
 }  // namespace
 
 int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
@@ -514,15 +746,41 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     return static_cast<int>(hipGetLastError());
 }
 
+size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
+{
+    return tile_lds_bytes(dtype == SWE_F64 ? 8 : 4, tl.max_halo, tl.max_edges);
+}
+
+int prepare_tile_kernels(size_t max_lds)
+{
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_step_kernel<double>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(max_lds));
+    if (e != hipSuccess) return static_cast<int>(e);
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_step_kernel<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(max_lds));
+    return static_cast<int>(e);
+}
+
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                int cur, const double *dt_seq, int64_t n_seq, void *stream)
+                int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nb = n_blocks(cfg.n_cells);
-    if (dtype == SWE_F64)
+    if (tl) {
+        const size_t lds = tile_lds_bytes_for(dtype, *tl);
+        const int64_t grid = 8 * ((tl->n_tiles + 7) / 8);
+        if (dtype == SWE_F64)
+            tile_step_kernel<double><<<dim3(grid), dim3(kBlock), lds, st>>>(
+                make_tile_args<double>(dm, s, cur, *tl), cfg);
+        else
+            tile_step_kernel<float><<<dim3(grid), dim3(kBlock), lds, st>>>(
+                make_tile_args<float>(dm, s, cur, *tl), cfg);
+    } else if (dtype == SWE_F64) {
         step_kernel<double><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<double>(dm, s, cur), cfg);
-    else
+    } else {
         step_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<float>(dm, s, cur), cfg);
+    }
     dt_pass_kernel<<<1, kPassThreads, 0, st>>>(static_cast<Ctrl *>(s.ctrl),
                                                partials_of(s.work, cfg.n_cells), nb, cfg.courant,
                                                dt_seq, n_seq, 1, 0.0, 0.0, 0);

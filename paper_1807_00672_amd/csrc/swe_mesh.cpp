@@ -54,6 +54,99 @@ void radix_sort_by_key(std::vector<uint32_t> &key, std::vector<int32_t> &idx)
     }
 }
 
+// Tiles of SWE_TILE consecutive mesh-order cells.  Per tile: the halo (cells outside it that
+// share an edge with it, ascending) and the edge list: every interface between two tile
+// cells once (owned by the lower local index), every interface to a halo cell or the
+// boundary once (owned by the tile cell).  Interior and halo entries come first, boundary
+// entries last, so that the waves evaluating them branch alike.  slot[k*T + i] points cell
+// i's local edge k at its entry, bit 15 marking the side b of an interior interface.
+void build_tiles(swe_mesh &m)
+{
+    const int64_t T = m.info.n_cells;
+    const int64_t nt = (T + SWE_TILE - 1) / SWE_TILE;
+    m.halo_off.assign(nt + 1, 0);
+    m.edge_off.assign(nt + 1, 0);
+    m.halo.clear();
+    m.edges.clear();
+    m.slot.assign(3 * T, 0);
+    int32_t max_halo = 0, max_edges = 0;
+    std::vector<int32_t> hl;
+    std::vector<uint32_t> inner, bnd;
+    std::vector<int32_t> inner_cell, bnd_cell;  // (local cell * 4 + k) of each entry
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t s0 = t * SWE_TILE, s1 = std::min<int64_t>(T, s0 + SWE_TILE);
+        hl.clear();
+        for (int64_t i = s0; i < s1; ++i)
+            for (int k = 0; k < 3; ++k) {
+                const int32_t j = m.nbr[k * T + i];
+                if (j >= 0 && (j < s0 || j >= s1)) hl.push_back(j);
+            }
+        std::sort(hl.begin(), hl.end());
+        hl.erase(std::unique(hl.begin(), hl.end()), hl.end());
+        if (static_cast<int64_t>(hl.size()) > 32767 - SWE_TILE)
+            throw Fail{SWE_EMESH, "tile halo too large"};
+        inner.clear(); bnd.clear(); inner_cell.clear(); bnd_cell.clear();
+        for (int64_t i = s0; i < s1; ++i) {
+            const uint32_t a = static_cast<uint32_t>(i - s0);
+            for (int k = 0; k < 3; ++k) {
+                const int32_t j = m.nbr[k * T + i];
+                int32_t b;
+                if (j >= s0 && j < s1) {
+                    if (j < i) continue;  // owned by the lower local index
+                    b = static_cast<int32_t>(j - s0);
+                } else if (j >= 0) {
+                    b = SWE_TILE + static_cast<int32_t>(
+                                       std::lower_bound(hl.begin(), hl.end(), j) - hl.begin());
+                } else {
+                    b = j;
+                }
+                const uint32_t w = a | (static_cast<uint32_t>(k) << 8) |
+                                   (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(b))) << 16);
+                if (b >= 0) {
+                    inner.push_back(w);
+                    inner_cell.push_back(static_cast<int32_t>(a) * 4 + k);
+                } else {
+                    bnd.push_back(w);
+                    bnd_cell.push_back(static_cast<int32_t>(a) * 4 + k);
+                }
+            }
+        }
+        const int32_t n_inner = static_cast<int32_t>(inner.size());
+        for (int32_t e = 0; e < n_inner + static_cast<int32_t>(bnd.size()); ++e) {
+            const uint32_t w = e < n_inner ? inner[e] : bnd[e - n_inner];
+            const int32_t ak = e < n_inner ? inner_cell[e] : bnd_cell[e - n_inner];
+            const int64_t i = s0 + ak / 4;
+            const int k = ak % 4;
+            m.slot[k * T + i] = static_cast<uint16_t>(e);
+            const int32_t b = static_cast<int16_t>(w >> 16);
+            if (b >= 0 && b < SWE_TILE) {  // side b of an interior interface
+                const int64_t jb = s0 + b;
+                int kb = -1;
+                for (int q = 0; q < 3; ++q)
+                    if (m.nbr[q * T + jb] == i) kb = q;
+                if (kb < 0) throw Fail{SWE_EMESH, "neighbour relation is not mutual"};
+                m.slot[kb * T + jb] = static_cast<uint16_t>(e | 0x8000);
+            }
+            m.edges.push_back(w);
+        }
+        m.halo.insert(m.halo.end(), hl.begin(), hl.end());
+        m.halo_off[t + 1] = static_cast<int32_t>(m.halo.size());
+        m.edge_off[t + 1] = static_cast<int32_t>(m.edges.size());
+        max_halo = std::max(max_halo, static_cast<int32_t>(hl.size()));
+        max_edges = std::max(max_edges, n_inner + static_cast<int32_t>(bnd.size()));
+    }
+    if (m.edges.size() > static_cast<size_t>(INT32_MAX) || m.halo.size() > static_cast<size_t>(INT32_MAX))
+        throw Fail{SWE_EINVAL, "mesh too large for int32 tile offsets"};
+    m.info.n_tiles = nt;
+    m.info.n_halo = static_cast<int64_t>(m.halo.size());
+    m.info.n_tile_edges = static_cast<int64_t>(m.edges.size());
+    m.info.max_halo = max_halo;
+    m.info.max_tile_edges = max_edges;
+    m.tiles.n_tiles = nt;
+    m.tiles.max_halo = max_halo;
+    m.tiles.max_edges = max_edges;
+}
+
 void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_t nt,
            const int32_t *tags, uint32_t flags)
 {
@@ -237,6 +330,7 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
         m.xy[2 * j] = xy[2 * m.node_perm[j]];
         m.xy[2 * j + 1] = xy[2 * m.node_perm[j] + 1];
     }
+    build_tiles(m);
 }
 
 }  // namespace
@@ -297,6 +391,13 @@ int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t 
     case SWE_ARR_XY: src = mesh->xy.data(); bytes = 8 * (int64_t)mesh->xy.size(); break;
     case SWE_ARR_NODE_PERM:
         src = mesh->node_perm.data(); bytes = 4 * (int64_t)mesh->node_perm.size(); break;
+    case SWE_ARR_HALO_OFF:
+        src = mesh->halo_off.data(); bytes = 4 * (int64_t)mesh->halo_off.size(); break;
+    case SWE_ARR_HALO: src = mesh->halo.data(); bytes = 4 * (int64_t)mesh->halo.size(); break;
+    case SWE_ARR_EDGE_OFF:
+        src = mesh->edge_off.data(); bytes = 4 * (int64_t)mesh->edge_off.size(); break;
+    case SWE_ARR_EDGES: src = mesh->edges.data(); bytes = 4 * (int64_t)mesh->edges.size(); break;
+    case SWE_ARR_SLOT: src = mesh->slot.data(); bytes = 2 * (int64_t)mesh->slot.size(); break;
     default:
         swe::set_error("swe_mesh_export: unknown array " + std::to_string(which));
         return SWE_EINVAL;

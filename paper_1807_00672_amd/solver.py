@@ -38,6 +38,14 @@ class Mesh:
         self.c2n = A.swe_mesh_export(self.handle, A.SWE_ARR_C2N, 3 * t, np.int32)
         self.xy = A.swe_mesh_export(self.handle, A.SWE_ARR_XY, 2 * v, np.float64)
         self.node_perm = A.swe_mesh_export(self.handle, A.SWE_ARR_NODE_PERM, v, np.int32)
+        nt = int(self.info.n_tiles)
+        self.halo_off = A.swe_mesh_export(self.handle, A.SWE_ARR_HALO_OFF, nt + 1, np.int32)
+        self.halo = A.swe_mesh_export(self.handle, A.SWE_ARR_HALO, max(1, int(self.info.n_halo)),
+                                      np.int32)
+        self.edge_off = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGE_OFF, nt + 1, np.int32)
+        self.edges = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGES, int(self.info.n_tile_edges),
+                                       np.uint32)
+        self.slot = A.swe_mesh_export(self.handle, A.SWE_ARR_SLOT, 3 * t, np.uint16)
         self.device = None
         if device is not None:
             self.to(device)
@@ -50,8 +58,14 @@ class Mesh:
         self.d_nbr = torch.from_numpy(self.nbr).to(self.device)
         self.d_c2n = torch.from_numpy(self.c2n).to(self.device)
         self.d_xy = torch.from_numpy(self.xy).to(self.device)
+        self.d_halo_off = torch.from_numpy(self.halo_off).to(self.device)
+        self.d_halo = torch.from_numpy(self.halo).to(self.device)
+        self.d_edge_off = torch.from_numpy(self.edge_off).to(self.device)
+        self.d_edges = torch.from_numpy(self.edges.view(np.int32)).to(self.device)
+        self.d_slot = torch.from_numpy(self.slot.view(np.int16)).to(self.device)
         self.dev = A.swe_dev_mesh(self.n_cells, self.n_nodes, _ptr(self.d_nbr), _ptr(self.d_c2n),
-                                  _ptr(self.d_xy))
+                                  _ptr(self.d_xy), _ptr(self.d_halo_off), _ptr(self.d_halo),
+                                  _ptr(self.d_edge_off), _ptr(self.d_edges), _ptr(self.d_slot))
         return self
 
     def to_mesh_order(self, a):
@@ -74,8 +88,10 @@ class Solver:
     """One simulation state on the device: U = (h, hu, hv) ping-pong buffers, bed, roughness,
     the control block (time, dt, counters) and the reduction workspace."""
 
+    VARIANTS = {"auto": A.SWE_AUTO, "cell": A.SWE_CELL, "tiled": A.SWE_TILED}
+
     def __init__(self, mesh: Mesh, z, n, h, hu, hv, dtype: str = "f64", g=9.81, courant=0.7,
-                 h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None):
+                 h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None, variant="auto"):
         if mesh.device is None:
             raise ValueError("mesh has no device arrays")
         self.mesh = mesh
@@ -84,7 +100,8 @@ class Solver:
         dev = mesh.device
         self._q = np.ascontiguousarray(inflow_q if inflow_q is not None else [], np.float64)
         self.params = A.swe_params(g, courant, h_dry, self.dtype, self._q.size,
-                                   self._q.ctypes.data_as(C.POINTER(C.c_double)))
+                                   self._q.ctypes.data_as(C.POINTER(C.c_double)),
+                                   self.VARIANTS[variant], 0)
         t = mesh.n_cells
 
         def field(a):

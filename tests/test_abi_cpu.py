@@ -148,3 +148,56 @@ def test_step_calls_reject_bad_arguments_without_touching_a_device():
     assert "null" in swe.swe_last_error()
     assert swe.lib.swe_run(None, None, None, None, 1, None, None, None) == swe.SWE_EINVAL
     assert swe.swe_workspace_bytes(10000) >= 40 * 16
+
+
+@pytest.mark.parametrize("k,morton", [(1, True), (2, True), (3, False)])
+def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton):
+    """The tiled step evaluates, per tile of 256 mesh-order cells, each interface between two
+    tile cells once, each interface to a halo cell or to the boundary once, and each cell
+    finds its three local edges through its slots."""
+    c = gen.small(k)
+    m = swe.Mesh(c.xy, c.tri, morton=morton, device=None)
+    t, tile = m.n_cells, swe.SWE_TILE
+    nbr = m.nbr.reshape(3, t)
+    slot = m.slot.reshape(3, t)
+    info = m.info
+    assert info.n_tiles == (t + tile - 1) // tile
+    seen = set()
+    for tt in range(info.n_tiles):
+        s0, s1 = tt * tile, min(t, (tt + 1) * tile)
+        halo = m.halo[m.halo_off[tt]:m.halo_off[tt + 1]]
+        cells = np.arange(s0, s1)
+        nb = nbr[:, s0:s1].ravel()
+        expect = np.unique(nb[(nb >= 0) & ((nb < s0) | (nb >= s1))])
+        assert np.array_equal(halo, expect)
+        ent = m.edges[m.edge_off[tt]:m.edge_off[tt + 1]]
+        a = (ent & 0xFF).astype(np.int64)
+        kk = ((ent >> 8) & 3).astype(np.int64)
+        b = (ent >> 16).astype(np.uint16).view(np.int16).astype(np.int64)
+        assert (a < s1 - s0).all() and (kk < 3).all()
+        bnd = b < 0
+        assert not (bnd[:-1] & ~bnd[1:]).any()          # boundary entries last
+        for e in range(len(ent)):
+            ia = s0 + a[e]
+            j = nbr[kk[e], ia]
+            if b[e] < 0:
+                assert j == b[e]
+            elif b[e] < tile:
+                assert j == s0 + b[e] and ia < j
+            else:
+                assert j == halo[b[e] - tile]
+            key = (tt, min(ia, j) if j >= 0 else ia, max(ia, j) if j >= 0 else (kk[e], j))
+            assert key not in seen
+            seen.add(key)
+        for i in cells:
+            for q in range(3):
+                sl = int(slot[q, i])
+                e, side_b = sl & 0x7FFF, bool(sl & 0x8000)
+                assert e < len(ent)
+                if side_b:
+                    assert b[e] == i - s0 and nbr[kk[e], s0 + a[e]] == i and nbr[q, i] == s0 + a[e]
+                else:
+                    assert a[e] == i - s0 and kk[e] == q
+    assert info.n_tile_edges == len(m.edges) and info.max_halo == max(
+        m.halo_off[1:] - m.halo_off[:-1])
+    assert len(seen) == info.n_tile_edges
