@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0     # MI355X HBM3E, public specification
-STEP_KERNEL = "step_kernel"
+STEP_KERNEL = "step_kernel"   # the per-cell step kernel the default variant launches
 
 
 def algorithmic_bytes(n_cells: int, n_nodes: int, word: int) -> int:
@@ -68,6 +68,53 @@ def time_gpu(solver, steps, warmup, stream):
     ms = ev0.elapsed_time(ev1)
     rc, st = solver.stats(stream=stream)
     return ms, rc, st
+
+
+def bench_ensemble(dtype: str, steps: int, warmup: int, stream) -> dict:
+    """Config 4: 256 scenarios (5e3 to 2e5 triangles, own inflow and roughness, own CFL dt)
+    stepped by one launch per step, against the same scenarios each run on its own."""
+    import torch
+
+    import gen
+    import paper_1807_00672_amd as swe
+    cases = gen.ensemble(256)
+    meshes = [swe.Mesh(c.xy, c.tri, c.edge_tag) for c in cases]
+    batch = swe.Batch(meshes)
+    bs = swe.BatchSolver(batch, cases, dtype=dtype)
+    bs.run(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        bs.run(steps, sync=False, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) * 1e-3
+    rc, st = bs.run(0, stream=stream)
+    assert rc == 0 and all(x["steps"] == warmup + steps for x in st), (rc, st[:2])
+    singles = [swe.Solver(m, c.z, c.n, c.h, c.hu, c.hv, dtype=dtype, inflow_q=c.inflow_q)
+               for m, c in zip(meshes, cases)]
+    for sv in singles:
+        sv.run(warmup, sync=False)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for sv in singles:
+            sv.run(steps, sync=False, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t_single = e0.elapsed_time(e1) * 1e-3
+    same = True
+    for k, sv in enumerate(singles):
+        rc1, st1 = sv.stats(stream=stream)
+        a, b = sv.numpy_state(), bs.numpy_state(k)
+        same &= rc1 == 0 and st1["t"] == st[k]["t"] and all(np.array_equal(x, y) for x, y in zip(a, b))
+    n_cells = int(batch.n_cells)
+    return {"scenarios": len(cases), "n_cells": n_cells, "steps": steps,
+            "batched_cell_updates_per_s": n_cells * steps / t_batch,
+            "separate_cell_updates_per_s": n_cells * steps / t_single,
+            "batched_s": t_batch, "separate_s": t_single, "speedup": t_single / t_batch,
+            "bitwise_equal_to_separate": bool(same)}
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=10):
@@ -120,6 +167,8 @@ def main():
                     help="small: the same recipe at 1e5 cells (quick checks)")
     ap.add_argument("--dtypes", default="f64,f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--ensemble-steps", type=int, default=2000,
+                    help="steps of the 256-scenario ensemble (0: skip it)")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="copy: run only a plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -172,6 +221,17 @@ def main():
         del solver
         torch.cuda.empty_cache()
 
+    ensemble = {}
+    if args.ensemble_steps > 0 and args.size == "full":
+        for dt in args.dtypes.split(","):
+            ensemble[dt] = bench_ensemble(dt, args.ensemble_steps, 10, stream)
+            e = ensemble[dt]
+            print(f"# ensemble {dt}: {e['n_cells']} cells in {e['scenarios']} scenarios, batched "
+                  f"{e['batched_cell_updates_per_s'] / 1e9:.2f} G/s vs separate "
+                  f"{e['separate_cell_updates_per_s'] / 1e9:.2f} G/s (x{e['speedup']:.2f}), "
+                  f"bitwise equal {e['bitwise_equal_to_separate']}", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+
     copy_gbps = copy_bandwidth()
     main_dt = "f64" if "f64" in results else next(iter(results))
     r = results[main_dt]
@@ -197,6 +257,7 @@ def main():
                      "alg_bytes_per_launch": r["alg_bytes_per_step"]},
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "t_end_state"}
                      for k, v in results.items()},
+        "ensemble": ensemble,
         "copy_GBps_measured": copy_gbps,
         "device": torch.cuda.get_device_name(0),
     }

@@ -267,3 +267,22 @@ def strip(nx: int, lx=20.0, ly=None, ny=2, cfg=21, jitter=0.0, **kw) -> Case:
     """Dam break on a narrow strip mesh (for closed-form 1D solutions)."""
     ly = lx / nx * ny if ly is None else ly
     return dam_break(nx=nx, ny=ny, lx=lx, ly=ly, cfg=cfg, jitter=jitter, **kw)
+
+
+def three_mounds(nx=120, ny=48, lx=60.0, ly=24.0, cfg=41, steps=600, eta0=1.5, x_dam=12.0,
+                 n_manning=0.02) -> Case:
+    """Wet/dry validation workload: a reservoir released over a dry floor with three mounds.
+
+    Parameters chosen for this suite (not a published geometry): 60 m x 24 m walled box, still
+    water at eta0 = 1.5 m behind x = 12 m, dry beyond; one tall mound (2.5 m high, 8 m wide) at
+    (40, 12) whose top never floods early, two low ones (1 m, 5 m) at (25, 6) and (25, 18) that
+    the wave overtops; uniform Manning n."""
+    xy, tri = split_square_mesh(nx, ny, lx, ly, cfg)
+    c = centroids(xy, tri)
+    z = np.zeros(tri.shape[0])
+    for (bx, by, a, w) in ((40.0, 12.0, 2.5, 8.0), (25.0, 6.0, 1.0, 5.0), (25.0, 18.0, 1.0, 5.0)):
+        z = z + a * np.exp(-((c[:, 0] - bx) ** 2 + (c[:, 1] - by) ** 2) / (w * w))
+    h = np.where(c[:, 0] < x_dam, np.maximum(eta0 - z, 0.0), 0.0)
+    t = tri.shape[0]
+    return Case(f"three_mounds_{t}", xy, tri, z, np.full(t, n_manning), h, np.zeros(t),
+                np.zeros(t), steps, extra={"eta0": eta0, "x_dam": x_dam})

@@ -48,10 +48,11 @@ extern "C" {
 #define SWE_MAX_INFLOW 16      /* inflow segments per mesh */
 #define SWE_CTRL_BYTES 512     /* size of the device control block of a state */
 #define SWE_WALL (-1)          /* boundary code of a reflective wall (section 3) */
-#define SWE_AUTO 0             /* variant: tiled when the device mesh has tile arrays and the
-                                  tile's LDS fits the device, else per-cell */
+#define SWE_AUTO 0             /* variant: the library's default, the per-cell kernel */
 #define SWE_CELL 1             /* variant: one work-item per cell gathering its neighbours */
 #define SWE_TILED 2            /* variant: tile-staged states, each tile interface once */
+#define SWE_NO_XCD_REMAP 1u    /* flag: launch tiles in mesh order instead of giving each XCD
+                                  a contiguous run of tiles (same results) */
 #define SWE_TILE 256           /* cells per tile: consecutive mesh-order cells stepped by one
                                   workgroup, which stages them and their neighbours in LDS */
 
@@ -117,7 +118,7 @@ typedef struct swe_params {
     int32_t n_inflow;      /* number of inflow segments, <= SWE_MAX_INFLOW */
     const double *inflow_q;/* host, n_inflow unit discharges (m^2/s) entering, >= 0 */
     int32_t variant;       /* step kernel: SWE_AUTO, SWE_CELL or SWE_TILED (same results) */
-    int32_t reserved;
+    int32_t flags;         /* SWE_NO_XCD_REMAP or 0 */
 } swe_params;
 
 /* Device state of one simulation.  All pointers device, element type given by dtype. */
@@ -214,6 +215,82 @@ int32_t swe_read_stats(swe_state *s, swe_run_stats *out, void *stream);
 
 /* Message of the calling thread's last failure ("" if none).  Valid until the next call. */
 const char *swe_last_error(void);
+
+/* ------------------------------------------------------------------ batches */
+
+/*
+ * A batch steps many independent meshes (scenarios: an ensemble of inflows and roughness) in
+ * one launch per step, each scenario with its own CFL dt and time.  Its arrays are the
+ * scenarios' mesh arrays concatenated (cells and nodes offset per scenario); its tiles never
+ * straddle two scenarios.
+ */
+typedef struct swe_batch swe_batch;
+
+typedef struct swe_batch_info {
+    int32_t n_scenarios;
+    int32_t max_inflow_segments;   /* largest inflow tag over the scenarios */
+    int64_t n_cells, n_nodes, n_tiles, n_halo, n_tile_edges;
+    int32_t max_halo, max_tile_edges;
+} swe_batch_info;
+
+/* Arrays of a batch besides the concatenated SWE_ARR_* ones (which swe_batch_export also
+ * gives: NBR, C2N, XY, HALO_OFF, HALO, EDGE_OFF, EDGES, SLOT, and PERM = each scenario's
+ * own SWE_ARR_PERM, concatenated). */
+enum swe_batch_array {
+    SWE_BARR_CELL_OFF = 16,      /* int64[n+1]: scenario s owns cells [off[s], off[s+1]) */
+    SWE_BARR_NODE_OFF = 17,      /* int64[n+1]: and nodes [off[s], off[s+1]) */
+    SWE_BARR_TILE_START = 18,    /* int32[n_tiles+1]: tile t holds cells [start[t], start[t+1]) */
+    SWE_BARR_TILE_SCEN = 19,     /* int32[n_tiles]: scenario of tile t */
+    SWE_BARR_SCEN_TILE_OFF = 20  /* int32[n+1]: scenario s owns tiles [off[s], off[s+1]) */
+};
+
+typedef struct swe_batch_dev {
+    swe_dev_mesh mesh;             /* device copies of the concatenated SWE_ARR_* arrays */
+    const int32_t *tile_start;     /* device, SWE_BARR_TILE_START */
+    const int32_t *tile_scen;      /* device, SWE_BARR_TILE_SCEN */
+    const int32_t *scen_tile_off;  /* device, SWE_BARR_SCEN_TILE_OFF */
+} swe_batch_dev;
+
+typedef struct swe_batch_params {
+    double g, courant, h_dry;      /* shared by all scenarios, as in swe_params */
+    int32_t dtype;                 /* SWE_F64 or SWE_F32 */
+    int32_t variant;               /* SWE_AUTO, SWE_CELL or SWE_TILED */
+    const double *inflow_q;        /* device, n_scenarios * SWE_MAX_INFLOW unit discharges
+                                      (m^2/s): scenario s's segment k at [s*16 + k-1] */
+    int32_t flags;                 /* SWE_NO_XCD_REMAP or 0 */
+    int32_t reserved;
+} swe_batch_params;
+
+/* Concatenate n built meshes (each keeps its own cell and node order).  The meshes may be
+ * destroyed afterwards.  Errors: SWE_EINVAL. */
+int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **out);
+int32_t swe_batch_info_get(const swe_batch *batch, swe_batch_info *out);
+/* Copy a SWE_ARR_* or SWE_BARR_* array of the batch to host memory.  Errors: SWE_EINVAL. */
+int32_t swe_batch_export(const swe_batch *batch, int32_t which, void *dst, int64_t dst_bytes);
+void swe_batch_destroy(swe_batch *batch);
+/* Workspace bytes of a batch state (its per-tile partials).  Errors: SWE_EINVAL. */
+int32_t swe_batch_workspace_bytes(const swe_batch *batch, int64_t *bytes);
+
+/*
+ * Start every scenario of a batch state at t0 (t_end as in swe_state_init).  The state's
+ * buffers hold the concatenated cells; ctrl holds n_scenarios control blocks of
+ * SWE_CTRL_BYTES each.  Queues work only.  Errors: SWE_EINVAL, SWE_EDEVICE.
+ */
+int32_t swe_batch_state_init(const swe_batch *batch, const swe_batch_dev *dev,
+                             const swe_batch_params *p, swe_state *s, double t0, double t_end,
+                             void *stream);
+
+/*
+ * n_steps steps of every scenario, one launch of the step kernel and one of the per-scenario dt
+ * pass per step, replayed from a captured graph.  Each scenario takes its own CFL dt and stops
+ * on its own at t_end or on an error.  out: NULL (queue only) or n_scenarios records; then the
+ * stream is synchronised and out[s].cur tells in which buffer scenario s's cells are.  Returns
+ * SWE_OK, or with out != NULL the first failing scenario's status.  Errors: SWE_EINVAL,
+ * SWE_EUNSUPPORTED (tile LDS does not fit the device), SWE_EDEVICE.
+ */
+int32_t swe_batch_run(const swe_batch *batch, const swe_batch_dev *dev,
+                      const swe_batch_params *p, swe_state *s, int64_t n_steps,
+                      swe_run_stats *out, void *stream);
 
 /* ------------------------------------------------------------------ test hook */
 

@@ -9,8 +9,10 @@ from ._abi import (  # noqa: F401
     SWE_WALL, SweError,
     lib, swe_dev_mesh, swe_flux_eval, swe_last_error, swe_mesh_create, swe_mesh_destroy,
     swe_mesh_export, swe_mesh_info, swe_mesh_info_get, swe_params, swe_read_stats, swe_run,
-    swe_run_stats, swe_state, swe_state_init, swe_step, swe_workspace_bytes)
-from .solver import Mesh, Solver  # noqa: F401
+    swe_run_stats, swe_state, swe_state_init, swe_step, swe_workspace_bytes, swe_batch_create,
+    swe_batch_destroy, swe_batch_export, swe_batch_info_get, swe_batch_run,
+    swe_batch_state_init, swe_batch_workspace_bytes)
+from .solver import Batch, BatchSolver, Mesh, Solver  # noqa: F401
 
 
 def require_gpu() -> None:

@@ -13,7 +13,8 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library then shares)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libswe.so")
+# SWE_LIB may name another build of the same sources (kernel-tuning builds); default in-tree.
+LIB_PATH = os.environ.get("SWE_LIB") or os.path.join(HERE, "libswe.so")
 
 SWE_OK = 0
 SWE_EINVAL = -1
@@ -31,6 +32,7 @@ SWE_CTRL_BYTES = 512
 SWE_WALL = -1
 
 SWE_AUTO, SWE_CELL, SWE_TILED = 0, 1, 2
+SWE_NO_XCD_REMAP = 1
 SWE_TILE = 256
 
 (SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,
@@ -68,7 +70,7 @@ class swe_params(C.Structure):
     _fields_ = [("g", C.c_double), ("courant", C.c_double), ("h_dry", C.c_double),
                 ("dtype", C.c_int32), ("n_inflow", C.c_int32),
                 ("inflow_q", C.POINTER(C.c_double)), ("variant", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 class swe_state(C.Structure):
@@ -87,10 +89,34 @@ class swe_run_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+SWE_BARR_CELL_OFF, SWE_BARR_NODE_OFF, SWE_BARR_TILE_START, SWE_BARR_TILE_SCEN, \
+    SWE_BARR_SCEN_TILE_OFF = range(16, 21)
+
+
+class swe_batch_info(C.Structure):
+    _fields_ = [("n_scenarios", C.c_int32), ("max_inflow_segments", C.c_int32),
+                ("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("n_tiles", C.c_int64),
+                ("n_halo", C.c_int64), ("n_tile_edges", C.c_int64), ("max_halo", C.c_int32),
+                ("max_tile_edges", C.c_int32)]
+
+
+class swe_batch_dev(C.Structure):
+    _fields_ = [("mesh", swe_dev_mesh), ("tile_start", C.c_void_p), ("tile_scen", C.c_void_p),
+                ("scen_tile_off", C.c_void_p)]
+
+
+class swe_batch_params(C.Structure):
+    _fields_ = [("g", C.c_double), ("courant", C.c_double), ("h_dry", C.c_double),
+                ("dtype", C.c_int32), ("variant", C.c_int32), ("inflow_q", C.c_void_p),
+                ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
 EXPORTS = [
     "swe_mesh_create", "swe_mesh_info_get", "swe_mesh_export", "swe_mesh_destroy",
     "swe_workspace_bytes", "swe_state_init", "swe_step", "swe_run", "swe_read_stats",
-    "swe_last_error", "swe_flux_eval",
+    "swe_last_error", "swe_flux_eval", "swe_batch_create", "swe_batch_info_get",
+    "swe_batch_export", "swe_batch_destroy", "swe_batch_workspace_bytes", "swe_batch_state_init",
+    "swe_batch_run",
 ]
 
 
@@ -116,8 +142,18 @@ def _load():
     L.swe_last_error.argtypes = []
     L.swe_last_error.restype = C.c_char_p
     L.swe_flux_eval.argtypes = [i32, i64, dbl, dbl] + [vp] * 12 + [vp]
+    L.swe_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
+    L.swe_batch_info_get.argtypes = [vp, C.POINTER(swe_batch_info)]
+    L.swe_batch_export.argtypes = [vp, i32, vp, i64]
+    L.swe_batch_destroy.argtypes = [vp]
+    L.swe_batch_destroy.restype = None
+    L.swe_batch_workspace_bytes.argtypes = [vp, C.POINTER(i64)]
+    L.swe_batch_state_init.argtypes = [vp, C.POINTER(swe_batch_dev), C.POINTER(swe_batch_params),
+                                       C.POINTER(swe_state), dbl, dbl, vp]
+    L.swe_batch_run.argtypes = [vp, C.POINTER(swe_batch_dev), C.POINTER(swe_batch_params),
+                                C.POINTER(swe_state), i64, vp, vp]
     for name in EXPORTS:
-        if name not in ("swe_mesh_destroy", "swe_last_error"):
+        if name not in ("swe_mesh_destroy", "swe_last_error", "swe_batch_destroy"):
             getattr(L, name).restype = i32
     return L
 
@@ -201,3 +237,47 @@ def swe_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny
                   stream=None) -> None:
     _check(lib.swe_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny, f,
                              p, stream), "swe_flux_eval")
+
+
+def swe_batch_create(meshes) -> C.c_void_p:
+    arr = (C.c_void_p * len(meshes))(*[m.value if isinstance(m, C.c_void_p) else m for m in meshes])
+    out = C.c_void_p()
+    _check(lib.swe_batch_create(arr, len(meshes), C.byref(out)), "swe_batch_create")
+    return out
+
+
+def swe_batch_info_get(batch) -> swe_batch_info:
+    info = swe_batch_info()
+    _check(lib.swe_batch_info_get(batch, C.byref(info)), "swe_batch_info_get")
+    return info
+
+
+def swe_batch_export(batch, which: int, n: int, dtype) -> np.ndarray:
+    out = np.empty(max(n, 1), dtype=dtype)
+    _check(lib.swe_batch_export(batch, which, _np_ptr(out), out.nbytes), "swe_batch_export")
+    return out[:n]
+
+
+def swe_batch_destroy(batch) -> None:
+    lib.swe_batch_destroy(batch)
+
+
+def swe_batch_workspace_bytes(batch) -> int:
+    b = C.c_int64()
+    _check(lib.swe_batch_workspace_bytes(batch, C.byref(b)), "swe_batch_workspace_bytes")
+    return int(b.value)
+
+
+def swe_batch_state_init(batch, dev, params, state, t0=0.0, t_end=0.0, stream=None) -> None:
+    _check(lib.swe_batch_state_init(batch, C.byref(dev), C.byref(params), C.byref(state), t0,
+                                    t_end, stream), "swe_batch_state_init")
+
+
+def swe_batch_run(batch, dev, params, state, n_steps: int, stats=None, stream=None) -> int:
+    """Queue n_steps steps of every scenario; with a stats array (one swe_run_stats per
+    scenario) synchronise and return the first failing scenario's status."""
+    rc = lib.swe_batch_run(batch, C.byref(dev), C.byref(params), C.byref(state), n_steps,
+                           None if stats is None else C.cast(stats, C.c_void_p), stream)
+    if rc in (SWE_EINVAL, SWE_EDEVICE, SWE_EMESH, SWE_EUNSUPPORTED):
+        _check(rc, "swe_batch_run")
+    return rc

@@ -98,14 +98,12 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
 {
     *out = nullptr;
     const std::string w(where);
-    if (p->variant == SWE_CELL) return SWE_OK;
-    if (p->variant != SWE_AUTO && p->variant != SWE_TILED)
+    if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
         return fail(SWE_EINVAL, w + ": unknown variant");
+    if (p->flags & ~SWE_NO_XCD_REMAP) return fail(SWE_EINVAL, w + ": unknown flags");
+    if (p->variant != SWE_TILED) return SWE_OK;   // the per-cell kernel
     const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot;
-    if (!have) {
-        if (p->variant == SWE_TILED) return fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
-        return SWE_OK;
-    }
+    if (!have) return fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
     int dev = 0;
     if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;
     if (dev < 0 || dev >= 64) return fail(SWE_EUNSUPPORTED, w + ": device index beyond 63");
@@ -117,12 +115,9 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
         d.limit = lim;
     }
     const size_t need = tile_lds_bytes_for(p->dtype, mesh->tiles);
-    if (need > static_cast<size_t>(d.limit)) {
-        if (p->variant == SWE_TILED)
-            return fail(SWE_EUNSUPPORTED, w + ": tile needs " + std::to_string(need) +
-                                              " bytes of LDS, device allows " + std::to_string(d.limit));
-        return SWE_OK;
-    }
+    if (need > static_cast<size_t>(d.limit))
+        return fail(SWE_EUNSUPPORTED, w + ": tile needs " + std::to_string(need) +
+                                          " bytes of LDS, device allows " + std::to_string(d.limit));
     if (need > 65536 && d.prepared < need) {
         if (int32_t rc = check_hip(prepare_tile_kernels(static_cast<size_t>(d.limit)), where)) return rc;
         d.prepared = static_cast<size_t>(d.limit);
@@ -131,12 +126,14 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     return SWE_OK;
 }
 
+int remap_of(const swe_params *p) { return (p->flags & SWE_NO_XCD_REMAP) ? 0 : 1; }
+
 // Two steps (even and odd buffer) captured once as a graph and replayed by swe_run; the
 // launch arguments it bakes in form its key.
 struct GraphKey {
     swe_dev_mesh dm;
     double g, courant, h_dry;
-    int32_t dtype, variant, n_inflow, cur;
+    int32_t dtype, variant, n_inflow, cur, flags;
     double q[SWE_MAX_INFLOW];
     void *h[2], *hu[2], *hv[2];
     const void *z, *n;
@@ -168,6 +165,7 @@ GraphKey make_key(const swe_dev_mesh *dm, const swe_params *p, const swe_state *
     k.dm = *dm;
     k.g = p->g; k.courant = p->courant; k.h_dry = p->h_dry;
     k.dtype = p->dtype; k.variant = p->variant; k.n_inflow = p->n_inflow; k.cur = s->cur;
+    k.flags = p->flags;
     for (int i = 0; i < p->n_inflow; ++i) k.q[i] = p->inflow_q[i];
     for (int b = 0; b < 2; ++b) { k.h[b] = s->h[b]; k.hu[b] = s->hu[b]; k.hv[b] = s->hv[b]; }
     k.z = s->z; k.n = s->n; k.ctrl = s->ctrl; k.work = s->work;
@@ -198,8 +196,9 @@ hipGraphExec_t two_step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, cons
     }
     hipStream_t cs = g_capture[dev];
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    int e0 = launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_seq, cs, tl);
-    int e1 = launch_step(p->dtype, *dm, cfg, *s, 1 - s->cur, dt_seq, n_seq, cs, tl);
+    int e0 = launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_seq, cs, tl, nullptr, remap_of(p));
+    int e1 = launch_step(p->dtype, *dm, cfg, *s, 1 - s->cur, dt_seq, n_seq, cs, tl, nullptr,
+                         remap_of(p));
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (e0 != hipSuccess || e1 != hipSuccess || ee != hipSuccess || !graph) {
@@ -265,7 +264,8 @@ int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
     const StepConfig cfg = make_config(mesh, p);
     const TileLayout *tl = nullptr;
     if (int32_t rc = choose_variant(mesh, dm, p, &tl, "swe_step")) return rc;
-    if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, nullptr, 0, stream, tl),
+    if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, nullptr, 0, stream, tl, nullptr,
+                                           remap_of(p)),
                                "swe_step"))
         return rc;
     s->cur ^= 1;
@@ -321,7 +321,7 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
     }
     for (; k < n_steps; ++k) {
         if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_steps,
-                                               stream, tl),
+                                               stream, tl, nullptr, remap_of(p)),
                                    "swe_run"))
             return rc;
         s->cur ^= 1;

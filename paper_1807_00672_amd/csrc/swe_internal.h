@@ -39,9 +39,9 @@ struct Partials {
 
 inline int64_t n_blocks(int64_t n_cells) { return (n_cells + kBlock - 1) / kBlock; }
 
-inline Partials partials_of(void *work, int64_t n_cells)
+// Partials of nb tiles laid out in a workspace.
+inline Partials partials_for(void *work, int64_t nb)
 {
-    const int64_t nb = n_blocks(n_cells);
     char *p = static_cast<char *>(work);
     Partials r;
     r.dt = reinterpret_cast<double *>(p);
@@ -50,11 +50,12 @@ inline Partials partials_of(void *work, int64_t n_cells)
     return r;
 }
 
-inline int64_t workspace_bytes(int64_t n_cells)
+inline int64_t workspace_bytes_for_tiles(int64_t nb)
 {
-    const int64_t nb = n_blocks(n_cells);
     return ((nb * 8 + 255) / 256) * 256 + 2 * ((nb + 63) / 64) * 64 * 4 + 256;
 }
+
+inline int64_t workspace_bytes(int64_t n_cells) { return workspace_bytes_for_tiles(n_blocks(n_cells)); }
 
 // Everything a launch needs besides the state: plain values, passed by value to kernels.
 struct StepConfig {
@@ -70,12 +71,23 @@ struct TileLayout {
     int32_t max_halo, max_edges;
 };
 
-// Launchers (swe_kernels.hip).  All queue work on `stream` and return a hipError_t as int.
+// Device arrays of a batch of meshes stepped together (swe_batch_*).
+struct BatchLaunch {
+    const int32_t *tile_start;      // [n_tiles + 1] first cell of each tile
+    const int32_t *tile_scen;       // [n_tiles] scenario of each tile
+    const int32_t *scen_tile_off;   // [n_scen + 1] tiles of each scenario
+    const double *q_table;          // [n_scen * SWE_MAX_INFLOW] inflow discharges
+    int32_t n_scen;
+    int64_t n_tiles;
+};
+
+// Launchers (swe_kernels.hip).  batch == nullptr: a single mesh.  All queue work on `stream` and return a hipError_t as int.
 int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                double t0, double t_end, void *stream);
+                double t0, double t_end, void *stream, const BatchLaunch *batch = nullptr);
 // tl == nullptr: the per-cell kernel; else the tiled kernel (its LDS must fit, see below).
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl);
+                int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
+                const BatchLaunch *batch = nullptr, int remap = 1);
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);
 int prepare_tile_kernels(size_t max_lds);   // allow dynamic LDS up to max_lds bytes
 int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);

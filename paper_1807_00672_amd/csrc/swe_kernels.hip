@@ -21,14 +21,92 @@ namespace {
 
 constexpr double kInf = __builtin_huge_val();
 
+// Division and square root of the step.  FP64: the correctly rounded operations (the same
+// results as the CPU oracle's).  FP32: the hardware reciprocal and square root (about 1 ulp),
+// a fraction of the instructions of the correctly rounded sequences; both are odd in their
+// sign arguments, so interface fluxes stay exact negatives of each other.
+// Minimum waves per SIMD the compiler must allow for (register budget) in the two step
+// kernels; 1 leaves the choice to the compiler.
+#ifndef SWE_CELL_WAVES
+#define SWE_CELL_WAVES 1
+#endif
+#ifndef SWE_TILE_WAVES
+#define SWE_TILE_WAVES 1
+#endif
+#ifndef SWE_F32_FAST
+#define SWE_F32_FAST 1
+#endif
+template <typename R>
+__device__ __forceinline__ R div_(R a, R b)
+{
+    return a / b;
+}
+template <typename R>
+__device__ __forceinline__ R sqrt_(R a)
+{
+    return sqrt(a);
+}
+#ifndef SWE_F64_FAST
+#define SWE_F64_FAST 0
+#endif
+#if SWE_F64_FAST
+// Reciprocal by v_rcp_f64 and two Newton steps, quotient with one residual correction; square
+// root by v_rsq_f64 and Goldschmidt's iteration with a final residual correction.
+template <>
+__device__ __forceinline__ double div_<double>(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    const double q = a * r;
+    const double rem = fma(-b, q, a);
+    return fma(rem, r, q);
+}
+template <>
+__device__ __forceinline__ double sqrt_<double>(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    return a > 0.0 ? g : a;   // sqrt(0) = 0 (rsq(0) is inf)
+}
+#endif
+#if SWE_F32_FAST
+template <>
+__device__ __forceinline__ float div_<float>(float a, float b)
+{
+    return a * __builtin_amdgcn_rcpf(b);
+}
+template <>
+__device__ __forceinline__ float sqrt_<float>(float a)
+{
+    return __builtin_amdgcn_sqrtf(a);
+}
+#endif
+
 // ------------------------------------------------------------------------ flux pieces
 
 // Velocity of a cell: zero at or below the dry threshold.
 template <typename R>
 __device__ __forceinline__ R velocity(R h, R hq, R h_dry)
 {
-    return h > h_dry ? hq / h : R(0);
+    return h > h_dry ? div_(hq, h) : R(0);
 }
+
+// Quotients with |num| below this fraction of |den| may round to zero; larger ones keep the
+// sign of num / den.
+template <typename R>
+__device__ __forceinline__ R tiny_ratio();
+template <>
+__device__ __forceinline__ double tiny_ratio<double>() { return 0x1p-1000; }
+template <>
+__device__ __forceinline__ float tiny_ratio<float>() { return 0x1p-100f; }
 
 // HLLC flux in the edge frame (section 2.2, ref. [6]).  Reconstructed depths (already zero
 // when dry), normal (q) and tangential (w) velocities of both sides; outputs the mass,
@@ -43,7 +121,7 @@ __device__ __forceinline__ void hllc_normal(R g, R hl, R ql, R wl, R hr, R qr, R
         fh = R(0); fq = R(0); fw = R(0);
         return;
     }
-    const R cl = sqrt(g * hl), cr = sqrt(g * hr);
+    const R cl = sqrt_(g * hl), cr = sqrt_(g * hr);
     R sl, sr;
     if (hl == R(0)) {
         sl = qr - R(2) * cr;
@@ -65,10 +143,14 @@ __device__ __forceinline__ void hllc_normal(R g, R hl, R ql, R wl, R hr, R qr, R
         fh = fhr; fq = fqr; fw = fh * wr;
     } else {
         const R den = sr - sl;
-        fh = ((sr * fhl - sl * fhr) + sl * sr * (hr - hl)) / den;
-        fq = ((sr * fql - sl * fqr) + sl * sr * (hr * qr - hl * ql)) / den;
-        const R sstar = (sl * hr * (qr - sr) - sr * hl * (ql - sl)) /
-                        (hr * (qr - sr) - hl * (ql - sl));
+        fh = div_((sr * fhl - sl * fhr) + sl * sr * (hr - hl), den);
+        fq = div_((sr * fql - sl * fqr) + sl * sr * (hr * qr - hl * ql), den);
+        // Only the sign of the contact speed S* = num / den is used.  In this branch a side is
+        // wet, S_L < q_L and S_R > q_R, so den < 0 and S* has the sign of -num; the quotient
+        // is formed only where it could underflow to zero.
+        const R num = sl * hr * (qr - sr) - sr * hl * (ql - sl);
+        const R den2 = hr * (qr - sr) - hl * (ql - sl);
+        const R sstar = fabs(num) < tiny_ratio<R>() * fabs(den2) ? div_(num, den2) : -num;
         const R wup = sstar > R(0) ? wl : (sstar < R(0) ? wr : (wl + wr) / R(2));
         fw = fh * wup;
     }
@@ -128,21 +210,21 @@ __device__ __forceinline__ void wall_flux(R g, R hd, R h, R u, R v, R nx, R ny, 
 template <typename R>
 __device__ __forceinline__ R inflow_flux(R g, R q_in, R h, R nx, R ny, R &fh, R &fx, R &fy)
 {
-    const R hc = cbrt(q_in * q_in / g);
+    const R hc = cbrt(div_(q_in * q_in, g));
     const R hb = fmax(h, hc);
-    const R mom = q_in * q_in / hb + R(0.5) * g * hb * hb;
+    const R mom = div_(q_in * q_in, hb) + R(0.5) * g * hb * hb;
     fh = -q_in;
     fx = mom * nx;
     fy = mom * ny;
-    return q_in / hb + sqrt(g * hb);
+    return div_(q_in, hb) + sqrt_(g * hb);
 }
 
 template <typename R>
 __device__ __forceinline__ R inflow_speed(R g, R q_in, R h)
 {
-    const R hc = cbrt(q_in * q_in / g);
+    const R hc = cbrt(div_(q_in * q_in, g));
     const R hb = fmax(h, hc);
-    return q_in / hb + sqrt(g * hb);
+    return div_(q_in, hb) + sqrt_(g * hb);
 }
 
 // ------------------------------------------------------------------------ geometry
@@ -166,13 +248,13 @@ __device__ __forceinline__ void cell_geometry(const double2 *__restrict__ xy, in
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const R dx = static_cast<R>(ex[k]), dy = static_cast<R>(ey[k]);
-        const R l = sqrt(dx * dx + dy * dy);
-        gm.nx[k] = dy / l;
-        gm.ny[k] = -dx / l;
+        const R l = sqrt_(dx * dx + dy * dy);
+        gm.nx[k] = div_(dy, l);
+        gm.ny[k] = div_(-dx, l);
         gm.l[k] = l;
     }
     gm.area = static_cast<R>(0.5 * (ex[0] * ey[1] - ey[0] * ex[1]));
-    gm.inradius = R(2) * gm.area / (gm.l[0] + gm.l[1] + gm.l[2]);
+    gm.inradius = div_(R(2) * gm.area, gm.l[0] + gm.l[1] + gm.l[2]);
 }
 
 // ------------------------------------------------------------------------ reductions
@@ -234,23 +316,55 @@ __device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
 }
 
 // CFL bound r / (|u| + sqrt(g h)) of a cell (inflow edges add their boundary speed);
-// +inf for a dry cell without inflow.
+// +inf for a dry cell without inflow.  qtab: the scenario's inflow discharges (nullptr: cfg's).
 template <typename R>
 __device__ __forceinline__ R cell_dt(R g, R hd, R h, R hu, R hv, R inradius, const int32_t *nb,
-                                     const StepConfig &cfg)
+                                     const StepConfig &cfg, const double *qtab = nullptr)
 {
     R s = R(0);
     if (h > hd) {
-        const R u = hu / h, v = hv / h;
-        s = sqrt(u * u + v * v) + sqrt(g * h);
+        const R u = div_(hu, h), v = div_(hv, h);
+        s = sqrt_(u * u + v * v) + sqrt_(g * h);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         if (nb[k] < SWE_WALL) {
-            const R sb = inflow_speed(g, static_cast<R>(cfg.inflow_q[-2 - nb[k]]), h);
+            const double q = qtab ? qtab[-2 - nb[k]] : cfg.inflow_q[-2 - nb[k]];
+            const R sb = inflow_speed(g, static_cast<R>(q), h);
             if (sb > s) s = sb;
         }
-    return s > R(0) ? inradius / s : static_cast<R>(kInf);
+    return s > R(0) ? div_(inradius, s) : static_cast<R>(kInf);
+}
+
+// Where a workgroup's cells live when several meshes (scenarios) are stepped together: tile t
+// holds cells [tile_start[t], tile_start[t+1]) of scenario tile_scen[t], whose control block
+// is ctrl + tile_scen[t] * SWE_CTRL_BYTES and inflow discharges q_table[16 s ..].  A single
+// mesh leaves tile_start null: tile t holds cells [256 t, 256 t + 256).
+struct Batch {
+    const int32_t *tile_start;
+    const int32_t *tile_scen;
+    const int32_t *scen_tile_off;   // [n_scen + 1] tiles of each scenario (dt pass)
+    const double *q_table;
+    int32_t n_scen;
+    int32_t remap;       // 1: XCD-contiguous tile order
+    int32_t n_tiles;
+    int32_t pad;
+};
+
+// Workgroups are handed to the eight XCDs in turn; give each XCD a contiguous run of tiles
+// so that a tile's neighbours were recently read into the same XCD's L2 by its neighbour
+// tiles (remap == 0 keeps the hardware order).
+__device__ __forceinline__ int xcd_tile(int b, int n_tiles, int remap)
+{
+    if (!remap) return b;
+    const int per = (n_tiles + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
+__device__ __forceinline__ const Ctrl *ctrl_of(const Ctrl *base, int scen)
+{
+    return reinterpret_cast<const Ctrl *>(reinterpret_cast<const unsigned char *>(base) +
+                                          static_cast<size_t>(scen) * SWE_CTRL_BYTES);
 }
 
 // ------------------------------------------------------------------------ kernels
@@ -274,16 +388,25 @@ struct StepArgs {
 
 // One explicit step for every cell (eq. 4 with the source treatments of section 2.2).
 template <typename R>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<R> a, StepConfig cfg)
+__global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a, StepConfig cfg,
+                                                                   Batch bt)
 {
-    if (a.ctrl->done) return;   // uniform over the grid: the state has stopped
+    const int tile = xcd_tile(blockIdx.x, bt.n_tiles, bt.remap);
+    if (tile >= bt.n_tiles) return;
+    const bool batched = bt.tile_start != nullptr;
+    const int scen = batched ? bt.tile_scen[tile] : 0;
+    const Ctrl *ctrl = ctrl_of(a.ctrl, scen);
+    const double *qtab = batched ? bt.q_table + scen * SWE_MAX_INFLOW : nullptr;
+    if (ctrl->done) return;   // uniform over the workgroup: its state has stopped
     const int64_t T = cfg.n_cells;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
+    const int64_t s1 = batched ? bt.tile_start[tile + 1] : s0 + kBlock;
+    const int64_t i = s0 + threadIdx.x;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
-    const R dt = static_cast<R>(a.ctrl->dt);
+    const R dt = static_cast<R>(ctrl->dt);
     R dtc = static_cast<R>(kInf);
     int clamp = 0, flag = 0;
-    if (i < T) {
+    if (i < s1 && i < T) {
         CellGeom<R> gm;
         cell_geometry<R>(a.xy, a.c2n[i], a.c2n[T + i], a.c2n[2 * T + i], gm);
         const R h = a.h[i], hu = a.hu[i], hv = a.hv[i], z = a.z[i];
@@ -301,7 +424,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<R> a, StepConfig 
             } else if (j == SWE_WALL) {
                 wall_flux<R>(g, hd, h, u, v, gm.nx[k], gm.ny[k], fh, fx, fy, p);
             } else {
-                inflow_flux<R>(g, static_cast<R>(cfg.inflow_q[-2 - j]), h, gm.nx[k], gm.ny[k],
+                inflow_flux<R>(g, static_cast<R>(qtab ? qtab[-2 - j] : cfg.inflow_q[-2 - j]), h,
+                               gm.nx[k], gm.ny[k],
                                fh, fx, fy);
                 p = R(0);
             }
@@ -315,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<R> a, StepConfig 
             }
         }
         // explicit Euler update, positivity clamp, semi-implicit friction
-        const R r = dt / gm.area;
+        const R r = div_(dt, gm.area);
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
@@ -326,10 +450,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<R> a, StepConfig 
         R hun, hvn;
         if (hs > hd) {
             const R nm = a.n[i];
-            const R mag = sqrt(hus * hus + hvs * hvs);
-            const R d = R(1) + dt * g * nm * nm * mag / (hs * hs * cbrt(hs));
-            hun = hus / d;
-            hvn = hvs / d;
+            const R mag = sqrt_(hus * hus + hvs * hvs);
+            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt(hs));
+            hun = div_(hus, d);
+            hvn = div_(hvs, d);
         } else {
             hun = R(0);
             hvn = R(0);
@@ -338,9 +462,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<R> a, StepConfig 
         a.huo[i] = hun;
         a.hvo[i] = hvn;
         if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
-        dtc = cell_dt<R>(g, hd, hs, hun, hvn, gm.inradius, nb, cfg);
+        dtc = cell_dt<R>(g, hd, hs, hun, hvn, gm.inradius, nb, cfg, qtab);
     }
-    block_partials(static_cast<double>(dtc), clamp, flag, a.part);
+    block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
 }
 
 // ------------------------------------------------------------------------ tiled step
@@ -364,14 +488,6 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
            7 * word * static_cast<size_t>(max_edges);
 }
 
-// Workgroups are handed to the eight XCDs in turn; give each XCD a contiguous run of tiles
-// so that a tile's halo was recently read into the same XCD's L2 by its neighbour tiles.
-__device__ __forceinline__ int xcd_tile(int b, int n_tiles)
-{
-    const int per = (n_tiles + 7) / 8;
-    return (b % 8) * per + b / 8;
-}
-
 // One explicit step, tiled.  Phase 1 stages the tile's cells and its halo in LDS as
 // (h, u, v, z), each velocity computed once.  Phase 2 evaluates every interface of the edge
 // list once (section 2.3's interface loop, restricted to the tile) and stores each side's
@@ -379,12 +495,17 @@ __device__ __forceinline__ int xcd_tile(int b, int n_tiles)
 // Phase 3 sums each cell's three contributions in local-edge order and applies the update of
 // eq. 4, the clamp, the friction and the next CFL bound, as the per-cell kernel does.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg)
+__global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
+                                                           Batch bt)
 {
     const StepArgs<R> &a = ta.s;
-    if (a.ctrl->done) return;
-    const int tile = xcd_tile(blockIdx.x, ta.n_tiles);
+    const int tile = xcd_tile(blockIdx.x, ta.n_tiles, bt.remap);
     if (tile >= ta.n_tiles) return;
+    const bool batched = bt.tile_start != nullptr;
+    const int scen = batched ? bt.tile_scen[tile] : 0;
+    const Ctrl *ctrl = ctrl_of(a.ctrl, scen);
+    const double *qtab = batched ? bt.q_table + scen * SWE_MAX_INFLOW : nullptr;
+    if (ctrl->done) return;   // uniform over the workgroup: its scenario has stopped
     extern __shared__ __align__(16) unsigned char smem[];
     const int ns = kBlock + ta.max_halo;
     R *s_h = reinterpret_cast<R *>(smem);
@@ -401,12 +522,13 @@ __global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepC
     R *e_l = e_b2 + ta.max_edges;
 
     const int64_t T = cfg.n_cells;
-    const int64_t s0 = static_cast<int64_t>(tile) * kBlock;
+    const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
+    const int64_t s1 = batched ? bt.tile_start[tile + 1] : s0 + kBlock;
     const int tid = threadIdx.x;
     const int64_t i = s0 + tid;
-    const bool mine = i < T;
+    const bool mine = i < s1 && i < T;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
-    const R dt = static_cast<R>(a.ctrl->dt);
+    const R dt = static_cast<R>(ctrl->dt);
 
     // phase 1: own cell and halo into LDS
     R h = R(0), hu = R(0), hv = R(0);
@@ -442,8 +564,8 @@ __global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepC
         const double2 p0 = a.xy[s_c2n[k * kBlock + ca]];
         const double2 p1 = a.xy[s_c2n[(k == 2 ? 0 : k + 1) * kBlock + ca]];
         const R dx = static_cast<R>(p1.x - p0.x), dy = static_cast<R>(p1.y - p0.y);
-        const R l = sqrt(dx * dx + dy * dy);
-        const R nx = dy / l, ny = -dx / l;
+        const R l = sqrt_(dx * dx + dy * dy);
+        const R nx = div_(dy, l), ny = div_(-dx, l);
         const R ha = s_h[ca], ua = s_u[ca], va = s_v[ca];
         R fh, fx, fy, pa, pb;
         const int q = e - eb;
@@ -458,7 +580,8 @@ __global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepC
         } else if (cb == SWE_WALL) {
             wall_flux<R>(g, hd, ha, ua, va, nx, ny, fh, fx, fy, pa);
         } else {
-            inflow_flux<R>(g, static_cast<R>(cfg.inflow_q[-2 - cb]), ha, nx, ny, fh, fx, fy);
+            const double qin = qtab ? qtab[-2 - cb] : cfg.inflow_q[-2 - cb];
+            inflow_flux<R>(g, static_cast<R>(qin), ha, nx, ny, fh, fx, fy);
             pa = R(0);
         }
         e_a0[q] = l * fh;
@@ -484,7 +607,8 @@ __global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepC
             const R c2 = side_b ? e_b2[q] : e_a2[q];
             l[k] = e_l[q];
             nb[k] = 0;
-            if (cfg.n_inflow > 0 && !side_b) nb[k] = static_cast<int16_t>(ta.edges[eb + q] >> 16);
+            if ((cfg.n_inflow > 0 || batched) && !side_b)
+                nb[k] = static_cast<int16_t>(ta.edges[eb + q] >> 16);
             if (k == 0) {
                 acc0 = c0; acc1 = c1; acc2 = c2;
             } else {
@@ -495,8 +619,8 @@ __global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepC
         const double e0x = p1.x - p0.x, e0y = p1.y - p0.y;
         const double e1x = p2.x - p1.x, e1y = p2.y - p1.y;
         const R area = static_cast<R>(0.5 * (e0x * e1y - e0y * e1x));
-        const R inradius = R(2) * area / (l[0] + l[1] + l[2]);
-        const R r = dt / area;
+        const R inradius = div_(R(2) * area, l[0] + l[1] + l[2]);
+        const R r = div_(dt, area);
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
@@ -507,10 +631,10 @@ __global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepC
         R hun, hvn;
         if (hs > hd) {
             const R nm = a.n[i];
-            const R mag = sqrt(hus * hus + hvs * hvs);
-            const R d = R(1) + dt * g * nm * nm * mag / (hs * hs * cbrt(hs));
-            hun = hus / d;
-            hvn = hvs / d;
+            const R mag = sqrt_(hus * hus + hvs * hvs);
+            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt(hs));
+            hun = div_(hus, d);
+            hvn = div_(hvs, d);
         } else {
             hun = R(0);
             hvn = R(0);
@@ -519,27 +643,31 @@ __global__ __launch_bounds__(kBlock) void tile_step_kernel(TileArgs<R> ta, StepC
         a.huo[i] = hun;
         a.hvo[i] = hvn;
         if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
-        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg);
+        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
     }
     block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
 }
 
 // CFL bounds of the initial state.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig cfg)
+__global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig cfg, Batch bt)
 {
     const int64_t T = cfg.n_cells;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const bool batched = bt.tile_start != nullptr;
+    const int64_t s0 = batched ? bt.tile_start[blockIdx.x] : static_cast<int64_t>(blockIdx.x) * kBlock;
+    const int64_t s1 = batched ? bt.tile_start[blockIdx.x + 1] : s0 + kBlock;
+    const double *qtab = batched ? bt.q_table + bt.tile_scen[blockIdx.x] * SWE_MAX_INFLOW : nullptr;
+    const int64_t i = s0 + threadIdx.x;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
     R dtc = static_cast<R>(kInf);
     int flag = 0;
-    if (i < T) {
+    if (i < s1 && i < T) {
         CellGeom<R> gm;
         cell_geometry<R>(a.xy, a.c2n[i], a.c2n[T + i], a.c2n[2 * T + i], gm);
         const int32_t nb[3] = {a.nbr[i], a.nbr[T + i], a.nbr[2 * T + i]};
         const R h = a.h[i], hu = a.hu[i], hv = a.hv[i];
         if (!isfinite(h) || !isfinite(hu) || !isfinite(hv)) flag = kStatusNonFinite;
-        dtc = cell_dt<R>(g, hd, h, hu, hv, gm.inradius, nb, cfg);
+        dtc = cell_dt<R>(g, hd, h, hu, hv, gm.inradius, nb, cfg, qtab);
     }
     block_partials(static_cast<double>(dtc), 0, flag, a.part);
 }
@@ -549,13 +677,17 @@ constexpr int kPassThreads = 1024;
 // Reduce the per-block partials into the control block: account for the step just taken
 // (mode 1) or start the state (mode 0), then set the next step's dt (CFL, replayed, or cut
 // at t_end).
-__global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl, Partials part,
+__global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, Partials part,
                                                                int64_t nb, double courant,
                                                                const double *dt_seq,
                                                                int64_t n_seq, int mode,
                                                                double t0, double t_end,
-                                                               int cur0)
+                                                               int cur0, Batch bt)
 {
+    // workgroup s reduces scenario s's tiles (a single mesh: all nb partials)
+    Ctrl *ctrl = const_cast<Ctrl *>(ctrl_of(ctrl_base, blockIdx.x));
+    const int64_t b_lo = bt.scen_tile_off ? bt.scen_tile_off[blockIdx.x] : 0;
+    const int64_t b_hi = bt.scen_tile_off ? bt.scen_tile_off[blockIdx.x + 1] : nb;
     __shared__ double s_dt[kPassThreads / 64];
     __shared__ long long s_cl[kPassThreads / 64];
     __shared__ int s_fl[kPassThreads / 64];
@@ -566,13 +698,13 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl, Parti
     // kUnroll independent loads per work-item in flight: the partials are few, so latency,
     // not bandwidth, bounds this loop
     constexpr int kUnroll = 16;
-    for (int64_t b0 = threadIdx.x; b0 < nb; b0 += kPassThreads * kUnroll) {
+    for (int64_t b0 = b_lo + threadIdx.x; b0 < b_hi; b0 += kPassThreads * kUnroll) {
         double v[kUnroll];
         int c[kUnroll], f[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t b = b0 + static_cast<int64_t>(u) * kPassThreads;
-            const bool in = b < nb;
+            const bool in = b < b_hi;
             v[u] = in ? part.dt[b] : kInf;
             c[u] = in ? part.clamps[b] : 0;
             f[u] = in ? part.flags[b] : 0;
@@ -707,7 +839,7 @@ StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
     a.huo = static_cast<R *>(s.hu[1 - cur]);
     a.hvo = static_cast<R *>(s.hv[1 - cur]);
     a.ctrl = static_cast<const Ctrl *>(s.ctrl);
-    a.part = partials_of(s.work, dm.n_cells);
+    a.part = partials_for(s.work, n_blocks(dm.n_cells));
     return a;
 }
 
@@ -731,18 +863,42 @@ TileArgs<R> make_tile_args(const swe_dev_mesh &dm, const swe_state &s, int cur,
 
 }  // namespace
 
+namespace {
+
+Batch batch_view(const BatchLaunch *b)
+{
+    Batch v;
+    v.tile_start = b ? b->tile_start : nullptr;
+    v.tile_scen = b ? b->tile_scen : nullptr;
+    v.scen_tile_off = b ? b->scen_tile_off : nullptr;
+    v.q_table = b ? b->q_table : nullptr;
+    v.n_scen = b ? b->n_scen : 1;
+    v.remap = 1;
+    v.n_tiles = 0;
+    v.pad = 0;
+    return v;
+}
+
+}  // namespace
+
 int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                double t0, double t_end, void *stream)
+                double t0, double t_end, void *stream, const BatchLaunch *batch)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t nb = n_blocks(cfg.n_cells);
-    if (dtype == SWE_F64)
-        init_kernel<double><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<double>(dm, s, s.cur), cfg);
-    else
-        init_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<float>(dm, s, s.cur), cfg);
-    dt_pass_kernel<<<1, kPassThreads, 0, st>>>(static_cast<Ctrl *>(s.ctrl),
-                                               partials_of(s.work, cfg.n_cells), nb, cfg.courant,
-                                               nullptr, 0, 0, t0, t_end, s.cur);
+    const int64_t nb = batch ? batch->n_tiles : n_blocks(cfg.n_cells);
+    const Batch bv = batch_view(batch);
+    const Partials part = partials_for(s.work, nb);
+    if (dtype == SWE_F64) {
+        StepArgs<double> a = make_args<double>(dm, s, s.cur);
+        a.part = part;
+        init_kernel<double><<<dim3(nb), dim3(kBlock), 0, st>>>(a, cfg, bv);
+    } else {
+        StepArgs<float> a = make_args<float>(dm, s, s.cur);
+        a.part = part;
+        init_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(a, cfg, bv);
+    }
+    dt_pass_kernel<<<dim3(bv.n_scen), kPassThreads, 0, st>>>(
+        static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, nullptr, 0, 0, t0, t_end, s.cur, bv);
     return static_cast<int>(hipGetLastError());
 }
 
@@ -763,27 +919,38 @@ int prepare_tile_kernels(size_t max_lds)
 }
 
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl)
+                int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
+                const BatchLaunch *batch, int remap)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t nb = n_blocks(cfg.n_cells);
+    const int64_t nb = batch ? batch->n_tiles : n_blocks(cfg.n_cells);
+    Batch bv = batch_view(batch);
+    bv.remap = remap;
+    bv.n_tiles = static_cast<int32_t>(nb);
+    const int64_t grid = remap ? 8 * ((nb + 7) / 8) : nb;
+    const Partials part = partials_for(s.work, nb);
     if (tl) {
         const size_t lds = tile_lds_bytes_for(dtype, *tl);
-        const int64_t grid = 8 * ((tl->n_tiles + 7) / 8);
-        if (dtype == SWE_F64)
-            tile_step_kernel<double><<<dim3(grid), dim3(kBlock), lds, st>>>(
-                make_tile_args<double>(dm, s, cur, *tl), cfg);
-        else
-            tile_step_kernel<float><<<dim3(grid), dim3(kBlock), lds, st>>>(
-                make_tile_args<float>(dm, s, cur, *tl), cfg);
+        if (dtype == SWE_F64) {
+            TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
+            ta.s.part = part;
+            tile_step_kernel<double><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+        } else {
+            TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
+            ta.s.part = part;
+            tile_step_kernel<float><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+        }
     } else if (dtype == SWE_F64) {
-        step_kernel<double><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<double>(dm, s, cur), cfg);
+        StepArgs<double> a = make_args<double>(dm, s, cur);
+        a.part = part;
+        step_kernel<double><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
     } else {
-        step_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(make_args<float>(dm, s, cur), cfg);
+        StepArgs<float> a = make_args<float>(dm, s, cur);
+        a.part = part;
+        step_kernel<float><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
     }
-    dt_pass_kernel<<<1, kPassThreads, 0, st>>>(static_cast<Ctrl *>(s.ctrl),
-                                               partials_of(s.work, cfg.n_cells), nb, cfg.courant,
-                                               dt_seq, n_seq, 1, 0.0, 0.0, 0);
+    dt_pass_kernel<<<dim3(bv.n_scen), kPassThreads, 0, st>>>(
+        static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, 1, 0.0, 0.0, 0, bv);
     return static_cast<int>(hipGetLastError());
 }
 

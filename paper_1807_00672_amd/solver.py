@@ -91,7 +91,8 @@ class Solver:
     VARIANTS = {"auto": A.SWE_AUTO, "cell": A.SWE_CELL, "tiled": A.SWE_TILED}
 
     def __init__(self, mesh: Mesh, z, n, h, hu, hv, dtype: str = "f64", g=9.81, courant=0.7,
-                 h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None, variant="auto"):
+                 h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None, variant="auto",
+                 xcd_remap=True):
         if mesh.device is None:
             raise ValueError("mesh has no device arrays")
         self.mesh = mesh
@@ -101,7 +102,7 @@ class Solver:
         self._q = np.ascontiguousarray(inflow_q if inflow_q is not None else [], np.float64)
         self.params = A.swe_params(g, courant, h_dry, self.dtype, self._q.size,
                                    self._q.ctypes.data_as(C.POINTER(C.c_double)),
-                                   self.VARIANTS[variant], 0)
+                                   self.VARIANTS[variant], 0 if xcd_remap else A.SWE_NO_XCD_REMAP)
         t = mesh.n_cells
 
         def field(a):
@@ -160,3 +161,107 @@ class Solver:
         self.stats()
         return tuple(self.mesh.to_input_order(t.double().cpu().numpy())
                      for t in self.device_state())
+
+
+class Batch:
+    """Several meshes (scenarios) concatenated by swe_batch_create, with device arrays."""
+
+    def __init__(self, meshes, device="cuda"):
+        self.meshes = list(meshes)
+        self.handle = A.swe_batch_create([m.handle for m in self.meshes])
+        self.info = A.swe_batch_info_get(self.handle)
+        i = self.info
+        n, t, v, nt = int(i.n_scenarios), int(i.n_cells), int(i.n_nodes), int(i.n_tiles)
+        self.n_scen, self.n_cells, self.n_nodes = n, t, v
+        ex = lambda w, k, dt: A.swe_batch_export(self.handle, w, k, dt)
+        self.cell_off = ex(A.SWE_BARR_CELL_OFF, n + 1, np.int64)
+        arrays = {
+            "nbr": ex(A.SWE_ARR_NBR, 3 * t, np.int32), "c2n": ex(A.SWE_ARR_C2N, 3 * t, np.int32),
+            "xy": ex(A.SWE_ARR_XY, 2 * v, np.float64),
+            "halo_off": ex(A.SWE_ARR_HALO_OFF, nt + 1, np.int32),
+            "halo": ex(A.SWE_ARR_HALO, max(1, int(i.n_halo)), np.int32),
+            "edge_off": ex(A.SWE_ARR_EDGE_OFF, nt + 1, np.int32),
+            "edges": ex(A.SWE_ARR_EDGES, int(i.n_tile_edges), np.uint32).view(np.int32),
+            "slot": ex(A.SWE_ARR_SLOT, 3 * t, np.uint16).view(np.int16),
+            "tile_start": ex(A.SWE_BARR_TILE_START, nt + 1, np.int32),
+            "tile_scen": ex(A.SWE_BARR_TILE_SCEN, nt, np.int32),
+            "scen_tile_off": ex(A.SWE_BARR_SCEN_TILE_OFF, n + 1, np.int32),
+        }
+        d = torch.device(device)
+        if d.type == "cuda" and d.index is None:
+            d = torch.device("cuda", torch.cuda.current_device())
+        self.device = d
+        self.d = {k: torch.from_numpy(a).to(d) for k, a in arrays.items()}
+        P = lambda k: _ptr(self.d[k])
+        mesh = A.swe_dev_mesh(t, v, P("nbr"), P("c2n"), P("xy"), P("halo_off"), P("halo"),
+                              P("edge_off"), P("edges"), P("slot"))
+        self.dev = A.swe_batch_dev(mesh, P("tile_start"), P("tile_scen"), P("scen_tile_off"))
+
+    def scenario_slice(self, s: int) -> slice:
+        return slice(int(self.cell_off[s]), int(self.cell_off[s + 1]))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and A is not None and A.lib is not None:
+            A.swe_batch_destroy(h)
+            self.handle = None
+
+
+class BatchSolver:
+    """All scenarios' states in concatenated buffers; one launch per step steps them all."""
+
+    def __init__(self, batch: Batch, cases, dtype="f64", g=9.81, courant=0.7, h_dry=1e-6,
+                 t0=0.0, t_end=0.0, stream=None, variant="auto", xcd_remap=True):
+        self.batch = batch
+        self.tdtype = torch.float64 if dtype == "f64" else torch.float32
+        dev = batch.device
+        q = np.zeros((batch.n_scen, A.SWE_MAX_INFLOW))
+        cat = {k: [] for k in ("z", "n", "h", "hu", "hv")}
+        for s, (m, c) in enumerate(zip(batch.meshes, cases)):
+            for k in cat:
+                cat[k].append(m.to_mesh_order(np.asarray(getattr(c, k), np.float64)))
+            if c.inflow_q is not None:
+                q[s, : len(c.inflow_q)] = c.inflow_q
+        f = {k: torch.from_numpy(np.concatenate(v)).to(device=dev, dtype=self.tdtype)
+             for k, v in cat.items()}
+        t = batch.n_cells
+        self.z, self.n = f["z"], f["n"]
+        self.h = [f["h"], torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.hu = [f["hu"], torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.hv = [f["hv"], torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.q = torch.from_numpy(q.ravel()).to(dev)
+        self.ctrl = torch.zeros(batch.n_scen * A.SWE_CTRL_BYTES // 8, dtype=torch.float64,
+                                device=dev)
+        self.work = torch.zeros(A.swe_batch_workspace_bytes(batch.handle), dtype=torch.uint8,
+                                device=dev)
+        self.params = A.swe_batch_params(g, courant, h_dry,
+                                         A.SWE_F64 if dtype == "f64" else A.SWE_F32,
+                                         Solver.VARIANTS[variant], _ptr(self.q),
+                                         0 if xcd_remap else A.SWE_NO_XCD_REMAP, 0)
+        self.state = A.swe_state(
+            (C.c_void_p * 2)(self.h[0].data_ptr(), self.h[1].data_ptr()),
+            (C.c_void_p * 2)(self.hu[0].data_ptr(), self.hu[1].data_ptr()),
+            (C.c_void_p * 2)(self.hv[0].data_ptr(), self.hv[1].data_ptr()),
+            _ptr(self.z), _ptr(self.n), _ptr(self.ctrl), _ptr(self.work), 0, 0)
+        A.swe_batch_state_init(batch.handle, batch.dev, self.params, self.state, t0, t_end,
+                               _stream_handle(stream))
+        self.last = None
+
+    def run(self, n_steps: int, sync=True, stream=None):
+        st = (A.swe_run_stats * self.batch.n_scen)() if sync else None
+        rc = A.swe_batch_run(self.batch.handle, self.batch.dev, self.params, self.state, n_steps,
+                             st, _stream_handle(stream))
+        if sync:
+            self.last = [x.as_dict() for x in st]
+            return rc, self.last
+        return None
+
+    def numpy_state(self, s: int):
+        """Scenario s's (h, hu, hv) in its input order (after a synchronising run)."""
+        if self.last is None:
+            self.run(0)
+        c = self.last[s]["cur"]
+        sl = self.batch.scenario_slice(s)
+        m = self.batch.meshes[s]
+        return tuple(m.to_input_order(b[c][sl].double().cpu().numpy())
+                     for b in (self.h, self.hu, self.hv))

@@ -201,3 +201,33 @@ def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton):
     assert info.n_tile_edges == len(m.edges) and info.max_halo == max(
         m.halo_off[1:] - m.halo_off[:-1])
     assert len(seen) == info.n_tile_edges
+
+
+def test_batch_concatenates_scenarios_without_straddling_tiles():
+    cases = [gen.ensemble_scenario(s) for s in range(5)]
+    meshes = [swe.Mesh(c.xy, c.tri, c.edge_tag, device=None) for c in cases]
+    b = swe.swe_batch_create([m.handle for m in meshes])
+    try:
+        info = swe.swe_batch_info_get(b)
+        n, t, nt = info.n_scenarios, info.n_cells, info.n_tiles
+        assert n == 5 and t == sum(m.n_cells for m in meshes)
+        assert nt == sum(m.info.n_tiles for m in meshes)
+        ex = lambda w, k, dt: swe.swe_batch_export(b, w, k, dt)
+        off = ex(swe._abi.SWE_BARR_CELL_OFF, n + 1, np.int64)
+        start = ex(swe._abi.SWE_BARR_TILE_START, nt + 1, np.int32)
+        scen = ex(swe._abi.SWE_BARR_TILE_SCEN, nt, np.int32)
+        toff = ex(swe._abi.SWE_BARR_SCEN_TILE_OFF, n + 1, np.int32)
+        nbr = ex(swe.SWE_ARR_NBR, 3 * t, np.int32).reshape(3, t)
+        for s, m in enumerate(meshes):
+            sl = slice(off[s], off[s + 1])
+            local = m.nbr.reshape(3, m.n_cells)
+            assert np.array_equal(np.where(local >= 0, local + off[s], local), nbr[:, sl])
+            tiles = np.arange(toff[s], toff[s + 1])
+            assert (scen[tiles] == s).all()
+            assert start[tiles[0]] == off[s] and start[tiles[-1] + 1] == off[s + 1]
+            assert (np.diff(start[toff[s]:toff[s + 1] + 1]) <= swe.SWE_TILE).all()
+        assert info.max_inflow_segments == 1
+        with pytest.raises(swe.SweError):
+            swe.swe_batch_create([])
+    finally:
+        swe.swe_batch_destroy(b)

@@ -129,6 +129,12 @@ def test_tiled_and_per_cell_kernels_agree_bitwise(gpu, dtype):
     b = run_gpu(case, dtype, steps=80, variant="cell")
     for x, y in zip(a[2:], b[2:]):
         assert np.array_equal(x, y)
+    import paper_1807_00672_amd as swe
+    m = swe.Mesh(case.xy, case.tri)
+    s = swe.Solver(m, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype, xcd_remap=False)
+    s.run(80)
+    for x, y in zip(s.numpy_state(), a[2:]):
+        assert np.array_equal(x, y)
     c = gen.ensemble_scenario(5)
     a = run_gpu(c, dtype, steps=50, variant="tiled")
     b = run_gpu(c, dtype, steps=50, variant="cell")
@@ -236,3 +242,33 @@ def test_dry_and_nonfinite_states_are_reported(gpu):
     bad = gen.Case("inf", case.xy, case.tri, z, z, h, z, z, 5)
     rc, st, *_ = run_gpu(bad, "f32")
     assert rc == swe.SWE_ENONFINITE
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_three_mound_wet_dry_parity(gpu, dtype):
+    case = gen.three_mounds()
+    rc_o, *ora, dts, st_o = run_oracle(case)
+    rc_g, st_g, *g = run_gpu(case, dtype)
+    assert rc_o == 0 and rc_g == 0 and st_g["steps"] == st_o["steps"] == case.steps
+    hmax = np.abs(ora[0]).max()
+    band = 0.0 if dtype == "f64" else TOL_F32 * hmax
+    mism, exempt = mask_mismatch(case, g[0], ora[0], band=band)
+    e = errors(case, g, ora)
+    print(f"three mounds {dtype}: errors {e}, mask mismatches {mism} (exempt {exempt}), "
+          f"clamps {st_g['clamps']} vs {st_o['clamps']}")
+    assert mism == 0
+    if dtype == "f64":
+        assert max(e) <= TOL_F64 and st_g["clamps"] == st_o["clamps"]
+    else:
+        assert e[0] <= TOL_F32
+        e_q = max(np.abs(g[1] - ora[1]).max(), np.abs(g[2] - ora[2]).max())
+        assert e_q <= fp32_momentum_tol(case, ora[0])
+
+
+def test_ritter_dry_bed_strip_parity(gpu):
+    case = gen.strip(400, h_right=0.0)
+    rc_o, *ora, dts, st_o = run_oracle(case, steps=100000, t_end=0.5)
+    rc_g, st_g, *g = run_gpu(case, "f64", steps=5000, t_end=0.5)
+    assert rc_o == 0 and rc_g == 0 and st_g["steps"] == st_o["steps"] and st_g["t"] == 0.5
+    assert max(errors(case, g, ora)) <= TOL_F64
+    assert np.array_equal(g[0] > case.h_dry, ora[0] > case.h_dry)

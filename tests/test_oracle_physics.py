@@ -252,3 +252,23 @@ def test_all_dry_and_nonfinite_states_are_reported():
     h[17] = np.nan
     rc, *_ = oracle.run(m, z, z, h, z, z, 5)
     assert rc == oracle.ENONFINITE
+
+
+def test_three_mound_wet_dry_run_keeps_its_invariants():
+    """Dam break over a dry floor with mounds: mass conserved, depths non-negative, dry cells
+    without momentum, the front advanced past the low mounds, the tall mound's top still dry."""
+    c = gen.three_mounds()
+    m = oracle.Mesh(c.xy, c.tri)
+    cn, _, area, _ = m.arrays()
+    rc, h, hu, hv, dts, st = oracle.run_case(c, mesh=m)
+    assert rc == 0 and st["steps"] == c.steps
+    m0 = mass(c.h, area)
+    assert abs(mass(h, area) - m0) <= 1e-12 * m0 + st["clamped_mass"]
+    assert h.min() >= 0.0
+    dry = h <= c.h_dry
+    assert (hu[dry] == 0).all() and (hv[dry] == 0).all()
+    xc = c.xy[cn].mean(axis=1)
+    wet0 = (c.h > c.h_dry)
+    assert xc[h > 1e-3, 0].max() > 30.0 > xc[wet0, 0].max()
+    top = np.hypot(xc[:, 0] - 40.0, xc[:, 1] - 12.0) < 1.0
+    assert (h[top] <= c.h_dry).all()
