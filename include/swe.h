@@ -292,6 +292,45 @@ int32_t swe_batch_run(const swe_batch *batch, const swe_batch_dev *dev,
                       const swe_batch_params *p, swe_state *s, int64_t n_steps,
                       swe_run_stats *out, void *stream);
 
+/* ------------------------------------------------------------------ adjoint */
+
+/* Gauge misfit J = sum over observations m = 1 .. n_steps/every and gauges g of
+ * (h_g after step m*every - obs[(m-1)*n_gauges + g])^2. */
+typedef struct swe_loss {
+    const int32_t *gauges;   /* device, n_gauges distinct mesh-order cells */
+    int32_t n_gauges;
+    int32_t every;           /* steps between observations, >= 1 */
+    const double *obs;       /* device, (n_steps/every) * n_gauges observed depths */
+} swe_loss;
+
+/* Gradients of J, device arrays of n_cells doubles each, mesh order (written). */
+typedef struct swe_grads {
+    double *dn;              /* dJ/d(Manning n) */
+    double *dz;              /* dJ/d(bed z) */
+    double *dh, *dhu, *dhv;  /* dJ/d(initial state) */
+} swe_grads;
+
+/* Workspace bytes of swe_adjoint: checkpoints, a recompute segment and the adjoint state.
+ * Errors: SWE_EINVAL. */
+int32_t swe_adjoint_workspace_bytes(const swe_mesh *mesh, int64_t n_steps, int32_t ckpt_every,
+                                    int64_t *bytes);
+
+/*
+ * Loss and gradient of a replayed run: n_steps FP64 steps from the state in buffer s->cur of
+ * s (with s->z and s->n) using dt_seq (device, n_steps doubles, not differentiated), the
+ * misfit J of `loss`, and the hand-written reverse sweep of the step (friction and clamp,
+ * then the transposed interface fluxes with hydrostatic reconstruction, every branch frozen
+ * to the forward run).  Forward states are checkpointed every ckpt_every steps and recomputed
+ * segment by segment in the reverse pass.  The caller's state is not modified.  ws: device,
+ * swe_adjoint_workspace_bytes bytes, 256-byte aligned.  *loss_out (host, may be NULL)
+ * receives J; then the stream is synchronised.  Errors: SWE_EINVAL, SWE_EUNSUPPORTED (FP32),
+ * SWE_EDEVICE.
+ */
+int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                    const swe_state *s, int64_t n_steps, const double *dt_seq,
+                    const swe_loss *loss, int32_t ckpt_every, swe_grads *out, double *loss_out,
+                    void *ws, int64_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ test hook */
 
 /*

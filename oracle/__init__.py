@@ -84,6 +84,13 @@ def _bind(L):
     L.om_interface_batch.argtypes = [C.c_long, C.c_double, C.c_double] + [_dp] * 13
     L.om_wall_batch.argtypes = [C.c_long, C.c_double, C.c_double] + [_dp] * 7
     L.om_wave_speeds_batch.argtypes = [C.c_long, C.c_double] + [_dp] * 6
+    L.om_run_tl.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                            C.POINTER(_Params), C.c_long, _dp, _ip, C.c_int, C.c_int, _dp, _dp,
+                            _dp]
+    L.om_run_tl.restype = C.c_int
+    L.om_run_loss.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.POINTER(_Params), C.c_long,
+                              _dp, _ip, C.c_int, C.c_int, _dp, _dp]
+    L.om_run_loss.restype = C.c_int
     L.om_set_threads.argtypes = [C.c_int]
     L.om_get_threads.restype = C.c_int
     return L
@@ -216,3 +223,64 @@ def wave_speeds(hl, ql, hr, qr, g=9.81):
     sr = np.empty(nn)
     lib().om_wave_speeds_batch(nn, g, *[_ptr(v) for v in a], _ptr(sl), _ptr(sr))
     return sl, sr
+
+
+def run_tl(mesh: Mesh, z, n, h, hu, hv, dt_seq, gauges, every, obs, dz=None, dn=None, dh=None,
+           dhu=None, dhv=None, g=9.81, h_dry=1e-6, inflow_q=None):
+    """Tangent-linear run (dt replayed): returns (J, dJ) for the gauge misfit along the
+    direction (dz, dn, dh, dhu, dhv) (None = zero)."""
+    z, n = _d(z), _d(n)
+    h, hu, hv = _d(h).copy(), _d(hu).copy(), _d(hv).copy()
+    dirs = [None if d is None else _d(d).copy() for d in (dz, dn, dh, dhu, dhv)]
+    seq = _d(dt_seq)
+    gg = np.ascontiguousarray(gauges, dtype=np.int32)
+    ob = _d(obs)
+    p, _keep = _params(g, 0.7, h_dry, inflow_q)
+    J = C.c_double()
+    dJ = C.c_double()
+    rc = lib().om_run_tl(mesh._h, _ptr(z), _ptr(dirs[0]), _ptr(n), _ptr(dirs[1]), _ptr(h),
+                         _ptr(dirs[2]), _ptr(hu), _ptr(dirs[3]), _ptr(hv), _ptr(dirs[4]),
+                         C.byref(p), seq.size, _ptr(seq), gg.ctypes.data_as(_ip), gg.size,
+                         int(every), _ptr(ob), C.byref(J), C.byref(dJ))
+    if rc != OK:
+        raise RuntimeError(f"oracle tangent run failed: {rc}")
+    return J.value, dJ.value
+
+
+def run_loss(mesh: Mesh, z, n, h, hu, hv, dt_seq, gauges, every, obs, g=9.81, h_dry=1e-6,
+             inflow_q=None) -> float:
+    """The gauge misfit of a plain run with the replayed dt sequence."""
+    z, n = _d(z), _d(n)
+    h, hu, hv = _d(h).copy(), _d(hu).copy(), _d(hv).copy()
+    seq = _d(dt_seq)
+    gg = np.ascontiguousarray(gauges, dtype=np.int32)
+    ob = _d(obs)
+    p, _keep = _params(g, 0.7, h_dry, inflow_q)
+    J = C.c_double()
+    rc = lib().om_run_loss(mesh._h, _ptr(z), _ptr(n), _ptr(h), _ptr(hu), _ptr(hv), C.byref(p),
+                           seq.size, _ptr(seq), gg.ctypes.data_as(_ip), gg.size, int(every),
+                           _ptr(ob), C.byref(J))
+    if rc != OK:
+        raise RuntimeError(f"oracle loss run failed: {rc}")
+    return J.value
+
+
+def observations(case, mesh: Mesh | None = None, steps=None):
+    """Synthetic observations of the calibration setup: a run with the hidden roughness and
+    the CFL dt, recording h at the gauges every `obs_every` steps.  Returns (dt_seq, obs)."""
+    mesh = mesh or Mesh(case.xy, case.tri, case.edge_tag)
+    steps = case.steps if steps is None else steps
+    every = case.extra["obs_every"]
+    gauges = case.extra["gauges"]
+    h, hu, hv = case.h.copy(), case.hu.copy(), case.hv.copy()
+    dts, obs = [], []
+    t = 0.0
+    for s in range(steps):
+        rc, h, hu, hv, d, st = run(mesh, case.z, case.extra["n_hidden"], h, hu, hv, 1, t0=t)
+        if rc != OK:
+            raise RuntimeError(f"observation run failed: {rc}")
+        t = st["t"]
+        dts.append(d[0])
+        if (s + 1) % every == 0:
+            obs.append(h[gauges].copy())
+    return np.array(dts), np.array(obs)

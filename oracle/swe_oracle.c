@@ -555,3 +555,259 @@ void om_wave_speeds_batch(long n, double g, const double *hl, const double *ql,
 {
     for (long i = 0; i < n; ++i) om_wave_speeds(g, hl[i], ql[i], hr[i], qr[i], sl + i, sr + i);
 }
+
+/* ----------------------------------------------------------------- tangent-linear model
+ *
+ * Forward-mode derivative of om_run with the dt sequence replayed (dt is not differentiated),
+ * for the gauge misfit J = sum over observation steps m*every (m >= 1) and gauges g of
+ * (h_g - obs[m-1][g])^2.  Every quantity carries (value, derivative along one direction);
+ * every branch (max, min, dry tests, wave-speed cases, the sign of S*) is taken on values, so
+ * the derivative is that of the branch the plain run takes.  Used to pin the GPU adjoint.
+ */
+typedef struct { double v, d; } om_dual;
+
+static inline om_dual dv(double v, double d) { om_dual r = {v, d}; return r; }
+static inline om_dual dc(double v) { return dv(v, 0.0); }
+static inline om_dual dadd(om_dual a, om_dual b) { return dv(a.v + b.v, a.d + b.d); }
+static inline om_dual dsub(om_dual a, om_dual b) { return dv(a.v - b.v, a.d - b.d); }
+static inline om_dual dmul(om_dual a, om_dual b) { return dv(a.v * b.v, a.d * b.v + a.v * b.d); }
+static inline om_dual ddiv(om_dual a, om_dual b)
+{
+    const double q = a.v / b.v;
+    return dv(q, (a.d - q * b.d) / b.v);
+}
+static inline om_dual dneg(om_dual a) { return dv(-a.v, -a.d); }
+static inline om_dual dscale(double s, om_dual a) { return dv(s * a.v, s * a.d); }
+static inline om_dual dsqrt(om_dual a)
+{
+    const double r = sqrt(a.v);
+    return dv(r, r > 0.0 ? a.d / (2.0 * r) : 0.0);
+}
+static inline om_dual dcbrt(om_dual a)
+{
+    const double r = cbrt(a.v);
+    return dv(r, r != 0.0 ? a.d / (3.0 * r * r) : 0.0);
+}
+static inline om_dual dmax(om_dual a, om_dual b) { return a.v >= b.v ? a : b; }
+static inline om_dual dmin(om_dual a, om_dual b) { return a.v <= b.v ? a : b; }
+
+static void om_hllc_normal_tl(double g, om_dual hl, om_dual ql, om_dual wl, om_dual hr,
+                              om_dual qr, om_dual wr, om_dual *fh_o, om_dual *fq_o,
+                              om_dual *fw_o)
+{
+    if (hl.v == 0.0 && hr.v == 0.0) { *fh_o = dc(0.0); *fq_o = dc(0.0); *fw_o = dc(0.0); return; }
+    const om_dual cl = dsqrt(dscale(g, hl)), cr = dsqrt(dscale(g, hr));
+    om_dual sl, sr;
+    if (hl.v == 0.0) {
+        sl = dsub(qr, dscale(2.0, cr));
+        sr = dadd(qr, cr);
+    } else if (hr.v == 0.0) {
+        sl = dsub(ql, cl);
+        sr = dadd(ql, dscale(2.0, cl));
+    } else {
+        const om_dual us = dadd(dscale(0.5, dadd(ql, qr)), dsub(cl, cr));
+        const om_dual cs = dadd(dscale(0.5, dadd(cl, cr)), dscale(0.25, dsub(ql, qr)));
+        sl = dmin(dsub(ql, cl), dsub(us, cs));
+        sr = dmax(dadd(qr, cr), dadd(us, cs));
+    }
+    const om_dual fhl = dmul(hl, ql);
+    const om_dual fql = dadd(dmul(dmul(hl, ql), ql), dmul(dscale(0.5 * g, hl), hl));
+    const om_dual fhr = dmul(hr, qr);
+    const om_dual fqr = dadd(dmul(dmul(hr, qr), qr), dmul(dscale(0.5 * g, hr), hr));
+    om_dual fh, fq, fw;
+    if (sl.v >= 0.0) {
+        fh = fhl; fq = fql; fw = dmul(fh, wl);
+    } else if (sr.v <= 0.0) {
+        fh = fhr; fq = fqr; fw = dmul(fh, wr);
+    } else {
+        const om_dual den = dsub(sr, sl);
+        const om_dual slsr = dmul(sl, sr);
+        fh = ddiv(dadd(dsub(dmul(sr, fhl), dmul(sl, fhr)), dmul(slsr, dsub(hr, hl))), den);
+        fq = ddiv(dadd(dsub(dmul(sr, fql), dmul(sl, fqr)),
+                       dmul(slsr, dsub(dmul(hr, qr), dmul(hl, ql)))), den);
+        const double sstar = (sl.v * hr.v * (qr.v - sr.v) - sr.v * hl.v * (ql.v - sl.v)) /
+                             (hr.v * (qr.v - sr.v) - hl.v * (ql.v - sl.v));
+        const om_dual wup = sstar > 0.0 ? wl : (sstar < 0.0 ? wr : dscale(0.5, dadd(wl, wr)));
+        fw = dmul(fh, wup);
+    }
+    *fh_o = fh; *fq_o = fq; *fw_o = fw;
+}
+
+static inline om_dual om_vel_tl(om_dual h, om_dual hq, double h_dry)
+{
+    return h.v > h_dry ? ddiv(hq, h) : dc(0.0);
+}
+
+static void om_interface_tl(double g, double hd, om_dual hl, om_dual hul, om_dual hvl,
+                            om_dual zl, om_dual hr, om_dual hur, om_dual hvr, om_dual zr,
+                            double nx, double ny, om_dual *f, om_dual *pl, om_dual *pr)
+{
+    /* max of the beds; at a tie the derivative is split between the two sides */
+    const om_dual zs = zl.v > zr.v ? zl : (zr.v > zl.v ? zr : dv(zl.v, 0.5 * (zl.d + zr.d)));
+    om_dual hsl = dmax(dc(0.0), dsub(hl, dsub(zs, zl)));
+    om_dual hsr = dmax(dc(0.0), dsub(hr, dsub(zs, zr)));
+    if (hsl.v <= hd) hsl = dc(0.0);
+    if (hsr.v <= hd) hsr = dc(0.0);
+    const om_dual ul = om_vel_tl(hl, hul, hd), vl = om_vel_tl(hl, hvl, hd);
+    const om_dual ur = om_vel_tl(hr, hur, hd), vr = om_vel_tl(hr, hvr, hd);
+    const om_dual ql = dadd(dscale(nx, ul), dscale(ny, vl)), wl = dsub(dscale(nx, vl), dscale(ny, ul));
+    const om_dual qr = dadd(dscale(nx, ur), dscale(ny, vr)), wr = dsub(dscale(nx, vr), dscale(ny, ur));
+    om_dual fh, fq, fw;
+    om_hllc_normal_tl(g, hsl, ql, wl, hsr, qr, wr, &fh, &fq, &fw);
+    f[0] = fh;
+    f[1] = dsub(dscale(nx, fq), dscale(ny, fw));
+    f[2] = dadd(dscale(ny, fq), dscale(nx, fw));
+    *pl = dscale(0.5 * g, dsub(dmul(hl, hl), dmul(hsl, hsl)));
+    *pr = dscale(0.5 * g, dsub(dmul(hr, hr), dmul(hsr, hsr)));
+}
+
+static void om_wall_tl(double g, double hd, om_dual h, om_dual hu, om_dual hv, double nx,
+                       double ny, om_dual *f, om_dual *p)
+{
+    const om_dual u = om_vel_tl(h, hu, hd), v = om_vel_tl(h, hv, hd);
+    const om_dual q = dadd(dscale(nx, u), dscale(ny, v)), w = dsub(dscale(nx, v), dscale(ny, u));
+    const om_dual hs = h.v > hd ? h : dc(0.0);
+    om_dual fh, fq, fw;
+    om_hllc_normal_tl(g, hs, q, w, hs, dneg(q), w, &fh, &fq, &fw);
+    f[0] = fh;
+    f[1] = dsub(dscale(nx, fq), dscale(ny, fw));
+    f[2] = dadd(dscale(ny, fq), dscale(nx, fw));
+    *p = dscale(0.5 * g, dsub(dmul(h, h), dmul(hs, hs)));
+}
+
+static void om_inflow_tl(double g, double q_in, om_dual h, double nx, double ny, om_dual *f)
+{
+    const om_dual hc = dc(cbrt(q_in * q_in / g));
+    const om_dual hb = dmax(h, hc);
+    const om_dual mom = dadd(ddiv(dc(q_in * q_in), hb), dmul(dscale(0.5 * g, hb), hb));
+    f[0] = dc(-q_in);
+    f[1] = dscale(nx, mom);
+    f[2] = dscale(ny, mom);
+}
+
+/* One step of the tangent-linear model (the same operations as om_step on duals). */
+static void om_step_tl(const om_mesh *m, const om_dual *z, const om_dual *n, om_dual *h,
+                       om_dual *hu, om_dual *hv, const om_params *p, double dt, om_dual *f,
+                       om_dual *pl, om_dual *pr)
+{
+    const double g = p->g, hd = p->h_dry;
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < m->ne; ++e) {
+        const int l = m->edge_l[e], r = m->edge_r[e];
+        if (r >= 0) {
+            om_interface_tl(g, hd, h[l], hu[l], hv[l], z[l], h[r], hu[r], hv[r], z[r],
+                            m->edge_nx[e], m->edge_ny[e], f + 3 * e, &pl[e], &pr[e]);
+        } else if (r == OM_WALL) {
+            om_wall_tl(g, hd, h[l], hu[l], hv[l], m->edge_nx[e], m->edge_ny[e], f + 3 * e, &pl[e]);
+            pr[e] = dc(0.0);
+        } else {
+            om_inflow_tl(g, p->inflow_q[-1 - r - 1], h[l], m->edge_nx[e], m->edge_ny[e], f + 3 * e);
+            pl[e] = dc(0.0);
+            pr[e] = dc(0.0);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < m->nt; ++c) {
+        om_dual acc[3];
+        for (int k = 0; k < 3; ++k) {
+            const int e = m->cell_edge[3 * c + k];
+            const double s = (m->edge_l[e] == c) ? 1.0 : -1.0;
+            const om_dual pk = (m->edge_l[e] == c) ? pl[e] : pr[e];
+            const double l = m->edge_len[e];
+            const double nx = s * m->edge_nx[e], ny = s * m->edge_ny[e];
+            const om_dual c0 = dscale(l, dscale(s, f[3 * e]));
+            const om_dual c1 = dscale(l, dadd(dscale(s, f[3 * e + 1]), dscale(nx, pk)));
+            const om_dual c2 = dscale(l, dadd(dscale(s, f[3 * e + 2]), dscale(ny, pk)));
+            if (k == 0) { acc[0] = c0; acc[1] = c1; acc[2] = c2; }
+            else { acc[0] = dadd(acc[0], c0); acc[1] = dadd(acc[1], c1); acc[2] = dadd(acc[2], c2); }
+        }
+        const double r = dt / m->area[c];
+        om_dual hs = dsub(h[c], dscale(r, acc[0]));
+        const om_dual hus = dsub(hu[c], dscale(r, acc[1]));
+        const om_dual hvs = dsub(hv[c], dscale(r, acc[2]));
+        if (hs.v < 0.0) hs = dc(0.0);
+        if (hs.v > hd) {
+            const om_dual mag = dsqrt(dadd(dmul(hus, hus), dmul(hvs, hvs)));
+            const om_dual kk = dmul(dmul(dc(dt * g), n[c]), n[c]);
+            const om_dual d = dadd(dc(1.0), ddiv(dmul(kk, mag), dmul(dmul(hs, hs), dcbrt(hs))));
+            hu[c] = ddiv(hus, d);
+            hv[c] = ddiv(hvs, d);
+        } else {
+            hu[c] = dc(0.0);
+            hv[c] = dc(0.0);
+        }
+        h[c] = hs;
+    }
+}
+
+/*
+ * Run nsteps tangent-linear steps from (U, dU) with the bed, roughness and their directions;
+ * J and its directional derivative dJ are returned for gauges (mesh cells of the oracle, i.e.
+ * input order) observed every `every` steps with obs[(m-1)*ng + g].  State arrays are
+ * overwritten with the final values and derivatives.
+ */
+int om_run_tl(const om_mesh *m, const double *z, const double *zd, const double *n,
+              const double *nd, double *h, double *hdot, double *hu, double *hudot, double *hv,
+              double *hvdot, const om_params *p, long nsteps, const double *dt_seq,
+              const int *gauges, int ng, int every, const double *obs, double *J, double *dJ)
+{
+    if (!dt_seq || every < 1) return OM_EINVAL;
+    const long T = m->nt;
+    om_dual *Z = (om_dual *)malloc(sizeof(om_dual) * T), *N = (om_dual *)malloc(sizeof(om_dual) * T);
+    om_dual *H = (om_dual *)malloc(sizeof(om_dual) * T), *HU = (om_dual *)malloc(sizeof(om_dual) * T);
+    om_dual *HV = (om_dual *)malloc(sizeof(om_dual) * T);
+    om_dual *f = (om_dual *)malloc(sizeof(om_dual) * 3 * m->ne);
+    om_dual *pl = (om_dual *)malloc(sizeof(om_dual) * m->ne), *pr = (om_dual *)malloc(sizeof(om_dual) * m->ne);
+    for (long c = 0; c < T; ++c) {
+        Z[c] = dv(z[c], zd ? zd[c] : 0.0);
+        N[c] = dv(n[c], nd ? nd[c] : 0.0);
+        H[c] = dv(h[c], hdot ? hdot[c] : 0.0);
+        HU[c] = dv(hu[c], hudot ? hudot[c] : 0.0);
+        HV[c] = dv(hv[c], hvdot ? hvdot[c] : 0.0);
+    }
+    double jv = 0.0, jd = 0.0;
+    for (long s = 0; s < nsteps; ++s) {
+        om_step_tl(m, Z, N, H, HU, HV, p, dt_seq[s], f, pl, pr);
+        if ((s + 1) % every == 0) {
+            const double *o = obs + ((s + 1) / every - 1) * (long)ng;
+            for (int q = 0; q < ng; ++q) {
+                const om_dual r = dsub(H[gauges[q]], dc(o[q]));
+                jv += r.v * r.v;
+                jd += 2.0 * r.v * r.d;
+            }
+        }
+    }
+    for (long c = 0; c < T; ++c) {
+        h[c] = H[c].v; hu[c] = HU[c].v; hv[c] = HV[c].v;
+        if (hdot) hdot[c] = H[c].d;
+        if (hudot) hudot[c] = HU[c].d;
+        if (hvdot) hvdot[c] = HV[c].d;
+    }
+    *J = jv;
+    *dJ = jd;
+    free(Z); free(N); free(H); free(HU); free(HV); free(f); free(pl); free(pr);
+    return OM_OK;
+}
+
+/* The misfit alone, from a plain run with the replayed dt sequence (for finite differences). */
+int om_run_loss(const om_mesh *m, const double *z, const double *n, double *h, double *hu,
+                double *hv, const om_params *p, long nsteps, const double *dt_seq,
+                const int *gauges, int ng, int every, const double *obs, double *J)
+{
+    double jv = 0.0;
+    om_stats st;
+    memset(&st, 0, sizeof(st));
+    for (long s = 0; s < nsteps; ++s) {
+        int rc = om_run(m, z, n, h, hu, hv, p, 1, 0.0, dt_seq + s, NULL, &st);
+        if (rc != OM_OK) return rc;
+        if ((s + 1) % every == 0) {
+            const double *o = obs + ((s + 1) / every - 1) * (long)ng;
+            for (int q = 0; q < ng; ++q) {
+                const double r = h[gauges[q]] - o[q];
+                jv += r * r;
+            }
+        }
+    }
+    *J = jv;
+    return OM_OK;
+}

@@ -111,12 +111,22 @@ class swe_batch_params(C.Structure):
                 ("flags", C.c_int32), ("reserved", C.c_int32)]
 
 
+class swe_loss(C.Structure):
+    _fields_ = [("gauges", C.c_void_p), ("n_gauges", C.c_int32), ("every", C.c_int32),
+                ("obs", C.c_void_p)]
+
+
+class swe_grads(C.Structure):
+    _fields_ = [("dn", C.c_void_p), ("dz", C.c_void_p), ("dh", C.c_void_p), ("dhu", C.c_void_p),
+                ("dhv", C.c_void_p)]
+
+
 EXPORTS = [
     "swe_mesh_create", "swe_mesh_info_get", "swe_mesh_export", "swe_mesh_destroy",
     "swe_workspace_bytes", "swe_state_init", "swe_step", "swe_run", "swe_read_stats",
     "swe_last_error", "swe_flux_eval", "swe_batch_create", "swe_batch_info_get",
     "swe_batch_export", "swe_batch_destroy", "swe_batch_workspace_bytes", "swe_batch_state_init",
-    "swe_batch_run",
+    "swe_batch_run", "swe_adjoint_workspace_bytes", "swe_adjoint",
 ]
 
 
@@ -152,6 +162,10 @@ def _load():
                                        C.POINTER(swe_state), dbl, dbl, vp]
     L.swe_batch_run.argtypes = [vp, C.POINTER(swe_batch_dev), C.POINTER(swe_batch_params),
                                 C.POINTER(swe_state), i64, vp, vp]
+    L.swe_adjoint_workspace_bytes.argtypes = [vp, i64, i32, C.POINTER(i64)]
+    L.swe_adjoint.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
+                              C.POINTER(swe_state), i64, vp, C.POINTER(swe_loss), i32,
+                              C.POINTER(swe_grads), C.POINTER(dbl), vp, i64, vp]
     for name in EXPORTS:
         if name not in ("swe_mesh_destroy", "swe_last_error", "swe_batch_destroy"):
             getattr(L, name).restype = i32
@@ -281,3 +295,20 @@ def swe_batch_run(batch, dev, params, state, n_steps: int, stats=None, stream=No
     if rc in (SWE_EINVAL, SWE_EDEVICE, SWE_EMESH, SWE_EUNSUPPORTED):
         _check(rc, "swe_batch_run")
     return rc
+
+
+def swe_adjoint_workspace_bytes(mesh, n_steps: int, ckpt_every: int) -> int:
+    b = C.c_int64()
+    _check(lib.swe_adjoint_workspace_bytes(mesh, n_steps, ckpt_every, C.byref(b)),
+           "swe_adjoint_workspace_bytes")
+    return int(b.value)
+
+
+def swe_adjoint(mesh, dm, params, state, n_steps, dt_seq, loss, ckpt_every, grads, ws,
+                ws_bytes, stream=None) -> float:
+    """Loss and gradients of a replayed run (see include/swe.h); returns the loss."""
+    j = C.c_double()
+    _check(lib.swe_adjoint(mesh, C.byref(dm), C.byref(params), C.byref(state), n_steps, dt_seq,
+                           C.byref(loss), ckpt_every, C.byref(grads), C.byref(j), ws, ws_bytes,
+                           stream), "swe_adjoint")
+    return j.value

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libswe.so")
 
-SOURCES = ["swe_mesh.cpp", "swe_api.cpp", "swe_batch.cpp", "swe_kernels.hip"]
+SOURCES = ["swe_mesh.cpp", "swe_api.cpp", "swe_batch.cpp", "swe_kernels.hip", "swe_adjoint.hip"]
 HEADERS = ["swe_internal.h"]
 
 # Contraction off: every product and sum rounds on its own, in the order the sources write

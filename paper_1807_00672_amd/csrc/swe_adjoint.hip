@@ -1,0 +1,556 @@
+// Hand-written reverse (adjoint) sweep of the FP64 step, for the gradient of a gauge misfit
+// with respect to the Manning roughness, the bed and the initial state.
+//
+// The forward map of one step is U^{n+1} = friction(clamp(U^n - dt/A sum_k c_k(U^n, z))) with
+// the interface contributions c_k of eq. 3 (HLLC with hydrostatic reconstruction) and the
+// semi-implicit friction of the S_f term of eq. 1.  Its transpose is applied in two per-cell
+// kernels: the friction/clamp adjoint mu = (dU^{n+1}/dU*)^T lambda^{n+1} (with the roughness
+// gradient), then the flux adjoint lambda^n = mu + sum over the cell's edges of the transposed
+// edge Jacobians applied to both sides' cotangents -dt/A mu.  Adjacency is symmetric, so each
+// cell gathers its own share: no atomics, deterministic.  Every branch of the forward step
+// (max of the beds, positive parts, dry tests, wave-speed cases, min/max of the speed
+// estimates, supersonic or HLL, the sign of the contact speed, the clamp) is re-evaluated on
+// the forward values and its derivative taken as is.  dt is replayed, not differentiated.
+//
+// Forward states are checkpointed every K steps; the reverse pass recomputes each segment
+// (storing U^n and the pre-friction U*) and then runs the adjoint through it backwards.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "swe_internal.h"
+
+namespace swe {
+namespace {
+
+struct Vjp3 {
+    double h, hu, hv;
+};
+
+__device__ __forceinline__ double vel(double h, double hq, double hd) { return h > hd ? hq / h : 0.0; }
+
+// Cotangents of (hl, ql, wl, hr, qr, wr) from those of the edge-frame HLLC flux (fh, fq, fw).
+__device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, double hr, double qr,
+                                double wr, double fhb, double fqb, double fwb, double &hlb,
+                                double &qlb, double &wlb, double &hrb, double &qrb, double &wrb)
+{
+    hlb = qlb = wlb = hrb = qrb = wrb = 0.0;
+    if (hl == 0.0 && hr == 0.0) return;
+    const double cl = sqrt(g * hl), cr = sqrt(g * hr);
+    double sl, sr, us = 0.0, cs = 0.0;
+    bool sl_a = true, sr_a = true;
+    if (hl == 0.0) {
+        sl = qr - 2.0 * cr;
+        sr = qr + cr;
+    } else if (hr == 0.0) {
+        sl = ql - cl;
+        sr = ql + 2.0 * cl;
+    } else {
+        us = (ql + qr) / 2.0 + (cl - cr);
+        cs = (cl + cr) / 2.0 + (ql - qr) / 4.0;
+        sl_a = (ql - cl) <= (us - cs);
+        sr_a = (qr + cr) >= (us + cs);
+        sl = sl_a ? ql - cl : us - cs;
+        sr = sr_a ? qr + cr : us + cs;
+    }
+    const double fhl = hl * ql, fql = hl * ql * ql + 0.5 * g * hl * hl;
+    const double fhr = hr * qr, fqr = hr * qr * qr + 0.5 * g * hr * hr;
+    double fhlb = 0.0, fqlb = 0.0, fhrb = 0.0, fqrb = 0.0, slb = 0.0, srb = 0.0;
+    if (sl >= 0.0) {
+        fhlb = fhb + fwb * wl;
+        wlb += fwb * fhl;
+        fqlb = fqb;
+    } else if (sr <= 0.0) {
+        fhrb = fhb + fwb * wr;
+        wrb += fwb * fhr;
+        fqrb = fqb;
+    } else {
+        const double den = sr - sl;
+        const double dh = hr - hl, dq = hr * qr - hl * ql;
+        const double fh = ((sr * fhl - sl * fhr) + sl * sr * dh) / den;
+        const double fq = ((sr * fql - sl * fqr) + sl * sr * dq) / den;
+        const double sstar = (sl * hr * (qr - sr) - sr * hl * (ql - sl)) /
+                             (hr * (qr - sr) - hl * (ql - sl));
+        const int sel = sstar > 0.0 ? 1 : (sstar < 0.0 ? 2 : 3);
+        const double wup = sel == 1 ? wl : (sel == 2 ? wr : (wl + wr) / 2.0);
+        const double fhtb = fhb + fwb * wup;
+        const double wupb = fwb * fh;
+        if (sel == 1) wlb += wupb;
+        else if (sel == 2) wrb += wupb;
+        else { wlb += 0.5 * wupb; wrb += 0.5 * wupb; }
+        const double nhb = fhtb / den, nqb = fqb / den;
+        const double denb = -(fhtb * fh + fqb * fq) / den;
+        srb += nhb * (fhl + sl * dh) + nqb * (fql + sl * dq) + denb;
+        slb += nhb * (-fhr + sr * dh) + nqb * (-fqr + sr * dq) - denb;
+        fhlb += nhb * sr;
+        fhrb -= nhb * sl;
+        fqlb += nqb * sr;
+        fqrb -= nqb * sl;
+        hrb += nhb * sl * sr;
+        hlb -= nhb * sl * sr;
+        const double dqb = nqb * sl * sr;
+        hrb += dqb * qr;
+        qrb += dqb * hr;
+        hlb -= dqb * ql;
+        qlb -= dqb * hl;
+    }
+    hlb += fhlb * ql + fqlb * (ql * ql + g * hl);
+    qlb += fhlb * hl + fqlb * 2.0 * hl * ql;
+    hrb += fhrb * qr + fqrb * (qr * qr + g * hr);
+    qrb += fhrb * hr + fqrb * 2.0 * hr * qr;
+    double clb = 0.0, crb = 0.0;
+    if (hl == 0.0) {
+        qrb += slb + srb;
+        crb += -2.0 * slb + srb;
+    } else if (hr == 0.0) {
+        qlb += slb + srb;
+        clb += -slb + 2.0 * srb;
+    } else {
+        double usb = 0.0, csb = 0.0;
+        if (sl_a) { qlb += slb; clb -= slb; } else { usb += slb; csb -= slb; }
+        if (sr_a) { qrb += srb; crb += srb; } else { usb += srb; csb += srb; }
+        qlb += 0.5 * usb;
+        qrb += 0.5 * usb;
+        clb += usb;
+        crb -= usb;
+        clb += 0.5 * csb;
+        crb += 0.5 * csb;
+        qlb += 0.25 * csb;
+        qrb -= 0.25 * csb;
+    }
+    if (cl > 0.0) hlb += clb * g / (2.0 * cl);
+    if (cr > 0.0) hrb += crb * g / (2.0 * cr);
+}
+
+// Cotangent of a cell's velocity pair (u, v) = (hu, hv)/h pulled back to (h, hu, hv).
+__device__ __forceinline__ void vel_vjp(double h, double hu, double hv, double hd, double ub,
+                                        double vb, Vjp3 &out)
+{
+    if (h > hd) {
+        const double u = hu / h, v = hv / h;
+        out.h -= (ub * u + vb * v) / h;
+        out.hu += ub / h;
+        out.hv += vb / h;
+    }
+}
+
+// Interior interface a-b (unit normal out of a, length l): cotangents of both sides' cells
+// and beds from those of a's and b's contributions l (F + p n) and l (-F - p_b n).
+__device__ void interface_vjp(double g, double hd, double ha, double hua, double hva, double za,
+                              double hb, double hub, double hvb, double zb, double nx, double ny,
+                              double l, const double *cab, const double *cbb, Vjp3 &ua_out,
+                              double &za_out, Vjp3 &ub_out, double &zb_out)
+{
+    const double zs = fmax(za, zb);
+    const double ra = ha - (zs - za), rb = hb - (zs - zb);
+    double hsa = fmax(0.0, ra), hsb = fmax(0.0, rb);
+    const bool act_a = ra > 0.0 && hsa > hd, act_b = rb > 0.0 && hsb > hd;
+    if (hsa <= hd) hsa = 0.0;
+    if (hsb <= hd) hsb = 0.0;
+    const double ua = vel(ha, hua, hd), va = vel(ha, hva, hd);
+    const double ubv = vel(hb, hub, hd), vbv = vel(hb, hvb, hd);
+    const double qa = ua * nx + va * ny, wa = va * nx - ua * ny;
+    const double qb = ubv * nx + vbv * ny, wb = vbv * nx - ubv * ny;
+    const double fhb = l * (cab[0] - cbb[0]);
+    const double fxb = l * (cab[1] - cbb[1]);
+    const double fyb = l * (cab[2] - cbb[2]);
+    const double pab = l * (cab[1] * nx + cab[2] * ny);
+    const double pbb = -l * (cbb[1] * nx + cbb[2] * ny);
+    const double fqb = fxb * nx + fyb * ny, fwb = -fxb * ny + fyb * nx;
+    double hsab, qab, wab, hsbb, qbb, wbb;
+    hllc_normal_vjp(g, hsa, qa, wa, hsb, qb, wb, fhb, fqb, fwb, hsab, qab, wab, hsbb, qbb, wbb);
+    ua_out = {pab * g * ha, 0.0, 0.0};
+    ub_out = {pbb * g * hb, 0.0, 0.0};
+    hsab -= pab * g * hsa;
+    hsbb -= pbb * g * hsb;
+    double zsb = 0.0;
+    za_out = 0.0;
+    zb_out = 0.0;
+    if (act_a) { ua_out.h += hsab; zsb -= hsab; za_out += hsab; }
+    if (act_b) { ub_out.h += hsbb; zsb -= hsbb; zb_out += hsbb; }
+    // max(za, zb) at a tie: half to each side (the convention of the tangent model too)
+    if (za > zb) za_out += zsb;
+    else if (zb > za) zb_out += zsb;
+    else { za_out += 0.5 * zsb; zb_out += 0.5 * zsb; }
+    vel_vjp(ha, hua, hva, hd, qab * nx - wab * ny, qab * ny + wab * nx, ua_out);
+    vel_vjp(hb, hub, hvb, hd, qbb * nx - wbb * ny, qbb * ny + wbb * nx, ub_out);
+}
+
+// Reflective wall: cotangent of the cell from that of its contribution.
+__device__ void wall_vjp(double g, double hd, double h, double hu, double hv, double nx,
+                         double ny, double l, const double *cb, Vjp3 &out)
+{
+    const double u = vel(h, hu, hd), v = vel(h, hv, hd);
+    const double q = u * nx + v * ny, w = v * nx - u * ny;
+    const double hs = h > hd ? h : 0.0;
+    const double fhb = l * cb[0], fxb = l * cb[1], fyb = l * cb[2];
+    const double pb = l * (cb[1] * nx + cb[2] * ny);
+    const double fqb = fxb * nx + fyb * ny, fwb = -fxb * ny + fyb * nx;
+    double hlb, qlb, wlb, hrb, qrb, wrb;
+    hllc_normal_vjp(g, hs, q, w, hs, -q, w, fhb, fqb, fwb, hlb, qlb, wlb, hrb, qrb, wrb);
+    const double qb = qlb - qrb, wb = wlb + wrb;
+    double hsb = hlb + hrb - pb * g * hs;
+    out = {pb * g * h, 0.0, 0.0};
+    if (h > hd) out.h += hsb;
+    vel_vjp(h, hu, hv, hd, qb * nx - wb * ny, qb * ny + wb * nx, out);
+}
+
+// Inflow segment: the flux depends on the cell only through h_b = max(h, h_c).
+__device__ void inflow_vjp(double g, double q_in, double h, double nx, double ny, double l,
+                           const double *cb, Vjp3 &out)
+{
+    const double hc = cbrt(q_in * q_in / g);
+    out = {0.0, 0.0, 0.0};
+    if (h >= hc) {
+        const double momb = l * (cb[1] * nx + cb[2] * ny);
+        out.h = momb * (-(q_in * q_in) / (h * h) + g * h);
+    }
+}
+
+struct AdjArgs {
+    int64_t T;
+    const int32_t *nbr;
+    const int32_t *c2n;
+    const double2 *xy;
+    const double *z, *n, *area;
+    const double *h, *hu, *hv;          // U^n
+    const double *sh, *shu, *shv;       // U*^n before the clamp
+    double *lh, *lhu, *lhv;             // lambda
+    double *mh, *mhu, *mhv;             // mu
+    double *gn, *gz;
+    const double *dt_seq;
+    int64_t step;
+    double g, hd;
+    double q[SWE_MAX_INFLOW];
+};
+
+__global__ __launch_bounds__(256) void area_kernel(int64_t T, const int32_t *c2n, const double2 *xy,
+                                                   double *area)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= T) return;
+    const double2 p0 = xy[c2n[i]], p1 = xy[c2n[T + i]], p2 = xy[c2n[2 * T + i]];
+    area[i] = 0.5 * ((p1.x - p0.x) * (p2.y - p1.y) - (p1.y - p0.y) * (p2.x - p1.x));
+}
+
+// mu = (dU^{n+1}/dU*)^T lambda^{n+1}; the roughness gradient gains (dU^{n+1}/dn)^T lambda.
+__global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= a.T) return;
+    const double dt = a.dt_seq[a.step], g = a.g;
+    const double hraw = a.sh[i], hus = a.shu[i], hvs = a.shv[i];
+    const bool clamped = hraw < 0.0;
+    const double hs = clamped ? 0.0 : hraw;
+    const double lh = a.lh[i], lhu = a.lhu[i], lhv = a.lhv[i];
+    double mh = lh, mhu = 0.0, mhv = 0.0;
+    if (hs > a.hd) {
+        const double nm = a.n[i];
+        const double mag = sqrt(hus * hus + hvs * hvs);
+        const double c = cbrt(hs);
+        const double P = hs * hs * c;
+        const double K = dt * g * nm * nm;
+        const double D = 1.0 + K * mag / P;
+        const double hun = hus / D, hvn = hvs / D;
+        const double Db = -(lhu * hun + lhv * hvn) / D;
+        mhu = lhu / D;
+        mhv = lhv / D;
+        if (mag > 0.0) {
+            const double magb = Db * K / P;
+            mhu += magb * hus / mag;
+            mhv += magb * hvs / mag;
+        }
+        const double Pb = -Db * K * mag / (P * P);
+        mh += Pb * (7.0 / 3.0) * hs * c;
+        a.gn[i] += Db * mag / P * 2.0 * dt * g * nm;
+    }
+    if (clamped) mh = 0.0;
+    a.mh[i] = mh;
+    a.mhu[i] = mhu;
+    a.mhv[i] = mhv;
+}
+
+// lambda^n = mu + sum over the cell's edges of its share of the edge adjoints; bed gradient.
+__global__ __launch_bounds__(256) void flux_adjoint_kernel(AdjArgs a)
+{
+    const int64_t T = a.T;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= T) return;
+    const double dt = a.dt_seq[a.step], g = a.g, hd = a.hd;
+    const double2 p[3] = {a.xy[a.c2n[i]], a.xy[a.c2n[T + i]], a.xy[a.c2n[2 * T + i]]};
+    const double h = a.h[i], hu = a.hu[i], hv = a.hv[i], z = a.z[i];
+    const double ri = dt / a.area[i];
+    const double ci[3] = {-ri * a.mh[i], -ri * a.mhu[i], -ri * a.mhv[i]};
+    double lh = a.mh[i], lhu = a.mhu[i], lhv = a.mhv[i], zb_sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double2 p0 = p[k], p1 = p[k == 2 ? 0 : k + 1];
+        const double dx = p1.x - p0.x, dy = p1.y - p0.y;
+        const double l = sqrt(dx * dx + dy * dy);
+        const double nx = dy / l, ny = -dx / l;
+        const int32_t j = a.nbr[k * T + i];
+        Vjp3 u{0.0, 0.0, 0.0};
+        if (j >= 0) {
+            const double rj = dt / a.area[j];
+            const double cj[3] = {-rj * a.mh[j], -rj * a.mhu[j], -rj * a.mhv[j]};
+            Vjp3 uj;
+            double zi_b, zj_b;
+            interface_vjp(g, hd, h, hu, hv, z, a.h[j], a.hu[j], a.hv[j], a.z[j], nx, ny, l, ci, cj,
+                          u, zi_b, uj, zj_b);
+            zb_sum += zi_b;
+        } else if (j == SWE_WALL) {
+            wall_vjp(g, hd, h, hu, hv, nx, ny, l, ci, u);
+        } else {
+            inflow_vjp(g, a.q[-2 - j], h, nx, ny, l, ci, u);
+        }
+        lh += u.h;
+        lhu += u.hu;
+        lhv += u.hv;
+    }
+    a.lh[i] = lh;
+    a.lhu[i] = lhu;
+    a.lhv[i] = lhv;
+    a.gz[i] += zb_sum;
+}
+
+// Misfit at an observation: the loss gains sum (h_g - obs_g)^2 (one work-item, fixed order);
+// with lam != nullptr the adjoint gains 2 (h_g - obs_g) at the gauges instead.
+__global__ void misfit_kernel(const double *h, const int32_t *gauges, int ng, const double *obs,
+                              double *loss, double *lam)
+{
+    if (lam) {
+        const int q = blockIdx.x * blockDim.x + threadIdx.x;
+        if (q < ng) lam[gauges[q]] += 2.0 * (h[gauges[q]] - obs[q]);
+        return;
+    }
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    for (int q = 0; q < ng; ++q) {
+        const double r = h[gauges[q]] - obs[q];
+        acc += r * r;
+    }
+    *loss += acc;
+}
+
+__global__ void fill_kernel(double *p, int64_t n, double v)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Workspace layout of swe_adjoint (all double unless noted).
+struct AdjLayout {
+    int64_t T, n_ckpt, K;
+    size_t ckpt, seg, segstar, lam, mu, area, loss, ctrl, work, total;
+};
+
+AdjLayout adj_layout(int64_t T, int64_t n_steps, int64_t K)
+{
+    AdjLayout L;
+    L.T = T;
+    L.K = K;
+    L.n_ckpt = (n_steps + K - 1) / K + 1;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t off = 0;
+    const size_t st = 3 * static_cast<size_t>(T) * 8;
+    L.ckpt = off; off += al(st * L.n_ckpt);
+    L.seg = off; off += al(st * (K + 1));
+    L.segstar = off; off += al(st * K);
+    L.lam = off; off += al(st);
+    L.mu = off; off += al(st);
+    L.area = off; off += al(static_cast<size_t>(T) * 8);
+    L.loss = off; off += 256;
+    L.ctrl = off; off += al(SWE_CTRL_BYTES);
+    L.work = off; off += al(static_cast<size_t>(workspace_bytes(T)));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+}  // namespace swe
+
+using namespace swe;
+
+namespace {
+
+int32_t afail(int32_t code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int32_t ahip(hipError_t e, const char *where)
+{
+    if (e == hipSuccess) return SWE_OK;
+    return afail(SWE_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t swe_adjoint_workspace_bytes(const swe_mesh *mesh, int64_t n_steps, int32_t ckpt_every,
+                                    int64_t *bytes)
+{
+    if (!mesh || !bytes || n_steps < 1 || ckpt_every < 1)
+        return afail(SWE_EINVAL, "swe_adjoint_workspace_bytes: bad argument");
+    *bytes = static_cast<int64_t>(adj_layout(mesh->info.n_cells, n_steps, ckpt_every).total);
+    return SWE_OK;
+}
+
+int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                    const swe_state *s, int64_t n_steps, const double *dt_seq,
+                    const swe_loss *loss, int32_t ckpt_every, swe_grads *out, double *loss_out,
+                    void *ws, int64_t ws_bytes, void *stream)
+{
+    const char *W = "swe_adjoint";
+    if (!mesh || !dm || !p || !s || !dt_seq || !loss || !out || !ws)
+        return afail(SWE_EINVAL, "swe_adjoint: null argument");
+    if (p->dtype != SWE_F64) return afail(SWE_EUNSUPPORTED, "swe_adjoint: FP64 only");
+    if (n_steps < 1 || ckpt_every < 1 || loss->every < 1 || loss->n_gauges < 0 ||
+        (loss->n_gauges > 0 && (!loss->gauges || !loss->obs)))
+        return afail(SWE_EINVAL, "swe_adjoint: bad steps, checkpoint interval or loss");
+    if (!out->dn || !out->dz || !out->dh || !out->dhu || !out->dhv)
+        return afail(SWE_EINVAL, "swe_adjoint: null gradient array");
+    if (!(p->g > 0.0) || !(p->h_dry >= 0.0) || p->n_inflow < 0 || p->n_inflow > SWE_MAX_INFLOW ||
+        (p->n_inflow > 0 && !p->inflow_q) || mesh->info.n_inflow_segments > p->n_inflow)
+        return afail(SWE_EINVAL, "swe_adjoint: bad parameters");
+    if (dm->n_cells != mesh->info.n_cells || !dm->nbr || !dm->c2n || !dm->xy)
+        return afail(SWE_EINVAL, "swe_adjoint: bad device mesh");
+    if (!s->h[s->cur] || !s->hu[s->cur] || !s->hv[s->cur] || !s->z || !s->n)
+        return afail(SWE_EINVAL, "swe_adjoint: null state array");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return afail(SWE_EINVAL, "swe_adjoint: ws not 256-byte aligned");
+    const int64_t T = mesh->info.n_cells, K = ckpt_every;
+    const AdjLayout L = adj_layout(T, n_steps, K);
+    if (ws_bytes < static_cast<int64_t>(L.total))
+        return afail(SWE_EINVAL, "swe_adjoint: workspace needs " + std::to_string(L.total) + " bytes");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    auto D = [&](size_t off) { return reinterpret_cast<double *>(base + off); };
+    const size_t S = static_cast<size_t>(T);
+    auto ck = [&](int64_t c, int f) { return D(L.ckpt) + (static_cast<size_t>(c) * 3 + f) * S; };
+    auto sg = [&](int64_t n, int f) { return D(L.seg) + (static_cast<size_t>(n) * 3 + f) * S; };
+    auto ss = [&](int64_t n, int f) { return D(L.segstar) + (static_cast<size_t>(n) * 3 + f) * S; };
+    double *lam = D(L.lam), *mu = D(L.mu), *area = D(L.area), *lossd = D(L.loss);
+    const unsigned blocks = static_cast<unsigned>((T + 255) / 256);
+
+    StepConfig cfg;
+    memset(&cfg, 0, sizeof(cfg));
+    cfg.n_cells = T;
+    cfg.g = p->g;
+    cfg.courant = p->courant > 0.0 && p->courant <= 1.0 ? p->courant : 0.7;
+    cfg.h_dry = p->h_dry;
+    cfg.n_inflow = p->n_inflow;
+    for (int k = 0; k < p->n_inflow; ++k) cfg.inflow_q[k] = p->inflow_q[k];
+
+    // a private state for the forward and recompute passes
+    swe_state ps;
+    memset(&ps, 0, sizeof(ps));
+    ps.z = s->z;
+    ps.n = s->n;
+    ps.ctrl = base + L.ctrl;
+    ps.work = base + L.work;
+    auto view = [&](double *h0, double *hu0, double *hv0, double *h1, double *hu1, double *hv1) {
+        swe_state v = ps;
+        v.h[0] = h0; v.hu[0] = hu0; v.hv[0] = hv0;
+        v.h[1] = h1; v.hu[1] = hu1; v.hv[1] = hv1;
+        v.cur = 0;
+        return v;
+    };
+    const size_t bytes3 = S * 8;
+    auto copy3 = [&](double *dh, double *dhu, double *dhv, const void *sh, const void *shu,
+                     const void *shv) -> int32_t {
+        if (int32_t rc = ahip(hipMemcpyAsync(dh, sh, bytes3, hipMemcpyDeviceToDevice, st), W)) return rc;
+        if (int32_t rc = ahip(hipMemcpyAsync(dhu, shu, bytes3, hipMemcpyDeviceToDevice, st), W)) return rc;
+        return ahip(hipMemcpyAsync(dhv, shv, bytes3, hipMemcpyDeviceToDevice, st), W);
+    };
+
+    area_kernel<<<blocks, 256, 0, st>>>(T, dm->c2n, reinterpret_cast<const double2 *>(dm->xy), area);
+    fill_kernel<<<1, 256, 0, st>>>(lossd, 1, 0.0);
+
+    // forward pass: checkpoints and the loss (segment slots 0 and 1 serve as ping-pong)
+    if (int32_t rc = copy3(ck(0, 0), ck(0, 1), ck(0, 2), s->h[s->cur], s->hu[s->cur], s->hv[s->cur])) return rc;
+    if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(0, 0), ck(0, 1), ck(0, 2))) return rc;
+    swe_state fw = view(sg(0, 0), sg(0, 1), sg(0, 2), sg(1, 0), sg(1, 1), sg(1, 2));
+    if (int32_t rc = ahip(static_cast<hipError_t>(launch_init(SWE_F64, *dm, cfg, fw, 0.0, 0.0, st)), W)) return rc;
+    if (int32_t rc = ahip(static_cast<hipError_t>(launch_run_begin(fw, dt_seq, st)), W)) return rc;
+    int cur = 0;
+    for (int64_t nstep = 0; nstep < n_steps; ++nstep) {
+        if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, fw, cur, dt_seq,
+                                                                  n_steps, st, nullptr)), W))
+            return rc;
+        cur ^= 1;
+        const double *hc = static_cast<const double *>(fw.h[cur]);
+        if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
+            misfit_kernel<<<1, 64, 0, st>>>(hc, loss->gauges, loss->n_gauges,
+                                            loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges,
+                                            lossd, nullptr);
+        if ((nstep + 1) % K == 0) {
+            const int64_t c = (nstep + 1) / K;
+            if (int32_t rc = copy3(ck(c, 0), ck(c, 1), ck(c, 2), fw.h[cur], fw.hu[cur], fw.hv[cur])) return rc;
+        }
+    }
+
+    // reverse pass
+    AdjArgs a;
+    memset(&a, 0, sizeof(a));
+    a.T = T;
+    a.nbr = dm->nbr;
+    a.c2n = dm->c2n;
+    a.xy = reinterpret_cast<const double2 *>(dm->xy);
+    a.z = static_cast<const double *>(s->z);
+    a.n = static_cast<const double *>(s->n);
+    a.area = area;
+    a.lh = lam; a.lhu = lam + S; a.lhv = lam + 2 * S;
+    a.mh = mu; a.mhu = mu + S; a.mhv = mu + 2 * S;
+    a.gn = out->dn;
+    a.gz = out->dz;
+    a.dt_seq = dt_seq;
+    a.g = p->g;
+    a.hd = p->h_dry;
+    for (int k = 0; k < p->n_inflow; ++k) a.q[k] = p->inflow_q[k];
+    fill_kernel<<<(3 * S + 255) / 256, 256, 0, st>>>(lam, 3 * T, 0.0);
+    fill_kernel<<<blocks, 256, 0, st>>>(out->dn, T, 0.0);
+    fill_kernel<<<blocks, 256, 0, st>>>(out->dz, T, 0.0);
+    const int64_t n_seg = (n_steps + K - 1) / K;
+    for (int64_t sgi = n_seg - 1; sgi >= 0; --sgi) {
+        const int64_t s0 = sgi * K, s1 = std::min(n_steps, s0 + K);
+        if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(sgi, 0), ck(sgi, 1), ck(sgi, 2))) return rc;
+        swe_state v0 = view(sg(0, 0), sg(0, 1), sg(0, 2), sg(1, 0), sg(1, 1), sg(1, 2));
+        if (int32_t rc = ahip(static_cast<hipError_t>(launch_init(SWE_F64, *dm, cfg, v0, 0.0, 0.0, st)), W)) return rc;
+        if (int32_t rc = ahip(static_cast<hipError_t>(launch_run_begin(v0, dt_seq + s0, st)), W)) return rc;
+        for (int64_t nstep = s0; nstep < s1; ++nstep) {
+            const int64_t q = nstep - s0;
+            swe_state v = view(sg(q, 0), sg(q, 1), sg(q, 2), sg(q + 1, 0), sg(q + 1, 1), sg(q + 1, 2));
+            double *ustar[3] = {ss(q, 0), ss(q, 1), ss(q, 2)};
+            if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, v, 0, dt_seq + s0,
+                                                                      s1 - s0, st, nullptr, nullptr,
+                                                                      1, ustar)), W))
+                return rc;
+        }
+        for (int64_t nstep = s1 - 1; nstep >= s0; --nstep) {
+            const int64_t q = nstep - s0;
+            if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
+                misfit_kernel<<<(loss->n_gauges + 63) / 64, 64, 0, st>>>(
+                    sg(q + 1, 0), loss->gauges, loss->n_gauges,
+                    loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges, nullptr, lam);
+            a.step = nstep;
+            a.sh = ss(q, 0); a.shu = ss(q, 1); a.shv = ss(q, 2);
+            friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+            a.h = sg(q, 0); a.hu = sg(q, 1); a.hv = sg(q, 2);
+            flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+        }
+        if (int32_t rc = ahip(hipGetLastError(), W)) return rc;
+    }
+    if (int32_t rc = copy3(out->dh, out->dhu, out->dhv, lam, lam + S, lam + 2 * S)) return rc;
+    if (loss_out) {
+        if (int32_t rc = ahip(hipMemcpyAsync(loss_out, lossd, 8, hipMemcpyDeviceToHost, st), W)) return rc;
+        if (int32_t rc = ahip(hipStreamSynchronize(st), W)) return rc;
+    }
+    return ahip(hipGetLastError(), W);
+}
+
+}  // extern "C"

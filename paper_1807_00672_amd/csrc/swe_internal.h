@@ -87,7 +87,8 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
 // tl == nullptr: the per-cell kernel; else the tiled kernel (its LDS must fit, see below).
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
-                const BatchLaunch *batch = nullptr, int remap = 1);
+                const BatchLaunch *batch = nullptr, int remap = 1,
+                double *const *ustar = nullptr);   // FP64 per-cell kernel: also write U*
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);
 int prepare_tile_kernels(size_t max_lds);   // allow dynamic LDS up to max_lds bytes
 int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);

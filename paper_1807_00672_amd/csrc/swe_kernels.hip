@@ -384,6 +384,7 @@ struct StepArgs {
     R *__restrict__ hvo;
     const Ctrl *ctrl;
     Partials part;
+    R *us_h, *us_hu, *us_hv;   // optional: U* before clamp and friction (adjoint recompute)
 };
 
 // One explicit step for every cell (eq. 4 with the source treatments of section 2.2).
@@ -443,6 +444,11 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
+        if (a.us_h) {
+            a.us_h[i] = hs;
+            a.us_hu[i] = hus;
+            a.us_hv[i] = hvs;
+        }
         if (hs < R(0)) {
             clamp = 1;
             hs = R(0);
@@ -840,6 +846,7 @@ StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
     a.hvo = static_cast<R *>(s.hv[1 - cur]);
     a.ctrl = static_cast<const Ctrl *>(s.ctrl);
     a.part = partials_for(s.work, n_blocks(dm.n_cells));
+    a.us_h = a.us_hu = a.us_hv = nullptr;
     return a;
 }
 
@@ -920,7 +927,7 @@ int prepare_tile_kernels(size_t max_lds)
 
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
-                const BatchLaunch *batch, int remap)
+                const BatchLaunch *batch, int remap, double *const *ustar)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nb = batch ? batch->n_tiles : n_blocks(cfg.n_cells);
@@ -943,6 +950,11 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     } else if (dtype == SWE_F64) {
         StepArgs<double> a = make_args<double>(dm, s, cur);
         a.part = part;
+        if (ustar) {
+            a.us_h = ustar[0];
+            a.us_hu = ustar[1];
+            a.us_hv = ustar[2];
+        }
         step_kernel<double><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
     } else {
         StepArgs<float> a = make_args<float>(dm, s, cur);

@@ -1,0 +1,86 @@
+"""Hand-written adjoint of the step against the oracle: the loss, a dot-product test against
+the oracle's tangent-linear model in every input direction, central finite differences on 32
+random cells (eps = 1e-6), independence of the checkpoint interval, and torch.autograd."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 200
+
+
+@pytest.fixture(scope="module")
+def setup(gpu):
+    from test_oracle_adjoint import tilted_calibration
+    case = tilted_calibration()
+    om = oracle.Mesh(case.xy, case.tri)
+    dts, obs = oracle.observations(case, om, steps=STEPS)
+    mesh = gpu.Mesh(case.xy, case.tri)
+    calib = gpu.Calibration(mesh, dts, case.extra["gauges"], obs, every=10, ckpt_every=50)
+    j, grads = calib.run(case.n, case.z, case.h, case.hu, case.hv)
+    return case, om, dts, obs, calib, j, grads
+
+
+def test_loss_matches_oracle(setup):
+    case, om, dts, obs, calib, j, grads = setup
+    jo = oracle.run_loss(om, case.z, case.n, case.h, case.hu, case.hv, dts,
+                         case.extra["gauges"], 10, obs)
+    assert j == pytest.approx(jo, rel=1e-12)
+    assert j > 0
+
+
+@pytest.mark.parametrize("which", ["n", "z", "h", "hu", "hv"])
+def test_dot_product_with_oracle_tangent(setup, which):
+    case, om, dts, obs, calib, j, grads = setup
+    k = ["n", "z", "h", "hu", "hv"].index(which)
+    rng = np.random.default_rng(100 + k)
+    v = rng.normal(size=case.n_cells)
+    jo, djo = oracle.run_tl(om, case.z, case.n, case.h, case.hu, case.hv, dts,
+                            case.extra["gauges"], 10, obs, **{"d" + which: v})
+    adj = float(np.dot(grads[k], v))
+    print(f"d{which}: adjoint <grad, v> = {adj!r}, tangent dJ[v] = {djo!r}")
+    assert adj == pytest.approx(djo, rel=1e-9, abs=1e-14 * abs(jo))
+
+
+def test_central_differences_on_random_cells(setup):
+    case, om, dts, obs, calib, j, grads = setup
+    rng = np.random.default_rng(7)
+    wet = np.flatnonzero(case.h > 1e-2)
+    cells = rng.choice(wet, size=32, replace=False)
+    dn = grads[0]
+    eps = 1e-6
+    bad = []
+    for c in cells:
+        n_p, n_m = case.n.copy(), case.n.copy()
+        n_p[c] += eps
+        n_m[c] -= eps
+        jp, _ = calib.run(n_p, case.z, case.h, case.hu, case.hv)
+        jm, _ = calib.run(n_m, case.z, case.h, case.hu, case.hv)
+        fd = (jp - jm) / (2 * eps)
+        if abs(fd - dn[c]) > 1e-6 * np.abs(dn).max() + 1e-4 * abs(dn[c]):
+            bad.append((int(c), fd, dn[c]))
+    print(f"max |dJ/dn| {np.abs(dn).max():.3e}; disagreements {bad}")
+    assert len(bad) == 0
+
+
+def test_checkpoint_interval_does_not_change_gradients(setup, gpu):
+    case, om, dts, obs, calib, j, grads = setup
+    c2 = gpu.Calibration(calib.mesh, dts, case.extra["gauges"], obs, every=10, ckpt_every=7)
+    j2, g2 = c2.run(case.n, case.z, case.h, case.hu, case.hv)
+    assert j2 == j
+    for a, b in zip(grads, g2):
+        assert np.array_equal(a, b)
+
+
+def test_autograd_function(setup, gpu):
+    import torch
+    case, om, dts, obs, calib, j, grads = setup
+    ts = [torch.tensor(a, requires_grad=True) for a in (case.n, case.z, case.h, case.hu, case.hv)]
+    loss = gpu.AdjointLoss.apply(calib, *ts)
+    (2.0 * loss).backward()
+    assert loss.item() == j
+    for t, g in zip(ts, grads):
+        assert np.array_equal(t.grad.numpy(), 2.0 * g)

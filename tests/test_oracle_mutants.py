@@ -25,7 +25,8 @@ MUTANTS = [
     ("star sound speed velocity term swapped", "(cl + cr) / 2.0 + (ql - qr) / 4.0", "(cl + cr) / 2.0 + (qr - ql) / 4.0"),
     ("HLL jump term sign", "+ sl * sr * (hr - hl)) / den", "- sl * sr * (hr - hl)) / den"),
     ("HLL momentum jump uses velocities", "sl * sr * (hr * qr - hl * ql)", "sl * sr * (qr - ql)"),
-    ("contact upwinding inverted", "sstar > 0.0 ? wl : (sstar < 0.0 ? wr", "sstar > 0.0 ? wr : (sstar < 0.0 ? wl"),
+    ("contact upwinding inverted", "const double wup = sstar > 0.0 ? wl : (sstar < 0.0 ? wr",
+     "const double wup = sstar > 0.0 ? wr : (sstar < 0.0 ? wl"),
     ("hydrostatic pressure without the half", "fql = hl * ql * ql + 0.5 * g * hl * hl", "fql = hl * ql * ql + g * hl * hl"),
     ("wall ghost keeps the normal velocity", "om_hllc_normal(g, hs, q, w, hs, -q, w,", "om_hllc_normal(g, hs, q, w, hs, q, w,"),
     ("friction depth exponent 1/3 short", "(hs * hs * cbrt(hs))", "(hs * cbrt(hs))"),
@@ -33,7 +34,8 @@ MUTANTS = [
     ("Euler update sign", "double hs = h[c] - r * acc[0];", "double hs = h[c] + r * acc[0];"),
     ("x-momentum update sign", "const double hus = hu[c] - r * acc[1];", "const double hus = hu[c] + r * acc[1];"),
     ("last edge of y-momentum dropped", "acc[2] = acc[2] + c2;", "acc[2] = acc[2];"),
-    ("neighbour side not negated", "const double s = (m->edge_l[e] == c) ? 1.0 : -1.0;", "const double s = 1.0;"),
+    ("neighbour side not negated", "const double s = (m->edge_l[e] == c) ? 1.0 : -1.0;\n            const double pk = (m->edge_l[e] == c) ? w->pl[e] : w->pr[e];",
+     "const double s = 1.0;\n            const double pk = (m->edge_l[e] == c) ? w->pl[e] : w->pr[e];"),
     ("inradius A/P", "m->inradius[c] = 2.0 * a / (l0 + l1 + l2);", "m->inradius[c] = a / (l0 + l1 + l2);"),
     ("CFL ignores the flow speed", "s = sqrt(u * u + v * v) + sqrt(p->g * h[c]);", "s = sqrt(p->g * h[c]);"),
     ("CFL misses the Courant number", "return p->courant * best;", "return best;"),
