@@ -127,7 +127,9 @@ typedef struct swe_state {
     const void *z;               /* bed elevation, T values */
     const void *n;               /* Manning coefficient, T values, >= 0 */
     void *ctrl;                  /* SWE_CTRL_BYTES, 16-byte aligned: time, dt, counters */
-    void *work;                  /* swe_workspace_bytes(T) bytes, 256-byte aligned */
+    void *work;                  /* swe_workspace_bytes(T) bytes, 256-byte aligned: step
+                                    partials and arrival counters that swe_state_init clears;
+                                    never shared by two states */
     int32_t cur;                 /* host: buffer holding the current state */
     int32_t reserved;
 } swe_state;

@@ -30,29 +30,53 @@ enum : int32_t { kStatusNonFinite = 1, kStatusDry = 2, kStatusBadDt = 4 };
 
 constexpr int kBlock = SWE_TILE;     // cells per workgroup of the step kernels
 
-// Per-block partial results of a step, laid out in the workspace.
+constexpr int kGroup = 256;          // tiles whose partials one workgroup folds together
+
+// Per-block partial results of a step and their second level, laid out in the workspace.  A
+// single-mesh step folds them itself: the last workgroup of each group of kGroup tiles to
+// finish reduces the group, the last group to finish reduces the groups and advances the
+// control block; count[] holds the arrivals and is zero between steps.
 struct Partials {
-    double *dt;        // [nblocks] min over the block's cells of r / (|u| + c)
-    int32_t *clamps;   // [nblocks]
-    int32_t *flags;    // [nblocks] kStatus* bits
+    double *dt;         // [nb] min over the block's cells of r / (|u| + c)
+    int32_t *clamps;    // [nb]
+    int32_t *flags;     // [nb] kStatus* bits
+    double *gdt;        // [n_groups(nb)] the same per group of kGroup tiles
+    int32_t *gclamps;   // [n_groups(nb)]
+    int32_t *gflags;    // [n_groups(nb)]
+    uint32_t *count;    // [n_groups(nb) + 1] arrivals per group, then of the groups
 };
 
 inline int64_t n_blocks(int64_t n_cells) { return (n_cells + kBlock - 1) / kBlock; }
+inline int64_t n_groups(int64_t nb) { return (nb + kGroup - 1) / kGroup; }
+inline int64_t round256(int64_t b) { return ((b + 255) / 256) * 256; }
 
-// Partials of nb tiles laid out in a workspace.
+// Partials of nb tiles laid out in a workspace (every array 256-byte aligned).
 inline Partials partials_for(void *work, int64_t nb)
 {
     char *p = static_cast<char *>(work);
+    const int64_t ng = n_groups(nb);
     Partials r;
     r.dt = reinterpret_cast<double *>(p);
-    r.clamps = reinterpret_cast<int32_t *>(p + ((nb * 8 + 255) / 256) * 256);
-    r.flags = r.clamps + ((nb + 63) / 64) * 64;
+    p += round256(nb * 8);
+    r.clamps = reinterpret_cast<int32_t *>(p);
+    p += round256(nb * 4);
+    r.flags = reinterpret_cast<int32_t *>(p);
+    p += round256(nb * 4);
+    r.gdt = reinterpret_cast<double *>(p);
+    p += round256(ng * 8);
+    r.gclamps = reinterpret_cast<int32_t *>(p);
+    p += round256(ng * 4);
+    r.gflags = reinterpret_cast<int32_t *>(p);
+    p += round256(ng * 4);
+    r.count = reinterpret_cast<uint32_t *>(p);
     return r;
 }
 
 inline int64_t workspace_bytes_for_tiles(int64_t nb)
 {
-    return ((nb * 8 + 255) / 256) * 256 + 2 * ((nb + 63) / 64) * 64 * 4 + 256;
+    const int64_t ng = n_groups(nb);
+    return round256(nb * 8) + 2 * round256(nb * 4) + round256(ng * 8) + 2 * round256(ng * 4) +
+           round256((ng + 1) * 4);
 }
 
 inline int64_t workspace_bytes(int64_t n_cells) { return workspace_bytes_for_tiles(n_blocks(n_cells)); }

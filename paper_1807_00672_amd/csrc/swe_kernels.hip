@@ -36,6 +36,11 @@ constexpr double kInf = __builtin_huge_val();
 #ifndef SWE_F32_FAST
 #define SWE_F32_FAST 1
 #endif
+// 1: a single mesh's step partials are folded by many workgroups (dt_fold_kernel); 0: by the
+// one-workgroup dt pass that batches use per scenario.
+#ifndef SWE_DT_FOLD
+#define SWE_DT_FOLD 1
+#endif
 template <typename R>
 __device__ __forceinline__ R div_(R a, R b)
 {
@@ -313,6 +318,46 @@ __device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
                                                const Partials &part)
 {
     block_partials_at(dtc, clamp, flag, part, blockIdx.x);
+}
+
+// Account for the step just taken (m: min CFL bound over the cells, cl: clamps, fl: status
+// bits of the new state), then set the next step's dt: CFL, replayed from dt_seq, or cut at
+// t_end (section 2.4).
+__device__ void advance_ctrl(Ctrl *ctrl, double m, long long cl, int fl, double courant,
+                             const double *dt_seq, int64_t n_seq)
+{
+    Ctrl c = *ctrl;
+    c.t = c.last ? c.t_end : c.t + c.dt;
+    c.dt_min = c.steps == 0 ? c.dt : fmin(c.dt_min, c.dt);
+    c.dt_max = c.steps == 0 ? c.dt : fmax(c.dt_max, c.dt);
+    c.dt_sum = c.dt_sum + c.dt;
+    c.steps += 1;
+    c.run_step += 1;
+    c.clamps += cl;
+    if (c.last) c.done = 1;
+    if (fl & kStatusNonFinite) {
+        c.status |= kStatusNonFinite;
+        c.done = 1;
+    }
+    if (!c.done) {
+        double dt = courant * m;
+        if (dt_seq) dt = c.run_step < n_seq ? dt_seq[c.run_step] : c.dt;
+        c.last = 0;
+        if (!(dt < kInf)) {
+            c.status |= kStatusDry;
+            c.done = 1;
+        } else if (!(dt > 0.0)) {
+            c.status |= kStatusBadDt;
+            c.done = 1;
+        } else {
+            if (c.t_end > 0.0 && dt >= c.t_end - c.t) {
+                dt = c.t_end - c.t;
+                c.last = 1;
+            }
+            c.dt = dt;
+        }
+    }
+    *ctrl = c;
 }
 
 // CFL bound r / (|u| + sqrt(g h)) of a cell (inflow edges add their boundary speed);
@@ -681,8 +726,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig 
 constexpr int kPassThreads = 1024;
 
 // Reduce the per-block partials into the control block: account for the step just taken
-// (mode 1) or start the state (mode 0), then set the next step's dt (CFL, replayed, or cut
-// at t_end).
+// (mode 1) or start the state (mode 0, which also clears the arrival counter of
+// dt_fold_kernel), then set the next step's dt (CFL, replayed, or cut at t_end).
 __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, Partials part,
                                                                int64_t nb, double courant,
                                                                const double *dt_seq,
@@ -697,6 +742,9 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
     __shared__ double s_dt[kPassThreads / 64];
     __shared__ long long s_cl[kPassThreads / 64];
     __shared__ int s_fl[kPassThreads / 64];
+    if (mode == 0 && blockIdx.x == 0)
+        for (int64_t q = threadIdx.x; q <= (nb + kGroup - 1) / kGroup; q += kPassThreads)
+            part.count[q] = 0;
     if (mode == 1 && ctrl->done) return;
     double m = kInf;
     long long cl = 0;
@@ -739,34 +787,25 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
         cl += s_cl[w];
         fl |= s_fl[w];
     }
-    Ctrl c = *ctrl;
-    if (mode == 0) {
-        c.t = t0;
-        c.dt = 0.0;
-        c.t_end = t_end;
-        c.dt_min = 0.0; c.dt_max = 0.0; c.dt_sum = 0.0;
-        c.steps = 0; c.run_step = 0; c.clamps = 0;
-        c.status = 0; c.done = 0; c.last = 0;
-        c.cur0 = cur0;
-        if (t_end > 0.0 && t0 >= t_end) c.done = 1;
-    } else {
-        c.t = c.last ? c.t_end : c.t + c.dt;
-        c.dt_min = c.steps == 0 ? c.dt : fmin(c.dt_min, c.dt);
-        c.dt_max = c.steps == 0 ? c.dt : fmax(c.dt_max, c.dt);
-        c.dt_sum = c.dt_sum + c.dt;
-        c.steps += 1;
-        c.run_step += 1;
-        c.clamps += cl;
-        if (c.last) c.done = 1;
+    if (mode == 1) {
+        advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq);
+        return;
     }
+    Ctrl c = *ctrl;
+    c.t = t0;
+    c.dt = 0.0;
+    c.t_end = t_end;
+    c.dt_min = 0.0; c.dt_max = 0.0; c.dt_sum = 0.0;
+    c.steps = 0; c.run_step = 0; c.clamps = 0;
+    c.status = 0; c.done = 0; c.last = 0;
+    c.cur0 = cur0;
+    if (t_end > 0.0 && t0 >= t_end) c.done = 1;
     if (fl & kStatusNonFinite) {
         c.status |= kStatusNonFinite;
         c.done = 1;
     }
     if (!c.done) {
         double dt = courant * m;
-        if (dt_seq) dt = c.run_step < n_seq ? dt_seq[c.run_step] : c.dt;
-        c.last = 0;
         if (!(dt < kInf)) {
             c.status |= kStatusDry;
             c.done = 1;
@@ -782,6 +821,74 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
         }
     }
     *ctrl = c;
+}
+
+// Fold kGroup work-items' (min, sum, or) into work-item 0's values.
+__device__ __forceinline__ void fold_group(double &m, long long &cl, int &fl)
+{
+    __shared__ double s_dt[kGroup / 64];
+    __shared__ long long s_cl[kGroup / 64];
+    __shared__ int s_fl[kGroup / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    m = wave_min(m);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cl += __shfl_xor(cl, off, 64);
+    fl = wave_or(fl);
+    if (lane == 0) {
+        s_dt[wv] = m;
+        s_cl[wv] = cl;
+        s_fl[wv] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < kGroup / 64; ++w) {
+            m = fmin(m, s_dt[w]);
+            cl += s_cl[w];
+            fl |= s_fl[w];
+        }
+    __syncthreads();
+}
+
+// The dt pass of a single mesh, spread over the chip: workgroup q folds the partials of tiles
+// [kGroup q, kGroup q + kGroup) into group partial q; the last workgroup to finish folds the
+// groups and advances the control block.  Nothing waits: arrivals are counted with a release
+// increment, and only the last arrival (acquire) reads what the others wrote.
+__global__ __launch_bounds__(kGroup) void dt_fold_kernel(Ctrl *ctrl, Partials part, int64_t nb,
+                                                        double courant, const double *dt_seq,
+                                                        int64_t n_seq)
+{
+    __shared__ int s_last;
+    // uniform; the control block changes only after every workgroup has arrived
+    if (ctrl->done) return;
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kGroup + threadIdx.x;
+    double m = b < nb ? part.dt[b] : kInf;
+    long long cl = b < nb ? part.clamps[b] : 0;
+    int fl = b < nb ? part.flags[b] : 0;
+    fold_group(m, cl, fl);
+    if (threadIdx.x == 0) {
+        part.gdt[blockIdx.x] = m;
+        part.gclamps[blockIdx.x] = static_cast<int32_t>(cl);
+        part.gflags[blockIdx.x] = fl;
+        const uint32_t old = __hip_atomic_fetch_add(part.count, 1u, __ATOMIC_RELEASE,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        s_last = old == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    m = kInf;
+    cl = 0;
+    fl = 0;
+    for (int q = threadIdx.x; q < static_cast<int>(gridDim.x); q += kGroup) {
+        m = fmin(m, part.gdt[q]);
+        cl += part.gclamps[q];
+        fl |= part.gflags[q];
+    }
+    fold_group(m, cl, fl);
+    if (threadIdx.x == 0) {
+        part.count[0] = 0;
+        advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq);
+    }
 }
 
 // Start a run: restart the dt_seq index and, when replaying, take dt_seq[0] (cut at t_end).
@@ -961,8 +1068,12 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
         a.part = part;
         step_kernel<float><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
     }
-    dt_pass_kernel<<<dim3(bv.n_scen), kPassThreads, 0, st>>>(
-        static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, 1, 0.0, 0.0, 0, bv);
+    if (SWE_DT_FOLD && batch == nullptr)
+        dt_fold_kernel<<<dim3(n_groups(nb)), dim3(kGroup), 0, st>>>(
+            static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq);
+    else
+        dt_pass_kernel<<<dim3(bv.n_scen), kPassThreads, 0, st>>>(
+            static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, 1, 0.0, 0.0, 0, bv);
     return static_cast<int>(hipGetLastError());
 }
 
