@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0     # MI355X HBM3E, public specification
-STEP_KERNEL = "step_kernel"   # the per-cell step kernel the default variant launches
+STEP_KERNEL = "tile_step_kernel"   # the step kernel the default variant launches at 10M cells
 
 
 def algorithmic_bytes(n_cells: int, n_nodes: int, word: int) -> int:
@@ -44,7 +44,7 @@ def kernel_source_hash() -> str:
 def load_traffic(dtype: str, n_cells: int):
     """HBM bytes per launch of the step kernel from committed counter runs, if they were taken
     on the current kernel source for this workload; else None."""
-    p = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    p = os.path.join(ROOT, "profiles", "tile_step_kernel_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -254,6 +254,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBPS,
                      "traffic": r["traffic"], "kernel": STEP_KERNEL,
+                     "timed": "whole step (step kernel + dt fold kernel) per step",
                      "alg_bytes_per_launch": r["alg_bytes_per_step"]},
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "t_end_state"}
                      for k, v in results.items()},

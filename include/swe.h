@@ -48,7 +48,7 @@ extern "C" {
 #define SWE_MAX_INFLOW 16      /* inflow segments per mesh */
 #define SWE_CTRL_BYTES 512     /* size of the device control block of a state */
 #define SWE_WALL (-1)          /* boundary code of a reflective wall (section 3) */
-#define SWE_AUTO 0             /* variant: the library's default, the per-cell kernel */
+#define SWE_AUTO 0             /* variant: the tiled kernel where its LDS fits, else per-cell */
 #define SWE_CELL 1             /* variant: one work-item per cell gathering its neighbours */
 #define SWE_TILED 2            /* variant: tile-staged states, each tile interface once */
 #define SWE_NO_XCD_REMAP 1u    /* flag: launch tiles in mesh order instead of giving each XCD

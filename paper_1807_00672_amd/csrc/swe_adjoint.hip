@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <string>
 
+#include "swe_device_math.h"
 #include "swe_internal.h"
 
 namespace swe {
@@ -202,7 +203,7 @@ __device__ void wall_vjp(double g, double hd, double h, double hu, double hv, do
 __device__ void inflow_vjp(double g, double q_in, double h, double nx, double ny, double l,
                            const double *cb, Vjp3 &out)
 {
-    const double hc = cbrt(q_in * q_in / g);
+    const double hc = cbrt_(q_in * q_in / g);
     out = {0.0, 0.0, 0.0};
     if (h >= hc) {
         const double momb = l * (cb[1] * nx + cb[2] * ny);
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
     if (hs > a.hd) {
         const double nm = a.n[i];
         const double mag = sqrt(hus * hus + hvs * hvs);
-        const double c = cbrt(hs);
+        const double c = cbrt_(hs);
         const double P = hs * hs * c;
         const double K = dt * g * nm * nm;
         const double D = 1.0 + K * mag / P;

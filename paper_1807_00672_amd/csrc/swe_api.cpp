@@ -92,7 +92,9 @@ struct DeviceLds {
 };
 DeviceLds g_lds[64];
 
-// Pick the step kernel: the tiled one when asked for or possible, else the per-cell one.
+// Pick the step kernel: SWE_CELL the per-cell one, SWE_TILED the tiled one (an error when it
+// cannot run), SWE_AUTO the tiled one when the device mesh carries the tile arrays and a
+// tile's LDS fits the device, else the per-cell one.
 int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
                        const TileLayout **out, const char *where)
 {
@@ -101,9 +103,10 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
         return fail(SWE_EINVAL, w + ": unknown variant");
     if (p->flags & ~SWE_NO_XCD_REMAP) return fail(SWE_EINVAL, w + ": unknown flags");
-    if (p->variant != SWE_TILED) return SWE_OK;   // the per-cell kernel
+    if (p->variant == SWE_CELL) return SWE_OK;
+    const bool auto_ = p->variant == SWE_AUTO;
     const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot;
-    if (!have) return fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
+    if (!have) return auto_ ? SWE_OK : fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
     int dev = 0;
     if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;
     if (dev < 0 || dev >= 64) return fail(SWE_EUNSUPPORTED, w + ": device index beyond 63");
@@ -115,6 +118,7 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
         d.limit = lim;
     }
     const size_t need = tile_lds_bytes_for(p->dtype, mesh->tiles);
+    if (need > static_cast<size_t>(d.limit) && auto_) return SWE_OK;
     if (need > static_cast<size_t>(d.limit))
         return fail(SWE_EUNSUPPORTED, w + ": tile needs " + std::to_string(need) +
                                           " bytes of LDS, device allows " + std::to_string(d.limit));

@@ -112,8 +112,12 @@ BatchLaunch launch_view(const swe_batch *b, const swe_batch_dev *d, const swe_ba
 }
 
 // The tile's LDS must fit the device; allow more than the default 64 KiB when needed.
-int32_t check_lds(const swe_batch *b, int dtype, const char *where)
+// Whether a batch step runs the tiled kernel (choose_variant's rule: SWE_AUTO takes it when a
+// tile's LDS fits the device); an explicit SWE_TILED that cannot run is an error.
+int32_t check_lds(const swe_batch *b, int dtype, int variant, bool *tiled, const char *where)
 {
+    *tiled = false;
+    if (variant == SWE_CELL) return SWE_OK;
     int dev = 0;
     if (int32_t rc = bcheck_hip(hipGetDevice(&dev), where)) return rc;
     if (dev < 0 || dev >= 64) return bfail(SWE_EUNSUPPORTED, std::string(where) + ": device index");
@@ -125,6 +129,7 @@ int32_t check_lds(const swe_batch *b, int dtype, const char *where)
         g_blimit_known[dev] = true;
     }
     const size_t need = tile_lds_bytes_for(dtype, b->tiles);
+    if (need > static_cast<size_t>(g_blimit[dev]) && variant == SWE_AUTO) return SWE_OK;
     if (need > static_cast<size_t>(g_blimit[dev]))
         return bfail(SWE_EUNSUPPORTED, std::string(where) + ": a tile needs " + std::to_string(need) +
                                            " bytes of LDS");
@@ -133,11 +138,12 @@ int32_t check_lds(const swe_batch *b, int dtype, const char *where)
             return rc;
         g_bprepared[dev] = static_cast<size_t>(g_blimit[dev]);
     }
+    *tiled = true;
     return SWE_OK;
 }
 
 hipGraphExec_t batch_graph(const swe_batch *b, const swe_batch_dev *d, const swe_batch_params *p,
-                           const StepConfig &cfg, const swe_state *s)
+                           const StepConfig &cfg, const swe_state *s, bool tiled)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
@@ -163,7 +169,7 @@ hipGraphExec_t batch_graph(const swe_batch *b, const swe_batch_dev *d, const swe
     hipStream_t cs = g_bcapture[dev];
     const BatchLaunch bl = launch_view(b, d, p);
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    const TileLayout *tl = p->variant == SWE_TILED ? &b->tiles : nullptr;
+    const TileLayout *tl = tiled ? &b->tiles : nullptr;
     const int rm = (p->flags & SWE_NO_XCD_REMAP) ? 0 : 1;
     const int e0 = launch_step(p->dtype, d->mesh, cfg, *s, s->cur, nullptr, 0, cs, tl, &bl, rm);
     const int e1 = launch_step(p->dtype, d->mesh, cfg, *s, 1 - s->cur, nullptr, 0, cs, tl, &bl, rm);
@@ -348,21 +354,21 @@ int32_t swe_batch_run(const swe_batch *batch, const swe_batch_dev *dev,
 {
     if (int32_t rc = check_batch_call(batch, dev, p, s, "swe_batch_run")) return rc;
     if (n_steps < 0) return bfail(SWE_EINVAL, "swe_batch_run: n_steps < 0");
-    if (p->variant == SWE_TILED)
-        if (int32_t rc = check_lds(batch, p->dtype, "swe_batch_run")) return rc;
+    bool tiled = false;
+    if (int32_t rc = check_lds(batch, p->dtype, p->variant, &tiled, "swe_batch_run")) return rc;
     const StepConfig cfg = batch_config(batch, p);
     const BatchLaunch bl = launch_view(batch, dev, p);
     hipStream_t st = static_cast<hipStream_t>(stream);
     int64_t k = 0;
     if (n_steps >= 4) {
-        if (hipGraphExec_t ex = batch_graph(batch, dev, p, cfg, s)) {
+        if (hipGraphExec_t ex = batch_graph(batch, dev, p, cfg, s, tiled)) {
             for (; k + 2 <= n_steps; k += 2)
                 if (int32_t rc = bcheck_hip(hipGraphLaunch(ex, st), "swe_batch_run")) return rc;
         }
     }
     for (; k < n_steps; ++k) {
         if (int32_t rc = bcheck_hip(launch_step(p->dtype, dev->mesh, cfg, *s, s->cur, nullptr, 0,
-                                                stream, p->variant == SWE_TILED ? &batch->tiles : nullptr,
+                                                stream, tiled ? &batch->tiles : nullptr,
                                                 &bl, (p->flags & SWE_NO_XCD_REMAP) ? 0 : 1),
                                     "swe_batch_run"))
             return rc;

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "swe_device_math.h"
 #include "swe_internal.h"
 
 namespace swe {
@@ -215,7 +216,7 @@ __device__ __forceinline__ void wall_flux(R g, R hd, R h, R u, R v, R nx, R ny, 
 template <typename R>
 __device__ __forceinline__ R inflow_flux(R g, R q_in, R h, R nx, R ny, R &fh, R &fx, R &fy)
 {
-    const R hc = cbrt(div_(q_in * q_in, g));
+    const R hc = cbrt_(div_(q_in * q_in, g));
     const R hb = fmax(h, hc);
     const R mom = div_(q_in * q_in, hb) + R(0.5) * g * hb * hb;
     fh = -q_in;
@@ -227,7 +228,7 @@ __device__ __forceinline__ R inflow_flux(R g, R q_in, R h, R nx, R ny, R &fh, R 
 template <typename R>
 __device__ __forceinline__ R inflow_speed(R g, R q_in, R h)
 {
-    const R hc = cbrt(div_(q_in * q_in, g));
+    const R hc = cbrt_(div_(q_in * q_in, g));
     const R hb = fmax(h, hc);
     return div_(q_in, hb) + sqrt_(g * hb);
 }
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         if (hs > hd) {
             const R nm = a.n[i];
             const R mag = sqrt_(hus * hus + hvs * hvs);
-            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt(hs));
+            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt_(hs));
             hun = div_(hus, d);
             hvn = div_(hvs, d);
         } else {
@@ -531,20 +532,23 @@ struct TileArgs {
     int32_t n_tiles, max_halo, max_edges, pad;
 };
 
-// LDS bytes of the tiled step: tile + halo states (h, u, v, z), the tile's node ids and
-// seven values per edge-list entry (both sides' contributions and the length).
+// LDS bytes of the tiled step: tile + halo states (h, u, v, z) and five values per edge-list
+// entry (side a's contribution and side b's momentum part; side b's mass part is -a's).
 inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
 {
-    return 4 * word * static_cast<size_t>(kBlock + max_halo) + 3 * 4 * kBlock +
-           7 * word * static_cast<size_t>(max_edges);
+    return 4 * word * static_cast<size_t>(kBlock + max_halo) +
+           5 * word * static_cast<size_t>(max_edges);
 }
 
-// One explicit step, tiled.  Phase 1 stages the tile's cells and its halo in LDS as
-// (h, u, v, z), each velocity computed once.  Phase 2 evaluates every interface of the edge
-// list once (section 2.3's interface loop, restricted to the tile) and stores each side's
-// contribution l (F + p n) to eq. 3, computed exactly as the per-cell form computes it.
-// Phase 3 sums each cell's three contributions in local-edge order and applies the update of
-// eq. 4, the clamp, the friction and the next CFL bound, as the per-cell kernel does.
+// One explicit step, tiled.  Every global load of the workgroup is issued up front: the own
+// cell (state, bed, Manning, nodes, edge slots), the halo states, and the first two rounds of
+// edge-list entries with their node coordinates.  Phase 1 stages the tile's cells and its
+// halo in LDS as (h, u, v, z), each velocity computed once.  Phase 2 evaluates every interface
+// of the edge list once (section 2.3's interface loop, restricted to the tile) and stores the
+// contributions l (F + p n) to eq. 3 of both sides, computed exactly as the per-cell form
+// computes them.  Phase 3 sums each cell's three contributions in local-edge order and
+// applies the update of eq. 4, the clamp, the friction and the next CFL bound, as the
+// per-cell kernel does.
 template <typename R>
 __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
                                                            Batch bt)
@@ -563,14 +567,11 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     R *s_u = s_h + ns;
     R *s_v = s_u + ns;
     R *s_z = s_v + ns;
-    int32_t *s_c2n = reinterpret_cast<int32_t *>(s_z + ns);
-    R *e_a0 = reinterpret_cast<R *>(s_c2n + 3 * kBlock);
-    R *e_a1 = e_a0 + ta.max_edges;
-    R *e_a2 = e_a1 + ta.max_edges;
-    R *e_b0 = e_a2 + ta.max_edges;
-    R *e_b1 = e_b0 + ta.max_edges;
+    R *e_a0 = s_z + ns;                  // side a: l f_h
+    R *e_a1 = e_a0 + ta.max_edges;       // side a: l (f_x + p_a n_x)
+    R *e_a2 = e_a1 + ta.max_edges;       // side a: l (f_y + p_a n_y)
+    R *e_b1 = e_a2 + ta.max_edges;       // side b: -(its momentum contribution)
     R *e_b2 = e_b1 + ta.max_edges;
-    R *e_l = e_b2 + ta.max_edges;
 
     const int64_t T = cfg.n_cells;
     const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
@@ -581,18 +582,32 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
     const R dt = static_cast<R>(ctrl->dt);
 
-    // phase 1: own cell and halo into LDS
-    R h = R(0), hu = R(0), hv = R(0);
-    int32_t n0 = 0, n1 = 0, n2 = 0;
+    // global loads: own cell
+    R h = R(0), hu = R(0), hv = R(0), zc = R(0), nm = R(0);
+    double2 p0 = {0.0, 0.0}, p1 = {0.0, 0.0}, p2 = {0.0, 0.0};
+    uint32_t sl0 = 0, sl1 = 0, sl2 = 0;
     if (mine) {
-        h = a.h[i]; hu = a.hu[i]; hv = a.hv[i];
-        s_h[tid] = h;
-        s_u[tid] = velocity(h, hu, hd);
-        s_v[tid] = velocity(h, hv, hd);
-        s_z[tid] = a.z[i];
-        n0 = a.c2n[i]; n1 = a.c2n[T + i]; n2 = a.c2n[2 * T + i];
-        s_c2n[tid] = n0; s_c2n[kBlock + tid] = n1; s_c2n[2 * kBlock + tid] = n2;
+        h = a.h[i]; hu = a.hu[i]; hv = a.hv[i]; zc = a.z[i]; nm = a.n[i];
+        sl0 = ta.slot[i]; sl1 = ta.slot[T + i]; sl2 = ta.slot[2 * T + i];
+        p0 = a.xy[a.c2n[i]]; p1 = a.xy[a.c2n[T + i]]; p2 = a.xy[a.c2n[2 * T + i]];
     }
+    // global loads: the edge-list entries of the first two rounds and their end nodes
+    const int eb = ta.edge_off[tile], ee = ta.edge_off[tile + 1];
+    uint32_t ew[2] = {0u, 0u};
+    double2 ep0[2] = {{0.0, 0.0}, {0.0, 0.0}}, ep1[2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int e = eb + tid + it * kBlock;
+        if (e < ee) {
+            const uint32_t w = ta.edges[e];
+            const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
+            const int k = static_cast<int>((w >> 8) & 3u);
+            ew[it] = w;
+            ep0[it] = a.xy[a.c2n[k * T + ca]];
+            ep1[it] = a.xy[a.c2n[(k == 2 ? 0 : k + 1) * T + ca]];
+        }
+    }
+    // phase 1: halo and own cell into LDS
     const int hb = ta.halo_off[tile], he = ta.halo_off[tile + 1];
     for (int j = hb + tid; j < he; j += kBlock) {
         const int32_t c = ta.halo[j];
@@ -603,31 +618,30 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         s_v[q] = velocity(hh, a.hv[c], hd);
         s_z[q] = a.z[c];
     }
+    if (mine) {
+        s_h[tid] = h;
+        s_u[tid] = velocity(h, hu, hd);
+        s_v[tid] = velocity(h, hv, hd);
+        s_z[tid] = zc;
+    }
     __syncthreads();
 
     // phase 2: the tile's interfaces, each once
-    const int eb = ta.edge_off[tile], ee = ta.edge_off[tile + 1];
-    for (int e = eb + tid; e < ee; e += kBlock) {
-        const uint32_t w = ta.edges[e];
+    auto edge = [&](uint32_t w, double2 q0, double2 q1, int q) {
         const int ca = static_cast<int>(w & 0xffu);
-        const int k = static_cast<int>((w >> 8) & 3u);
         const int cb = static_cast<int16_t>(w >> 16);
-        const double2 p0 = a.xy[s_c2n[k * kBlock + ca]];
-        const double2 p1 = a.xy[s_c2n[(k == 2 ? 0 : k + 1) * kBlock + ca]];
-        const R dx = static_cast<R>(p1.x - p0.x), dy = static_cast<R>(p1.y - p0.y);
+        const R dx = static_cast<R>(q1.x - q0.x), dy = static_cast<R>(q1.y - q0.y);
         const R l = sqrt_(dx * dx + dy * dy);
         const R nx = div_(dy, l), ny = div_(-dx, l);
         const R ha = s_h[ca], ua = s_u[ca], va = s_v[ca];
         R fh, fx, fy, pa, pb;
-        const int q = e - eb;
         if (cb >= 0) {
             interface_flux_uv<R>(g, hd, ha, ua, va, s_z[ca], s_h[cb], s_u[cb], s_v[cb], s_z[cb],
                                  nx, ny, fh, fx, fy, pa, pb);
-            if (cb < kBlock) {
-                e_b0[q] = l * (-fh);
-                e_b1[q] = l * (-fx + pb * (-nx));
-                e_b2[q] = l * (-fy + pb * (-ny));
-            }
+            // side b's contributions are l (-f_h) = -(l f_h) and l (-f + p_b (-n)) =
+            // -(l (f + p_b n)), exactly
+            e_b1[q] = l * (fx + pb * nx);
+            e_b2[q] = l * (fy + pb * ny);
         } else if (cb == SWE_WALL) {
             wall_flux<R>(g, hd, ha, ua, va, nx, ny, fh, fx, fy, pa);
         } else {
@@ -638,7 +652,17 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         e_a0[q] = l * fh;
         e_a1[q] = l * (fx + pa * nx);
         e_a2[q] = l * (fy + pa * ny);
-        e_l[q] = l;
+    };
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int e = eb + tid + it * kBlock;
+        if (e < ee) edge(ew[it], ep0[it], ep1[it], e - eb);
+    }
+    for (int e = eb + tid + 2 * kBlock; e < ee; e += kBlock) {
+        const uint32_t w = ta.edges[e];
+        const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
+        const int k = static_cast<int>((w >> 8) & 3u);
+        edge(w, a.xy[a.c2n[k * T + ca]], a.xy[a.c2n[(k == 2 ? 0 : k + 1) * T + ca]], e - eb);
     }
     __syncthreads();
 
@@ -646,17 +670,20 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     R dtc = static_cast<R>(kInf);
     int clamp = 0, flag = 0;
     if (mine) {
+        const double ex[3] = {p1.x - p0.x, p2.x - p1.x, p0.x - p2.x};
+        const double ey[3] = {p1.y - p0.y, p2.y - p1.y, p0.y - p2.y};
+        const uint32_t sl[3] = {sl0, sl1, sl2};
         R acc0 = R(0), acc1 = R(0), acc2 = R(0), l[3];
         int32_t nb[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const uint32_t sl = ta.slot[k * T + i];
-            const int q = static_cast<int>(sl & 0x7fffu);
-            const bool side_b = (sl & 0x8000u) != 0;
-            const R c0 = side_b ? e_b0[q] : e_a0[q];
-            const R c1 = side_b ? e_b1[q] : e_a1[q];
-            const R c2 = side_b ? e_b2[q] : e_a2[q];
-            l[k] = e_l[q];
+            const int q = static_cast<int>(sl[k] & 0x7fffu);
+            const bool side_b = (sl[k] & 0x8000u) != 0;
+            const R c0 = side_b ? -e_a0[q] : e_a0[q];
+            const R c1 = side_b ? -e_b1[q] : e_a1[q];
+            const R c2 = side_b ? -e_b2[q] : e_a2[q];
+            const R dx = static_cast<R>(ex[k]), dy = static_cast<R>(ey[k]);
+            l[k] = sqrt_(dx * dx + dy * dy);
             nb[k] = 0;
             if ((cfg.n_inflow > 0 || batched) && !side_b)
                 nb[k] = static_cast<int16_t>(ta.edges[eb + q] >> 16);
@@ -666,10 +693,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
                 acc0 = acc0 + c0; acc1 = acc1 + c1; acc2 = acc2 + c2;
             }
         }
-        const double2 p0 = a.xy[n0], p1 = a.xy[n1], p2 = a.xy[n2];
-        const double e0x = p1.x - p0.x, e0y = p1.y - p0.y;
-        const double e1x = p2.x - p1.x, e1y = p2.y - p1.y;
-        const R area = static_cast<R>(0.5 * (e0x * e1y - e0y * e1x));
+        const R area = static_cast<R>(0.5 * (ex[0] * ey[1] - ey[0] * ex[1]));
         const R inradius = div_(R(2) * area, l[0] + l[1] + l[2]);
         const R r = div_(dt, area);
         R hs = h - r * acc0;
@@ -681,9 +705,8 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         }
         R hun, hvn;
         if (hs > hd) {
-            const R nm = a.n[i];
             const R mag = sqrt_(hus * hus + hvs * hvs);
-            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt(hs));
+            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt_(hs));
             hun = div_(hus, d);
             hvn = div_(hvs, d);
         } else {
