@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0     # MI355X HBM3E, public specification
-STEP_KERNEL = "tile_step_kernel"   # the step kernel the default variant launches at 10M cells
+KERNELS = {"tiled": "tile_step_kernel", "cell": "step_kernel"}   # step kernel of each variant
+PROFILED_KERNEL = "tile_step_kernel"   # the kernel whose counters profiles/ holds
 
 
 def algorithmic_bytes(n_cells: int, n_nodes: int, word: int) -> int:
@@ -117,6 +118,76 @@ def bench_ensemble(dtype: str, steps: int, warmup: int, stream) -> dict:
             "bitwise_equal_to_separate": bool(same)}
 
 
+def bench_adjoint(stream, steps: int = 2000) -> dict:
+    """Config 5: the gauge-misfit adjoint (checkpointing forward + reverse sweep) of 2,000 FP64
+    steps on the 250,000-cell calibration setup, against the plain forward run of the same
+    steps with the same replayed dt sequence."""
+    import torch
+
+    import gen
+    import paper_1807_00672_amd as swe
+    from paper_1807_00672_amd import _abi as A
+    from paper_1807_00672_amd.solver import _ptr, _stream_handle
+    case = gen.calibration(steps=steps)
+    ex = case.extra
+    mesh = swe.Mesh(case.xy, case.tri)
+    inv = np.empty(mesh.n_cells, np.int64)
+    inv[mesh.perm] = np.arange(mesh.n_cells)
+    g_mesh = torch.as_tensor(inv[ex["gauges"]], device=mesh.device)
+    # observations: the hidden roughness with the CFL dt, h at the gauges every obs_every steps
+    sv = swe.Solver(mesh, case.z, ex["n_hidden"], case.h, case.hu, case.hv, dtype="f64")
+    dts, obs = [], []
+    for k in range(steps):
+        dts.append(sv.stats()[1]["dt_next"])
+        sv.step()
+        if (k + 1) % ex["obs_every"] == 0:
+            obs.append(sv.device_state()[0][g_mesh].cpu().numpy())
+    calib = swe.Calibration(mesh, np.array(dts), ex["gauges"], np.array(obs), ex["obs_every"],
+                            ckpt_every=ex["ckpt_every"])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def forward():
+        fw = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            fw.run(steps, dt_seq=calib.dt, sync=False, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    def adjoint():
+        sa = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64")
+        out = [torch.empty(mesh.n_cells, dtype=torch.float64, device=mesh.device)
+               for _ in range(5)]
+        grads = A.swe_grads(*[_ptr(o) for o in out])
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            j = A.swe_adjoint(mesh.handle, mesh.dev, sa.params, sa.state, steps, _ptr(calib.dt),
+                              calib.loss, calib.ckpt_every, grads, _ptr(calib.ws),
+                              calib.ws.numel(), _stream_handle(stream))
+            e1.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms, rev_ms = A.swe_adjoint_timings()
+        return e0.elapsed_time(e1) * 1e-3, fwd_ms * 1e-3, rev_ms * 1e-3, j
+
+    forward()
+    adjoint()
+    t_fwd = min(forward() for _ in range(3))
+    runs = sorted(adjoint() for _ in range(3))
+    t_adj, t_ckpt, t_rev, loss = runs[0]
+    return {"n_cells": mesh.n_cells, "steps": steps, "ckpt_every": calib.ckpt_every,
+            "forward_s": t_fwd, "adjoint_s": t_adj, "adjoint_forward_pass_s": t_ckpt,
+            "adjoint_reverse_sweep_s": t_rev,
+            "reverse_over_forward": t_rev / t_fwd, "adjoint_over_forward": t_adj / t_fwd,
+            "loss": loss,
+            "timing": "best of 3 after one warm-up, HIP events on the stream. forward_s: swe_run "
+                      "of the steps with the replayed dt. adjoint_s: the whole swe_adjoint call; "
+                      "its checkpointing forward pass and its reverse sweep (segment recompute "
+                      "and adjoint steps) from swe_adjoint_timings"}
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=10):
     """Plain device copy: achieved GB/s (read + write) as a measured ceiling for context."""
     import torch
@@ -135,27 +206,39 @@ def copy_bandwidth(nbytes=2 << 30, reps=10):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def cpu_baseline(case, budget_s=12.0, threads=None):
-    """The oracle, as it is, on this host: a bounded number of steps of the same workload."""
+def cpu_baseline(case, budget_s=12.0, single_budget_s=8.0):
+    """The oracle, as it is, on this host: a bounded number of steps of the same workload, on
+    all its OpenMP threads (`value`) and on one thread (`single_thread`, the paper's one-core
+    reference point)."""
     import oracle
-    if threads:
-        oracle.set_threads(threads)
-    nth = oracle.threads()
     t0 = time.perf_counter()
     mesh = oracle.Mesh(case.xy, case.tri, case.edge_tag)
     build_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rc, *_ = oracle.run_case(case, steps=1, mesh=mesh)
-    one = time.perf_counter() - t0
-    steps = int(max(1, min(50, budget_s / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    rc, *_ = oracle.run_case(case, steps=steps, mesh=mesh)
-    el = time.perf_counter() - t0
-    assert rc == 0, rc
+
+    def timed(budget, max_steps):
+        t0 = time.perf_counter()
+        rc, *_ = oracle.run_case(case, steps=1, mesh=mesh)
+        one = time.perf_counter() - t0
+        steps = int(max(1, min(max_steps, budget / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        rc, *_ = oracle.run_case(case, steps=steps, mesh=mesh)
+        el = time.perf_counter() - t0
+        assert rc == 0, rc
+        return steps, el
+
+    nth = oracle.threads()
+    steps, el = timed(budget_s, 50)
+    oracle.set_threads(1)
+    try:
+        steps1, el1 = timed(single_budget_s, 20)
+    finally:
+        oracle.set_threads(nth)
     return {"value": case.n_cells * steps / el, "unit": "cell-updates/s", "cores": nth,
             "kind": "oracle",
             "sample": f"{case.n_cells} cells, {steps} steps from the initial state "
-                      f"({el:.1f} s on {nth} OpenMP threads; mesh build {build_s:.1f} s untimed)"}
+                      f"({el:.1f} s on {nth} OpenMP threads; mesh build {build_s:.1f} s untimed)",
+            "single_thread": {"value": case.n_cells * steps1 / el1, "cores": 1,
+                              "sample": f"{steps1} steps ({el1:.1f} s)"}}
 
 
 def main():
@@ -169,6 +252,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the 256-scenario ensemble (0: skip it)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the 250,000-cell adjoint timing (0: skip it)")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="copy: run only a plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -199,7 +284,12 @@ def main():
 
     stream = torch.cuda.Stream()
     results = {}
+    tuning = {}
     for dt in args.dtypes.split(","):
+        # the autotuner picks the step variant and workgroup order that SWE_AUTO then runs
+        tuning[dt] = swe.tune.tune(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt,
+                                   steps=20)
+        print(f"# tuned {dt}: {tuning[dt]}", file=sys.stderr, flush=True)
         solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt)
         ms, rc, st = time_gpu(solver, args.steps, args.warmup, stream)
         if rc != swe.SWE_OK or st["steps"] != args.warmup + args.steps:
@@ -212,7 +302,9 @@ def main():
             "ms_per_step": ms / args.steps,
             "alg_bytes_per_step": alg,
             "achieved_GBps": alg / per_step_s / 1e9,
-            "traffic": load_traffic(dt, case.n_cells),
+            "kernel": KERNELS[tuning[dt]["variant"]],
+            "traffic": (load_traffic(dt, case.n_cells)
+                        if KERNELS[tuning[dt]["variant"]] == PROFILED_KERNEL else None),
             "t_end_state": st["t"],
         }
         print(f"# {dt}: {ms / args.steps:.4f} ms/step, {results[dt]['value'] / 1e9:.2f} G "
@@ -231,6 +323,15 @@ def main():
                   f"{e['separate_cell_updates_per_s'] / 1e9:.2f} G/s (x{e['speedup']:.2f}), "
                   f"bitwise equal {e['bitwise_equal_to_separate']}", file=sys.stderr, flush=True)
             torch.cuda.empty_cache()
+
+    adjoint = {}
+    if args.adjoint_steps > 0 and args.size == "full":
+        adjoint = bench_adjoint(stream, args.adjoint_steps)
+        print(f"# adjoint: {adjoint['n_cells']} cells, {adjoint['steps']} steps: forward "
+              f"{adjoint['forward_s']:.3f} s, adjoint {adjoint['adjoint_s']:.3f} s "
+              f"(x{adjoint['adjoint_over_forward']:.2f}; reverse sweep "
+              f"x{adjoint['reverse_over_forward']:.2f})", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
 
     copy_gbps = copy_bandwidth()
     main_dt = "f64" if "f64" in results else next(iter(results))
@@ -253,12 +354,14 @@ def main():
                    "n_cells": case.n_cells, "n_nodes": case.n_nodes, "parallelism": "none"},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBPS,
-                     "traffic": r["traffic"], "kernel": STEP_KERNEL,
+                     "traffic": r["traffic"], "kernel": r["kernel"],
                      "timed": "whole step (step kernel + dt fold kernel) per step",
                      "alg_bytes_per_launch": r["alg_bytes_per_step"]},
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "t_end_state"}
                      for k, v in results.items()},
+        "tuning": tuning,
         "ensemble": ensemble,
+        "adjoint": adjoint,
         "copy_GBps_measured": copy_gbps,
         "device": torch.cuda.get_device_name(0),
     }

@@ -333,6 +333,45 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
                     const swe_loss *loss, int32_t ckpt_every, swe_grads *out, double *loss_out,
                     void *ws, int64_t ws_bytes, void *stream);
 
+/* Device time of this thread's last completed swe_adjoint call, in milliseconds, from HIP
+ * events on its stream: the checkpointing forward pass (with the loss) and the reverse sweep
+ * (segment recompute and adjoint steps).  Waits for that call's work to finish.
+ * Errors: SWE_EINVAL (no completed call on this thread), SWE_EDEVICE. */
+int32_t swe_adjoint_timings(double *forward_ms, double *reverse_ms);
+
+/* ------------------------------------------------------------------ launch tuning */
+
+/* Timings of the step variants on one mesh (milliseconds per step, 0: not run), and the
+ * fastest.  Order of ms_per_step: per-cell + XCD remap, per-cell, tiled + XCD remap, tiled. */
+typedef struct swe_tune_result {
+    int32_t variant;         /* SWE_CELL or SWE_TILED; SWE_AUTO: nothing recorded */
+    int32_t xcd_remap;       /* 1: XCD-contiguous tile order, 0: hardware order */
+    double ms_per_step[4];
+} swe_tune_result;
+
+/*
+ * Autotuning of the step launch (section 2.3's loops as GPU launches; the paper leaves the
+ * mapping to the hardware open).  Times each variant x workgroup order for n_steps >= 2 steps
+ * (graph replay, after 4 warm-up steps each) in three interleaved rounds, keeping each one's
+ * best, on the initialised state s, which it advances by 16 + 12 n_steps steps at most (pass a
+ * scratch state, or re-initialise afterwards), and records the fastest for this device, the
+ * params' dtype and the size class floor(log2 n_cells) in a process-wide table.  SWE_AUTO then
+ * launches that choice (SWE_NO_XCD_REMAP still forces the hardware order).  All candidates
+ * compute the same bits.  Synchronises the stream.  *out (host) receives the timings.
+ * Errors: SWE_EINVAL (bad argument, or the state stopped while tuning), SWE_EDEVICE, and any
+ * status of swe_run.
+ */
+int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                 swe_state *s, int32_t n_steps, swe_tune_result *out, void *stream);
+
+/* The recorded choice for (device, dtype, size class of n_cells); variant SWE_AUTO if none.
+ * Errors: SWE_EINVAL. */
+int32_t swe_tune_get(int32_t device, int32_t dtype, int64_t n_cells, swe_tune_result *out);
+
+/* Record a choice (e.g. one saved from an earlier process); variant SWE_AUTO erases it.
+ * Errors: SWE_EINVAL (unknown variant, xcd_remap not 0 or 1). */
+int32_t swe_tune_set(int32_t device, int32_t dtype, int64_t n_cells, const swe_tune_result *r);
+
 /* ------------------------------------------------------------------ test hook */
 
 /*

@@ -11,10 +11,11 @@ from ._abi import (  # noqa: F401
     swe_mesh_export, swe_mesh_info, swe_mesh_info_get, swe_params, swe_read_stats, swe_run,
     swe_run_stats, swe_state, swe_state_init, swe_step, swe_workspace_bytes, swe_batch_create,
     swe_batch_destroy, swe_batch_export, swe_batch_info_get, swe_batch_run,
-    swe_batch_state_init, swe_batch_workspace_bytes, swe_adjoint, swe_adjoint_workspace_bytes,
-    swe_grads, swe_loss)
+    swe_batch_state_init, swe_batch_workspace_bytes, swe_adjoint, swe_adjoint_timings, swe_adjoint_workspace_bytes,
+    swe_grads, swe_loss, swe_tune, swe_tune_get, swe_tune_result, swe_tune_set)
 from .solver import Batch, BatchSolver, Mesh, Solver  # noqa: F401
 from .adjoint import AdjointLoss, Calibration  # noqa: F401
+from . import tune  # noqa: F401
 
 
 def require_gpu() -> None:

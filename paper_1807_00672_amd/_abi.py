@@ -93,6 +93,16 @@ SWE_BARR_CELL_OFF, SWE_BARR_NODE_OFF, SWE_BARR_TILE_START, SWE_BARR_TILE_SCEN, \
     SWE_BARR_SCEN_TILE_OFF = range(16, 21)
 
 
+class swe_tune_result(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("xcd_remap", C.c_int32),
+                ("ms_per_step", C.c_double * 4)]
+
+    def as_dict(self):
+        return {"variant": {SWE_AUTO: "auto", SWE_CELL: "cell", SWE_TILED: "tiled"}[self.variant],
+                "xcd_remap": bool(self.xcd_remap),
+                "ms_per_step": {k: self.ms_per_step[i] for i, k in
+                                enumerate(("cell+remap", "cell", "tiled+remap", "tiled"))}}
+
 class swe_batch_info(C.Structure):
     _fields_ = [("n_scenarios", C.c_int32), ("max_inflow_segments", C.c_int32),
                 ("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("n_tiles", C.c_int64),
@@ -126,7 +136,8 @@ EXPORTS = [
     "swe_workspace_bytes", "swe_state_init", "swe_step", "swe_run", "swe_read_stats",
     "swe_last_error", "swe_flux_eval", "swe_batch_create", "swe_batch_info_get",
     "swe_batch_export", "swe_batch_destroy", "swe_batch_workspace_bytes", "swe_batch_state_init",
-    "swe_batch_run", "swe_adjoint_workspace_bytes", "swe_adjoint",
+    "swe_batch_run", "swe_adjoint_workspace_bytes", "swe_adjoint", "swe_adjoint_timings", "swe_tune", "swe_tune_get",
+    "swe_tune_set",
 ]
 
 
@@ -152,6 +163,11 @@ def _load():
     L.swe_last_error.argtypes = []
     L.swe_last_error.restype = C.c_char_p
     L.swe_flux_eval.argtypes = [i32, i64, dbl, dbl] + [vp] * 12 + [vp]
+    L.swe_adjoint_timings.argtypes = [C.POINTER(dbl), C.POINTER(dbl)]
+    L.swe_tune.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
+                           C.POINTER(swe_state), i32, C.POINTER(swe_tune_result), vp]
+    L.swe_tune_get.argtypes = [i32, i32, i64, C.POINTER(swe_tune_result)]
+    L.swe_tune_set.argtypes = [i32, i32, i64, C.POINTER(swe_tune_result)]
     L.swe_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
     L.swe_batch_info_get.argtypes = [vp, C.POINTER(swe_batch_info)]
     L.swe_batch_export.argtypes = [vp, i32, vp, i64]
@@ -312,3 +328,27 @@ def swe_adjoint(mesh, dm, params, state, n_steps, dt_seq, loss, ckpt_every, grad
                            C.byref(loss), ckpt_every, C.byref(grads), C.byref(j), ws, ws_bytes,
                            stream), "swe_adjoint")
     return j.value
+
+
+def swe_tune(mesh, dm, params, state, n_steps: int, stream=None) -> swe_tune_result:
+    out = swe_tune_result()
+    _check(lib.swe_tune(mesh, C.byref(dm), C.byref(params), C.byref(state), n_steps,
+                        C.byref(out), stream), "swe_tune")
+    return out
+
+
+def swe_tune_get(device: int, dtype: int, n_cells: int) -> swe_tune_result:
+    out = swe_tune_result()
+    _check(lib.swe_tune_get(device, dtype, n_cells, C.byref(out)), "swe_tune_get")
+    return out
+
+
+def swe_tune_set(device: int, dtype: int, n_cells: int, r: swe_tune_result) -> None:
+    _check(lib.swe_tune_set(device, dtype, n_cells, C.byref(r)), "swe_tune_set")
+
+
+def swe_adjoint_timings() -> tuple[float, float]:
+    """(forward_ms, reverse_ms) of this thread's last swe_adjoint call."""
+    f, r = C.c_double(), C.c_double()
+    _check(lib.swe_adjoint_timings(C.byref(f), C.byref(r)), "swe_adjoint_timings")
+    return f.value, r.value

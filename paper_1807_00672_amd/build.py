@@ -12,8 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libswe.so")
 
-SOURCES = ["swe_mesh.cpp", "swe_api.cpp", "swe_batch.cpp", "swe_kernels.hip", "swe_adjoint.hip"]
-HEADERS = ["swe_internal.h"]
+SOURCES = ["swe_mesh.cpp", "swe_api.cpp", "swe_batch.cpp", "swe_tune.cpp", "swe_kernels.hip",
+           "swe_adjoint.hip"]
+HEADERS = ["swe_internal.h", "swe_device_math.h"]
 
 # Contraction off: every product and sum rounds on its own, in the order the sources write
 # it.  Packed FP32 instructions are disabled for every kernel.

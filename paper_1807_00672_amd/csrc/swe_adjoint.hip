@@ -389,6 +389,28 @@ int32_t ahip(hipError_t e, const char *where)
     return afail(SWE_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// Events around the two passes of this thread's last swe_adjoint call.
+struct Timing {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool recorded = false;
+    hipError_t create()
+    {
+        for (hipEvent_t &e : ev)
+            if (hipError_t r = hipEventCreate(&e)) return r;
+        return hipSuccess;
+    }
+    void reset()
+    {
+        for (hipEvent_t &e : ev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+        recorded = false;
+    }
+    // no destructor: the runtime may be gone when thread-local objects die at exit
+};
+thread_local Timing g_timing;
+
 }  // namespace
 
 extern "C" {
@@ -428,7 +450,14 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     const AdjLayout L = adj_layout(T, n_steps, K);
     if (ws_bytes < static_cast<int64_t>(L.total))
         return afail(SWE_EINVAL, "swe_adjoint: workspace needs " + std::to_string(L.total) + " bytes");
+    const TileLayout *tl = nullptr;   // the step kernel of the forward and recompute passes
+    int remap = 1;
+    if (int32_t rc = choose_variant(mesh, dm, p, &tl, &remap, W)) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    Timing &tm = g_timing;
+    tm.reset();
+    if (int32_t rc = ahip(tm.create(), W)) return rc;
+    if (int32_t rc = ahip(hipEventRecord(tm.ev[0], st), W)) return rc;
     char *base = static_cast<char *>(ws);
     auto D = [&](size_t off) { return reinterpret_cast<double *>(base + off); };
     const size_t S = static_cast<size_t>(T);
@@ -481,7 +510,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     int cur = 0;
     for (int64_t nstep = 0; nstep < n_steps; ++nstep) {
         if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, fw, cur, dt_seq,
-                                                                  n_steps, st, nullptr)), W))
+                                                                  n_steps, st, tl, nullptr, remap)), W))
             return rc;
         cur ^= 1;
         const double *hc = static_cast<const double *>(fw.h[cur]);
@@ -496,6 +525,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     }
 
     // reverse pass
+    if (int32_t rc = ahip(hipEventRecord(tm.ev[1], st), W)) return rc;
     AdjArgs a;
     memset(&a, 0, sizeof(a));
     a.T = T;
@@ -528,8 +558,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
             swe_state v = view(sg(q, 0), sg(q, 1), sg(q, 2), sg(q + 1, 0), sg(q + 1, 1), sg(q + 1, 2));
             double *ustar[3] = {ss(q, 0), ss(q, 1), ss(q, 2)};
             if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, v, 0, dt_seq + s0,
-                                                                      s1 - s0, st, nullptr, nullptr,
-                                                                      1, ustar)), W))
+                                                                      s1 - s0, st, tl, nullptr,
+                                                                      remap, ustar)), W))
                 return rc;
         }
         for (int64_t nstep = s1 - 1; nstep >= s0; --nstep) {
@@ -547,11 +577,28 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         if (int32_t rc = ahip(hipGetLastError(), W)) return rc;
     }
     if (int32_t rc = copy3(out->dh, out->dhu, out->dhv, lam, lam + S, lam + 2 * S)) return rc;
+    if (int32_t rc = ahip(hipEventRecord(tm.ev[2], st), W)) return rc;
+    tm.recorded = true;
     if (loss_out) {
         if (int32_t rc = ahip(hipMemcpyAsync(loss_out, lossd, 8, hipMemcpyDeviceToHost, st), W)) return rc;
         if (int32_t rc = ahip(hipStreamSynchronize(st), W)) return rc;
     }
     return ahip(hipGetLastError(), W);
+}
+
+int32_t swe_adjoint_timings(double *forward_ms, double *reverse_ms)
+{
+    if (!forward_ms || !reverse_ms) return afail(SWE_EINVAL, "swe_adjoint_timings: null argument");
+    Timing &tm = g_timing;
+    if (!tm.recorded) return afail(SWE_EINVAL, "swe_adjoint_timings: no completed swe_adjoint call");
+    const char *W = "swe_adjoint_timings";
+    if (int32_t rc = ahip(hipEventSynchronize(tm.ev[2]), W)) return rc;
+    float f = 0.0f, r = 0.0f;
+    if (int32_t rc = ahip(hipEventElapsedTime(&f, tm.ev[0], tm.ev[1]), W)) return rc;
+    if (int32_t rc = ahip(hipEventElapsedTime(&r, tm.ev[1], tm.ev[2]), W)) return rc;
+    *forward_ms = f;
+    *reverse_ms = r;
+    return SWE_OK;
 }
 
 }  // extern "C"

@@ -92,52 +92,13 @@ struct DeviceLds {
 };
 DeviceLds g_lds[64];
 
-// Pick the step kernel: SWE_CELL the per-cell one, SWE_TILED the tiled one (an error when it
-// cannot run), SWE_AUTO the tiled one when the device mesh carries the tile arrays and a
-// tile's LDS fits the device, else the per-cell one.
-int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
-                       const TileLayout **out, const char *where)
-{
-    *out = nullptr;
-    const std::string w(where);
-    if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
-        return fail(SWE_EINVAL, w + ": unknown variant");
-    if (p->flags & ~SWE_NO_XCD_REMAP) return fail(SWE_EINVAL, w + ": unknown flags");
-    if (p->variant == SWE_CELL) return SWE_OK;
-    const bool auto_ = p->variant == SWE_AUTO;
-    const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot;
-    if (!have) return auto_ ? SWE_OK : fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
-    int dev = 0;
-    if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;
-    if (dev < 0 || dev >= 64) return fail(SWE_EUNSUPPORTED, w + ": device index beyond 63");
-    DeviceLds &d = g_lds[dev];
-    if (d.limit < 0) {
-        int lim = 0;
-        if (int32_t rc = check_hip(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), where))
-            return rc;
-        d.limit = lim;
-    }
-    const size_t need = tile_lds_bytes_for(p->dtype, mesh->tiles);
-    if (need > static_cast<size_t>(d.limit) && auto_) return SWE_OK;
-    if (need > static_cast<size_t>(d.limit))
-        return fail(SWE_EUNSUPPORTED, w + ": tile needs " + std::to_string(need) +
-                                          " bytes of LDS, device allows " + std::to_string(d.limit));
-    if (need > 65536 && d.prepared < need) {
-        if (int32_t rc = check_hip(prepare_tile_kernels(static_cast<size_t>(d.limit)), where)) return rc;
-        d.prepared = static_cast<size_t>(d.limit);
-    }
-    *out = &mesh->tiles;
-    return SWE_OK;
-}
-
-int remap_of(const swe_params *p) { return (p->flags & SWE_NO_XCD_REMAP) ? 0 : 1; }
 
 // Two steps (even and odd buffer) captured once as a graph and replayed by swe_run; the
 // launch arguments it bakes in form its key.
 struct GraphKey {
     swe_dev_mesh dm;
     double g, courant, h_dry;
-    int32_t dtype, variant, n_inflow, cur, flags;
+    int32_t dtype, variant, n_inflow, cur, remap;
     double q[SWE_MAX_INFLOW];
     void *h[2], *hu[2], *hv[2];
     const void *z, *n;
@@ -162,14 +123,14 @@ struct GraphCache {
 hipStream_t g_capture[64] = {};
 
 GraphKey make_key(const swe_dev_mesh *dm, const swe_params *p, const swe_state *s,
-                  const double *dt_seq, int64_t n_seq, const TileLayout *tl, int dev)
+                  const double *dt_seq, int64_t n_seq, const TileLayout *tl, int remap, int dev)
 {
     GraphKey k;
     memset(&k, 0, sizeof(k));
     k.dm = *dm;
     k.g = p->g; k.courant = p->courant; k.h_dry = p->h_dry;
     k.dtype = p->dtype; k.variant = p->variant; k.n_inflow = p->n_inflow; k.cur = s->cur;
-    k.flags = p->flags;
+    k.remap = remap;
     for (int i = 0; i < p->n_inflow; ++i) k.q[i] = p->inflow_q[i];
     for (int b = 0; b < 2; ++b) { k.h[b] = s->h[b]; k.hu[b] = s->hu[b]; k.hv[b] = s->hv[b]; }
     k.z = s->z; k.n = s->n; k.ctrl = s->ctrl; k.work = s->work;
@@ -184,11 +145,11 @@ GraphKey make_key(const swe_dev_mesh *dm, const swe_params *p, const swe_state *
 // (nullptr if graphs are unavailable: the caller then launches step by step).
 hipGraphExec_t two_step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
                               const StepConfig &cfg, const swe_state *s, const double *dt_seq,
-                              int64_t n_seq, const TileLayout *tl)
+                              int64_t n_seq, const TileLayout *tl, int remap)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    const GraphKey key = make_key(dm, p, s, dt_seq, n_seq, tl, dev);
+    const GraphKey key = make_key(dm, p, s, dt_seq, n_seq, tl, remap, dev);
     swe_mesh *m = const_cast<swe_mesh *>(mesh);
     GraphCache *gc = static_cast<GraphCache *>(m->graph);
     if (gc && memcmp(&gc->key, &key, sizeof(key)) == 0) return gc->exec;
@@ -200,9 +161,8 @@ hipGraphExec_t two_step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, cons
     }
     hipStream_t cs = g_capture[dev];
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    int e0 = launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_seq, cs, tl, nullptr, remap_of(p));
-    int e1 = launch_step(p->dtype, *dm, cfg, *s, 1 - s->cur, dt_seq, n_seq, cs, tl, nullptr,
-                         remap_of(p));
+    int e0 = launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_seq, cs, tl, nullptr, remap);
+    int e1 = launch_step(p->dtype, *dm, cfg, *s, 1 - s->cur, dt_seq, n_seq, cs, tl, nullptr, remap);
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     if (e0 != hipSuccess || e1 != hipSuccess || ee != hipSuccess || !graph) {
@@ -234,6 +194,54 @@ int32_t status_code(int32_t bits)
 }  // namespace
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+// Pick the step kernel: SWE_CELL the per-cell one, SWE_TILED the tiled one (an error when it
+// cannot run), SWE_AUTO the tiled one when the device mesh carries the tile arrays and a
+// tile's LDS fits the device, else the per-cell one.
+int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                       const TileLayout **out, int *remap, const char *where)
+{
+    *out = nullptr;
+    *remap = (p->flags & SWE_NO_XCD_REMAP) ? 0 : 1;
+    const std::string w(where);
+    if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
+        return fail(SWE_EINVAL, w + ": unknown variant");
+    if (p->flags & ~SWE_NO_XCD_REMAP) return fail(SWE_EINVAL, w + ": unknown flags");
+    int variant = p->variant;
+    if (variant == SWE_AUTO) {
+        // a swe_tune result for this device, precision and size class decides, if there is one
+        int dev = 0, tv = SWE_AUTO, trm = 1;
+        if (hipGetDevice(&dev) == hipSuccess && tuned_choice(dev, p->dtype, mesh->info.n_cells, &tv, &trm)) {
+            if (!(p->flags & SWE_NO_XCD_REMAP)) *remap = trm;
+            if (tv == SWE_CELL) return SWE_OK;
+        }
+    }
+    if (variant == SWE_CELL) return SWE_OK;
+    const bool auto_ = variant == SWE_AUTO;
+    const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot;
+    if (!have) return auto_ ? SWE_OK : fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
+    int dev = 0;
+    if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;
+    if (dev < 0 || dev >= 64) return fail(SWE_EUNSUPPORTED, w + ": device index beyond 63");
+    DeviceLds &d = g_lds[dev];
+    if (d.limit < 0) {
+        int lim = 0;
+        if (int32_t rc = check_hip(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), where))
+            return rc;
+        d.limit = lim;
+    }
+    const size_t need = tile_lds_bytes_for(p->dtype, mesh->tiles);
+    if (need > static_cast<size_t>(d.limit) && auto_) return SWE_OK;
+    if (need > static_cast<size_t>(d.limit))
+        return fail(SWE_EUNSUPPORTED, w + ": tile needs " + std::to_string(need) +
+                                          " bytes of LDS, device allows " + std::to_string(d.limit));
+    if (need > 65536 && d.prepared < need) {
+        if (int32_t rc = check_hip(prepare_tile_kernels(static_cast<size_t>(d.limit)), where)) return rc;
+        d.prepared = static_cast<size_t>(d.limit);
+    }
+    *out = &mesh->tiles;
+    return SWE_OK;
+}
 
 }  // namespace swe
 
@@ -267,9 +275,10 @@ int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
     if (int32_t rc = check_call(mesh, dm, p, s, "swe_step")) return rc;
     const StepConfig cfg = make_config(mesh, p);
     const TileLayout *tl = nullptr;
-    if (int32_t rc = choose_variant(mesh, dm, p, &tl, "swe_step")) return rc;
+    int remap = 1;
+    if (int32_t rc = choose_variant(mesh, dm, p, &tl, &remap, "swe_step")) return rc;
     if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, nullptr, 0, stream, tl, nullptr,
-                                           remap_of(p)),
+                                           remap),
                                "swe_step"))
         return rc;
     s->cur ^= 1;
@@ -312,11 +321,12 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
     if (dt_seq && n_steps < 1) return fail(SWE_EINVAL, "swe_run: dt_seq needs n_steps >= 1");
     const StepConfig cfg = make_config(mesh, p);
     const TileLayout *tl = nullptr;
-    if (int32_t rc = choose_variant(mesh, dm, p, &tl, "swe_run")) return rc;
+    int remap = 1;
+    if (int32_t rc = choose_variant(mesh, dm, p, &tl, &remap, "swe_run")) return rc;
     if (int32_t rc = check_hip(launch_run_begin(*s, dt_seq, stream), "swe_run")) return rc;
     int64_t k = 0;
     if (n_steps >= 4) {
-        if (hipGraphExec_t ex = two_step_graph(mesh, dm, p, cfg, s, dt_seq, n_steps, tl)) {
+        if (hipGraphExec_t ex = two_step_graph(mesh, dm, p, cfg, s, dt_seq, n_steps, tl, remap)) {
             for (; k + 2 <= n_steps; k += 2)
                 if (int32_t rc = check_hip(hipGraphLaunch(ex, static_cast<hipStream_t>(stream)),
                                            "swe_run"))
@@ -325,7 +335,7 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
     }
     for (; k < n_steps; ++k) {
         if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_steps,
-                                               stream, tl, nullptr, remap_of(p)),
+                                               stream, tl, nullptr, remap),
                                    "swe_run"))
             return rc;
         s->cur ^= 1;

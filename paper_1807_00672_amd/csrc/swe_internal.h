@@ -112,7 +112,7 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
                 const BatchLaunch *batch = nullptr, int remap = 1,
-                double *const *ustar = nullptr);   // FP64 per-cell kernel: also write U*
+                double *const *ustar = nullptr);   // FP64: also write U* (before clamp)
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);
 int prepare_tile_kernels(size_t max_lds);   // allow dynamic LDS up to max_lds bytes
 int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);
@@ -122,6 +122,15 @@ int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *h
                      const void *ny, void *f, void *p, void *stream);
 
 void set_error(const std::string &msg);
+
+// The step kernel a launch uses (swe_api.cpp): *tl = the mesh's tile layout for the tiled
+// kernel, nullptr for the per-cell one; *remap = 1 for the XCD-contiguous workgroup order.
+int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                       const TileLayout **tl, int *remap, const char *where);
+
+// swe_tune's result for (device, dtype, size class of n_cells), if one was recorded: the
+// variant (SWE_CELL or SWE_TILED) and XCD order (1 remapped) that ran fastest (swe_tune.cpp).
+bool tuned_choice(int device, int dtype, int64_t n_cells, int *variant, int *remap);
 
 }  // namespace swe
 

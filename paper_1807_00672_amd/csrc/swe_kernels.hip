@@ -699,6 +699,11 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
+        if (a.us_h) {
+            a.us_h[i] = hs;
+            a.us_hu[i] = hus;
+            a.us_hv[i] = hvs;
+        }
         if (hs < R(0)) {
             clamp = 1;
             hs = R(0);
@@ -1071,6 +1076,11 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
         if (dtype == SWE_F64) {
             TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
             ta.s.part = part;
+            if (ustar) {
+                ta.s.us_h = ustar[0];
+                ta.s.us_hu = ustar[1];
+                ta.s.us_hv = ustar[2];
+            }
             tile_step_kernel<double><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         } else {
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);

@@ -1,0 +1,97 @@
+"""Launch autotuning (swe_tune): which step kernel variant and workgroup order run fastest for
+a mesh size class on this device, remembered for SWE_AUTO; optional persistence as JSON keyed by
+device name, precision and size class, and a choice between Morton and input cell order."""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import _abi as A
+from .solver import Mesh, Solver
+
+_DT = {"f64": A.SWE_F64, "f32": A.SWE_F32}
+_VAR = {"auto": A.SWE_AUTO, "cell": A.SWE_CELL, "tiled": A.SWE_TILED}
+_recorded: dict[tuple[str, int], dict] = {}   # (dtype, size class) -> result, this process
+
+
+def size_class(n_cells: int) -> int:
+    return int(n_cells).bit_length() - 1
+
+
+def _device_index(mesh: Mesh) -> int:
+    return mesh.device.index if mesh.device.index is not None else torch.cuda.current_device()
+
+
+def tune(mesh: Mesh, z, n, h, hu, hv, dtype: str = "f64", steps: int = 20, **solver_kw) -> dict:
+    """Time every variant x workgroup order on a scratch state of this setup (the caller's
+    arrays are not touched) and record the fastest for SWE_AUTO.  Returns the timings."""
+    s = Solver(mesh, z, n, h, hu, hv, dtype=dtype, **solver_kw)
+    with torch.cuda.device(mesh.device):
+        r = A.swe_tune(mesh.handle, mesh.dev, s.params, s.state, steps, None).as_dict()
+    _recorded[(dtype, size_class(mesh.n_cells))] = r
+    return r
+
+
+def tuning(dtype: str, n_cells: int, device: int | None = None) -> dict | None:
+    """The recorded choice for this device, precision and size class, or None."""
+    dev = torch.cuda.current_device() if device is None else device
+    r = A.swe_tune_get(dev, _DT[dtype], n_cells).as_dict()
+    return None if r["variant"] == "auto" else r
+
+
+def forget(dtype: str, n_cells: int, device: int | None = None) -> None:
+    dev = torch.cuda.current_device() if device is None else device
+    A.swe_tune_set(dev, _DT[dtype], n_cells, A.swe_tune_result())
+
+
+def save(path: str) -> None:
+    """Add this process's tuning results to a JSON file under this device's name."""
+    name = torch.cuda.get_device_name(torch.cuda.current_device())
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    entries = data.setdefault(name, {})
+    for (dt, cls), r in _recorded.items():
+        entries[f"{dt}:{cls}"] = {"variant": r["variant"], "xcd_remap": r["xcd_remap"],
+                                  "ms_per_step": r["ms_per_step"]}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
+def load(path: str) -> int:
+    """Record the choices a JSON file holds for this device's name; returns how many."""
+    name = torch.cuda.get_device_name(torch.cuda.current_device())
+    with open(path) as f:
+        entries = json.load(f).get(name, {})
+    dev = torch.cuda.current_device()
+    for key, e in entries.items():
+        dt, cls = key.split(":")
+        r = A.swe_tune_result()
+        r.variant = _VAR[e["variant"]]
+        r.xcd_remap = 1 if e["xcd_remap"] else 0
+        A.swe_tune_set(dev, _DT[dt], 1 << int(cls), r)
+    return len(entries)
+
+
+def tune_order(xy, tri, z, n, h, hu, hv, edge_tag=None, dtype: str = "f64",
+               steps: int = 20, **solver_kw) -> tuple[bool, dict]:
+    """Build the mesh in Morton and in input cell order, tune both, and return (morton?, the
+    timings of each order).  The faster order's best variant stays recorded."""
+    res = {}
+    for morton in (True, False):
+        m = Mesh(xy, tri, edge_tag, morton=morton)
+        res["morton" if morton else "input"] = tune(m, z, n, h, hu, hv, dtype, steps, **solver_kw)
+    best = {k: min(v["ms_per_step"][x] for x in v["ms_per_step"] if v["ms_per_step"][x] > 0)
+            for k, v in res.items()}
+    morton = best["morton"] <= best["input"]
+    if morton:   # the input-order run was tuned last: record the Morton choice again
+        r = res["morton"]
+        rr = A.swe_tune_result()
+        rr.variant = _VAR[r["variant"]]
+        rr.xcd_remap = 1 if r["xcd_remap"] else 0
+        A.swe_tune_set(torch.cuda.current_device(), _DT[dtype], len(tri), rr)
+        _recorded[(dtype, size_class(len(tri)))] = r
+    return morton, res

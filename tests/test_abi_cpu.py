@@ -231,3 +231,23 @@ def test_batch_concatenates_scenarios_without_straddling_tiles():
             swe.swe_batch_create([])
     finally:
         swe.swe_batch_destroy(b)
+
+
+def test_tuning_table_records_erases_and_rejects_without_a_device():
+    r = swe.swe_tune_result()
+    r.variant, r.xcd_remap = swe.SWE_CELL, 0
+    swe.swe_tune_set(5, swe.SWE_F32, 1000, r)
+    got = swe.swe_tune_get(5, swe.SWE_F32, 1023)    # same size class floor(log2 n) = 9
+    assert got.variant == swe.SWE_CELL and got.xcd_remap == 0
+    assert swe.swe_tune_get(5, swe.SWE_F32, 1024).variant == swe.SWE_AUTO   # class 10
+    assert swe.swe_tune_get(5, swe.SWE_F64, 1000).variant == swe.SWE_AUTO   # other precision
+    assert swe.swe_tune_get(4, swe.SWE_F32, 1000).variant == swe.SWE_AUTO   # other device
+    swe.swe_tune_set(5, swe.SWE_F32, 600, swe.swe_tune_result())           # SWE_AUTO erases
+    assert swe.swe_tune_get(5, swe.SWE_F32, 1000).variant == swe.SWE_AUTO
+    bad = swe.swe_tune_result()
+    bad.variant = 9
+    assert swe.lib.swe_tune_set(0, swe.SWE_F64, 10, C.byref(bad)) == swe.SWE_EINVAL
+    bad.variant, bad.xcd_remap = swe.SWE_TILED, 2
+    assert swe.lib.swe_tune_set(0, swe.SWE_F64, 10, C.byref(bad)) == swe.SWE_EINVAL
+    assert swe.lib.swe_tune_get(0, 7, 10, C.byref(r)) == swe.SWE_EINVAL
+    assert swe.lib.swe_tune(None, None, None, None, 10, None, None) == swe.SWE_EINVAL

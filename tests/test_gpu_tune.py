@@ -1,0 +1,69 @@
+"""Launch autotuning: swe_tune times the step variants and workgroup orders, records the
+fastest for SWE_AUTO, and never changes results (every candidate computes the same bits)."""
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tuning_records_a_choice_that_auto_follows_with_identical_results(gpu, dtype):
+    swe = gpu
+    case = gen.small(3)
+    mesh = swe.Mesh(case.xy, case.tri)
+    swe.tune.forget(dtype, mesh.n_cells)
+    before = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype)
+    rc0, st0 = before.run(60)
+    r = swe.tune.tune(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype, steps=6)
+    print(f"{dtype} {mesh.n_cells} cells: {r}")
+    ms = r["ms_per_step"]
+    assert r["variant"] in ("cell", "tiled") and all(v > 0 for v in ms.values())
+    best = min(ms, key=ms.get)
+    assert best.startswith(r["variant"]) and r["xcd_remap"] == best.endswith("+remap")
+    got = swe.tune.tuning(dtype, mesh.n_cells)
+    assert got["variant"] == r["variant"] and got["xcd_remap"] == r["xcd_remap"]
+    after = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype)
+    rc1, st1 = after.run(60)
+    assert rc0 == rc1 == swe.SWE_OK and st0["t"] == st1["t"] and st0["steps"] == st1["steps"]
+    for a, b in zip(before.numpy_state(), after.numpy_state()):
+        assert np.array_equal(a, b)
+    # the opposite choice, recorded by hand, gives the same bits as well
+    other = swe.swe_tune_result()
+    other.variant = swe.SWE_CELL if r["variant"] == "tiled" else swe.SWE_TILED
+    other.xcd_remap = 0 if r["xcd_remap"] else 1
+    code = {"f64": swe.SWE_F64, "f32": swe.SWE_F32}[dtype]
+    swe.swe_tune_set(mesh.device.index, code, mesh.n_cells, other)
+    third = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype)
+    rc2, st2 = third.run(60)
+    assert rc2 == swe.SWE_OK and st2["t"] == st0["t"]
+    for a, b in zip(before.numpy_state(), third.numpy_state()):
+        assert np.array_equal(a, b)
+    swe.tune.forget(dtype, mesh.n_cells)
+
+
+def test_tuning_results_persist_through_a_json_file(gpu, tmp_path):
+    swe = gpu
+    case = gen.small(1)
+    mesh = swe.Mesh(case.xy, case.tri)
+    r = swe.tune.tune(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64", steps=4)
+    path = str(tmp_path / "tuning.json")
+    swe.tune.save(path)
+    swe.tune.forget("f64", mesh.n_cells)
+    assert swe.tune.tuning("f64", mesh.n_cells) is None
+    assert swe.tune.load(path) >= 1
+    got = swe.tune.tuning("f64", mesh.n_cells)
+    assert got["variant"] == r["variant"] and got["xcd_remap"] == r["xcd_remap"]
+    swe.tune.forget("f64", mesh.n_cells)
+
+
+def test_tuning_a_stopped_state_is_an_error(gpu):
+    swe = gpu
+    case = gen.small(1)
+    mesh = swe.Mesh(case.xy, case.tri)
+    s = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64", t_end=1e-9)
+    s.run(1)
+    with pytest.raises(swe.SweError):
+        swe.swe_tune(mesh.handle, mesh.dev, s.params, s.state, 4)
+    assert swe.tune.tuning("f64", mesh.n_cells) is None
