@@ -118,6 +118,72 @@ def bench_ensemble(dtype: str, steps: int, warmup: int, stream) -> dict:
             "bitwise_equal_to_separate": bool(same)}
 
 
+def bench_shards(mesh, case, stream, parts: int = 8, steps: int = 100) -> dict:
+    """One GPU's share of the 10M-cell mesh split over `parts` devices: a contiguous Morton
+    range of T/parts cells with its halo, stepped on its own (the kernel at its real shape);
+    and all the shards stepped in turn on this device with their halo exchanges (pack, copy,
+    unpack) and the dt all-reduce, FP64."""
+    import torch
+
+    import paper_1807_00672_amd as swe
+    sh = swe.ShardedSolver(mesh, parts, case.z, case.n, case.h, case.hu, case.hv, dtype="f64")
+    q = parts // 2
+    m = sh.meshes[q]
+    one = swe.Solver(m, *[np.asarray(a, np.float64)[mesh.perm][m.global_ids]
+                          for a in (case.z, case.n, case.h, case.hu, case.hv)], dtype="f64")
+    ms_one, rc, st = time_gpu(one, steps, 10, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sh.step(5)
+    torch.cuda.synchronize()
+    e0.record()
+    sh.step(steps // 5)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_all = e0.elapsed_time(e1) / (steps // 5)
+    e0.record()
+    for _ in range(steps // 5):
+        sh.exchange()
+    e1.record()
+    torch.cuda.synchronize()
+    us_x = e0.elapsed_time(e1) * 1e3 / (steps // 5)
+    halos = [mm.n_cells - mm.n_owned for mm in sh.meshes]
+    return {"parts": parts, "shard": q, "n_owned": m.n_owned, "n_halo": m.n_cells - m.n_owned,
+            "shard_ms_per_step": ms_one / steps,
+            "shard_cell_updates_per_s": m.n_owned * steps / (ms_one * 1e-3),
+            "all_shards_on_one_gpu_ms_per_step": ms_all,
+            "exchange_us_per_step": us_x, "halo_cells_total": int(sum(halos))}
+
+
+def bench_configs(stream, dtypes, with_oracle: bool) -> dict:
+    """Configs 1 (10,000-cell dam break, 200 steps) and 2 (1,000,000-cell wet/dry bumps, 1,000
+    steps) in full on the GPU, and with the CPU oracle on this host beside them."""
+    import gen
+    import paper_1807_00672_amd as swe
+    out = {}
+    for k in (1, 2):
+        case = gen.config(k)
+        mesh = swe.Mesh(case.xy, case.tri)
+        r = {"n_cells": case.n_cells, "steps": case.steps}
+        for dt in dtypes:
+            solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt)
+            ms, rc, st = time_gpu(solver, case.steps, 0, stream)
+            if rc != swe.SWE_OK or st["steps"] != case.steps:
+                raise RuntimeError(f"config {k} {dt}: rc={rc} stats={st}")
+            r[dt] = {"cell_updates_per_s": case.n_cells * case.steps / (ms * 1e-3),
+                     "ms_per_step": ms / case.steps}
+        if with_oracle:
+            import oracle
+            om = oracle.Mesh(case.xy, case.tri, case.edge_tag)
+            t0 = time.perf_counter()
+            rc, *_ = oracle.run_case(case, mesh=om)
+            el = time.perf_counter() - t0
+            assert rc == 0, rc
+            r["oracle"] = {"cell_updates_per_s": case.n_cells * case.steps / el,
+                           "threads": oracle.threads(), "s": el}
+        out[f"config{k}"] = r
+    return out
+
+
 def bench_adjoint(stream, steps: int = 2000) -> dict:
     """Config 5: the gauge-misfit adjoint (checkpointing forward + reverse sweep) of 2,000 FP64
     steps on the 250,000-cell calibration setup, against the plain forward run of the same
@@ -252,6 +318,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the 256-scenario ensemble (0: skip it)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 10,000- and 1,000,000-cell configurations")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the 250,000-cell adjoint timing (0: skip it)")
     ap.add_argument("--probe", choices=["copy"], default=None,
@@ -324,6 +392,26 @@ def main():
                   f"bitwise equal {e['bitwise_equal_to_separate']}", file=sys.stderr, flush=True)
             torch.cuda.empty_cache()
 
+    shards = {}
+    if args.size == "full" and not args.no_configs:
+        shards = bench_shards(mesh, case, stream)
+        print(f"# shard {shards['shard']} of {shards['parts']}: {shards['n_owned']} owned + "
+              f"{shards['n_halo']} halo cells, {shards['shard_ms_per_step']:.4f} ms/step alone; "
+              f"all shards in turn {shards['all_shards_on_one_gpu_ms_per_step']:.4f} ms/step, "
+              f"exchange {shards['exchange_us_per_step']:.0f} us/step",
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
+    configs = {}
+    if args.size == "full" and not args.no_configs:
+        configs = bench_configs(stream, args.dtypes.split(","), not args.no_cpu)
+        for k, v in configs.items():
+            print(f"# {k}: {v['n_cells']} cells x {v['steps']} steps: " +
+                  ", ".join(f"{dt} {v[dt]['cell_updates_per_s'] / 1e9:.2f} G/s"
+                            for dt in args.dtypes.split(",")) +
+                  (f", oracle {v['oracle']['cell_updates_per_s'] / 1e6:.0f} M/s" if "oracle" in v
+                   else ""), file=sys.stderr, flush=True)
+
     adjoint = {}
     if args.adjoint_steps > 0 and args.size == "full":
         adjoint = bench_adjoint(stream, args.adjoint_steps)
@@ -360,6 +448,8 @@ def main():
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "t_end_state"}
                      for k, v in results.items()},
         "tuning": tuning,
+        "configs": configs,
+        "shards": shards,
         "ensemble": ensemble,
         "adjoint": adjoint,
         "copy_GBps_measured": copy_gbps,

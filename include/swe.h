@@ -53,6 +53,8 @@ extern "C" {
 #define SWE_TILED 2            /* variant: tile-staged states, each tile interface once */
 #define SWE_NO_XCD_REMAP 1u    /* flag: launch tiles in mesh order instead of giving each XCD
                                   a contiguous run of tiles (same results) */
+#define SWE_SHARD 2u           /* flag: the state is one shard of a mesh run on several devices;
+                                  its steps leave the next dt to swe_shard_dt_combine */
 #define SWE_TILE 256           /* cells per tile: consecutive mesh-order cells stepped by one
                                   workgroup, which stages them and their neighbours in LDS */
 
@@ -73,6 +75,8 @@ typedef struct swe_mesh_info {
     int64_t n_tile_edges;      /* total edge-list entries over all tiles */
     int32_t max_halo;          /* largest halo of a tile */
     int32_t max_tile_edges;    /* longest edge list of a tile */
+    int64_t n_owned;           /* cells [0, n_owned) are owned: they alone enter the dt
+                                  reduction and the counters (T except for shards) */
 } swe_mesh_info;
 
 /* Arrays swe_mesh_export copies out (sizes in elements). */
@@ -92,8 +96,10 @@ enum swe_mesh_array {
                               bits 0-7 owning cell a (tile-local), bits 8-9 a's local edge k,
                               bits 16-31 int16 b: tile-local cell (< SWE_TILE), halo slot
                               SWE_TILE + j, or a boundary code (SWE_WALL, -1 - s) */
-    SWE_ARR_SLOT = 9       /* uint16[3T], [k*T + i]: entry of cell i's local edge k in its
+    SWE_ARR_SLOT = 9,      /* uint16[3T], [k*T + i]: entry of cell i's local edge k in its
                               tile's edge list; bit 15 set when i is the edge's side b */
+    SWE_ARR_GLOBAL = 10    /* int32[T]: index of cell i in the mesh a shard was cut from
+                              (swe_mesh_create_shard); i for other meshes */
 };
 
 /* Device view of a mesh: the arrays of swe_mesh_export copied to device memory. */
@@ -118,7 +124,7 @@ typedef struct swe_params {
     int32_t n_inflow;      /* number of inflow segments, <= SWE_MAX_INFLOW */
     const double *inflow_q;/* host, n_inflow unit discharges (m^2/s) entering, >= 0 */
     int32_t variant;       /* step kernel: SWE_AUTO, SWE_CELL or SWE_TILED (same results) */
-    int32_t flags;         /* SWE_NO_XCD_REMAP or 0 */
+    int32_t flags;         /* SWE_NO_XCD_REMAP, SWE_SHARD or 0 */
 } swe_params;
 
 /* Device state of one simulation.  All pointers device, element type given by dtype. */
@@ -338,6 +344,44 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
  * (segment recompute and adjoint steps).  Waits for that call's work to finish.
  * Errors: SWE_EINVAL (no completed call on this thread), SWE_EDEVICE. */
 int32_t swe_adjoint_timings(double *forward_ms, double *reverse_ms);
+
+/* ------------------------------------------------------------------ shards */
+
+/*
+ * A shard of a mesh, for running one mesh on several devices (section 2.3's two loops
+ * restricted to a range of cells; section 5 names multi-GPU runs as the continuation): cells
+ * [c0, c1) of `full` in its mesh order (Morton ranges keep the halo small), followed by their
+ * halo — every cell outside the range that shares an edge with it, ascending — as a mesh of
+ * its own in that order (no renumbering).  info.n_owned = c1 - c0.  A step updates every cell
+ * of the shard but only owned cells enter the dt reduction and the counters; halo edges to
+ * cells outside the shard act as walls, so the halo's own update is meaningless and the halo
+ * must be refreshed from its owners (swe_halo_pack, then swe_halo_unpack) before each step.
+ * Inflow tags are kept.  SWE_ARR_GLOBAL maps shard cells to `full` cells.  On success *out
+ * owns a new mesh.  Errors: SWE_EINVAL (null argument, bad range).
+ */
+int32_t swe_mesh_create_shard(const swe_mesh *full, int64_t c0, int64_t c1, swe_mesh **out);
+
+/* Gather rows idx[0..n) (device int32) of the device arrays h, hu, hv (dtype) into the device
+ * buffer buf: n values of h, then n of hu, then n of hv.  Queues work only.
+ * Errors: SWE_EINVAL. */
+int32_t swe_halo_pack(int32_t dtype, int64_t n, const int32_t *idx, const void *h,
+                      const void *hu, const void *hv, void *buf, void *stream);
+
+/* Scatter a buffer laid out as swe_halo_pack writes it into rows idx[0..n) of h, hu, hv.
+ * Queues work only.  Errors: SWE_EINVAL. */
+int32_t swe_halo_unpack(int32_t dtype, int64_t n, const int32_t *idx, const void *buf,
+                        void *h, void *hu, void *hv, void *stream);
+
+/*
+ * The dt all-reduce of a sharded run: states initialised or stepped with SWE_SHARD hold their
+ * own CFL candidate (C min r/(|u|+c) over owned cells); this sets every shard's next dt to the
+ * minimum over the shards, cut at t_end (then marking the last step), or stops them all (a
+ * shard that stopped on an error stops every shard; no wet cell anywhere is SWE_EDRY).
+ * ctrls: host array of n <= 64 device pointers to the shards' control blocks, all on the
+ * current device (a multi-device run reduces the one candidate over the interconnect
+ * instead).  Queues work only.  Errors: SWE_EINVAL.
+ */
+int32_t swe_shard_dt_combine(void *const *ctrls, int32_t n, void *stream);
 
 /* ------------------------------------------------------------------ launch tuning */
 

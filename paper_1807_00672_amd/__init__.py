@@ -12,10 +12,13 @@ from ._abi import (  # noqa: F401
     swe_run_stats, swe_state, swe_state_init, swe_step, swe_workspace_bytes, swe_batch_create,
     swe_batch_destroy, swe_batch_export, swe_batch_info_get, swe_batch_run,
     swe_batch_state_init, swe_batch_workspace_bytes, swe_adjoint, swe_adjoint_timings, swe_adjoint_workspace_bytes,
-    swe_grads, swe_loss, swe_tune, swe_tune_get, swe_tune_result, swe_tune_set)
+    swe_grads, swe_loss, swe_tune, swe_tune_get, swe_tune_result, swe_tune_set,
+    swe_mesh_create_shard, swe_halo_pack, swe_halo_unpack, swe_shard_dt_combine, SWE_SHARD,
+    SWE_ARR_GLOBAL)
 from .solver import Batch, BatchSolver, Mesh, Solver  # noqa: F401
 from .adjoint import AdjointLoss, Calibration  # noqa: F401
 from . import tune  # noqa: F401
+from .shard import ShardedSolver  # noqa: F401
 
 
 def require_gpu() -> None:

@@ -33,10 +33,11 @@ SWE_WALL = -1
 
 SWE_AUTO, SWE_CELL, SWE_TILED = 0, 1, 2
 SWE_NO_XCD_REMAP = 1
+SWE_SHARD = 2
 SWE_TILE = 256
 
 (SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,
- SWE_ARR_HALO, SWE_ARR_EDGE_OFF, SWE_ARR_EDGES, SWE_ARR_SLOT) = range(10)
+ SWE_ARR_HALO, SWE_ARR_EDGE_OFF, SWE_ARR_EDGES, SWE_ARR_SLOT, SWE_ARR_GLOBAL) = range(11)
 
 _NAMES = {0: "SWE_OK", -1: "SWE_EINVAL", -2: "SWE_EMESH", -3: "SWE_EDEVICE",
           -4: "SWE_ENONFINITE", -5: "SWE_EDRY", -6: "SWE_EUNSUPPORTED"}
@@ -56,7 +57,7 @@ class swe_mesh_info(C.Structure):
                 ("total_area", C.c_double), ("min_inradius", C.c_double),
                 ("bbox", C.c_double * 4), ("n_tiles", C.c_int64), ("n_halo", C.c_int64),
                 ("n_tile_edges", C.c_int64), ("max_halo", C.c_int32),
-                ("max_tile_edges", C.c_int32)]
+                ("max_tile_edges", C.c_int32), ("n_owned", C.c_int64)]
 
 
 class swe_dev_mesh(C.Structure):
@@ -137,7 +138,8 @@ EXPORTS = [
     "swe_last_error", "swe_flux_eval", "swe_batch_create", "swe_batch_info_get",
     "swe_batch_export", "swe_batch_destroy", "swe_batch_workspace_bytes", "swe_batch_state_init",
     "swe_batch_run", "swe_adjoint_workspace_bytes", "swe_adjoint", "swe_adjoint_timings", "swe_tune", "swe_tune_get",
-    "swe_tune_set",
+    "swe_tune_set", "swe_mesh_create_shard", "swe_halo_pack", "swe_halo_unpack",
+    "swe_shard_dt_combine",
 ]
 
 
@@ -164,6 +166,10 @@ def _load():
     L.swe_last_error.restype = C.c_char_p
     L.swe_flux_eval.argtypes = [i32, i64, dbl, dbl] + [vp] * 12 + [vp]
     L.swe_adjoint_timings.argtypes = [C.POINTER(dbl), C.POINTER(dbl)]
+    L.swe_mesh_create_shard.argtypes = [vp, i64, i64, C.POINTER(vp)]
+    L.swe_halo_pack.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
+    L.swe_halo_unpack.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
+    L.swe_shard_dt_combine.argtypes = [C.POINTER(vp), i32, vp]
     L.swe_tune.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
                            C.POINTER(swe_state), i32, C.POINTER(swe_tune_result), vp]
     L.swe_tune_get.argtypes = [i32, i32, i64, C.POINTER(swe_tune_result)]
@@ -352,3 +358,22 @@ def swe_adjoint_timings() -> tuple[float, float]:
     f, r = C.c_double(), C.c_double()
     _check(lib.swe_adjoint_timings(C.byref(f), C.byref(r)), "swe_adjoint_timings")
     return f.value, r.value
+
+
+def swe_mesh_create_shard(full, c0: int, c1: int) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(lib.swe_mesh_create_shard(full, c0, c1, C.byref(out)), "swe_mesh_create_shard")
+    return out
+
+
+def swe_halo_pack(dtype, n, idx, h, hu, hv, buf, stream=None) -> None:
+    _check(lib.swe_halo_pack(dtype, n, idx, h, hu, hv, buf, stream), "swe_halo_pack")
+
+
+def swe_halo_unpack(dtype, n, idx, buf, h, hu, hv, stream=None) -> None:
+    _check(lib.swe_halo_unpack(dtype, n, idx, buf, h, hu, hv, stream), "swe_halo_unpack")
+
+
+def swe_shard_dt_combine(ctrls, stream=None) -> None:
+    arr = (C.c_void_p * len(ctrls))(*ctrls)
+    _check(lib.swe_shard_dt_combine(arr, len(ctrls), stream), "swe_shard_dt_combine")

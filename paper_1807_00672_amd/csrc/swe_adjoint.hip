@@ -443,6 +443,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         return afail(SWE_EINVAL, "swe_adjoint: bad parameters");
     if (dm->n_cells != mesh->info.n_cells || !dm->nbr || !dm->c2n || !dm->xy)
         return afail(SWE_EINVAL, "swe_adjoint: bad device mesh");
+    if (mesh->info.n_owned != mesh->info.n_cells || (p->flags & SWE_SHARD))
+        return afail(SWE_EUNSUPPORTED, "swe_adjoint: not for shards");
     if (!s->h[s->cur] || !s->hu[s->cur] || !s->hv[s->cur] || !s->z || !s->n)
         return afail(SWE_EINVAL, "swe_adjoint: null state array");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return afail(SWE_EINVAL, "swe_adjoint: ws not 256-byte aligned");
@@ -470,6 +472,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     StepConfig cfg;
     memset(&cfg, 0, sizeof(cfg));
     cfg.n_cells = T;
+    cfg.n_owned = T;
     cfg.g = p->g;
     cfg.courant = p->courant > 0.0 && p->courant <= 1.0 ? p->courant : 0.7;
     cfg.h_dry = p->h_dry;

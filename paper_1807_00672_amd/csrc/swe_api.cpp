@@ -76,6 +76,8 @@ StepConfig make_config(const swe_mesh *mesh, const swe_params *p)
     StepConfig c;
     memset(&c, 0, sizeof(c));
     c.n_cells = mesh->info.n_cells;
+    c.n_owned = mesh->info.n_owned;
+    c.shard = (p->flags & SWE_SHARD) ? 1 : 0;
     c.g = p->g;
     c.courant = p->courant;
     c.h_dry = p->h_dry;
@@ -98,7 +100,7 @@ DeviceLds g_lds[64];
 struct GraphKey {
     swe_dev_mesh dm;
     double g, courant, h_dry;
-    int32_t dtype, variant, n_inflow, cur, remap;
+    int32_t dtype, variant, n_inflow, cur, remap, flags;
     double q[SWE_MAX_INFLOW];
     void *h[2], *hu[2], *hv[2];
     const void *z, *n;
@@ -131,6 +133,7 @@ GraphKey make_key(const swe_dev_mesh *dm, const swe_params *p, const swe_state *
     k.g = p->g; k.courant = p->courant; k.h_dry = p->h_dry;
     k.dtype = p->dtype; k.variant = p->variant; k.n_inflow = p->n_inflow; k.cur = s->cur;
     k.remap = remap;
+    k.flags = p->flags;
     for (int i = 0; i < p->n_inflow; ++i) k.q[i] = p->inflow_q[i];
     for (int b = 0; b < 2; ++b) { k.h[b] = s->h[b]; k.hu[b] = s->hu[b]; k.hv[b] = s->hv[b]; }
     k.z = s->z; k.n = s->n; k.ctrl = s->ctrl; k.work = s->work;
@@ -206,7 +209,7 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     const std::string w(where);
     if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
         return fail(SWE_EINVAL, w + ": unknown variant");
-    if (p->flags & ~SWE_NO_XCD_REMAP) return fail(SWE_EINVAL, w + ": unknown flags");
+    if (p->flags & ~(SWE_NO_XCD_REMAP | SWE_SHARD)) return fail(SWE_EINVAL, w + ": unknown flags");
     int variant = p->variant;
     if (variant == SWE_AUTO) {
         // a swe_tune result for this device, precision and size class decides, if there is one
@@ -319,6 +322,8 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
     if (int32_t rc = check_call(mesh, dm, p, s, "swe_run")) return rc;
     if (n_steps < 0) return fail(SWE_EINVAL, "swe_run: n_steps < 0");
     if (dt_seq && n_steps < 1) return fail(SWE_EINVAL, "swe_run: dt_seq needs n_steps >= 1");
+    if (dt_seq && (p->flags & SWE_SHARD))
+        return fail(SWE_EINVAL, "swe_run: a shard takes its dt from swe_shard_dt_combine");
     const StepConfig cfg = make_config(mesh, p);
     const TileLayout *tl = nullptr;
     int remap = 1;
@@ -359,6 +364,40 @@ int32_t swe_flux_eval(int32_t dtype, int64_t n, double g, double h_dry, const vo
     return check_hip(launch_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx,
                                       ny, f, p, stream),
                      "swe_flux_eval");
+}
+
+int32_t swe_halo_pack(int32_t dtype, int64_t n, const int32_t *idx, const void *h,
+                      const void *hu, const void *hv, void *buf, void *stream)
+{
+    if (dtype != SWE_F64 && dtype != SWE_F32) return fail(SWE_EINVAL, "swe_halo_pack: bad dtype");
+    if (n < 0 || n > INT32_MAX) return fail(SWE_EINVAL, "swe_halo_pack: bad n");
+    if (n == 0) return SWE_OK;
+    if (!idx || !h || !hu || !hv || !buf) return fail(SWE_EINVAL, "swe_halo_pack: null argument");
+    return check_hip(launch_halo(dtype, true, n, idx, nullptr, buf, h, hu, hv, nullptr, nullptr,
+                                 nullptr, stream),
+                     "swe_halo_pack");
+}
+
+int32_t swe_halo_unpack(int32_t dtype, int64_t n, const int32_t *idx, const void *buf, void *h,
+                        void *hu, void *hv, void *stream)
+{
+    if (dtype != SWE_F64 && dtype != SWE_F32) return fail(SWE_EINVAL, "swe_halo_unpack: bad dtype");
+    if (n < 0 || n > INT32_MAX) return fail(SWE_EINVAL, "swe_halo_unpack: bad n");
+    if (n == 0) return SWE_OK;
+    if (!idx || !h || !hu || !hv || !buf) return fail(SWE_EINVAL, "swe_halo_unpack: null argument");
+    return check_hip(launch_halo(dtype, false, n, idx, buf, nullptr, nullptr, nullptr, nullptr, h,
+                                 hu, hv, stream),
+                     "swe_halo_unpack");
+}
+
+int32_t swe_shard_dt_combine(void *const *ctrls, int32_t n, void *stream)
+{
+    if (!ctrls || n < 1 || n > kMaxShards)
+        return fail(SWE_EINVAL, "swe_shard_dt_combine: need 1 to 64 control blocks");
+    for (int32_t p = 0; p < n; ++p)
+        if (!ctrls[p] || !aligned(ctrls[p], 16))
+            return fail(SWE_EINVAL, "swe_shard_dt_combine: null or misaligned control block");
+    return check_hip(launch_shard_combine(ctrls, n, stream), "swe_shard_dt_combine");
 }
 
 }  // extern "C"

@@ -92,6 +92,7 @@ StepConfig batch_config(const swe_batch *b, const swe_batch_params *p)
     StepConfig c;
     memset(&c, 0, sizeof(c));
     c.n_cells = b->info.n_cells;
+    c.n_owned = b->info.n_cells;
     c.g = p->g;
     c.courant = p->courant;
     c.h_dry = p->h_dry;

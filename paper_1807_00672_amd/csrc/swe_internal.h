@@ -23,6 +23,7 @@ struct Ctrl {
     int32_t done;      // 1: steps change nothing (t_end reached or error)
     int32_t last;      // 1: the next step ends at t_end exactly
     int32_t cur0;      // buffer holding the state at swe_state_init
+    double dt_cfl;     // SWE_SHARD: this shard's CFL candidate for the next dt
 };
 static_assert(sizeof(Ctrl) <= SWE_CTRL_BYTES, "control block too large");
 
@@ -84,8 +85,10 @@ inline int64_t workspace_bytes(int64_t n_cells) { return workspace_bytes_for_til
 // Everything a launch needs besides the state: plain values, passed by value to kernels.
 struct StepConfig {
     int64_t n_cells;
+    int64_t n_owned;   // cells [0, n_owned) enter the dt reduction and the counters
     double g, courant, h_dry;
     int32_t n_inflow;
+    int32_t shard;     // 1: leave the next dt to swe_shard_dt_combine (SWE_SHARD)
     double inflow_q[SWE_MAX_INFLOW];
 };
 
@@ -116,6 +119,11 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);
 int prepare_tile_kernels(size_t max_lds);   // allow dynamic LDS up to max_lds bytes
 int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);
+int launch_halo(int dtype, bool pack, int64_t n, const int32_t *idx, const void *buf_in,
+                void *buf_out, const void *h, const void *hu, const void *hv, void *ho, void *huo,
+                void *hvo, void *stream);
+constexpr int kMaxShards = 64;
+int launch_shard_combine(void *const *ctrls, int n, void *stream);
 int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *hl,
                      const void *hul, const void *hvl, const void *zl, const void *hr,
                      const void *hur, const void *hvr, const void *zr, const void *nx,
@@ -147,6 +155,7 @@ struct swe_mesh {
     std::vector<int32_t> edge_off;   // [n_tiles + 1]
     std::vector<uint32_t> edges;     // packed edge-list entries, per tile
     std::vector<uint16_t> slot;      // [3][T]
+    std::vector<int32_t> global;     // shards: cell index in the mesh cut from; else empty
     swe::TileLayout tiles;           // sizes the tiled step needs at launch
     void *graph = nullptr;           // cached two-step graph of swe_run (swe_api.cpp)
     ~swe_mesh();

@@ -42,6 +42,10 @@ constexpr double kInf = __builtin_huge_val();
 #ifndef SWE_DT_FOLD
 #define SWE_DT_FOLD 1
 #endif
+// 1: the tiled kernel addresses arrays below 4 GiB by 32-bit byte offsets; 0: always 64-bit.
+#ifndef SWE_OFF32
+#define SWE_OFF32 1
+#endif
 template <typename R>
 __device__ __forceinline__ R div_(R a, R b)
 {
@@ -325,7 +329,7 @@ __device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
 // bits of the new state), then set the next step's dt: CFL, replayed from dt_seq, or cut at
 // t_end (section 2.4).
 __device__ void advance_ctrl(Ctrl *ctrl, double m, long long cl, int fl, double courant,
-                             const double *dt_seq, int64_t n_seq)
+                             const double *dt_seq, int64_t n_seq, int shard)
 {
     Ctrl c = *ctrl;
     c.t = c.last ? c.t_end : c.t + c.dt;
@@ -340,7 +344,10 @@ __device__ void advance_ctrl(Ctrl *ctrl, double m, long long cl, int fl, double 
         c.status |= kStatusNonFinite;
         c.done = 1;
     }
-    if (!c.done) {
+    if (shard) {
+        // a shard keeps its candidate; the all-reduce over shards decides dt and last
+        c.dt_cfl = courant * m;
+    } else if (!c.done) {
         double dt = courant * m;
         if (dt_seq) dt = c.run_step < n_seq ? dt_seq[c.run_step] : c.dt;
         c.last = 0;
@@ -515,11 +522,41 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         a.hvo[i] = hvn;
         if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
         dtc = cell_dt<R>(g, hd, hs, hun, hvn, gm.inradius, nb, cfg, qtab);
+        if (i >= cfg.n_owned) {   // a shard's halo cell: refreshed by its owner
+            dtc = static_cast<R>(kInf);
+            clamp = 0;
+            flag = 0;
+        }
     }
     block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
 }
 
 // ------------------------------------------------------------------------ tiled step
+
+// Element i of an array: with O32 (every array the kernel indexes spans less than 4 GiB,
+// checked at launch) addressed by a 32-bit byte offset from its base, which the hardware adds
+// to the scalar base itself; else by 64-bit index arithmetic.
+template <bool O32, typename T>
+__device__ __forceinline__ T ld(const T *p, int64_t i)
+{
+    if constexpr (O32)
+        return *reinterpret_cast<const T *>(
+            reinterpret_cast<const char *>(p) +
+            static_cast<uint32_t>(static_cast<uint32_t>(i) * static_cast<uint32_t>(sizeof(T))));
+    else
+        return p[i];
+}
+
+template <bool O32, typename T>
+__device__ __forceinline__ void st(T *p, int64_t i, T v)
+{
+    if constexpr (O32)
+        *reinterpret_cast<T *>(
+            reinterpret_cast<char *>(p) +
+            static_cast<uint32_t>(static_cast<uint32_t>(i) * static_cast<uint32_t>(sizeof(T)))) = v;
+    else
+        p[i] = v;
+}
 
 template <typename R>
 struct TileArgs {
@@ -549,7 +586,7 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
 // computes them.  Phase 3 sums each cell's three contributions in local-edge order and
 // applies the update of eq. 4, the clamp, the friction and the next CFL bound, as the
 // per-cell kernel does.
-template <typename R>
+template <typename R, bool O32>
 __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
                                                            Batch bt)
 {
@@ -587,9 +624,12 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     double2 p0 = {0.0, 0.0}, p1 = {0.0, 0.0}, p2 = {0.0, 0.0};
     uint32_t sl0 = 0, sl1 = 0, sl2 = 0;
     if (mine) {
-        h = a.h[i]; hu = a.hu[i]; hv = a.hv[i]; zc = a.z[i]; nm = a.n[i];
-        sl0 = ta.slot[i]; sl1 = ta.slot[T + i]; sl2 = ta.slot[2 * T + i];
-        p0 = a.xy[a.c2n[i]]; p1 = a.xy[a.c2n[T + i]]; p2 = a.xy[a.c2n[2 * T + i]];
+        h = ld<O32>(a.h, i); hu = ld<O32>(a.hu, i); hv = ld<O32>(a.hv, i);
+        zc = ld<O32>(a.z, i); nm = ld<O32>(a.n, i);
+        sl0 = ld<O32>(ta.slot, i); sl1 = ld<O32>(ta.slot, T + i); sl2 = ld<O32>(ta.slot, 2 * T + i);
+        p0 = ld<O32>(a.xy, ld<O32>(a.c2n, i));
+        p1 = ld<O32>(a.xy, ld<O32>(a.c2n, T + i));
+        p2 = ld<O32>(a.xy, ld<O32>(a.c2n, 2 * T + i));
     }
     // global loads: the edge-list entries of the first two rounds and their end nodes
     const int eb = ta.edge_off[tile], ee = ta.edge_off[tile + 1];
@@ -599,24 +639,24 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     for (int it = 0; it < 2; ++it) {
         const int e = eb + tid + it * kBlock;
         if (e < ee) {
-            const uint32_t w = ta.edges[e];
+            const uint32_t w = ld<O32>(ta.edges, e);
             const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
             const int k = static_cast<int>((w >> 8) & 3u);
             ew[it] = w;
-            ep0[it] = a.xy[a.c2n[k * T + ca]];
-            ep1[it] = a.xy[a.c2n[(k == 2 ? 0 : k + 1) * T + ca]];
+            ep0[it] = ld<O32>(a.xy, ld<O32>(a.c2n, k * T + ca));
+            ep1[it] = ld<O32>(a.xy, ld<O32>(a.c2n, (k == 2 ? 0 : k + 1) * T + ca));
         }
     }
     // phase 1: halo and own cell into LDS
     const int hb = ta.halo_off[tile], he = ta.halo_off[tile + 1];
     for (int j = hb + tid; j < he; j += kBlock) {
-        const int32_t c = ta.halo[j];
-        const R hh = a.h[c];
+        const int32_t c = ld<O32>(ta.halo, j);
+        const R hh = ld<O32>(a.h, c);
         const int q = kBlock + (j - hb);
         s_h[q] = hh;
-        s_u[q] = velocity(hh, a.hu[c], hd);
-        s_v[q] = velocity(hh, a.hv[c], hd);
-        s_z[q] = a.z[c];
+        s_u[q] = velocity(hh, ld<O32>(a.hu, c), hd);
+        s_v[q] = velocity(hh, ld<O32>(a.hv, c), hd);
+        s_z[q] = ld<O32>(a.z, c);
     }
     if (mine) {
         s_h[tid] = h;
@@ -659,10 +699,11 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         if (e < ee) edge(ew[it], ep0[it], ep1[it], e - eb);
     }
     for (int e = eb + tid + 2 * kBlock; e < ee; e += kBlock) {
-        const uint32_t w = ta.edges[e];
+        const uint32_t w = ld<O32>(ta.edges, e);
         const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
         const int k = static_cast<int>((w >> 8) & 3u);
-        edge(w, a.xy[a.c2n[k * T + ca]], a.xy[a.c2n[(k == 2 ? 0 : k + 1) * T + ca]], e - eb);
+        edge(w, ld<O32>(a.xy, ld<O32>(a.c2n, k * T + ca)),
+             ld<O32>(a.xy, ld<O32>(a.c2n, (k == 2 ? 0 : k + 1) * T + ca)), e - eb);
     }
     __syncthreads();
 
@@ -686,7 +727,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
             l[k] = sqrt_(dx * dx + dy * dy);
             nb[k] = 0;
             if ((cfg.n_inflow > 0 || batched) && !side_b)
-                nb[k] = static_cast<int16_t>(ta.edges[eb + q] >> 16);
+                nb[k] = static_cast<int16_t>(ld<O32>(ta.edges, eb + q) >> 16);
             if (k == 0) {
                 acc0 = c0; acc1 = c1; acc2 = c2;
             } else {
@@ -700,9 +741,9 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
         if (a.us_h) {
-            a.us_h[i] = hs;
-            a.us_hu[i] = hus;
-            a.us_hv[i] = hvs;
+            st<O32>(a.us_h, i, hs);
+            st<O32>(a.us_hu, i, hus);
+            st<O32>(a.us_hv, i, hvs);
         }
         if (hs < R(0)) {
             clamp = 1;
@@ -718,11 +759,16 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
             hun = R(0);
             hvn = R(0);
         }
-        a.ho[i] = hs;
-        a.huo[i] = hun;
-        a.hvo[i] = hvn;
+        st<O32>(a.ho, i, hs);
+        st<O32>(a.huo, i, hun);
+        st<O32>(a.hvo, i, hvn);
         if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
         dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
+        if (i >= cfg.n_owned) {   // a shard's halo cell: refreshed by its owner
+            dtc = static_cast<R>(kInf);
+            clamp = 0;
+            flag = 0;
+        }
     }
     block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
 }
@@ -747,6 +793,10 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig 
         const R h = a.h[i], hu = a.hu[i], hv = a.hv[i];
         if (!isfinite(h) || !isfinite(hu) || !isfinite(hv)) flag = kStatusNonFinite;
         dtc = cell_dt<R>(g, hd, h, hu, hv, gm.inradius, nb, cfg, qtab);
+        if (i >= cfg.n_owned) {
+            dtc = static_cast<R>(kInf);
+            flag = 0;
+        }
     }
     block_partials(static_cast<double>(dtc), 0, flag, a.part);
 }
@@ -761,7 +811,7 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
                                                                const double *dt_seq,
                                                                int64_t n_seq, int mode,
                                                                double t0, double t_end,
-                                                               int cur0, Batch bt)
+                                                               int cur0, Batch bt, int shard)
 {
     // workgroup s reduces scenario s's tiles (a single mesh: all nb partials)
     Ctrl *ctrl = const_cast<Ctrl *>(ctrl_of(ctrl_base, blockIdx.x));
@@ -816,7 +866,7 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
         fl |= s_fl[w];
     }
     if (mode == 1) {
-        advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq);
+        advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq, shard);
         return;
     }
     Ctrl c = *ctrl;
@@ -832,7 +882,8 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
         c.status |= kStatusNonFinite;
         c.done = 1;
     }
-    if (!c.done) {
+    c.dt_cfl = courant * m;
+    if (!c.done && !shard) {
         double dt = courant * m;
         if (!(dt < kInf)) {
             c.status |= kStatusDry;
@@ -883,7 +934,7 @@ __device__ __forceinline__ void fold_group(double &m, long long &cl, int &fl)
 // increment, and only the last arrival (acquire) reads what the others wrote.
 __global__ __launch_bounds__(kGroup) void dt_fold_kernel(Ctrl *ctrl, Partials part, int64_t nb,
                                                         double courant, const double *dt_seq,
-                                                        int64_t n_seq)
+                                                        int64_t n_seq, int shard)
 {
     __shared__ int s_last;
     // uniform; the control block changes only after every workgroup has arrived
@@ -915,7 +966,71 @@ __global__ __launch_bounds__(kGroup) void dt_fold_kernel(Ctrl *ctrl, Partials pa
     fold_group(m, cl, fl);
     if (threadIdx.x == 0) {
         part.count[0] = 0;
-        advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq);
+        advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq, shard);
+    }
+}
+
+// Control blocks of the shards of one mesh (swe_shard_dt_combine).
+struct ShardCtrls {
+    Ctrl *c[kMaxShards];
+};
+
+// The dt all-reduce of a sharded run: the minimum of the shards' CFL candidates, cut at t_end,
+// becomes every shard's next dt; a shard that stopped stops them all.
+__global__ void shard_combine_kernel(ShardCtrls sc, int n)
+{
+    if (threadIdx.x != 0) return;
+    double m = kInf;
+    int32_t status = 0, done = 0;
+    for (int p = 0; p < n; ++p) {
+        m = fmin(m, sc.c[p]->dt_cfl);
+        status |= sc.c[p]->status;
+        done |= sc.c[p]->done;
+    }
+    for (int p = 0; p < n; ++p) {
+        Ctrl c = *sc.c[p];
+        c.status |= status;
+        c.last = 0;
+        if (done) {
+            c.done = 1;
+        } else if (!(m < kInf)) {
+            c.status |= kStatusDry;
+            c.done = 1;
+        } else if (!(m > 0.0)) {
+            c.status |= kStatusBadDt;
+            c.done = 1;
+        } else {
+            double dt = m;
+            if (c.t_end > 0.0 && dt >= c.t_end - c.t) {
+                dt = c.t_end - c.t;
+                c.last = 1;
+            }
+            c.dt = dt;
+        }
+        *sc.c[p] = c;
+    }
+}
+
+// Halo exchange of a sharded run: gather rows idx of (h, hu, hv) into a buffer of 3n values
+// (pack), or scatter such a buffer into rows idx (unpack).
+template <typename R>
+__global__ void halo_kernel(int64_t n, const int32_t *__restrict__ idx, int pack,
+                            const R *__restrict__ buf_in, R *__restrict__ buf_out,
+                            const R *__restrict__ h, const R *__restrict__ hu,
+                            const R *__restrict__ hv, R *__restrict__ ho, R *__restrict__ huo,
+                            R *__restrict__ hvo)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t r = idx[k];
+    if (pack) {
+        buf_out[k] = h[r];
+        buf_out[n + k] = hu[r];
+        buf_out[2 * n + k] = hv[r];
+    } else {
+        ho[r] = buf_in[k];
+        huo[r] = buf_in[n + k];
+        hvo[r] = buf_in[2 * n + k];
     }
 }
 
@@ -1040,7 +1155,8 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
         init_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(a, cfg, bv);
     }
     dt_pass_kernel<<<dim3(bv.n_scen), kPassThreads, 0, st>>>(
-        static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, nullptr, 0, 0, t0, t_end, s.cur, bv);
+        static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, nullptr, 0, 0, t0, t_end, s.cur, bv,
+        cfg.shard);
     return static_cast<int>(hipGetLastError());
 }
 
@@ -1051,14 +1167,30 @@ size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
 
 int prepare_tile_kernels(size_t max_lds)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_step_kernel<double>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(max_lds));
-    if (e != hipSuccess) return static_cast<int>(e);
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_step_kernel<float>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(max_lds));
-    return static_cast<int>(e);
+    const void *k[4] = {reinterpret_cast<const void *>(&tile_step_kernel<double, true>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<double, false>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<float, true>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<float, false>)};
+    for (const void *f : k) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(max_lds));
+        if (e != hipSuccess) return static_cast<int>(e);
+    }
+    return static_cast<int>(hipSuccess);
 }
+
+namespace {
+
+// Whether every array the tiled kernel indexes spans less than 4 GiB (32-bit byte offsets).
+bool offsets_fit_32(const swe_dev_mesh &dm, int64_t n_cells, const TileLayout &tl)
+{
+    const int64_t lim = int64_t{1} << 32;
+    return SWE_OFF32 && 12 * n_cells < lim && 16 * dm.n_nodes < lim &&
+           4 * tl.n_tiles * static_cast<int64_t>(tl.max_edges) < lim &&
+           4 * tl.n_tiles * static_cast<int64_t>(tl.max_halo) < lim;
+}
+
+}  // namespace
 
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
@@ -1073,6 +1205,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     const Partials part = partials_for(s.work, nb);
     if (tl) {
         const size_t lds = tile_lds_bytes_for(dtype, *tl);
+        const bool o32 = offsets_fit_32(dm, dm.n_cells, *tl);
         if (dtype == SWE_F64) {
             TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
             ta.s.part = part;
@@ -1081,11 +1214,17 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
                 ta.s.us_hu = ustar[1];
                 ta.s.us_hv = ustar[2];
             }
-            tile_step_kernel<double><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            if (o32)
+                tile_step_kernel<double, true><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            else
+                tile_step_kernel<double, false><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         } else {
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
             ta.s.part = part;
-            tile_step_kernel<float><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            if (o32)
+                tile_step_kernel<float, true><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            else
+                tile_step_kernel<float, false><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         }
     } else if (dtype == SWE_F64) {
         StepArgs<double> a = make_args<double>(dm, s, cur);
@@ -1103,10 +1242,11 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     }
     if (SWE_DT_FOLD && batch == nullptr)
         dt_fold_kernel<<<dim3(n_groups(nb)), dim3(kGroup), 0, st>>>(
-            static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq);
+            static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, cfg.shard);
     else
         dt_pass_kernel<<<dim3(bv.n_scen), kPassThreads, 0, st>>>(
-            static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, 1, 0.0, 0.0, 0, bv);
+            static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, 1, 0.0, 0.0, 0, bv,
+            cfg.shard);
     return static_cast<int>(hipGetLastError());
 }
 
@@ -1114,6 +1254,34 @@ int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream)
 {
     run_begin_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(static_cast<Ctrl *>(s.ctrl),
                                                                       dt_seq);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_halo(int dtype, bool pack, int64_t n, const int32_t *idx, const void *buf_in,
+                void *buf_out, const void *h, const void *hu, const void *hv, void *ho, void *huo,
+                void *hvo, void *stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256));
+    if (dtype == SWE_F64) {
+        using R = double;
+        halo_kernel<R><<<grid, 256, 0, st>>>(n, idx, pack ? 1 : 0, (const R *)buf_in, (R *)buf_out,
+                                             (const R *)h, (const R *)hu, (const R *)hv, (R *)ho,
+                                             (R *)huo, (R *)hvo);
+    } else {
+        using R = float;
+        halo_kernel<R><<<grid, 256, 0, st>>>(n, idx, pack ? 1 : 0, (const R *)buf_in, (R *)buf_out,
+                                             (const R *)h, (const R *)hu, (const R *)hv, (R *)ho,
+                                             (R *)huo, (R *)hvo);
+    }
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_shard_combine(void *const *ctrls, int n, void *stream)
+{
+    ShardCtrls sc;
+    for (int p = 0; p < kMaxShards; ++p) sc.c[p] = p < n ? static_cast<Ctrl *>(ctrls[p]) : nullptr;
+    shard_combine_kernel<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(sc, n);
     return static_cast<int>(hipGetLastError());
 }
 

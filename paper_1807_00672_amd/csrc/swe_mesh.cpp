@@ -248,6 +248,7 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
     swe_mesh_info &inf = m.info;
     memset(&inf, 0, sizeof(inf));
     inf.n_cells = T;
+    inf.n_owned = T;
     inf.n_nodes = nv;
     inf.n_edges = ne;
     inf.n_boundary_edges = nbnd;
@@ -333,9 +334,87 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
     build_tiles(m);
 }
 
+// Shard [c0, c1) of `full` and its halo as a mesh of its own (swe_mesh_create_shard).
+void build_shard(swe_mesh &m, const swe_mesh &full, int64_t c0, int64_t c1)
+{
+    const int64_t T = full.info.n_cells;
+    if (c0 < 0 || c1 <= c0 || c1 > T) throw Fail{SWE_EINVAL, "bad cell range"};
+    std::vector<int32_t> cells;
+    cells.reserve(static_cast<size_t>(c1 - c0));
+    for (int64_t i = c0; i < c1; ++i) cells.push_back(static_cast<int32_t>(i));
+    std::vector<int32_t> halo;
+    for (int64_t i = c0; i < c1; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const int32_t j = full.nbr[k * T + i];
+            if (j >= 0 && (j < c0 || j >= c1)) halo.push_back(j);
+        }
+    std::sort(halo.begin(), halo.end());
+    halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+    cells.insert(cells.end(), halo.begin(), halo.end());
+    const int64_t n = static_cast<int64_t>(cells.size());
+    // nodes the shard uses, numbered in the full mesh's order
+    std::vector<int32_t> node_of(static_cast<size_t>(full.info.n_nodes), -1);
+    std::vector<int32_t> nodes;
+    for (int32_t c : cells)
+        for (int k = 0; k < 3; ++k) {
+            const int32_t v = full.c2n[k * T + c];
+            if (node_of[v] < 0) {
+                node_of[v] = 0;
+                nodes.push_back(v);
+            }
+        }
+    std::sort(nodes.begin(), nodes.end());
+    for (size_t q = 0; q < nodes.size(); ++q) node_of[nodes[q]] = static_cast<int32_t>(q);
+    std::vector<double> xy(2 * nodes.size());
+    for (size_t q = 0; q < nodes.size(); ++q) {
+        xy[2 * q] = full.xy[2 * static_cast<size_t>(nodes[q])];
+        xy[2 * q + 1] = full.xy[2 * static_cast<size_t>(nodes[q]) + 1];
+    }
+    // triangles in the full mesh's (counter-clockwise) node order; inflow tags kept
+    std::vector<int32_t> tri(3 * n), tag(3 * n, 0);
+    for (int64_t q = 0; q < n; ++q)
+        for (int k = 0; k < 3; ++k) {
+            const int32_t c = cells[q];
+            tri[3 * q + k] = node_of[full.c2n[k * T + c]];
+            const int32_t code = full.nbr[k * T + c];
+            if (code < SWE_WALL) tag[3 * q + k] = -1 - code;
+        }
+    build(m, xy.data(), static_cast<int64_t>(nodes.size()), tri.data(), n, tag.data(), 0);
+    m.info.n_owned = c1 - c0;
+    m.global = std::move(cells);
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t swe_mesh_create_shard(const swe_mesh *full, int64_t c0, int64_t c1, swe_mesh **out)
+{
+    if (!out || !full) {
+        swe::set_error("swe_mesh_create_shard: null argument");
+        return SWE_EINVAL;
+    }
+    *out = nullptr;
+    swe_mesh *m = nullptr;
+    try {
+        m = new swe_mesh();
+        build_shard(*m, *full, c0, c1);
+    } catch (const Fail &f) {
+        delete m;
+        swe::set_error("swe_mesh_create_shard: " + f.msg);
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        delete m;
+        swe::set_error("swe_mesh_create_shard: out of host memory");
+        return SWE_EINVAL;
+    } catch (...) {
+        delete m;
+        swe::set_error("swe_mesh_create_shard: unexpected failure");
+        return SWE_EINVAL;
+    }
+    *out = m;
+    return SWE_OK;
+}
 
 int32_t swe_mesh_create(const double *xy, int64_t nv, const int32_t *tri, int64_t nt,
                         const int32_t *edge_tag, uint32_t flags, swe_mesh **out)
@@ -398,6 +477,16 @@ int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t 
         src = mesh->edge_off.data(); bytes = 4 * (int64_t)mesh->edge_off.size(); break;
     case SWE_ARR_EDGES: src = mesh->edges.data(); bytes = 4 * (int64_t)mesh->edges.size(); break;
     case SWE_ARR_SLOT: src = mesh->slot.data(); bytes = 2 * (int64_t)mesh->slot.size(); break;
+    case SWE_ARR_GLOBAL:
+        bytes = 4 * mesh->info.n_cells;
+        if (!mesh->global.empty()) {
+            src = mesh->global.data();
+            break;
+        }
+        if (dst_bytes < bytes) break;   // reported below
+        for (int64_t i = 0; i < mesh->info.n_cells; ++i)   // not a shard: the identity
+            static_cast<int32_t *>(dst)[i] = static_cast<int32_t>(i);
+        return SWE_OK;
     default:
         swe::set_error("swe_mesh_export: unknown array " + std::to_string(which));
         return SWE_EINVAL;

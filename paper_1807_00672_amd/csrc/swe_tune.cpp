@@ -60,6 +60,7 @@ int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
 {
     if (!mesh || !dm || !p || !s || !out) return tfail(SWE_EINVAL, "swe_tune: null argument");
     if (n_steps < 2) return tfail(SWE_EINVAL, "swe_tune: n_steps must be >= 2");
+    if (p->flags & SWE_SHARD) return tfail(SWE_EINVAL, "swe_tune: tune the unsharded mesh");
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return tfail(SWE_EDEVICE, "swe_tune: no device");
     hipStream_t st = static_cast<hipStream_t>(stream);

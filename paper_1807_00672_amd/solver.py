@@ -28,8 +28,9 @@ class Mesh:
     [T, 3] boundary tags (0 wall, s >= 1 inflow segment s) of input edge (k, k+1).
     """
 
-    def __init__(self, xy, tri, edge_tag=None, morton: bool = True, device="cuda"):
-        self.handle = A.swe_mesh_create(xy, tri, edge_tag, A.SWE_MORTON if morton else 0)
+    def __init__(self, xy, tri, edge_tag=None, morton: bool = True, device="cuda", handle=None):
+        self.handle = handle if handle is not None else A.swe_mesh_create(
+            xy, tri, edge_tag, A.SWE_MORTON if morton else 0)
         self.info = A.swe_mesh_info_get(self.handle)
         t, v = int(self.info.n_cells), int(self.info.n_nodes)
         self.n_cells, self.n_nodes = t, v
@@ -46,9 +47,17 @@ class Mesh:
         self.edges = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGES, int(self.info.n_tile_edges),
                                        np.uint32)
         self.slot = A.swe_mesh_export(self.handle, A.SWE_ARR_SLOT, 3 * t, np.uint16)
+        self.n_owned = int(self.info.n_owned)
+        self.global_ids = A.swe_mesh_export(self.handle, A.SWE_ARR_GLOBAL, t, np.int32)
         self.device = None
         if device is not None:
             self.to(device)
+
+    @classmethod
+    def shard(cls, full: "Mesh", c0: int, c1: int, device="cuda") -> "Mesh":
+        """Cells [c0, c1) of `full` (its mesh order) followed by their halo, as a mesh of its own
+        (swe_mesh_create_shard); `global_ids` maps its cells to `full`'s."""
+        return cls(None, None, handle=A.swe_mesh_create_shard(full.handle, c0, c1), device=device)
 
     def to(self, device="cuda"):
         d = torch.device(device)
@@ -92,7 +101,7 @@ class Solver:
 
     def __init__(self, mesh: Mesh, z, n, h, hu, hv, dtype: str = "f64", g=9.81, courant=0.7,
                  h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None, variant="auto",
-                 xcd_remap=True):
+                 xcd_remap=True, shard=False):
         if mesh.device is None:
             raise ValueError("mesh has no device arrays")
         self.mesh = mesh
@@ -102,7 +111,9 @@ class Solver:
         self._q = np.ascontiguousarray(inflow_q if inflow_q is not None else [], np.float64)
         self.params = A.swe_params(g, courant, h_dry, self.dtype, self._q.size,
                                    self._q.ctypes.data_as(C.POINTER(C.c_double)),
-                                   self.VARIANTS[variant], 0 if xcd_remap else A.SWE_NO_XCD_REMAP)
+                                   self.VARIANTS[variant],
+                                   (0 if xcd_remap else A.SWE_NO_XCD_REMAP) |
+                                   (A.SWE_SHARD if shard else 0))
         t = mesh.n_cells
 
         def field(a):

@@ -251,3 +251,49 @@ def test_tuning_table_records_erases_and_rejects_without_a_device():
     assert swe.lib.swe_tune_set(0, swe.SWE_F64, 10, C.byref(bad)) == swe.SWE_EINVAL
     assert swe.lib.swe_tune_get(0, 7, 10, C.byref(r)) == swe.SWE_EINVAL
     assert swe.lib.swe_tune(None, None, None, None, 10, None, None) == swe.SWE_EINVAL
+
+
+@pytest.mark.parametrize("k,c0,c1", [(3, 0, 2500), (3, 2500, 7700), (3, 7700, 10200), (2, 1000, 1001)])
+def test_shard_mesh_is_the_range_and_its_halo_with_matching_neighbours(k, c0, c1):
+    c = gen.small(k)
+    full = swe.Mesh(c.xy, c.tri, device=None)
+    sh = swe.Mesh.shard(full, c0, c1, device=None)
+    T, t = full.n_cells, sh.n_cells
+    g = sh.global_ids.astype(np.int64)
+    assert sh.n_owned == c1 - c0 and np.array_equal(g[:sh.n_owned], np.arange(c0, c1))
+    fn = full.nbr.reshape(3, T)
+    own = fn[:, c0:c1]
+    halo = np.unique(own[(own >= 0) & ((own < c0) | (own >= c1))])
+    assert np.array_equal(g[sh.n_owned:], halo)            # exactly the outside neighbours
+    sn = sh.nbr.reshape(3, t)
+    # owned cells keep their neighbours (through the global map) and boundary codes, in the
+    # same local edge order
+    mapped = np.where(sn[:, :sh.n_owned] >= 0, g[np.maximum(sn[:, :sh.n_owned], 0)],
+                      sn[:, :sh.n_owned])
+    assert np.array_equal(mapped, own)
+    # halo cells: neighbours inside the shard are kept, the rest became walls
+    hn = sn[:, sh.n_owned:]
+    fh = fn[:, g[sh.n_owned:]]
+    inside = np.isin(fh, g)
+    assert np.array_equal(np.where(hn >= 0, g[np.maximum(hn, 0)], -1)[inside], fh[inside])
+    assert np.all(hn[~inside & (fh >= 0)] == swe.SWE_WALL)
+    # same triangles (coordinates of the nodes, counter-clockwise order kept)
+    fxy, sxy = full.xy.reshape(-1, 2), sh.xy.reshape(-1, 2)
+    assert np.array_equal(sxy[sh.c2n.reshape(3, t)], fxy[full.c2n.reshape(3, T)[:, g]])
+    assert full.n_owned == T and np.array_equal(full.global_ids, np.arange(T))
+
+
+def test_shard_keeps_inflow_tags_and_rejects_bad_ranges():
+    c = gen.ensemble_scenario(0, t_max=6e3, t_min=5e3)
+    full = swe.Mesh(c.xy, c.tri, c.edge_tag, device=None)
+    T = full.n_cells
+    sh = swe.Mesh.shard(full, 0, T // 2, device=None)
+    codes = full.nbr.reshape(3, T)[:, : T // 2]
+    assert np.array_equal(sh.nbr.reshape(3, -1)[:, : T // 2][codes < -1], codes[codes < -1])
+    assert (codes < -1).any()
+    for a, b in ((-1, 5), (5, 5), (10, 3), (0, T + 1)):
+        with pytest.raises(swe.SweError):
+            swe.swe_mesh_create_shard(full.handle, a, b)
+    assert swe.lib.swe_shard_dt_combine(None, 1, None) == swe.SWE_EINVAL
+    assert swe.lib.swe_halo_pack(0, 5, None, None, None, None, None, None) == swe.SWE_EINVAL
+    assert swe.lib.swe_halo_pack(0, 0, None, None, None, None, None, None) == swe.SWE_OK
