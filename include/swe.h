@@ -55,6 +55,8 @@ extern "C" {
                                   a contiguous run of tiles (same results) */
 #define SWE_SHARD 2u           /* flag: the state is one shard of a mesh run on several devices;
                                   its steps leave the next dt to swe_shard_dt_combine */
+#define SWE_INDEX64 4u         /* flag: 64-bit index arithmetic in the tiled kernel even where
+                                  every array spans less than 4 GiB (same results) */
 #define SWE_TILE 256           /* cells per tile: consecutive mesh-order cells stepped by one
                                   workgroup, which stages them and their neighbours in LDS */
 
@@ -124,7 +126,7 @@ typedef struct swe_params {
     int32_t n_inflow;      /* number of inflow segments, <= SWE_MAX_INFLOW */
     const double *inflow_q;/* host, n_inflow unit discharges (m^2/s) entering, >= 0 */
     int32_t variant;       /* step kernel: SWE_AUTO, SWE_CELL or SWE_TILED (same results) */
-    int32_t flags;         /* SWE_NO_XCD_REMAP, SWE_SHARD or 0 */
+    int32_t flags;         /* SWE_NO_XCD_REMAP | SWE_SHARD | SWE_INDEX64, or 0 */
 } swe_params;
 
 /* Device state of one simulation.  All pointers device, element type given by dtype. */

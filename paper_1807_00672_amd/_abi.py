@@ -34,6 +34,7 @@ SWE_WALL = -1
 SWE_AUTO, SWE_CELL, SWE_TILED = 0, 1, 2
 SWE_NO_XCD_REMAP = 1
 SWE_SHARD = 2
+SWE_INDEX64 = 4
 SWE_TILE = 256
 
 (SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,

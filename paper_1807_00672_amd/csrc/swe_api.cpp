@@ -78,6 +78,7 @@ StepConfig make_config(const swe_mesh *mesh, const swe_params *p)
     c.n_cells = mesh->info.n_cells;
     c.n_owned = mesh->info.n_owned;
     c.shard = (p->flags & SWE_SHARD) ? 1 : 0;
+    c.index64 = (p->flags & SWE_INDEX64) ? 1 : 0;
     c.g = p->g;
     c.courant = p->courant;
     c.h_dry = p->h_dry;
@@ -209,7 +210,8 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     const std::string w(where);
     if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
         return fail(SWE_EINVAL, w + ": unknown variant");
-    if (p->flags & ~(SWE_NO_XCD_REMAP | SWE_SHARD)) return fail(SWE_EINVAL, w + ": unknown flags");
+    if (p->flags & ~(SWE_NO_XCD_REMAP | SWE_SHARD | SWE_INDEX64))
+        return fail(SWE_EINVAL, w + ": unknown flags");
     int variant = p->variant;
     if (variant == SWE_AUTO) {
         // a swe_tune result for this device, precision and size class decides, if there is one

@@ -89,6 +89,7 @@ struct StepConfig {
     double g, courant, h_dry;
     int32_t n_inflow;
     int32_t shard;     // 1: leave the next dt to swe_shard_dt_combine (SWE_SHARD)
+    int32_t index64;   // 1: 64-bit index arithmetic in the tiled kernel (SWE_INDEX64)
     double inflow_q[SWE_MAX_INFLOW];
 };
 

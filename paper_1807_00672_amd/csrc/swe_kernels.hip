@@ -1205,7 +1205,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     const Partials part = partials_for(s.work, nb);
     if (tl) {
         const size_t lds = tile_lds_bytes_for(dtype, *tl);
-        const bool o32 = offsets_fit_32(dm, dm.n_cells, *tl);
+        const bool o32 = !cfg.index64 && offsets_fit_32(dm, dm.n_cells, *tl);
         if (dtype == SWE_F64) {
             TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
             ta.s.part = part;

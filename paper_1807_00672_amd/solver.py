@@ -101,7 +101,7 @@ class Solver:
 
     def __init__(self, mesh: Mesh, z, n, h, hu, hv, dtype: str = "f64", g=9.81, courant=0.7,
                  h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None, variant="auto",
-                 xcd_remap=True, shard=False):
+                 xcd_remap=True, shard=False, index64=False):
         if mesh.device is None:
             raise ValueError("mesh has no device arrays")
         self.mesh = mesh
@@ -113,7 +113,8 @@ class Solver:
                                    self._q.ctypes.data_as(C.POINTER(C.c_double)),
                                    self.VARIANTS[variant],
                                    (0 if xcd_remap else A.SWE_NO_XCD_REMAP) |
-                                   (A.SWE_SHARD if shard else 0))
+                                   (A.SWE_SHARD if shard else 0) |
+                                   (A.SWE_INDEX64 if index64 else 0))
         t = mesh.n_cells
 
         def field(a):

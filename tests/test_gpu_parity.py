@@ -135,6 +135,12 @@ def test_tiled_and_per_cell_kernels_agree_bitwise(gpu, dtype):
     s.run(80)
     for x, y in zip(s.numpy_state(), a[2:]):
         assert np.array_equal(x, y)
+    # the tiled kernel's 64-bit index arithmetic (meshes beyond 4 GiB arrays) on a small mesh
+    s = swe.Solver(m, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype, variant="tiled",
+                   index64=True)
+    s.run(80)
+    for x, y in zip(s.numpy_state(), a[2:]):
+        assert np.array_equal(x, y)
     c = gen.ensemble_scenario(5)
     a = run_gpu(c, dtype, steps=50, variant="tiled")
     b = run_gpu(c, dtype, steps=50, variant="cell")
