@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the 256-scenario ensemble (0: skip it)")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the FP64 run with correctly rounded division and square root")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 10,000- and 1,000,000-cell configurations")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
@@ -353,30 +355,36 @@ def main():
     stream = torch.cuda.Stream()
     results = {}
     tuning = {}
-    for dt in args.dtypes.split(","):
-        # the autotuner picks the step variant and workgroup order that SWE_AUTO then runs
-        tuning[dt] = swe.tune.tune(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt,
-                                   steps=20)
-        print(f"# tuned {dt}: {tuning[dt]}", file=sys.stderr, flush=True)
-        solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt)
+    runs = [(dt, dt, False) for dt in args.dtypes.split(",")]
+    if "f64" in args.dtypes.split(",") and not args.no_exact:
+        runs.append(("f64_exact", "f64", True))   # correctly rounded FP64 division and sqrt
+    for key, dt, exact in runs:
+        if dt not in tuning:
+            # the autotuner picks the step variant and workgroup order that SWE_AUTO then runs
+            tuning[dt] = swe.tune.tune(mesh, case.z, case.n, case.h, case.hu, case.hv,
+                                       dtype=dt, steps=20)
+            print(f"# tuned {dt}: {tuning[dt]}", file=sys.stderr, flush=True)
+        solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt,
+                            exact=exact)
         ms, rc, st = time_gpu(solver, args.steps, args.warmup, stream)
         if rc != swe.SWE_OK or st["steps"] != args.warmup + args.steps:
-            raise RuntimeError(f"{dt}: run failed rc={rc} stats={st}")
+            raise RuntimeError(f"{key}: run failed rc={rc} stats={st}")
         word = 8 if dt == "f64" else 4
         per_step_s = ms * 1e-3 / args.steps
         alg = algorithmic_bytes(case.n_cells, case.n_nodes, word)
-        results[dt] = {
+        kernel = KERNELS[tuning[dt]["variant"]]
+        results[key] = {
             "value": case.n_cells * args.steps / (ms * 1e-3),
             "ms_per_step": ms / args.steps,
             "alg_bytes_per_step": alg,
             "achieved_GBps": alg / per_step_s / 1e9,
-            "kernel": KERNELS[tuning[dt]["variant"]],
-            "traffic": (load_traffic(dt, case.n_cells)
-                        if KERNELS[tuning[dt]["variant"]] == PROFILED_KERNEL else None),
+            "kernel": kernel,
+            "math": "correctly rounded" if exact else ("newton" if dt == "f64" else "hardware"),
+            "traffic": (load_traffic(key, case.n_cells) if kernel == PROFILED_KERNEL else None),
             "t_end_state": st["t"],
         }
-        print(f"# {dt}: {ms / args.steps:.4f} ms/step, {results[dt]['value'] / 1e9:.2f} G "
-              f"cell-updates/s, {results[dt]['achieved_GBps']:.0f} GB/s algorithmic",
+        print(f"# {key}: {ms / args.steps:.4f} ms/step, {results[key]['value'] / 1e9:.2f} G "
+              f"cell-updates/s, {results[key]['achieved_GBps']:.0f} GB/s algorithmic",
               file=sys.stderr, flush=True)
         del solver
         torch.cuda.empty_cache()
@@ -422,7 +430,7 @@ def main():
         torch.cuda.empty_cache()
 
     copy_gbps = copy_bandwidth()
-    main_dt = "f64" if "f64" in results else next(iter(results))
+    main_dt = "f64" if "f64" in results else next(iter(results))   # default FP64 arithmetic
     r = results[main_dt]
     line = {
         "metric": "cell-updates/s at 10M triangles (FP64 step; FP32 under variants)",

@@ -57,6 +57,9 @@ extern "C" {
                                   its steps leave the next dt to swe_shard_dt_combine */
 #define SWE_INDEX64 4u         /* flag: 64-bit index arithmetic in the tiled kernel even where
                                   every array spans less than 4 GiB (same results) */
+#define SWE_EXACT 8u           /* flag: FP64 division and square root correctly rounded, the
+                                  same bits as the host's IEEE operations in the same order;
+                                  default: hardware-seeded Newton forms, within an ulp */
 #define SWE_TILE 256           /* cells per tile: consecutive mesh-order cells stepped by one
                                   workgroup, which stages them and their neighbours in LDS */
 
@@ -126,7 +129,7 @@ typedef struct swe_params {
     int32_t n_inflow;      /* number of inflow segments, <= SWE_MAX_INFLOW */
     const double *inflow_q;/* host, n_inflow unit discharges (m^2/s) entering, >= 0 */
     int32_t variant;       /* step kernel: SWE_AUTO, SWE_CELL or SWE_TILED (same results) */
-    int32_t flags;         /* SWE_NO_XCD_REMAP | SWE_SHARD | SWE_INDEX64, or 0 */
+    int32_t flags;         /* SWE_NO_XCD_REMAP | SWE_SHARD | SWE_INDEX64 | SWE_EXACT, or 0 */
 } swe_params;
 
 /* Device state of one simulation.  All pointers device, element type given by dtype. */
@@ -267,7 +270,7 @@ typedef struct swe_batch_params {
     int32_t variant;               /* SWE_AUTO, SWE_CELL or SWE_TILED */
     const double *inflow_q;        /* device, n_scenarios * SWE_MAX_INFLOW unit discharges
                                       (m^2/s): scenario s's segment k at [s*16 + k-1] */
-    int32_t flags;                 /* SWE_NO_XCD_REMAP or 0 */
+    int32_t flags;                 /* SWE_NO_XCD_REMAP | SWE_EXACT, or 0 */
     int32_t reserved;
 } swe_batch_params;
 
@@ -426,9 +429,10 @@ int32_t swe_tune_set(int32_t device, int32_t dtype, int64_t n_cells, const swe_t
  * arrays of n elements of the dtype: left and right states (h, hu, hv, z) and a unit normal
  * (nx, ny) pointing from left to right; outputs f (3n: mass, x- and y-momentum flux per unit
  * length, at [3i..3i+2]) and the left bed correction p (n).  right_h == NULL evaluates a
- * reflective wall instead of a neighbour.  Queues work only.  Errors: SWE_EINVAL, SWE_EDEVICE.
+ * reflective wall instead of a neighbour.  flags: SWE_EXACT or 0, as for the step.  Queues work
+ * only.  Errors: SWE_EINVAL, SWE_EDEVICE.
  */
-int32_t swe_flux_eval(int32_t dtype, int64_t n, double g, double h_dry, const void *hl,
+int32_t swe_flux_eval(int32_t dtype, int32_t flags, int64_t n, double g, double h_dry, const void *hl,
                       const void *hul, const void *hvl, const void *zl, const void *hr,
                       const void *hur, const void *hvr, const void *zr, const void *nx,
                       const void *ny, void *f, void *p, void *stream);

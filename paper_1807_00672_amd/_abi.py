@@ -35,6 +35,7 @@ SWE_AUTO, SWE_CELL, SWE_TILED = 0, 1, 2
 SWE_NO_XCD_REMAP = 1
 SWE_SHARD = 2
 SWE_INDEX64 = 4
+SWE_EXACT = 8
 SWE_TILE = 256
 
 (SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,
@@ -165,7 +166,7 @@ def _load():
     L.swe_read_stats.argtypes = [C.POINTER(swe_state), C.POINTER(swe_run_stats), vp]
     L.swe_last_error.argtypes = []
     L.swe_last_error.restype = C.c_char_p
-    L.swe_flux_eval.argtypes = [i32, i64, dbl, dbl] + [vp] * 12 + [vp]
+    L.swe_flux_eval.argtypes = [i32, i32, i64, dbl, dbl] + [vp] * 12 + [vp]
     L.swe_adjoint_timings.argtypes = [C.POINTER(dbl), C.POINTER(dbl)]
     L.swe_mesh_create_shard.argtypes = [vp, i64, i64, C.POINTER(vp)]
     L.swe_halo_pack.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
@@ -271,9 +272,9 @@ def swe_read_stats(state, stats, stream=None) -> int:
 
 
 def swe_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny, f, p,
-                  stream=None) -> None:
-    _check(lib.swe_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx, ny, f,
-                             p, stream), "swe_flux_eval")
+                  stream=None, flags=0) -> None:
+    _check(lib.swe_flux_eval(dtype, flags, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx,
+                             ny, f, p, stream), "swe_flux_eval")
 
 
 def swe_batch_create(meshes) -> C.c_void_p:

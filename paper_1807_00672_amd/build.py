@@ -12,8 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libswe.so")
 
-SOURCES = ["swe_mesh.cpp", "swe_api.cpp", "swe_batch.cpp", "swe_tune.cpp", "swe_kernels.hip",
-           "swe_adjoint.hip"]
+SOURCES = ["swe_mesh.cpp", "swe_api.cpp", "swe_batch.cpp", "swe_tune.cpp", "swe_launch.cpp",
+           "swe_kernels.hip", "swe_kernels_fast.hip", "swe_adjoint.hip"]
 HEADERS = ["swe_internal.h", "swe_device_math.h"]
 
 # Contraction off: every product and sum rounds on its own, in the order the sources write

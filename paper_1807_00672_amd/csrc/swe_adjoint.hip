@@ -473,6 +473,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     memset(&cfg, 0, sizeof(cfg));
     cfg.n_cells = T;
     cfg.n_owned = T;
+    cfg.fast = (p->flags & SWE_EXACT) ? 0 : 1;
     cfg.g = p->g;
     cfg.courant = p->courant > 0.0 && p->courant <= 1.0 ? p->courant : 0.7;
     cfg.h_dry = p->h_dry;

@@ -79,6 +79,7 @@ StepConfig make_config(const swe_mesh *mesh, const swe_params *p)
     c.n_owned = mesh->info.n_owned;
     c.shard = (p->flags & SWE_SHARD) ? 1 : 0;
     c.index64 = (p->flags & SWE_INDEX64) ? 1 : 0;
+    c.fast = (p->dtype == SWE_F64 && !(p->flags & SWE_EXACT)) ? 1 : 0;
     c.g = p->g;
     c.courant = p->courant;
     c.h_dry = p->h_dry;
@@ -210,7 +211,7 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     const std::string w(where);
     if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
         return fail(SWE_EINVAL, w + ": unknown variant");
-    if (p->flags & ~(SWE_NO_XCD_REMAP | SWE_SHARD | SWE_INDEX64))
+    if (p->flags & ~(SWE_NO_XCD_REMAP | SWE_SHARD | SWE_INDEX64 | SWE_EXACT))
         return fail(SWE_EINVAL, w + ": unknown flags");
     int variant = p->variant;
     if (variant == SWE_AUTO) {
@@ -351,20 +352,22 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
     return swe_read_stats(s, out, stream);
 }
 
-int32_t swe_flux_eval(int32_t dtype, int64_t n, double g, double h_dry, const void *hl,
+int32_t swe_flux_eval(int32_t dtype, int32_t flags, int64_t n, double g, double h_dry, const void *hl,
                       const void *hul, const void *hvl, const void *zl, const void *hr,
                       const void *hur, const void *hvr, const void *zr, const void *nx,
                       const void *ny, void *f, void *p, void *stream)
 {
     if (dtype != SWE_F64 && dtype != SWE_F32) return fail(SWE_EINVAL, "swe_flux_eval: bad dtype");
+    if (flags & ~SWE_EXACT) return fail(SWE_EINVAL, "swe_flux_eval: unknown flags");
     if (n < 0) return fail(SWE_EINVAL, "swe_flux_eval: n < 0");
     if (n == 0) return SWE_OK;
     if (!hl || !hul || !hvl || !zl || !nx || !ny || !f || !p)
         return fail(SWE_EINVAL, "swe_flux_eval: null argument");
     if (hr && (!hur || !hvr || !zr)) return fail(SWE_EINVAL, "swe_flux_eval: partial right state");
     if (!(g > 0.0) || !(h_dry >= 0.0)) return fail(SWE_EINVAL, "swe_flux_eval: bad g or h_dry");
-    return check_hip(launch_flux_eval(dtype, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr, zr, nx,
-                                      ny, f, p, stream),
+    const bool fast_math = dtype == SWE_F64 && !(flags & SWE_EXACT);
+    return check_hip(launch_flux_eval(dtype, fast_math, n, g, h_dry, hl, hul, hvl, zl, hr, hur, hvr,
+                                      zr, nx, ny, f, p, stream),
                      "swe_flux_eval");
 }
 

@@ -68,7 +68,7 @@ int32_t check_batch_call(const swe_batch *b, const swe_batch_dev *d, const swe_b
     if (p->dtype != SWE_F64 && p->dtype != SWE_F32) return bfail(SWE_EINVAL, w + ": bad dtype");
     if (p->variant != SWE_AUTO && p->variant != SWE_CELL && p->variant != SWE_TILED)
         return bfail(SWE_EINVAL, w + ": unknown variant");
-    if (p->flags & ~SWE_NO_XCD_REMAP) return bfail(SWE_EINVAL, w + ": unknown flags");
+    if (p->flags & ~(SWE_NO_XCD_REMAP | SWE_EXACT)) return bfail(SWE_EINVAL, w + ": unknown flags");
     if (b->info.max_inflow_segments > 0 && !p->inflow_q)
         return bfail(SWE_EINVAL, w + ": scenarios have inflow segments but inflow_q is null");
     const swe_dev_mesh &m = d->mesh;
@@ -93,6 +93,7 @@ StepConfig batch_config(const swe_batch *b, const swe_batch_params *p)
     memset(&c, 0, sizeof(c));
     c.n_cells = b->info.n_cells;
     c.n_owned = b->info.n_cells;
+    c.fast = (p->dtype == SWE_F64 && !(p->flags & SWE_EXACT)) ? 1 : 0;
     c.g = p->g;
     c.courant = p->courant;
     c.h_dry = p->h_dry;

@@ -90,6 +90,7 @@ struct StepConfig {
     int32_t n_inflow;
     int32_t shard;     // 1: leave the next dt to swe_shard_dt_combine (SWE_SHARD)
     int32_t index64;   // 1: 64-bit index arithmetic in the tiled kernel (SWE_INDEX64)
+    int32_t fast;      // 1: FP64 division and square root by Newton forms (not SWE_EXACT)
     double inflow_q[SWE_MAX_INFLOW];
 };
 
@@ -109,26 +110,45 @@ struct BatchLaunch {
     int64_t n_tiles;
 };
 
-// Launchers (swe_kernels.hip).  batch == nullptr: a single mesh.  All queue work on `stream` and return a hipError_t as int.
-int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                double t0, double t_end, void *stream, const BatchLaunch *batch = nullptr);
-// tl == nullptr: the per-cell kernel; else the tiled kernel (its LDS must fit, see below).
-int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
-                int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
-                const BatchLaunch *batch = nullptr, int remap = 1,
-                double *const *ustar = nullptr);   // FP64: also write U* (before clamp)
-size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);
-int prepare_tile_kernels(size_t max_lds);   // allow dynamic LDS up to max_lds bytes
-int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);
-int launch_halo(int dtype, bool pack, int64_t n, const int32_t *idx, const void *buf_in,
-                void *buf_out, const void *h, const void *hu, const void *hv, void *ho, void *huo,
-                void *hvo, void *stream);
 constexpr int kMaxShards = 64;
-int launch_shard_combine(void *const *ctrls, int n, void *stream);
-int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *hl,
-                     const void *hul, const void *hvl, const void *zl, const void *hr,
-                     const void *hur, const void *hvr, const void *zr, const void *nx,
-                     const void *ny, void *f, void *p, void *stream);
+
+// Launchers.  swe_kernels.hip defines them twice, in swe::exact (correctly rounded FP64
+// division and square root) and swe::fast (their hardware-seeded Newton forms, within an ulp);
+// the ones in swe itself (swe_launch.cpp) pick by StepConfig::fast.  batch == nullptr: a single
+// mesh.  All queue work on `stream` and return a hipError_t as int.
+#define SWE_LAUNCHERS                                                                          \
+    int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg,                  \
+                    const swe_state &s, double t0, double t_end, void *stream,                 \
+                    const BatchLaunch *batch = nullptr);                                       \
+    /* tl == nullptr: the per-cell kernel; else the tiled kernel (its LDS must fit) */         \
+    int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg,                  \
+                    const swe_state &s, int cur, const double *dt_seq, int64_t n_seq,          \
+                    void *stream, const TileLayout *tl, const BatchLaunch *batch = nullptr,    \
+                    int remap = 1,                                                             \
+                    double *const *ustar = nullptr); /* FP64: also write U* before clamp */    \
+    size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);                                \
+    int prepare_tile_kernels(size_t max_lds); /* allow dynamic LDS up to max_lds bytes */      \
+    int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);              \
+    int launch_halo(int dtype, bool pack, int64_t n, const int32_t *idx, const void *buf_in,   \
+                    void *buf_out, const void *h, const void *hu, const void *hv, void *ho,    \
+                    void *huo, void *hvo, void *stream);                                       \
+    int launch_shard_combine(void *const *ctrls, int n, void *stream);                         \
+    int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *hl,         \
+                         const void *hul, const void *hvl, const void *zl, const void *hr,     \
+                         const void *hur, const void *hvr, const void *zr, const void *nx,     \
+                         const void *ny, void *f, void *p, void *stream);
+namespace exact {
+SWE_LAUNCHERS
+}
+namespace fast {
+SWE_LAUNCHERS
+}
+SWE_LAUNCHERS
+// the flux test hook in either mode
+int launch_flux_eval(int dtype, bool fast_math, int64_t n, double g, double h_dry,
+                     const void *hl, const void *hul, const void *hvl, const void *zl,
+                     const void *hr, const void *hur, const void *hvr, const void *zr,
+                     const void *nx, const void *ny, void *f, void *p, void *stream);
 
 void set_error(const std::string &msg);
 

@@ -1,23 +1,32 @@
-// HIP kernels of libswe for gfx950: the fused per-cell step, the dt reduction pass, the
-// initial-dt pass and the flux test hook.
+// HIP kernels of libswe for gfx950: the tiled and the per-cell step, the dt reductions, the
+// initial-dt pass, the shard helpers and the flux test hook.
 //
-// One work-item per cell (cells in Morton order).  Each cell gathers its three neighbours,
-// evaluates the three interface fluxes itself (section 2.2: HLLC with hydrostatic
-// reconstruction), accumulates them in local-edge order, applies the explicit Euler update of
-// eq. 4, clamps negative depths, applies semi-implicit Manning friction and finally computes
-// its CFL bound for the next step.  An interior edge is thus evaluated by both of its cells;
-// the flux is written so that the two evaluations are exact negatives of each other, which
-// keeps mass conservation exact up to the rounding of the cell sums, with no atomics.
+// Cells are in Morton order.  The tiled step (the default) stages a tile of 256 cells and its
+// halo in LDS and evaluates each interface of the tile once; the per-cell step has each cell
+// gather its three neighbours and evaluate its three interface fluxes itself (section 2.2: HLLC
+// with hydrostatic reconstruction).  Both accumulate a cell's contributions in local-edge
+// order, apply the explicit Euler update of eq. 4, clamp negative depths, apply semi-implicit
+// Manning friction and compute the cell's CFL bound for the next step.  The flux is written so
+// that the two sides' evaluations of an interface are exact negatives of each other, so both
+// kernels give the same bits and mass is conserved up to the rounding of the cell sums, with
+// no atomics.
 //
 // Every product and sum is rounded on its own (the library is built with contraction off),
-// in the order written here.
+// in the order written here.  This file is compiled twice: into swe::exact with correctly
+// rounded FP64 division and square root, and (swe_kernels_fast.hip) into swe::fast with their
+// hardware-seeded Newton forms; FP32 is the same in both.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include "swe_device_math.h"
 #include "swe_internal.h"
 
+#ifndef SWE_MATH_NS
+#define SWE_MATH_NS exact
+#endif
+
 namespace swe {
+namespace SWE_MATH_NS {
 namespace {
 
 constexpr double kInf = __builtin_huge_val();
@@ -1204,7 +1213,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     const int64_t grid = remap ? 8 * ((nb + 7) / 8) : nb;
     const Partials part = partials_for(s.work, nb);
     if (tl) {
-        const size_t lds = tile_lds_bytes_for(dtype, *tl);
+        const size_t lds = SWE_MATH_NS::tile_lds_bytes_for(dtype, *tl);
         const bool o32 = !cfg.index64 && offsets_fit_32(dm, dm.n_cells, *tl);
         if (dtype == SWE_F64) {
             TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
@@ -1308,4 +1317,5 @@ int launch_flux_eval(int dtype, int64_t n, double g, double h_dry, const void *h
     return static_cast<int>(hipGetLastError());
 }
 
+}  // namespace SWE_MATH_NS
 }  // namespace swe

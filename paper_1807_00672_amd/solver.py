@@ -101,7 +101,7 @@ class Solver:
 
     def __init__(self, mesh: Mesh, z, n, h, hu, hv, dtype: str = "f64", g=9.81, courant=0.7,
                  h_dry=1e-6, inflow_q=None, t0=0.0, t_end=0.0, stream=None, variant="auto",
-                 xcd_remap=True, shard=False, index64=False):
+                 xcd_remap=True, shard=False, index64=False, exact=False):
         if mesh.device is None:
             raise ValueError("mesh has no device arrays")
         self.mesh = mesh
@@ -114,7 +114,8 @@ class Solver:
                                    self.VARIANTS[variant],
                                    (0 if xcd_remap else A.SWE_NO_XCD_REMAP) |
                                    (A.SWE_SHARD if shard else 0) |
-                                   (A.SWE_INDEX64 if index64 else 0))
+                                   (A.SWE_INDEX64 if index64 else 0) |
+                                   (A.SWE_EXACT if exact else 0))
         t = mesh.n_cells
 
         def field(a):
@@ -223,7 +224,7 @@ class BatchSolver:
     """All scenarios' states in concatenated buffers; one launch per step steps them all."""
 
     def __init__(self, batch: Batch, cases, dtype="f64", g=9.81, courant=0.7, h_dry=1e-6,
-                 t0=0.0, t_end=0.0, stream=None, variant="auto", xcd_remap=True):
+                 t0=0.0, t_end=0.0, stream=None, variant="auto", xcd_remap=True, exact=False):
         self.batch = batch
         self.tdtype = torch.float64 if dtype == "f64" else torch.float32
         dev = batch.device
@@ -249,7 +250,8 @@ class BatchSolver:
         self.params = A.swe_batch_params(g, courant, h_dry,
                                          A.SWE_F64 if dtype == "f64" else A.SWE_F32,
                                          Solver.VARIANTS[variant], _ptr(self.q),
-                                         0 if xcd_remap else A.SWE_NO_XCD_REMAP, 0)
+                                         (0 if xcd_remap else A.SWE_NO_XCD_REMAP) |
+                                         (A.SWE_EXACT if exact else 0), 0)
         self.state = A.swe_state(
             (C.c_void_p * 2)(self.h[0].data_ptr(), self.h[1].data_ptr()),
             (C.c_void_p * 2)(self.hu[0].data_ptr(), self.hu[1].data_ptr()),
