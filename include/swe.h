@@ -403,12 +403,13 @@ typedef struct swe_tune_result {
  * mapping to the hardware open).  Times each variant x workgroup order for n_steps >= 2 steps
  * (graph replay, after 4 warm-up steps each) in three interleaved rounds, keeping each one's
  * best, on the initialised state s, which it advances by 16 + 12 n_steps steps at most (pass a
- * scratch state, or re-initialise afterwards), and records the fastest for this device, the
- * params' dtype and the size class floor(log2 n_cells) in a process-wide table.  SWE_AUTO then
- * launches that choice (SWE_NO_XCD_REMAP still forces the hardware order).  All candidates
- * compute the same bits.  Synchronises the stream.  *out (host) receives the timings.
- * Errors: SWE_EINVAL (bad argument, or the state stopped while tuning), SWE_EDEVICE, and any
- * status of swe_run.
+ * scratch state, or re-initialise afterwards).  Records the fastest for this device, the
+ * params' dtype and the size class floor(log2 n_cells) in a process-wide table, keeping the
+ * XCD-contiguous order unless the hardware order is more than 2 % faster (it moves fewer HBM
+ * bytes at equal time).  SWE_AUTO then launches that choice (SWE_NO_XCD_REMAP still forces
+ * the hardware order).  All candidates compute the same bits.  Synchronises the stream.
+ * *out (host) receives the timings.  Errors: SWE_EINVAL (bad argument, a shard, or the state
+ * stopped while tuning), SWE_EDEVICE, and any status of swe_run.
  */
 int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
                  swe_state *s, int32_t n_steps, swe_tune_result *out, void *stream);

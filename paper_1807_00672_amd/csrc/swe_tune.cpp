@@ -111,14 +111,23 @@ int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
             rc = tfail(SWE_EINVAL, "swe_tune: the state stopped (t_end or an error) while tuning");
     }
     double best = INFINITY;
+    int pick = -1;
     for (int c = 0; c < 4 && rc == SWE_OK; ++c) {
         if (!runs[c]) continue;
         r.ms_per_step[c] = best_ms[c];
         if (best_ms[c] < best) {
             best = best_ms[c];
-            r.variant = q[c].variant;
-            r.xcd_remap = (c & 1) ? 0 : 1;
+            pick = c;
         }
+    }
+    // The XCD-contiguous order keeps a tile's neighbours in its XCD's L2 and moves far fewer
+    // HBM bytes; keep it unless the hardware order is clearly (kTieBreak) faster.
+    constexpr double kTieBreak = 1.02;
+    if (pick >= 0 && (pick & 1) && runs[pick - 1] && best_ms[pick - 1] <= kTieBreak * best_ms[pick])
+        --pick;
+    if (pick >= 0) {
+        r.variant = q[pick].variant;
+        r.xcd_remap = (pick & 1) ? 0 : 1;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -21,7 +21,10 @@ def test_tuning_records_a_choice_that_auto_follows_with_identical_results(gpu, d
     ms = r["ms_per_step"]
     assert r["variant"] in ("cell", "tiled") and all(v > 0 for v in ms.values())
     best = min(ms, key=ms.get)
-    assert best.startswith(r["variant"]) and r["xcd_remap"] == best.endswith("+remap")
+    assert best.startswith(r["variant"])
+    # the XCD-contiguous order unless the hardware order is more than 2 % faster
+    assert r["xcd_remap"] == (best.endswith("+remap") or
+                              ms[r["variant"] + "+remap"] <= 1.02 * ms[r["variant"]])
     got = swe.tune.tuning(dtype, mesh.n_cells)
     assert got["variant"] == r["variant"] and got["xcd_remap"] == r["xcd_remap"]
     after = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype)
