@@ -154,9 +154,9 @@ def bench_shards(mesh, case, stream, parts: int = 8, steps: int = 100) -> dict:
             "exchange_us_per_step": us_x, "halo_cells_total": int(sum(halos))}
 
 
-def bench_configs(stream, dtypes, with_oracle: bool) -> dict:
+def bench_configs(stream, dtypes) -> dict:
     """Configs 1 (10,000-cell dam break, 200 steps) and 2 (1,000,000-cell wet/dry bumps, 1,000
-    steps) in full on the GPU, and with the CPU oracle on this host beside them."""
+    steps) in full on the GPU."""
     import gen
     import paper_1807_00672_amd as swe
     out = {}
@@ -171,15 +171,6 @@ def bench_configs(stream, dtypes, with_oracle: bool) -> dict:
                 raise RuntimeError(f"config {k} {dt}: rc={rc} stats={st}")
             r[dt] = {"cell_updates_per_s": case.n_cells * case.steps / (ms * 1e-3),
                      "ms_per_step": ms / case.steps}
-        if with_oracle:
-            import oracle
-            om = oracle.Mesh(case.xy, case.tri, case.edge_tag)
-            t0 = time.perf_counter()
-            rc, *_ = oracle.run_case(case, mesh=om)
-            el = time.perf_counter() - t0
-            assert rc == 0, rc
-            r["oracle"] = {"cell_updates_per_s": case.n_cells * case.steps / el,
-                           "threads": oracle.threads(), "s": el}
         out[f"config{k}"] = r
     return out
 
@@ -272,10 +263,11 @@ def copy_bandwidth(nbytes=2 << 30, reps=10):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def cpu_baseline(case, budget_s=12.0, single_budget_s=8.0):
+def cpu_baseline(case, budget_s=12.0, single_budget_s=8.0, config_ks=()):
     """The oracle, as it is, on this host: a bounded number of steps of the same workload, on
     all its OpenMP threads (`value`) and on one thread (`single_thread`, the paper's one-core
-    reference point)."""
+    reference point); and the configurations `config_ks` run in full (`configs`)."""
+    import gen
     import oracle
     t0 = time.perf_counter()
     mesh = oracle.Mesh(case.xy, case.tri, case.edge_tag)
@@ -299,12 +291,23 @@ def cpu_baseline(case, budget_s=12.0, single_budget_s=8.0):
         steps1, el1 = timed(single_budget_s, 20)
     finally:
         oracle.set_threads(nth)
+    configs = {}
+    for k in config_ks:   # the small configurations in full, beside the GPU's
+        c = gen.config(k)
+        om = oracle.Mesh(c.xy, c.tri, c.edge_tag)
+        t0 = time.perf_counter()
+        rc, *_ = oracle.run_case(c, mesh=om)
+        ek = time.perf_counter() - t0
+        assert rc == 0, rc
+        configs[f"config{k}"] = {"value": c.n_cells * c.steps / ek, "cores": nth,
+                                 "sample": f"{c.n_cells} cells, all {c.steps} steps ({ek:.1f} s)"}
     return {"value": case.n_cells * steps / el, "unit": "cell-updates/s", "cores": nth,
             "kind": "oracle",
             "sample": f"{case.n_cells} cells, {steps} steps from the initial state "
                       f"({el:.1f} s on {nth} OpenMP threads; mesh build {build_s:.1f} s untimed)",
             "single_thread": {"value": case.n_cells * steps1 / el1, "cores": 1,
-                              "sample": f"{steps1} steps ({el1:.1f} s)"}}
+                              "sample": f"{steps1} steps ({el1:.1f} s)"},
+            "configs": configs}
 
 
 def main():
@@ -412,13 +415,11 @@ def main():
 
     configs = {}
     if args.size == "full" and not args.no_configs:
-        configs = bench_configs(stream, args.dtypes.split(","), not args.no_cpu)
+        configs = bench_configs(stream, args.dtypes.split(","))
         for k, v in configs.items():
             print(f"# {k}: {v['n_cells']} cells x {v['steps']} steps: " +
                   ", ".join(f"{dt} {v[dt]['cell_updates_per_s'] / 1e9:.2f} G/s"
-                            for dt in args.dtypes.split(",")) +
-                  (f", oracle {v['oracle']['cell_updates_per_s'] / 1e6:.0f} M/s" if "oracle" in v
-                   else ""), file=sys.stderr, flush=True)
+                            for dt in args.dtypes.split(",")), file=sys.stderr, flush=True)
 
     adjoint = {}
     if args.adjoint_steps > 0 and args.size == "full":
@@ -464,7 +465,11 @@ def main():
         "device": torch.cuda.get_device_name(0),
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(case)
+        line["cpu_baseline"] = cpu_baseline(
+            case, config_ks=(1, 2) if args.size == "full" and not args.no_configs else ())
+        for k, v in line["cpu_baseline"]["configs"].items():
+            print(f"# oracle {k}: {v['value'] / 1e6:.0f} M cell-updates/s ({v['sample']})",
+                  file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
