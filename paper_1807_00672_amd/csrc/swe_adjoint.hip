@@ -13,7 +13,9 @@
 // the forward values and its derivative taken as is.  dt is replayed, not differentiated.
 //
 // Forward states are checkpointed every K steps; the reverse pass recomputes each segment
-// (storing U^n and the pre-friction U*) and then runs the adjoint through it backwards.
+// (storing U^n and the pre-friction U*) and then runs the adjoint through it backwards.  The
+// forward passes replay dt without the control block.  FP64 divisions and square roots of the
+// adjoint use the Newton forms of swe_device_math.h (within an ulp).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -31,7 +33,7 @@ struct Vjp3 {
     double h, hu, hv;
 };
 
-__device__ __forceinline__ double vel(double h, double hq, double hd) { return h > hd ? hq / h : 0.0; }
+__device__ __forceinline__ double vel(double h, double hq, double hd) { return h > hd ? div_nr(hq, h) : 0.0; }
 
 // Cotangents of (hl, ql, wl, hr, qr, wr) from those of the edge-frame HLLC flux (fh, fq, fw).
 __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, double hr, double qr,
@@ -40,7 +42,7 @@ __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, doubl
 {
     hlb = qlb = wlb = hrb = qrb = wrb = 0.0;
     if (hl == 0.0 && hr == 0.0) return;
-    const double cl = sqrt(g * hl), cr = sqrt(g * hr);
+    const double cl = sqrt_nr(g * hl), cr = sqrt_nr(g * hr);
     double sl, sr, us = 0.0, cs = 0.0;
     bool sl_a = true, sr_a = true;
     if (hl == 0.0) {
@@ -71,10 +73,10 @@ __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, doubl
     } else {
         const double den = sr - sl;
         const double dh = hr - hl, dq = hr * qr - hl * ql;
-        const double fh = ((sr * fhl - sl * fhr) + sl * sr * dh) / den;
-        const double fq = ((sr * fql - sl * fqr) + sl * sr * dq) / den;
-        const double sstar = (sl * hr * (qr - sr) - sr * hl * (ql - sl)) /
-                             (hr * (qr - sr) - hl * (ql - sl));
+        const double fh = div_nr((sr * fhl - sl * fhr) + sl * sr * dh, den);
+        const double fq = div_nr((sr * fql - sl * fqr) + sl * sr * dq, den);
+        const double sstar = div_nr(sl * hr * (qr - sr) - sr * hl * (ql - sl),
+                                    hr * (qr - sr) - hl * (ql - sl));
         const int sel = sstar > 0.0 ? 1 : (sstar < 0.0 ? 2 : 3);
         const double wup = sel == 1 ? wl : (sel == 2 ? wr : (wl + wr) / 2.0);
         const double fhtb = fhb + fwb * wup;
@@ -82,8 +84,8 @@ __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, doubl
         if (sel == 1) wlb += wupb;
         else if (sel == 2) wrb += wupb;
         else { wlb += 0.5 * wupb; wrb += 0.5 * wupb; }
-        const double nhb = fhtb / den, nqb = fqb / den;
-        const double denb = -(fhtb * fh + fqb * fq) / den;
+        const double nhb = div_nr(fhtb, den), nqb = div_nr(fqb, den);
+        const double denb = -div_nr(fhtb * fh + fqb * fq, den);
         srb += nhb * (fhl + sl * dh) + nqb * (fql + sl * dq) + denb;
         slb += nhb * (-fhr + sr * dh) + nqb * (-fqr + sr * dq) - denb;
         fhlb += nhb * sr;
@@ -122,8 +124,8 @@ __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, doubl
         qlb += 0.25 * csb;
         qrb -= 0.25 * csb;
     }
-    if (cl > 0.0) hlb += clb * g / (2.0 * cl);
-    if (cr > 0.0) hrb += crb * g / (2.0 * cr);
+    if (cl > 0.0) hlb += div_nr(clb * g, 2.0 * cl);
+    if (cr > 0.0) hrb += div_nr(crb * g, 2.0 * cr);
 }
 
 // Cotangent of a cell's velocity pair (u, v) = (hu, hv)/h pulled back to (h, hu, hv).
@@ -131,10 +133,10 @@ __device__ __forceinline__ void vel_vjp(double h, double hu, double hv, double h
                                         double vb, Vjp3 &out)
 {
     if (h > hd) {
-        const double u = hu / h, v = hv / h;
-        out.h -= (ub * u + vb * v) / h;
-        out.hu += ub / h;
-        out.hv += vb / h;
+        const double u = div_nr(hu, h), v = div_nr(hv, h);
+        out.h -= div_nr(ub * u + vb * v, h);
+        out.hu += div_nr(ub, h);
+        out.hv += div_nr(vb, h);
     }
 }
 
@@ -203,11 +205,11 @@ __device__ void wall_vjp(double g, double hd, double h, double hu, double hv, do
 __device__ void inflow_vjp(double g, double q_in, double h, double nx, double ny, double l,
                            const double *cb, Vjp3 &out)
 {
-    const double hc = cbrt_(q_in * q_in / g);
+    const double hc = cbrt_(div_nr(q_in * q_in, g));
     out = {0.0, 0.0, 0.0};
     if (h >= hc) {
         const double momb = l * (cb[1] * nx + cb[2] * ny);
-        out.h = momb * (-(q_in * q_in) / (h * h) + g * h);
+        out.h = momb * (-div_nr(q_in * q_in, h * h) + g * h);
     }
 }
 
@@ -250,23 +252,25 @@ __global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
     double mh = lh, mhu = 0.0, mhv = 0.0;
     if (hs > a.hd) {
         const double nm = a.n[i];
-        const double mag = sqrt(hus * hus + hvs * hvs);
+        const double mag = sqrt_nr(hus * hus + hvs * hvs);
         const double c = cbrt_(hs);
         const double P = hs * hs * c;
         const double K = dt * g * nm * nm;
-        const double D = 1.0 + K * mag / P;
-        const double hun = hus / D, hvn = hvs / D;
-        const double Db = -(lhu * hun + lhv * hvn) / D;
-        mhu = lhu / D;
-        mhv = lhv / D;
+        const double D = 1.0 + div_nr(K * mag, P);
+        const double rD = div_nr(1.0, D);
+        const double hun = hus * rD, hvn = hvs * rD;
+        const double Db = -(lhu * hun + lhv * hvn) * rD;
+        mhu = lhu * rD;
+        mhv = lhv * rD;
         if (mag > 0.0) {
-            const double magb = Db * K / P;
-            mhu += magb * hus / mag;
-            mhv += magb * hvs / mag;
+            const double magb = div_nr(Db * K, P);
+            const double rm = div_nr(1.0, mag);
+            mhu += magb * hus * rm;
+            mhv += magb * hvs * rm;
         }
-        const double Pb = -Db * K * mag / (P * P);
+        const double Pb = -div_nr(Db * K * mag, P * P);
         mh += Pb * (7.0 / 3.0) * hs * c;
-        a.gn[i] += Db * mag / P * 2.0 * dt * g * nm;
+        a.gn[i] += div_nr(Db * mag, P) * 2.0 * dt * g * nm;
     }
     if (clamped) mh = 0.0;
     a.mh[i] = mh;
@@ -283,19 +287,19 @@ __global__ __launch_bounds__(256) void flux_adjoint_kernel(AdjArgs a)
     const double dt = a.dt_seq[a.step], g = a.g, hd = a.hd;
     const double2 p[3] = {a.xy[a.c2n[i]], a.xy[a.c2n[T + i]], a.xy[a.c2n[2 * T + i]]};
     const double h = a.h[i], hu = a.hu[i], hv = a.hv[i], z = a.z[i];
-    const double ri = dt / a.area[i];
+    const double ri = div_nr(dt, a.area[i]);
     const double ci[3] = {-ri * a.mh[i], -ri * a.mhu[i], -ri * a.mhv[i]};
     double lh = a.mh[i], lhu = a.mhu[i], lhv = a.mhv[i], zb_sum = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double2 p0 = p[k], p1 = p[k == 2 ? 0 : k + 1];
         const double dx = p1.x - p0.x, dy = p1.y - p0.y;
-        const double l = sqrt(dx * dx + dy * dy);
-        const double nx = dy / l, ny = -dx / l;
+        const double l = sqrt_nr(dx * dx + dy * dy);
+        const double nx = div_nr(dy, l), ny = div_nr(-dx, l);
         const int32_t j = a.nbr[k * T + i];
         Vjp3 u{0.0, 0.0, 0.0};
         if (j >= 0) {
-            const double rj = dt / a.area[j];
+            const double rj = div_nr(dt, a.area[j]);
             const double cj[3] = {-rj * a.mh[j], -rj * a.mhu[j], -rj * a.mhv[j]};
             Vjp3 uj;
             double zi_b, zj_b;
@@ -508,13 +512,13 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     // forward pass: checkpoints and the loss (segment slots 0 and 1 serve as ping-pong)
     if (int32_t rc = copy3(ck(0, 0), ck(0, 1), ck(0, 2), s->h[s->cur], s->hu[s->cur], s->hv[s->cur])) return rc;
     if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(0, 0), ck(0, 1), ck(0, 2))) return rc;
+    // the steps replay dt_seq directly: no control block, no dt reduction
     swe_state fw = view(sg(0, 0), sg(0, 1), sg(0, 2), sg(1, 0), sg(1, 1), sg(1, 2));
-    if (int32_t rc = ahip(static_cast<hipError_t>(launch_init(SWE_F64, *dm, cfg, fw, 0.0, 0.0, st)), W)) return rc;
-    if (int32_t rc = ahip(static_cast<hipError_t>(launch_run_begin(fw, dt_seq, st)), W)) return rc;
     int cur = 0;
     for (int64_t nstep = 0; nstep < n_steps; ++nstep) {
         if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, fw, cur, dt_seq,
-                                                                  n_steps, st, tl, nullptr, remap)), W))
+                                                                  n_steps, st, tl, nullptr, remap,
+                                                                  nullptr, dt_seq + nstep)), W))
             return rc;
         cur ^= 1;
         const double *hc = static_cast<const double *>(fw.h[cur]);
@@ -554,16 +558,13 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     for (int64_t sgi = n_seg - 1; sgi >= 0; --sgi) {
         const int64_t s0 = sgi * K, s1 = std::min(n_steps, s0 + K);
         if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(sgi, 0), ck(sgi, 1), ck(sgi, 2))) return rc;
-        swe_state v0 = view(sg(0, 0), sg(0, 1), sg(0, 2), sg(1, 0), sg(1, 1), sg(1, 2));
-        if (int32_t rc = ahip(static_cast<hipError_t>(launch_init(SWE_F64, *dm, cfg, v0, 0.0, 0.0, st)), W)) return rc;
-        if (int32_t rc = ahip(static_cast<hipError_t>(launch_run_begin(v0, dt_seq + s0, st)), W)) return rc;
         for (int64_t nstep = s0; nstep < s1; ++nstep) {
             const int64_t q = nstep - s0;
             swe_state v = view(sg(q, 0), sg(q, 1), sg(q, 2), sg(q + 1, 0), sg(q + 1, 1), sg(q + 1, 2));
             double *ustar[3] = {ss(q, 0), ss(q, 1), ss(q, 2)};
             if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, v, 0, dt_seq + s0,
                                                                       s1 - s0, st, tl, nullptr,
-                                                                      remap, ustar)), W))
+                                                                      remap, ustar, dt_seq + nstep)), W))
                 return rc;
         }
         for (int64_t nstep = s1 - 1; nstep >= s0; --nstep) {

@@ -5,6 +5,35 @@
 
 namespace swe {
 
+// FP64 division by the hardware reciprocal refined by two Newton steps, the quotient by one
+// residual correction: within an ulp of the correctly rounded quotient for normal operands,
+// odd in each argument.
+__device__ __forceinline__ double div_nr(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    const double q = a * r;
+    const double rem = fma(-b, q, a);
+    return fma(rem, r, q);
+}
+
+// FP64 square root by the hardware reciprocal square root refined by Goldschmidt's iteration
+// and one residual correction: within an ulp of the correctly rounded root; sqrt(0) = 0.
+__device__ __forceinline__ double sqrt_nr(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    return a > 0.0 ? g : a;   // rsq(0) is inf
+}
+
 // Cube root of a positive normal argument by Newton's iteration for r = x^(-1/3), which needs
 // no division: r <- r + r (1 - x r^3) / 3, from the single-precision seed 2^(-log2(x) / 3) (the
 // hardware log2 and exp2, relative error a few 1e-6 over the range taken here).  Two steps

@@ -125,7 +125,8 @@ constexpr int kMaxShards = 64;
                     const swe_state &s, int cur, const double *dt_seq, int64_t n_seq,          \
                     void *stream, const TileLayout *tl, const BatchLaunch *batch = nullptr,    \
                     int remap = 1,                                                             \
-                    double *const *ustar = nullptr); /* FP64: also write U* before clamp */    \
+                    double *const *ustar = nullptr,  /* FP64: also write U* before clamp */    \
+                    const double *dt_direct = nullptr); /* replay: dt here, no reduction */    \
     size_t tile_lds_bytes_for(int dtype, const TileLayout &tl);                                \
     int prepare_tile_kernels(size_t max_lds); /* allow dynamic LDS up to max_lds bytes */      \
     int launch_run_begin(const swe_state &s, const double *dt_seq, void *stream);              \

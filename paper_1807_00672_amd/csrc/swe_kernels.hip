@@ -69,31 +69,16 @@ __device__ __forceinline__ R sqrt_(R a)
 #define SWE_F64_FAST 0
 #endif
 #if SWE_F64_FAST
-// Reciprocal by v_rcp_f64 and two Newton steps, quotient with one residual correction; square
-// root by v_rsq_f64 and Goldschmidt's iteration with a final residual correction.
+// Newton forms of swe_device_math.h (within an ulp, odd in their sign arguments).
 template <>
 __device__ __forceinline__ double div_<double>(double a, double b)
 {
-    double r = __builtin_amdgcn_rcp(b);
-    double e = fma(-b, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-b, r, 1.0);
-    r = fma(r, e, r);
-    const double q = a * r;
-    const double rem = fma(-b, q, a);
-    return fma(rem, r, q);
+    return div_nr(a, b);
 }
 template <>
 __device__ __forceinline__ double sqrt_<double>(double a)
 {
-    const double y = __builtin_amdgcn_rsq(a);
-    double g = a * y, h = 0.5 * y;
-    const double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    const double d = fma(-g, g, a);
-    g = fma(d, h, g);
-    return a > 0.0 ? g : a;   // sqrt(0) = 0 (rsq(0) is inf)
+    return sqrt_nr(a);
 }
 #endif
 #if SWE_F32_FAST
@@ -447,6 +432,7 @@ struct StepArgs {
     const Ctrl *ctrl;
     Partials part;
     R *us_h, *us_hu, *us_hv;   // optional: U* before clamp and friction (adjoint recompute)
+    const double *dt_direct;   // optional: this step's dt; then no control block, no partials
 };
 
 // One explicit step for every cell (eq. 4 with the source treatments of section 2.2).
@@ -460,13 +446,13 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
     const int scen = batched ? bt.tile_scen[tile] : 0;
     const Ctrl *ctrl = ctrl_of(a.ctrl, scen);
     const double *qtab = batched ? bt.q_table + scen * SWE_MAX_INFLOW : nullptr;
-    if (ctrl->done) return;   // uniform over the workgroup: its state has stopped
+    if (!a.dt_direct && ctrl->done) return;   // uniform over the workgroup: its state stopped
     const int64_t T = cfg.n_cells;
     const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
     const int64_t s1 = batched ? bt.tile_start[tile + 1] : s0 + kBlock;
     const int64_t i = s0 + threadIdx.x;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
-    const R dt = static_cast<R>(ctrl->dt);
+    const R dt = static_cast<R>(a.dt_direct ? *a.dt_direct : ctrl->dt);
     R dtc = static_cast<R>(kInf);
     int clamp = 0, flag = 0;
     if (i < s1 && i < T) {
@@ -537,6 +523,7 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
             flag = 0;
         }
     }
+    if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
     block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
 }
 
@@ -606,7 +593,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     const int scen = batched ? bt.tile_scen[tile] : 0;
     const Ctrl *ctrl = ctrl_of(a.ctrl, scen);
     const double *qtab = batched ? bt.q_table + scen * SWE_MAX_INFLOW : nullptr;
-    if (ctrl->done) return;   // uniform over the workgroup: its scenario has stopped
+    if (!a.dt_direct && ctrl->done) return;   // uniform over the workgroup: its scenario stopped
     extern __shared__ __align__(16) unsigned char smem[];
     const int ns = kBlock + ta.max_halo;
     R *s_h = reinterpret_cast<R *>(smem);
@@ -626,7 +613,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     const int64_t i = s0 + tid;
     const bool mine = i < s1 && i < T;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
-    const R dt = static_cast<R>(ctrl->dt);
+    const R dt = static_cast<R>(a.dt_direct ? *a.dt_direct : ctrl->dt);
 
     // global loads: own cell
     R h = R(0), hu = R(0), hv = R(0), zc = R(0), nm = R(0);
@@ -779,6 +766,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
             flag = 0;
         }
     }
+    if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
     block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
 }
 
@@ -1106,6 +1094,7 @@ StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
     a.ctrl = static_cast<const Ctrl *>(s.ctrl);
     a.part = partials_for(s.work, n_blocks(dm.n_cells));
     a.us_h = a.us_hu = a.us_hv = nullptr;
+    a.dt_direct = nullptr;
     return a;
 }
 
@@ -1203,7 +1192,8 @@ bool offsets_fit_32(const swe_dev_mesh &dm, int64_t n_cells, const TileLayout &t
 
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
-                const BatchLaunch *batch, int remap, double *const *ustar)
+                const BatchLaunch *batch, int remap, double *const *ustar,
+                const double *dt_direct)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nb = batch ? batch->n_tiles : n_blocks(cfg.n_cells);
@@ -1218,6 +1208,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
         if (dtype == SWE_F64) {
             TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
             ta.s.part = part;
+            ta.s.dt_direct = dt_direct;
             if (ustar) {
                 ta.s.us_h = ustar[0];
                 ta.s.us_hu = ustar[1];
@@ -1230,6 +1221,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
         } else {
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
             ta.s.part = part;
+            ta.s.dt_direct = dt_direct;
             if (o32)
                 tile_step_kernel<float, true><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
             else
@@ -1238,6 +1230,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     } else if (dtype == SWE_F64) {
         StepArgs<double> a = make_args<double>(dm, s, cur);
         a.part = part;
+        a.dt_direct = dt_direct;
         if (ustar) {
             a.us_h = ustar[0];
             a.us_hu = ustar[1];
@@ -1247,8 +1240,10 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     } else {
         StepArgs<float> a = make_args<float>(dm, s, cur);
         a.part = part;
+        a.dt_direct = dt_direct;
         step_kernel<float><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
     }
+    if (dt_direct) return static_cast<int>(hipGetLastError());   // no reduction to finish
     if (SWE_DT_FOLD && batch == nullptr)
         dt_fold_kernel<<<dim3(n_groups(nb)), dim3(kGroup), 0, st>>>(
             static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, cfg.shard);

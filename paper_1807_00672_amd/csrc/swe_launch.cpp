@@ -16,12 +16,13 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
 
 int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 int cur, const double *dt_seq, int64_t n_seq, void *stream, const TileLayout *tl,
-                const BatchLaunch *batch, int remap, double *const *ustar)
+                const BatchLaunch *batch, int remap, double *const *ustar,
+                const double *dt_direct)
 {
     return cfg.fast ? fast::launch_step(dtype, dm, cfg, s, cur, dt_seq, n_seq, stream, tl, batch,
-                                        remap, ustar)
+                                        remap, ustar, dt_direct)
                     : exact::launch_step(dtype, dm, cfg, s, cur, dt_seq, n_seq, stream, tl, batch,
-                                         remap, ustar);
+                                         remap, ustar, dt_direct);
 }
 
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
