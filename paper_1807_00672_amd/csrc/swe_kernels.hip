@@ -51,6 +51,14 @@ constexpr double kInf = __builtin_huge_val();
 #ifndef SWE_DT_FOLD
 #define SWE_DT_FOLD 1
 #endif
+// Single-mesh steps of at most this many tiles finish their dt reduction themselves (the last
+// workgroup to arrive folds the partials) instead of launching the fold kernel.  Each
+// workgroup's release then writes back its XCD's L2, which costs more than the fold launch
+// beyond a few hundred workgroups (measured: 10,000 cells 14.4 -> 12.4 us per step, 250,000
+// cells 21.4 -> 40.4 us).
+#ifndef SWE_FUSE_TILES
+#define SWE_FUSE_TILES 128
+#endif
 // 1: the tiled kernel addresses arrays below 4 GiB by 32-bit byte offsets; 0: always 64-bit.
 #ifndef SWE_OFF32
 #define SWE_OFF32 1
@@ -321,7 +329,7 @@ __device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
 
 // Account for the step just taken (m: min CFL bound over the cells, cl: clamps, fl: status
 // bits of the new state), then set the next step's dt: CFL, replayed from dt_seq, or cut at
-// t_end (section 2.4).
+// t_end (section 2.2, Courant number).
 __device__ void advance_ctrl(Ctrl *ctrl, double m, long long cl, int fl, double courant,
                              const double *dt_seq, int64_t n_seq, int shard)
 {
@@ -360,6 +368,51 @@ __device__ void advance_ctrl(Ctrl *ctrl, double m, long long cl, int fl, double 
         }
     }
     *ctrl = c;
+}
+
+// How a small single-mesh step finishes its dt reduction itself (ctrl == nullptr: a fold
+// kernel follows the step instead).
+struct Advance {
+    Ctrl *ctrl;
+    const double *dt_seq;
+    int64_t n_seq;
+    double courant;
+    int32_t shard;
+    int32_t pad;
+};
+
+// Block partials of tile `slot`; with adv.ctrl, the last workgroup to arrive (a release
+// increment by each, an acquire before reading) folds all n_tiles partials and advances the
+// control block.  No workgroup waits for another; every one read the control block before it
+// arrived.
+__device__ __forceinline__ void finish_step(double dtc, int clamp, int flag, const Partials &part,
+                                            int slot, int n_tiles, const Advance &adv)
+{
+    block_partials_at(dtc, clamp, flag, part, slot);
+    if (!adv.ctrl || threadIdx.x >= 64) return;
+    // wave 0 only; work-item 0 wrote the partial
+    uint32_t old = 0;
+    if (threadIdx.x == 0)
+        old = __hip_atomic_fetch_add(part.count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    old = __shfl(old, 0, 64);
+    if (old != static_cast<uint32_t>(n_tiles - 1)) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double m = kInf;
+    long long cl = 0;
+    int fl = 0;
+    for (int b = static_cast<int>(threadIdx.x); b < n_tiles; b += 64) {
+        m = fmin(m, part.dt[b]);
+        cl += part.clamps[b];
+        fl |= part.flags[b];
+    }
+    m = wave_min(m);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cl += __shfl_xor(cl, off, 64);
+    fl = wave_or(fl);
+    if (threadIdx.x == 0) {
+        part.count[0] = 0;
+        advance_ctrl(adv.ctrl, m, cl, fl, adv.courant, adv.dt_seq, adv.n_seq, adv.shard);
+    }
 }
 
 // CFL bound r / (|u| + sqrt(g h)) of a cell (inflow edges add their boundary speed);
@@ -433,6 +486,7 @@ struct StepArgs {
     Partials part;
     R *us_h, *us_hu, *us_hv;   // optional: U* before clamp and friction (adjoint recompute)
     const double *dt_direct;   // optional: this step's dt; then no control block, no partials
+    Advance adv;               // small grids: the step folds its own partials
 };
 
 // One explicit step for every cell (eq. 4 with the source treatments of section 2.2).
@@ -524,7 +578,7 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
+    finish_step(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv);
 }
 
 // ------------------------------------------------------------------------ tiled step
@@ -767,7 +821,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    block_partials_at(static_cast<double>(dtc), clamp, flag, a.part, tile);
+    finish_step(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv);
 }
 
 // CFL bounds of the initial state.
@@ -1095,6 +1149,7 @@ StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
     a.part = partials_for(s.work, n_blocks(dm.n_cells));
     a.us_h = a.us_hu = a.us_hv = nullptr;
     a.dt_direct = nullptr;
+    a.adv = Advance{nullptr, nullptr, 0, 0.0, 0, 0};
     return a;
 }
 
@@ -1202,6 +1257,9 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     bv.n_tiles = static_cast<int32_t>(nb);
     const int64_t grid = remap ? 8 * ((nb + 7) / 8) : nb;
     const Partials part = partials_for(s.work, nb);
+    const bool fuse = batch == nullptr && dt_direct == nullptr && nb <= SWE_FUSE_TILES;
+    const Advance adv{fuse ? static_cast<Ctrl *>(s.ctrl) : nullptr, dt_seq, n_seq, cfg.courant,
+                      cfg.shard, 0};
     if (tl) {
         const size_t lds = SWE_MATH_NS::tile_lds_bytes_for(dtype, *tl);
         const bool o32 = !cfg.index64 && offsets_fit_32(dm, dm.n_cells, *tl);
@@ -1209,6 +1267,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
             TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
             ta.s.part = part;
             ta.s.dt_direct = dt_direct;
+            ta.s.adv = adv;
             if (ustar) {
                 ta.s.us_h = ustar[0];
                 ta.s.us_hu = ustar[1];
@@ -1222,6 +1281,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
             ta.s.part = part;
             ta.s.dt_direct = dt_direct;
+            ta.s.adv = adv;
             if (o32)
                 tile_step_kernel<float, true><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
             else
@@ -1231,6 +1291,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
         StepArgs<double> a = make_args<double>(dm, s, cur);
         a.part = part;
         a.dt_direct = dt_direct;
+        a.adv = adv;
         if (ustar) {
             a.us_h = ustar[0];
             a.us_hu = ustar[1];
@@ -1241,9 +1302,10 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
         StepArgs<float> a = make_args<float>(dm, s, cur);
         a.part = part;
         a.dt_direct = dt_direct;
+        a.adv = adv;
         step_kernel<float><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
     }
-    if (dt_direct) return static_cast<int>(hipGetLastError());   // no reduction to finish
+    if (dt_direct || fuse) return static_cast<int>(hipGetLastError());   // nothing to launch
     if (SWE_DT_FOLD && batch == nullptr)
         dt_fold_kernel<<<dim3(n_groups(nb)), dim3(kGroup), 0, st>>>(
             static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, cfg.shard);
