@@ -37,11 +37,12 @@ class Calibration:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.loss = A.swe_loss(_ptr(self.gauges), len(gauges), self.every, _ptr(self.obs))
 
-    def run(self, n, z, h, hu, hv, stream=None):
-        """J and its gradients (dn, dz, dh, dhu, dhv) as float64 numpy arrays in input order."""
+    def run(self, n, z, h, hu, hv, stream=None, variant="auto"):
+        """J and its gradients (dn, dz, dh, dhu, dhv) as float64 numpy arrays in input order.
+        variant: the step kernel of the forward passes ("tiled" also tiles the flux adjoint)."""
         m = self.mesh
         sv = Solver(m, z, n, h, hu, hv, dtype="f64", g=self.g, h_dry=self.h_dry,
-                    inflow_q=self.inflow_q, stream=stream)
+                    inflow_q=self.inflow_q, stream=stream, variant=variant)
         t = m.n_cells
         out = [torch.empty(t, dtype=torch.float64, device=m.device) for _ in range(5)]
         grads = A.swe_grads(*[_ptr(o) for o in out])

@@ -26,6 +26,11 @@
 #include "swe_device_math.h"
 #include "swe_internal.h"
 
+// 1: the flux adjoint runs tiled (each interface once) wherever the step runs tiled.
+#ifndef SWE_TILE_ADJOINT
+#define SWE_TILE_ADJOINT 1
+#endif
+
 namespace swe {
 namespace {
 
@@ -321,6 +326,111 @@ __global__ __launch_bounds__(256) void flux_adjoint_kernel(AdjArgs a)
     a.gz[i] += zb_sum;
 }
 
+// Tile lists of the mesh (as the tiled step uses them).
+struct AdjTiles {
+    const int32_t *halo_off, *halo, *edge_off;
+    const uint32_t *edges;
+    const uint16_t *slot;
+    int32_t n_tiles, max_halo, max_edges, pad;
+};
+
+// LDS of the tiled flux adjoint: 7 words per staged cell (h, hu, hv, z and the cotangent
+// -dt/A mu of its contribution), 8 per edge-list entry (both sides' cotangents and bed terms).
+inline size_t tile_adj_lds_bytes(int64_t max_halo, int64_t max_edges)
+{
+    return 8 * static_cast<size_t>(7 * (SWE_TILE + max_halo) + 8 * max_edges);
+}
+
+// The flux adjoint of flux_adjoint_kernel, tiled: each interface of a tile's edge list is
+// differentiated once (both sides' cotangents at once) into LDS, then each cell gathers its
+// three shares in local-edge order.  Same quantities as the per-cell kernel, up to rounding.
+__global__ __launch_bounds__(256) void tile_flux_adjoint_kernel(AdjArgs a, AdjTiles t)
+{
+    const int tile = blockIdx.x;
+    if (tile >= t.n_tiles) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ns = SWE_TILE + t.max_halo, M = t.max_edges;
+    double *s_h = reinterpret_cast<double *>(smem);
+    double *s_hu = s_h + ns, *s_hv = s_hu + ns, *s_z = s_hv + ns;
+    double *s_c0 = s_z + ns, *s_c1 = s_c0 + ns, *s_c2 = s_c1 + ns;
+    double *e_a = s_c2 + ns;        // [4][M]: side a's (h, hu, hv) cotangent and bed term
+    double *e_b = e_a + 4 * M;      // [4][M]: side b's, for interfaces inside the tile
+    const int64_t T = a.T, s0 = static_cast<int64_t>(tile) * SWE_TILE;
+    const int tid = threadIdx.x;
+    const int64_t i = s0 + tid;
+    const bool mine = i < T;
+    const double dt = a.dt_seq[a.step], g = a.g, hd = a.hd;
+    auto stage = [&](int q, int64_t c) {
+        s_h[q] = a.h[c];
+        s_hu[q] = a.hu[c];
+        s_hv[q] = a.hv[c];
+        s_z[q] = a.z[c];
+        const double r = div_nr(dt, a.area[c]);
+        s_c0[q] = -r * a.mh[c];
+        s_c1[q] = -r * a.mhu[c];
+        s_c2[q] = -r * a.mhv[c];
+    };
+    if (mine) stage(tid, i);
+    const int hb = t.halo_off[tile], he = t.halo_off[tile + 1];
+    for (int j = hb + tid; j < he; j += SWE_TILE) stage(SWE_TILE + (j - hb), t.halo[j]);
+    __syncthreads();
+
+    const int eb = t.edge_off[tile], ee = t.edge_off[tile + 1];
+    for (int e = eb + tid; e < ee; e += SWE_TILE) {
+        const uint32_t w = t.edges[e];
+        const int ca = static_cast<int>(w & 0xffu);
+        const int k = static_cast<int>((w >> 8) & 3u);
+        const int cb = static_cast<int16_t>(w >> 16);
+        const double2 p0 = a.xy[a.c2n[k * T + s0 + ca]];
+        const double2 p1 = a.xy[a.c2n[(k == 2 ? 0 : k + 1) * T + s0 + ca]];
+        const double dx = p1.x - p0.x, dy = p1.y - p0.y;
+        const double l = sqrt_nr(dx * dx + dy * dy);
+        const double nx = div_nr(dy, l), ny = div_nr(-dx, l);
+        const double ci[3] = {s_c0[ca], s_c1[ca], s_c2[ca]};
+        Vjp3 u{0.0, 0.0, 0.0};
+        double za_b = 0.0;
+        const int q = e - eb;
+        if (cb >= 0) {
+            const double cj[3] = {s_c0[cb], s_c1[cb], s_c2[cb]};
+            Vjp3 ub;
+            double zb_b;
+            interface_vjp(g, hd, s_h[ca], s_hu[ca], s_hv[ca], s_z[ca], s_h[cb], s_hu[cb],
+                          s_hv[cb], s_z[cb], nx, ny, l, ci, cj, u, za_b, ub, zb_b);
+            if (cb < SWE_TILE) {
+                e_b[q] = ub.h;
+                e_b[M + q] = ub.hu;
+                e_b[2 * M + q] = ub.hv;
+                e_b[3 * M + q] = zb_b;
+            }
+        } else if (cb == SWE_WALL) {
+            wall_vjp(g, hd, s_h[ca], s_hu[ca], s_hv[ca], nx, ny, l, ci, u);
+        } else {
+            inflow_vjp(g, a.q[-2 - cb], s_h[ca], nx, ny, l, ci, u);
+        }
+        e_a[q] = u.h;
+        e_a[M + q] = u.hu;
+        e_a[2 * M + q] = u.hv;
+        e_a[3 * M + q] = za_b;
+    }
+    __syncthreads();
+    if (!mine) return;
+    double lh = a.mh[i], lhu = a.mhu[i], lhv = a.mhv[i], zb_sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t sl = t.slot[k * T + i];
+        const int q = static_cast<int>(sl & 0x7fffu);
+        const double *ed = (sl & 0x8000u) ? e_b : e_a;
+        lh += ed[q];
+        lhu += ed[M + q];
+        lhv += ed[2 * M + q];
+        zb_sum += ed[3 * M + q];
+    }
+    a.lh[i] = lh;
+    a.lhu[i] = lhu;
+    a.lhv[i] = lhv;
+    a.gz[i] += zb_sum;
+}
+
 // Misfit at an observation: the loss gains sum (h_g - obs_g)^2 (one work-item, fixed order);
 // with lam != nullptr the adjoint gains 2 (h_g - obs_g) at the gauges instead.
 __global__ void misfit_kernel(const double *h, const int32_t *gauges, int ng, const double *obs,
@@ -551,6 +661,24 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     a.g = p->g;
     a.hd = p->h_dry;
     for (int k = 0; k < p->n_inflow; ++k) a.q[k] = p->inflow_q[k];
+    // the tiled flux adjoint where the step is tiled and its LDS fits the default 64 KiB
+    AdjTiles at;
+    memset(&at, 0, sizeof(at));
+    size_t adj_lds = 0;
+    if (tl && SWE_TILE_ADJOINT) {
+        const size_t need = tile_adj_lds_bytes(tl->max_halo, tl->max_edges);
+        if (need <= 65536) {
+            adj_lds = need;
+            at.halo_off = dm->halo_off;
+            at.halo = dm->halo;
+            at.edge_off = dm->edge_off;
+            at.edges = dm->edges;
+            at.slot = dm->slot;
+            at.n_tiles = static_cast<int32_t>(tl->n_tiles);
+            at.max_halo = tl->max_halo;
+            at.max_edges = tl->max_edges;
+        }
+    }
     fill_kernel<<<(3 * S + 255) / 256, 256, 0, st>>>(lam, 3 * T, 0.0);
     fill_kernel<<<blocks, 256, 0, st>>>(out->dn, T, 0.0);
     fill_kernel<<<blocks, 256, 0, st>>>(out->dz, T, 0.0);
@@ -577,7 +705,10 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
             a.sh = ss(q, 0); a.shu = ss(q, 1); a.shv = ss(q, 2);
             friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
             a.h = sg(q, 0); a.hu = sg(q, 1); a.hv = sg(q, 2);
-            flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+            if (adj_lds)
+                tile_flux_adjoint_kernel<<<dim3(static_cast<unsigned>(at.n_tiles)), 256, adj_lds, st>>>(a, at);
+            else
+                flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
         }
         if (int32_t rc = ahip(hipGetLastError(), W)) return rc;
     }

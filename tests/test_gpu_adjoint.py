@@ -75,6 +75,19 @@ def test_checkpoint_interval_does_not_change_gradients(setup, gpu):
         assert np.array_equal(a, b)
 
 
+def test_tiled_and_per_cell_adjoints_agree(setup, gpu):
+    """The tiled flux adjoint differentiates each interface once, the per-cell one once per
+    side: the same quantities, summed in the same order, up to rounding."""
+    case, om, dts, obs, calib, j, grads = setup
+    jc, gc = calib.run(case.n, case.z, case.h, case.hu, case.hv, variant="cell")
+    jt, gt = calib.run(case.n, case.z, case.h, case.hu, case.hv, variant="tiled")
+    assert jc == jt == j
+    for a, b in zip(gc, gt):
+        scale = np.abs(a).max()
+        print(f"max |grad| {scale:.3e}, max difference {np.abs(a - b).max():.3e}")
+        assert np.abs(a - b).max() <= 1e-12 * scale
+
+
 def test_autograd_function(setup, gpu):
     import torch
     case, om, dts, obs, calib, j, grads = setup
