@@ -385,10 +385,14 @@ struct Advance {
 // increment by each, an acquire before reading) folds all n_tiles partials and advances the
 // control block.  No workgroup waits for another; every one read the control block before it
 // arrived.
+// Fuse selects this at compile time: the kernels without it run measurably faster on large
+// grids even though the branch is never taken there.
+template <bool Fuse>
 __device__ __forceinline__ void finish_step(double dtc, int clamp, int flag, const Partials &part,
                                             int slot, int n_tiles, const Advance &adv)
 {
     block_partials_at(dtc, clamp, flag, part, slot);
+    if constexpr (Fuse) {
     if (!adv.ctrl || threadIdx.x >= 64) return;
     // wave 0 only; work-item 0 wrote the partial
     uint32_t old = 0;
@@ -412,6 +416,7 @@ __device__ __forceinline__ void finish_step(double dtc, int clamp, int flag, con
     if (threadIdx.x == 0) {
         part.count[0] = 0;
         advance_ctrl(adv.ctrl, m, cl, fl, adv.courant, adv.dt_seq, adv.n_seq, adv.shard);
+    }
     }
 }
 
@@ -490,7 +495,7 @@ struct StepArgs {
 };
 
 // One explicit step for every cell (eq. 4 with the source treatments of section 2.2).
-template <typename R>
+template <typename R, bool Fuse>
 __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a, StepConfig cfg,
                                                                    Batch bt)
 {
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv);
+    finish_step<Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv);
 }
 
 // ------------------------------------------------------------------------ tiled step
@@ -636,7 +641,7 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
 // computes them.  Phase 3 sums each cell's three contributions in local-edge order and
 // applies the update of eq. 4, the clamp, the friction and the next CFL bound, as the
 // per-cell kernel does.
-template <typename R, bool O32>
+template <typename R, bool O32, bool Fuse>
 __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
                                                            Batch bt)
 {
@@ -821,7 +826,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv);
+    finish_step<Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv);
 }
 
 // CFL bounds of the initial state.
@@ -1220,10 +1225,14 @@ size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
 
 int prepare_tile_kernels(size_t max_lds)
 {
-    const void *k[4] = {reinterpret_cast<const void *>(&tile_step_kernel<double, true>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<double, false>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<float, true>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<float, false>)};
+    const void *k[8] = {reinterpret_cast<const void *>(&tile_step_kernel<double, true, false>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<double, false, false>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<float, true, false>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<float, false, false>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<double, true, true>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<double, false, true>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<float, true, true>),
+                        reinterpret_cast<const void *>(&tile_step_kernel<float, false, true>)};
     for (const void *f : k) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(max_lds));
@@ -1273,19 +1282,17 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
                 ta.s.us_hu = ustar[1];
                 ta.s.us_hv = ustar[2];
             }
-            if (o32)
-                tile_step_kernel<double, true><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
-            else
-                tile_step_kernel<double, false><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            auto k = o32 ? (fuse ? tile_step_kernel<double, true, true> : tile_step_kernel<double, true, false>)
+                         : (fuse ? tile_step_kernel<double, false, true> : tile_step_kernel<double, false, false>);
+            k<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         } else {
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
             ta.s.part = part;
             ta.s.dt_direct = dt_direct;
             ta.s.adv = adv;
-            if (o32)
-                tile_step_kernel<float, true><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
-            else
-                tile_step_kernel<float, false><<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            auto k = o32 ? (fuse ? tile_step_kernel<float, true, true> : tile_step_kernel<float, true, false>)
+                         : (fuse ? tile_step_kernel<float, false, true> : tile_step_kernel<float, false, false>);
+            k<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         }
     } else if (dtype == SWE_F64) {
         StepArgs<double> a = make_args<double>(dm, s, cur);
@@ -1297,13 +1304,15 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
             a.us_hu = ustar[1];
             a.us_hv = ustar[2];
         }
-        step_kernel<double><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
+        (fuse ? step_kernel<double, true> : step_kernel<double, false>)<<<dim3(grid), dim3(kBlock), 0, st>>>(
+            a, cfg, bv);
     } else {
         StepArgs<float> a = make_args<float>(dm, s, cur);
         a.part = part;
         a.dt_direct = dt_direct;
         a.adv = adv;
-        step_kernel<float><<<dim3(grid), dim3(kBlock), 0, st>>>(a, cfg, bv);
+        (fuse ? step_kernel<float, true> : step_kernel<float, false>)<<<dim3(grid), dim3(kBlock), 0, st>>>(
+            a, cfg, bv);
     }
     if (dt_direct || fuse) return static_cast<int>(hipGetLastError());   // nothing to launch
     if (SWE_DT_FOLD && batch == nullptr)

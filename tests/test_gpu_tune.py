@@ -70,3 +70,17 @@ def test_tuning_a_stopped_state_is_an_error(gpu):
     with pytest.raises(swe.SweError):
         swe.swe_tune(mesh.handle, mesh.dev, s.params, s.state, 4)
     assert swe.tune.tuning("f64", mesh.n_cells) is None
+
+
+def test_tune_order_compares_morton_and_input_order(gpu):
+    swe = gpu
+    case = gen.small(2)
+    morton, res = swe.tune.tune_order(case.xy, case.tri, case.z, case.n, case.h, case.hu,
+                                      case.hv, dtype="f64", steps=4)
+    print(f"Morton order chosen: {morton}; {res}")
+    assert set(res) == {"morton", "input"}
+    best = {k: min(v for v in r["ms_per_step"].values() if v > 0) for k, r in res.items()}
+    assert morton == (best["morton"] <= best["input"])
+    kept = swe.tune.tuning("f64", case.n_cells)
+    assert kept["variant"] == res["morton" if morton else "input"]["variant"]
+    swe.tune.forget("f64", case.n_cells)
