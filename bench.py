@@ -453,7 +453,9 @@ def main():
                      "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBPS,
                      "traffic": r["traffic"], "kernel": r["kernel"],
                      "timed": "whole step (step kernel + dt fold kernel) per step",
-                     "alg_bytes_per_launch": r["alg_bytes_per_step"]},
+                     "alg_bytes_per_launch": r["alg_bytes_per_step"],
+                     "copy_GBps_measured": copy_gbps,
+                     "frac_of_measured_copy": r["achieved_GBps"] / copy_gbps},
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "t_end_state"}
                      for k, v in results.items()},
         "tuning": tuning,
