@@ -48,7 +48,9 @@ extern "C" {
 #define SWE_MAX_INFLOW 16      /* inflow segments per mesh */
 #define SWE_CTRL_BYTES 512     /* size of the device control block of a state */
 #define SWE_WALL (-1)          /* boundary code of a reflective wall (section 3) */
-#define SWE_AUTO 0             /* variant: the tiled kernel where its LDS fits, else per-cell */
+#define SWE_AUTO 0             /* variant: swe_tune's choice for this device, precision and
+                                  size class if one is recorded; else the tiled kernel where
+                                  its LDS fits, else the per-cell one */
 #define SWE_CELL 1             /* variant: one work-item per cell gathering its neighbours */
 #define SWE_TILED 2            /* variant: tile-staged states, each tile interface once */
 #define SWE_NO_XCD_REMAP 1u    /* flag: launch tiles in mesh order instead of giving each XCD
@@ -203,19 +205,23 @@ int32_t swe_state_init(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
  * One explicit Euler step (eq. 4) of the dt held in the control block: hydrostatic
  * reconstruction and HLLC flux on each cell's three edges, bed correction, update, negative
  * depths clamped, semi-implicit Manning friction, then the CFL dt of the next step reduced
- * over all cells.  Reads buffer s->cur, writes the other one and flips s->cur.  Once the state
- * is done (t_end reached, or an error) the step changes nothing and s->cur is kept.  Queues
- * work only.  Errors: SWE_EINVAL, SWE_EDEVICE.
+ * over the owned cells (every cell but a shard's halo; under SWE_SHARD the candidate is left
+ * for swe_shard_dt_combine).  Reads buffer s->cur, writes the other one and flips s->cur.  Once
+ * the state is done (t_end reached, or an error) the step changes nothing and s->cur is kept.
+ * Queues work only.  Errors: SWE_EINVAL, SWE_EDEVICE.
  */
 int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
                  swe_state *s, void *stream);
 
 /*
- * n_steps steps (the host time loop of section 2.3) with no host round trip between them.
- * dt_seq: NULL (CFL dt) or a device array of n_steps doubles replayed as the steps' dt (the
- * t_end clip still applies).  out: NULL to only queue the work, or a stats record: then the
- * stream is synchronised, *out filled, and s->cur set to the buffer holding the result; the
- * return value is then also the state's status (SWE_ENONFINITE, SWE_EDRY).
+ * n_steps steps (the host time loop of section 2.3) with no host round trip between them:
+ * pairs of steps are captured once as a hipGraph (cached on the mesh, keyed by the launch's
+ * arguments) and replayed.  dt_seq: NULL (CFL dt) or a device array of n_steps doubles
+ * replayed as the steps' dt (the t_end clip still applies; not with SWE_SHARD).  out: NULL to
+ * only queue the work, or a stats record: then the stream is synchronised, *out filled, and
+ * s->cur set to the buffer holding the result; the return value is then also the state's
+ * status (SWE_ENONFINITE, SWE_EDRY).  The graph cache makes calls on one mesh from several
+ * threads at once unsafe; use one mesh object per thread.
  * Errors: SWE_EINVAL, SWE_EDEVICE, and with out != NULL the state's status.
  */
 int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,

@@ -1,5 +1,5 @@
 // Batches: many scenarios (independent meshes with their own dt and time) stepped by one launch
-// of the tiled step per step.  The builder concatenates built meshes so that no tile straddles
+// of the step kernel (tiled or per-cell) per step.  The builder concatenates built meshes so that no tile straddles
 // two scenarios; the per-tile scenario index selects the control block (dt, time, counters)
 // and the inflow discharges, and a dt pass with one workgroup per scenario reduces each
 // scenario's tile partials on its own.
