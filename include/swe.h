@@ -45,6 +45,7 @@ extern "C" {
 #define SWE_F64 0              /* state, bed and roughness in double */
 #define SWE_F32 1              /* state, bed and roughness in float (coordinates stay double) */
 #define SWE_MORTON 1u          /* swe_mesh_create flag: renumber cells along a Morton curve */
+#define SWE_HILBERT 2u         /* swe_mesh_create flag: renumber cells along a Hilbert curve */
 #define SWE_MAX_INFLOW 16      /* inflow segments per mesh */
 #define SWE_CTRL_BYTES 512     /* size of the device control block of a state */
 #define SWE_WALL (-1)          /* boundary code of a reflective wall (section 3) */
@@ -168,7 +169,9 @@ typedef struct swe_run_stats {
  * tri: host int32[3*nt] node ids, either orientation (clockwise triangles are reordered
  * (v0, v2, v1)); edge_tag: host int32[3*nt] or NULL (all walls): for a boundary edge k of
  * triangle t (nodes k, k+1 of the input triangle), 0 = wall, s >= 1 = inflow segment s.
- * flags: SWE_MORTON or 0 (keep the input order).  On success *out owns a new mesh.
+ * flags: SWE_MORTON, SWE_HILBERT or 0 (keep the input order); the curves run through the
+ * centroids quantised to 16 bits per axis over the bounding box, ties keep the input order.
+ * On success *out owns a new mesh.
  * Errors: SWE_EINVAL (null pointer, nv < 3, nt < 1, sizes beyond int32, non-finite
  * coordinates, tag out of range), SWE_EMESH (repeated or out-of-range node, zero-area
  * triangle, edge shared by more than two triangles or twice in the same direction).

@@ -27,6 +27,7 @@ SWE_EUNSUPPORTED = -6
 SWE_F64 = 0
 SWE_F32 = 1
 SWE_MORTON = 1
+SWE_HILBERT = 2
 SWE_MAX_INFLOW = 16
 SWE_CTRL_BYTES = 512
 SWE_WALL = -1

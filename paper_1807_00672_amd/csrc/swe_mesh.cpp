@@ -33,6 +33,27 @@ inline uint32_t spread_bits(uint32_t v)  // 16 bits -> even bit positions of 32
     return v;
 }
 
+// Position of the cell (x, y) of a 65536 x 65536 grid along a Hilbert curve: at each scale,
+// take the quadrant, add the cells of the quadrants the curve visits before it, and rotate or
+// reflect the coordinates into the quadrant's own orientation.
+inline uint32_t hilbert_key(uint32_t x, uint32_t y)
+{
+    const uint32_t n = 1u << 16;
+    uint32_t d = 0;
+    for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
 // Stable LSD radix sort of (key, index) by a 32-bit key, two 16-bit passes.
 void radix_sort_by_key(std::vector<uint32_t> &key, std::vector<int32_t> &idx)
 {
@@ -154,7 +175,9 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
     if (nv < 3 || nt < 1) throw Fail{SWE_EINVAL, "need at least 3 nodes and 1 triangle"};
     if (nv > INT32_MAX / 2 || nt > INT32_MAX / 3)
         throw Fail{SWE_EINVAL, "mesh too large for int32 indices"};
-    if (flags & ~SWE_MORTON) throw Fail{SWE_EINVAL, "unknown flags"};
+    if (flags & ~(SWE_MORTON | SWE_HILBERT)) throw Fail{SWE_EINVAL, "unknown flags"};
+    if ((flags & SWE_MORTON) && (flags & SWE_HILBERT))
+        throw Fail{SWE_EINVAL, "SWE_MORTON and SWE_HILBERT exclude each other"};
     for (int64_t j = 0; j < 2 * nv; ++j)
         if (!isfinite(xy[j])) throw Fail{SWE_EINVAL, "non-finite node coordinate"};
 
@@ -287,13 +310,15 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
         const double cy = (xy[2 * v[0] + 1] + xy[2 * v[1] + 1] + xy[2 * v[2] + 1]) / 3.0;
         const uint32_t qx = static_cast<uint32_t>(std::min(65535.0, std::max(0.0, (cx - inf.bbox[0]) * sx)));
         const uint32_t qy = static_cast<uint32_t>(std::min(65535.0, std::max(0.0, (cy - inf.bbox[1]) * sy)));
-        key[c] = spread_bits(qx) | (spread_bits(qy) << 1);
+        key[c] = (flags & SWE_HILBERT) ? hilbert_key(qx, qy)
+                                       : spread_bits(qx) | (spread_bits(qy) << 1);
     }
 
-    // 4. cell order: Morton key, ties by input index (stable sort of increasing indices)
+    // 4. cell order: Morton or Hilbert key, ties by input index (stable sort of increasing
+    // indices); else the input order
     m.perm.resize(T);
     for (int64_t c = 0; c < T; ++c) m.perm[c] = static_cast<int32_t>(c);
-    if (flags & SWE_MORTON) radix_sort_by_key(key, m.perm);
+    if (flags & (SWE_MORTON | SWE_HILBERT)) radix_sort_by_key(key, m.perm);
     std::vector<int32_t> inv(T);
     for (int64_t i = 0; i < T; ++i) inv[m.perm[i]] = static_cast<int32_t>(i);
 

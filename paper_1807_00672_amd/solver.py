@@ -28,9 +28,13 @@ class Mesh:
     [T, 3] boundary tags (0 wall, s >= 1 inflow segment s) of input edge (k, k+1).
     """
 
-    def __init__(self, xy, tri, edge_tag=None, morton: bool = True, device="cuda", handle=None):
-        self.handle = handle if handle is not None else A.swe_mesh_create(
-            xy, tri, edge_tag, A.SWE_MORTON if morton else 0)
+    ORDERS = {"morton": A.SWE_MORTON, "hilbert": A.SWE_HILBERT, "input": 0}
+
+    def __init__(self, xy, tri, edge_tag=None, morton: bool = True, device="cuda", handle=None,
+                 order: str | None = None):
+        """order: "morton", "hilbert" or "input" cell order (default: morton unless morton=False)."""
+        flags = self.ORDERS[order or ("morton" if morton else "input")]
+        self.handle = handle if handle is not None else A.swe_mesh_create(xy, tri, edge_tag, flags)
         self.info = A.swe_mesh_info_get(self.handle)
         t, v = int(self.info.n_cells), int(self.info.n_nodes)
         self.n_cells, self.n_nodes = t, v

@@ -1,6 +1,6 @@
 """Launch autotuning (swe_tune): which step kernel variant and workgroup order run fastest for
 a mesh size class on this device, remembered for SWE_AUTO; optional persistence as JSON keyed by
-device name, precision and size class, and a choice between Morton and input cell order."""
+device name, precision and size class, and a choice among Morton, Hilbert and input cell order."""
 from __future__ import annotations
 
 import json
@@ -77,21 +77,21 @@ def load(path: str) -> int:
 
 
 def tune_order(xy, tri, z, n, h, hu, hv, edge_tag=None, dtype: str = "f64",
-               steps: int = 20, **solver_kw) -> tuple[bool, dict]:
-    """Build the mesh in Morton and in input cell order, tune both, and return (morton?, the
-    timings of each order).  The faster order's best variant stays recorded."""
+               steps: int = 20, orders=("morton", "hilbert", "input"),
+               **solver_kw) -> tuple[str, dict]:
+    """Build the mesh in each cell order, tune each, and return (the fastest order, the
+    timings of every order).  The fastest order's best variant stays recorded."""
     res = {}
-    for morton in (True, False):
-        m = Mesh(xy, tri, edge_tag, morton=morton)
-        res["morton" if morton else "input"] = tune(m, z, n, h, hu, hv, dtype, steps, **solver_kw)
+    for order in orders:
+        m = Mesh(xy, tri, edge_tag, order=order)
+        res[order] = tune(m, z, n, h, hu, hv, dtype, steps, **solver_kw)
     best = {k: min(v["ms_per_step"][x] for x in v["ms_per_step"] if v["ms_per_step"][x] > 0)
             for k, v in res.items()}
-    morton = best["morton"] <= best["input"]
-    if morton:   # the input-order run was tuned last: record the Morton choice again
-        r = res["morton"]
-        rr = A.swe_tune_result()
-        rr.variant = _VAR[r["variant"]]
-        rr.xcd_remap = 1 if r["xcd_remap"] else 0
-        A.swe_tune_set(torch.cuda.current_device(), _DT[dtype], len(tri), rr)
-        _recorded[(dtype, size_class(len(tri)))] = r
-    return morton, res
+    order = min(best, key=best.get)
+    r = res[order]   # the order tuned last may not be the fastest: record the fastest again
+    rr = A.swe_tune_result()
+    rr.variant = _VAR[r["variant"]]
+    rr.xcd_remap = 1 if r["xcd_remap"] else 0
+    A.swe_tune_set(torch.cuda.current_device(), _DT[dtype], len(tri), rr)
+    _recorded[(dtype, size_class(len(tri)))] = r
+    return order, res

@@ -89,6 +89,28 @@ def test_morton_order_brings_neighbours_closer():
     assert same[True] > 0.85 > 0.7 > same[False]
 
 
+def test_hilbert_order_keeps_consecutive_cells_adjacent():
+    """Along a Hilbert curve consecutive cells of the quantised grid are edge neighbours, so
+    consecutive mesh cells stay close everywhere; a Morton curve jumps at every quadrant
+    boundary.  Both keep tiles compact."""
+    c = gen.wetdry(nx=128, ny=128, lx=1280.0, ly=1280.0, steps=1)   # 10 m squares
+    jump, same = {}, {}
+    for order in ("hilbert", "morton"):
+        m = swe.Mesh(c.xy, c.tri, order=order, device=None)
+        t = m.n_cells
+        assert sorted(m.perm.tolist()) == list(range(t))
+        xy = m.xy.reshape(-1, 2)[m.c2n.reshape(3, t)].mean(axis=0)   # centroids, mesh order
+        jump[order] = np.linalg.norm(np.diff(xy, axis=0), axis=1).max()
+        nbr = m.nbr.reshape(3, t).T
+        i = np.repeat(np.arange(t)[:, None], 3, 1)
+        ok = nbr >= 0
+        same[order] = (nbr[ok] // 256 == i[ok] // 256).mean()
+    assert jump["hilbert"] < 40.0 < 320.0 < jump["morton"]
+    assert same["hilbert"] > 0.85 and same["morton"] > 0.85
+    with pytest.raises(swe.SweError):
+        swe.swe_mesh_create(c.xy, c.tri, None, swe.SWE_MORTON | swe.SWE_HILBERT)
+
+
 def test_clockwise_input_and_edge_tags_are_reoriented():
     c = gen.ensemble_scenario(3)
     tri = c.tri.copy()

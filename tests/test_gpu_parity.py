@@ -174,12 +174,14 @@ def test_tiled_and_per_cell_kernels_agree_bitwise(gpu, dtype):
         assert np.array_equal(x, y)
 
 
-def test_morton_order_does_not_change_results(gpu):
+def test_cell_order_does_not_change_results(gpu):
+    import paper_1807_00672_amd as swe
     case = gen.small(2)
     a = run_gpu(case, "f64", steps=100, morton=True)
     b = run_gpu(case, "f64", steps=100, morton=False)
-    for x, y in zip(a[2:], b[2:]):
-        assert np.array_equal(x, y)
+    c = run_gpu(case, "f64", steps=100, mesh=swe.Mesh(case.xy, case.tri, order="hilbert"))
+    for x, y, w in zip(a[2:], b[2:], c[2:]):
+        assert np.array_equal(x, y) and np.array_equal(x, w)
 
 
 def test_runs_are_bitwise_repeatable_and_stepwise_equal(gpu):

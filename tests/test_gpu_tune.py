@@ -72,15 +72,15 @@ def test_tuning_a_stopped_state_is_an_error(gpu):
     assert swe.tune.tuning("f64", mesh.n_cells) is None
 
 
-def test_tune_order_compares_morton_and_input_order(gpu):
+def test_tune_order_compares_the_cell_orders(gpu):
     swe = gpu
     case = gen.small(2)
-    morton, res = swe.tune.tune_order(case.xy, case.tri, case.z, case.n, case.h, case.hu,
-                                      case.hv, dtype="f64", steps=4)
-    print(f"Morton order chosen: {morton}; {res}")
-    assert set(res) == {"morton", "input"}
+    order, res = swe.tune.tune_order(case.xy, case.tri, case.z, case.n, case.h, case.hu,
+                                     case.hv, dtype="f64", steps=4)
+    print(f"order chosen: {order}; {res}")
+    assert set(res) == {"morton", "hilbert", "input"}
     best = {k: min(v for v in r["ms_per_step"].values() if v > 0) for k, r in res.items()}
-    assert morton == (best["morton"] <= best["input"])
+    assert order == min(best, key=best.get)
     kept = swe.tune.tuning("f64", case.n_cells)
-    assert kept["variant"] == res["morton" if morton else "input"]["variant"]
+    assert kept["variant"] == res[order]["variant"]
     swe.tune.forget("f64", case.n_cells)
