@@ -218,8 +218,8 @@ int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
 
 /*
  * n_steps steps (the host time loop of section 2.3) with no host round trip between them:
- * pairs of steps are captured once as a hipGraph (cached on the mesh, keyed by the launch's
- * arguments) and replayed.  dt_seq: NULL (CFL dt) or a device array of n_steps doubles
+ * groups of 8 steps are captured once as a hipGraph (cached on the mesh, keyed by the
+ * launch's arguments) and replayed; runs shorter than 16 steps launch step by step.  dt_seq: NULL (CFL dt) or a device array of n_steps doubles
  * replayed as the steps' dt (the t_end clip still applies; not with SWE_SHARD).  out: NULL to
  * only queue the work, or a stats record: then the stream is synchronised, *out filled, and
  * s->cur set to the buffer holding the result; the return value is then also the state's

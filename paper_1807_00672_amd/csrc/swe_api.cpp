@@ -146,9 +146,10 @@ GraphKey make_key(const swe_dev_mesh *dm, const swe_params *p, const swe_state *
     return k;
 }
 
-// The executable two-step graph for these arguments, captured on a library-owned stream
-// (nullptr if graphs are unavailable: the caller then launches step by step).
-hipGraphExec_t two_step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+// The executable graph of kGraphSteps steps (an even number, so the state returns to the same
+// buffer) for these arguments, captured on a library-owned stream (nullptr if graphs are
+// unavailable: the caller then launches step by step).
+hipGraphExec_t step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
                               const StepConfig &cfg, const swe_state *s, const double *dt_seq,
                               int64_t n_seq, const TileLayout *tl, int remap)
 {
@@ -166,11 +167,13 @@ hipGraphExec_t two_step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, cons
     }
     hipStream_t cs = g_capture[dev];
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    int e0 = launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_seq, cs, tl, nullptr, remap);
-    int e1 = launch_step(p->dtype, *dm, cfg, *s, 1 - s->cur, dt_seq, n_seq, cs, tl, nullptr, remap);
+    int e0 = hipSuccess;
+    for (int q = 0; q < kGraphSteps && e0 == hipSuccess; ++q)
+        e0 = launch_step(p->dtype, *dm, cfg, *s, (s->cur + q) & 1, dt_seq, n_seq, cs, tl, nullptr,
+                         remap);
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
-    if (e0 != hipSuccess || e1 != hipSuccess || ee != hipSuccess || !graph) {
+    if (e0 != hipSuccess || ee != hipSuccess || !graph) {
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipGetLastError();
         return nullptr;
@@ -333,9 +336,9 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
     if (int32_t rc = choose_variant(mesh, dm, p, &tl, &remap, "swe_run")) return rc;
     if (int32_t rc = check_hip(launch_run_begin(*s, dt_seq, stream), "swe_run")) return rc;
     int64_t k = 0;
-    if (n_steps >= 4) {
-        if (hipGraphExec_t ex = two_step_graph(mesh, dm, p, cfg, s, dt_seq, n_steps, tl, remap)) {
-            for (; k + 2 <= n_steps; k += 2)
+    if (n_steps >= 2 * kGraphSteps) {
+        if (hipGraphExec_t ex = step_graph(mesh, dm, p, cfg, s, dt_seq, n_steps, tl, remap)) {
+            for (; k + kGraphSteps <= n_steps; k += kGraphSteps)
                 if (int32_t rc = check_hip(hipGraphLaunch(ex, static_cast<hipStream_t>(stream)),
                                            "swe_run"))
                     return rc;

@@ -173,11 +173,12 @@ hipGraphExec_t batch_graph(const swe_batch *b, const swe_batch_dev *d, const swe
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
     const TileLayout *tl = tiled ? &b->tiles : nullptr;
     const int rm = (p->flags & SWE_NO_XCD_REMAP) ? 0 : 1;
-    const int e0 = launch_step(p->dtype, d->mesh, cfg, *s, s->cur, nullptr, 0, cs, tl, &bl, rm);
-    const int e1 = launch_step(p->dtype, d->mesh, cfg, *s, 1 - s->cur, nullptr, 0, cs, tl, &bl, rm);
+    int e0 = hipSuccess;
+    for (int q = 0; q < kGraphSteps && e0 == hipSuccess; ++q)
+        e0 = launch_step(p->dtype, d->mesh, cfg, *s, (s->cur + q) & 1, nullptr, 0, cs, tl, &bl, rm);
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
-    if (e0 != hipSuccess || e1 != hipSuccess || ee != hipSuccess || !graph) {
+    if (e0 != hipSuccess || ee != hipSuccess || !graph) {
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipGetLastError();
         return nullptr;
@@ -362,9 +363,9 @@ int32_t swe_batch_run(const swe_batch *batch, const swe_batch_dev *dev,
     const BatchLaunch bl = launch_view(batch, dev, p);
     hipStream_t st = static_cast<hipStream_t>(stream);
     int64_t k = 0;
-    if (n_steps >= 4) {
+    if (n_steps >= 2 * kGraphSteps) {
         if (hipGraphExec_t ex = batch_graph(batch, dev, p, cfg, s, tiled)) {
-            for (; k + 2 <= n_steps; k += 2)
+            for (; k + kGraphSteps <= n_steps; k += kGraphSteps)
                 if (int32_t rc = bcheck_hip(hipGraphLaunch(ex, st), "swe_batch_run")) return rc;
         }
     }

@@ -112,6 +112,13 @@ struct BatchLaunch {
 
 constexpr int kMaxShards = 64;
 
+// Steps per captured graph of swe_run and swe_batch_run (even: the state returns to its buffer).
+#ifndef SWE_GRAPH_STEPS
+#define SWE_GRAPH_STEPS 8
+#endif
+constexpr int kGraphSteps = SWE_GRAPH_STEPS;
+static_assert(kGraphSteps >= 2 && kGraphSteps % 2 == 0, "graph step count must be even");
+
 // Launchers.  swe_kernels.hip defines them twice, in swe::exact (correctly rounded FP64
 // division and square root) and swe::fast (their hardware-seeded Newton forms, within an ulp);
 // the ones in swe itself (swe_launch.cpp) pick by StepConfig::fast.  batch == nullptr: a single
