@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "swe_device_math.h"
 #include "swe_internal.h"
 
@@ -36,12 +38,14 @@ constexpr double kInf = __builtin_huge_val();
 // a fraction of the instructions of the correctly rounded sequences; both are odd in their
 // sign arguments, so interface fluxes stay exact negatives of each other.
 // Minimum waves per SIMD the compiler must allow for (register budget) in the two step
-// kernels; 1 leaves the choice to the compiler.
+// kernels; 1 leaves the choice to the compiler.  Six holds the FP64 tiled kernels to 80
+// VGPRs (the correctly rounded one needs 81 unconstrained), which the shared LDS layout
+// lets six tiles per CU use; FP32 needs fewer anyway.
 #ifndef SWE_CELL_WAVES
 #define SWE_CELL_WAVES 1
 #endif
 #ifndef SWE_TILE_WAVES
-#define SWE_TILE_WAVES 1
+#define SWE_TILE_WAVES 6
 #endif
 #ifndef SWE_F32_FAST
 #define SWE_F32_FAST 1
@@ -62,6 +66,11 @@ constexpr double kInf = __builtin_huge_val();
 // 1: the tiled kernel addresses arrays below 4 GiB by 32-bit byte offsets; 0: always 64-bit.
 #ifndef SWE_OFF32
 #define SWE_OFF32 1
+#endif
+// 1: tiles whose LDS limits occupancy write their second round of interface results over
+// the states (tile_alias); 0: never.
+#ifndef SWE_TILE_ALIAS
+#define SWE_TILE_ALIAS 1
 #endif
 template <typename R>
 __device__ __forceinline__ R div_(R a, R b)
@@ -624,24 +633,54 @@ struct TileArgs {
     int32_t n_tiles, max_halo, max_edges, pad;
 };
 
-// LDS bytes of the tiled step: tile + halo states (h, u, v, z) and five values per edge-list
+// LDS of the tiled step: the tile + halo states (h, u, v, z) and five values per edge-list
 // entry (side a's contribution and side b's momentum part; side b's mass part is -a's).
-inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
+// Plain layout: [states | 5 rows of max_edges].  Shared layout (at most 2 kBlock entries):
+// [5 rows of kBlock for entries 0..kBlock-1 | states], the entries from kBlock on written in
+// 5 rows of kBlock over the states once every interface of the tile has been evaluated.
+inline size_t tile_lds_plain(size_t word, int64_t max_halo, int64_t max_edges)
 {
     return 4 * word * static_cast<size_t>(kBlock + max_halo) +
            5 * word * static_cast<size_t>(max_edges);
 }
 
+inline size_t tile_lds_shared(size_t word, int64_t max_halo)
+{
+    return word * (5 * static_cast<size_t>(kBlock) +
+                   std::max(4 * static_cast<size_t>(kBlock + max_halo), 5 * static_cast<size_t>(kBlock)));
+}
+
+// The shared layout costs one more barrier per tile; take it only where the plain layout
+// limits a CU (160 KiB of LDS, four waves per workgroup) to fewer than eight waves per SIMD
+// and the shared one fits more workgroups.  FP64 only: FP32 tiles of the meshes built here
+// reach eight waves in the plain layout.
+inline bool tile_alias(size_t word, int64_t max_halo, int64_t max_edges)
+{
+    if (!SWE_TILE_ALIAS || word != 8 || max_edges > 2 * kBlock) return false;
+    constexpr size_t kLdsPerCu = 160 * 1024;
+    const size_t plain = kLdsPerCu / tile_lds_plain(word, max_halo, max_edges);
+    const size_t shared = kLdsPerCu / tile_lds_shared(word, max_halo);
+    return plain < 8 && shared > plain;
+}
+
+inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
+{
+    return tile_alias(word, max_halo, max_edges) ? tile_lds_shared(word, max_halo)
+                                                 : tile_lds_plain(word, max_halo, max_edges);
+}
+
 // One explicit step, tiled.  Every global load of the workgroup is issued up front: the own
 // cell (state, bed, Manning, nodes, edge slots), the halo states, and the first two rounds of
 // edge-list entries with their node coordinates.  Phase 1 stages the tile's cells and its
-// halo in LDS as (h, u, v, z), each velocity computed once.  Phase 2 evaluates every interface
-// of the edge list once (section 2.3's interface loop, restricted to the tile) and stores the
-// contributions l (F + p n) to eq. 3 of both sides, computed exactly as the per-cell form
-// computes them.  Phase 3 sums each cell's three contributions in local-edge order and
-// applies the update of eq. 4, the clamp, the friction and the next CFL bound, as the
-// per-cell kernel does.
-template <typename R, bool O32, bool Fuse>
+// halo in LDS as (h, u, v, z), each velocity computed once, and forms the cell's area and
+// inradius and the edge vectors, so that no node coordinate is held through phase 2.  Phase 2
+// evaluates every interface of the edge list once (section 2.3's interface loop, restricted
+// to the tile) and stores the contributions l (F + p n) to eq. 3 of both sides, computed
+// exactly as the per-cell form computes them; with the shared layout (Shared) the second
+// round's results wait in registers until every work-item has read the states they replace.
+// Phase 3 sums each cell's three contributions in local-edge order and applies the update of
+// eq. 4, the clamp, the friction and the next CFL bound, as the per-cell kernel does.
+template <typename R, bool O32, bool Fuse, bool Shared>
 __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
                                                            Batch bt)
 {
@@ -654,16 +693,19 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     const double *qtab = batched ? bt.q_table + scen * SWE_MAX_INFLOW : nullptr;
     if (!a.dt_direct && ctrl->done) return;   // uniform over the workgroup: its scenario stopped
     extern __shared__ __align__(16) unsigned char smem[];
+    R *const lds = reinterpret_cast<R *>(smem);
     const int ns = kBlock + ta.max_halo;
-    R *s_h = reinterpret_cast<R *>(smem);
+    // word offsets: states, and edge-list entry q of row j at ebase + j estride + q (+ bshift
+    // from entry kBlock on)
+    constexpr bool alias = Shared;
+    const int sbase = alias ? 5 * kBlock : 0;
+    const int ebase = alias ? 0 : 4 * ns;
+    const int estride = alias ? kBlock : ta.max_edges;
+    const int bshift = alias ? 4 * kBlock : 0;
+    R *s_h = lds + sbase;
     R *s_u = s_h + ns;
     R *s_v = s_u + ns;
     R *s_z = s_v + ns;
-    R *e_a0 = s_z + ns;                  // side a: l f_h
-    R *e_a1 = e_a0 + ta.max_edges;       // side a: l (f_x + p_a n_x)
-    R *e_a2 = e_a1 + ta.max_edges;       // side a: l (f_y + p_a n_y)
-    R *e_b1 = e_a2 + ta.max_edges;       // side b: -(its momentum contribution)
-    R *e_b2 = e_b1 + ta.max_edges;
 
     const int64_t T = cfg.n_cells;
     const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
@@ -673,6 +715,11 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     const bool mine = i < s1 && i < T;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
     const R dt = static_cast<R>(a.dt_direct ? *a.dt_direct : ctrl->dt);
+    // Work-item positions in the edge list (pt) and the halo list (ph).  About 1.7 interfaces
+    // per cell leave one wave of four a single round of phase 2; the halo loads go to that
+    // wave, and which wave it is turns with the tile, so that no SIMD idles through a round.
+    const int pt = (tid + 64 * (tile & 3)) & (kBlock - 1);
+    const int ph = kBlock - 1 - pt;
 
     // global loads: own cell
     R h = R(0), hu = R(0), hv = R(0), zc = R(0), nm = R(0);
@@ -692,7 +739,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     double2 ep0[2] = {{0.0, 0.0}, {0.0, 0.0}}, ep1[2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-        const int e = eb + tid + it * kBlock;
+        const int e = eb + pt + it * kBlock;
         if (e < ee) {
             const uint32_t w = ld<O32>(ta.edges, e);
             const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
@@ -704,7 +751,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     }
     // phase 1: halo and own cell into LDS
     const int hb = ta.halo_off[tile], he = ta.halo_off[tile + 1];
-    for (int j = hb + tid; j < he; j += kBlock) {
+    for (int j = hb + ph; j < he; j += kBlock) {
         const int32_t c = ld<O32>(ta.halo, j);
         const R hh = ld<O32>(a.h, c);
         const int q = kBlock + (j - hb);
@@ -719,13 +766,37 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         s_v[tid] = velocity(h, hv, hd);
         s_z[tid] = zc;
     }
+    // the cell's area and inradius and the edges' vectors, formed here so that the node
+    // coordinates are not held through phase 2
+    R area = R(0), inradius = R(1);
+    if (mine) {
+        const double ex[3] = {p1.x - p0.x, p2.x - p1.x, p0.x - p2.x};
+        const double ey[3] = {p1.y - p0.y, p2.y - p1.y, p0.y - p2.y};
+        R l[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const R dx = static_cast<R>(ex[k]), dy = static_cast<R>(ey[k]);
+            l[k] = sqrt_(dx * dx + dy * dy);
+        }
+        area = static_cast<R>(0.5 * (ex[0] * ey[1] - ey[0] * ex[1]));
+        inradius = div_(R(2) * area, l[0] + l[1] + l[2]);
+    }
+    R edx[2], edy[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        edx[it] = static_cast<R>(ep1[it].x - ep0[it].x);
+        edy[it] = static_cast<R>(ep1[it].y - ep0[it].y);
+    }
     __syncthreads();
 
     // phase 2: the tile's interfaces, each once
-    auto edge = [&](uint32_t w, double2 q0, double2 q1, int q) {
+    struct EdgeOut {
+        R a0, a1, a2, b1, b2;
+    };
+    // returns whether side b is a cell (its momentum parts b1, b2 set)
+    auto flux = [&](uint32_t w, R dx, R dy, EdgeOut &o) {
         const int ca = static_cast<int>(w & 0xffu);
         const int cb = static_cast<int16_t>(w >> 16);
-        const R dx = static_cast<R>(q1.x - q0.x), dy = static_cast<R>(q1.y - q0.y);
         const R l = sqrt_(dx * dx + dy * dy);
         const R nx = div_(dy, l), ny = div_(-dx, l);
         const R ha = s_h[ca], ua = s_u[ca], va = s_v[ca];
@@ -735,8 +806,8 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
                                  nx, ny, fh, fx, fy, pa, pb);
             // side b's contributions are l (-f_h) = -(l f_h) and l (-f + p_b (-n)) =
             // -(l (f + p_b n)), exactly
-            e_b1[q] = l * (fx + pb * nx);
-            e_b2[q] = l * (fy + pb * ny);
+            o.b1 = l * (fx + pb * nx);
+            o.b2 = l * (fy + pb * ny);
         } else if (cb == SWE_WALL) {
             wall_flux<R>(g, hd, ha, ua, va, nx, ny, fh, fx, fy, pa);
         } else {
@@ -744,21 +815,38 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
             inflow_flux<R>(g, static_cast<R>(qin), ha, nx, ny, fh, fx, fy);
             pa = R(0);
         }
-        e_a0[q] = l * fh;
-        e_a1[q] = l * (fx + pa * nx);
-        e_a2[q] = l * (fy + pa * ny);
+        o.a0 = l * fh;
+        o.a1 = l * (fx + pa * nx);
+        o.a2 = l * (fy + pa * ny);
+        return cb >= 0;
     };
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const int e = eb + tid + it * kBlock;
-        if (e < ee) edge(ew[it], ep0[it], ep1[it], e - eb);
+    auto put = [&](int q, const EdgeOut &o, bool two) {
+        R *e = lds + ebase + q + (q >= kBlock ? bshift : 0);
+        e[0] = o.a0;
+        e[estride] = o.a1;
+        e[2 * estride] = o.a2;
+        if (two) {
+            e[3 * estride] = o.b1;
+            e[4 * estride] = o.b2;
+        }
+    };
+    {
+        EdgeOut o;
+        if (eb + pt < ee) put(pt, o, flux(ew[0], edx[0], edy[0], o));
+        const bool has1 = eb + pt + kBlock < ee;
+        bool two1 = false;
+        if (has1) two1 = flux(ew[1], edx[1], edy[1], o);
+        if constexpr (alias) __syncthreads();   // every read of the states is done
+        if (has1) put(pt + kBlock, o, two1);
     }
-    for (int e = eb + tid + 2 * kBlock; e < ee; e += kBlock) {
+    for (int e = eb + pt + 2 * kBlock; e < ee; e += kBlock) {   // plain layout only
         const uint32_t w = ld<O32>(ta.edges, e);
         const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
         const int k = static_cast<int>((w >> 8) & 3u);
-        edge(w, ld<O32>(a.xy, ld<O32>(a.c2n, k * T + ca)),
-             ld<O32>(a.xy, ld<O32>(a.c2n, (k == 2 ? 0 : k + 1) * T + ca)), e - eb);
+        const double2 q0 = ld<O32>(a.xy, ld<O32>(a.c2n, k * T + ca));
+        const double2 q1 = ld<O32>(a.xy, ld<O32>(a.c2n, (k == 2 ? 0 : k + 1) * T + ca));
+        EdgeOut o;
+        put(e - eb, o, flux(w, static_cast<R>(q1.x - q0.x), static_cast<R>(q1.y - q0.y), o));
     }
     __syncthreads();
 
@@ -766,20 +854,17 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     R dtc = static_cast<R>(kInf);
     int clamp = 0, flag = 0;
     if (mine) {
-        const double ex[3] = {p1.x - p0.x, p2.x - p1.x, p0.x - p2.x};
-        const double ey[3] = {p1.y - p0.y, p2.y - p1.y, p0.y - p2.y};
         const uint32_t sl[3] = {sl0, sl1, sl2};
-        R acc0 = R(0), acc1 = R(0), acc2 = R(0), l[3];
+        R acc0 = R(0), acc1 = R(0), acc2 = R(0);
         int32_t nb[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int q = static_cast<int>(sl[k] & 0x7fffu);
             const bool side_b = (sl[k] & 0x8000u) != 0;
-            const R c0 = side_b ? -e_a0[q] : e_a0[q];
-            const R c1 = side_b ? -e_b1[q] : e_a1[q];
-            const R c2 = side_b ? -e_b2[q] : e_a2[q];
-            const R dx = static_cast<R>(ex[k]), dy = static_cast<R>(ey[k]);
-            l[k] = sqrt_(dx * dx + dy * dy);
+            const R *e = lds + ebase + q + (q >= kBlock ? bshift : 0);
+            const R c0 = side_b ? -e[0] : e[0];
+            const R c1 = side_b ? -e[3 * estride] : e[estride];
+            const R c2 = side_b ? -e[4 * estride] : e[2 * estride];
             nb[k] = 0;
             if ((cfg.n_inflow > 0 || batched) && !side_b)
                 nb[k] = static_cast<int16_t>(ld<O32>(ta.edges, eb + q) >> 16);
@@ -789,8 +874,6 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
                 acc0 = acc0 + c0; acc1 = acc1 + c1; acc2 = acc2 + c2;
             }
         }
-        const R area = static_cast<R>(0.5 * (ex[0] * ey[1] - ey[0] * ex[1]));
-        const R inradius = div_(R(2) * area, l[0] + l[1] + l[2]);
         const R r = div_(dt, area);
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
@@ -1218,6 +1301,22 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     return static_cast<int>(hipGetLastError());
 }
 
+// The tiled kernel for a launch (FP32 has no shared-layout instances).
+template <typename R>
+using TileKernel = void (*)(TileArgs<R>, StepConfig, Batch);
+
+template <typename R>
+TileKernel<R> tile_kernel(bool o32, bool fuse, bool shared)
+{
+    if constexpr (sizeof(R) == 8) {
+        if (shared)
+            return o32 ? (fuse ? tile_step_kernel<R, true, true, true> : tile_step_kernel<R, true, false, true>)
+                       : (fuse ? tile_step_kernel<R, false, true, true> : tile_step_kernel<R, false, false, true>);
+    }
+    return o32 ? (fuse ? tile_step_kernel<R, true, true, false> : tile_step_kernel<R, true, false, false>)
+               : (fuse ? tile_step_kernel<R, false, true, false> : tile_step_kernel<R, false, false, false>);
+}
+
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
 {
     return tile_lds_bytes(dtype == SWE_F64 ? 8 : 4, tl.max_halo, tl.max_edges);
@@ -1225,14 +1324,14 @@ size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
 
 int prepare_tile_kernels(size_t max_lds)
 {
-    const void *k[8] = {reinterpret_cast<const void *>(&tile_step_kernel<double, true, false>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<double, false, false>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<float, true, false>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<float, false, false>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<double, true, true>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<double, false, true>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<float, true, true>),
-                        reinterpret_cast<const void *>(&tile_step_kernel<float, false, true>)};
+    const void *k[12];
+    int n = 0;
+    for (int o32 = 0; o32 < 2; ++o32)
+        for (int fuse = 0; fuse < 2; ++fuse) {
+            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, false));
+            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, true));
+            k[n++] = reinterpret_cast<const void *>(tile_kernel<float>(o32, fuse, false));
+        }
     for (const void *f : k) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(max_lds));
@@ -1282,17 +1381,14 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
                 ta.s.us_hu = ustar[1];
                 ta.s.us_hv = ustar[2];
             }
-            auto k = o32 ? (fuse ? tile_step_kernel<double, true, true> : tile_step_kernel<double, true, false>)
-                         : (fuse ? tile_step_kernel<double, false, true> : tile_step_kernel<double, false, false>);
-            k<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            const bool shared = tile_alias(sizeof(double), tl->max_halo, tl->max_edges);
+            tile_kernel<double>(o32, fuse, shared)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         } else {
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
             ta.s.part = part;
             ta.s.dt_direct = dt_direct;
             ta.s.adv = adv;
-            auto k = o32 ? (fuse ? tile_step_kernel<float, true, true> : tile_step_kernel<float, true, false>)
-                         : (fuse ? tile_step_kernel<float, false, true> : tile_step_kernel<float, false, false>);
-            k<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            tile_kernel<float>(o32, fuse, false)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         }
     } else if (dtype == SWE_F64) {
         StepArgs<double> a = make_args<double>(dm, s, cur);
