@@ -178,7 +178,9 @@ def bench_configs(stream, dtypes) -> dict:
 def bench_adjoint(stream, steps: int = 2000) -> dict:
     """Config 5: the gauge-misfit adjoint (checkpointing forward + reverse sweep) of 2,000 FP64
     steps on the 250,000-cell calibration setup, against the plain forward run of the same
-    steps with the same replayed dt sequence."""
+    steps with the same replayed dt sequence; then the same adjoint storing every step
+    (ckpt_every = 1, no recompute), whose gradients must equal the checkpointed ones bit for
+    bit."""
     import torch
 
     import gen
@@ -199,21 +201,20 @@ def bench_adjoint(stream, steps: int = 2000) -> dict:
         sv.step()
         if (k + 1) % ex["obs_every"] == 0:
             obs.append(sv.device_state()[0][g_mesh].cpu().numpy())
-    calib = swe.Calibration(mesh, np.array(dts), ex["gauges"], np.array(obs), ex["obs_every"],
-                            ckpt_every=ex["ckpt_every"])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dt_dev = torch.as_tensor(np.array(dts, np.float64), device=mesh.device)
 
     def forward():
         fw = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64")
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
             e0.record(stream)
-            fw.run(steps, dt_seq=calib.dt, sync=False, stream=stream)
+            fw.run(steps, dt_seq=dt_dev, sync=False, stream=stream)
             e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e-3
 
-    def adjoint():
+    def adjoint(calib):
         sa = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64")
         out = [torch.empty(mesh.n_cells, dtype=torch.float64, device=mesh.device)
                for _ in range(5)]
@@ -227,22 +228,35 @@ def bench_adjoint(stream, steps: int = 2000) -> dict:
             e1.record(stream)
         torch.cuda.synchronize()
         fwd_ms, rev_ms = A.swe_adjoint_timings()
-        return e0.elapsed_time(e1) * 1e-3, fwd_ms * 1e-3, rev_ms * 1e-3, j
+        return e0.elapsed_time(e1) * 1e-3, fwd_ms * 1e-3, rev_ms * 1e-3, j, out
 
     forward()
-    adjoint()
     t_fwd = min(forward() for _ in range(3))
-    runs = sorted(adjoint() for _ in range(3))
-    t_adj, t_ckpt, t_rev, loss = runs[0]
-    return {"n_cells": mesh.n_cells, "steps": steps, "ckpt_every": calib.ckpt_every,
-            "forward_s": t_fwd, "adjoint_s": t_adj, "adjoint_forward_pass_s": t_ckpt,
-            "adjoint_reverse_sweep_s": t_rev,
-            "reverse_over_forward": t_rev / t_fwd, "adjoint_over_forward": t_adj / t_fwd,
-            "loss": loss,
+    res, grads = {}, {}
+    for k in (ex["ckpt_every"], 1):
+        calib = swe.Calibration(mesh, np.array(dts), ex["gauges"], np.array(obs), ex["obs_every"],
+                                ckpt_every=k)
+        adjoint(calib)
+        runs = sorted((adjoint(calib) for _ in range(3)), key=lambda r: r[0])
+        t_adj, t_ckpt, t_rev, loss, out = runs[0]
+        grads[k] = [o.cpu() for o in out]
+        res[k] = {"ckpt_every": k, "workspace_GB": calib.ws.numel() / 1e9,
+                  "adjoint_s": t_adj, "adjoint_forward_pass_s": t_ckpt,
+                  "adjoint_reverse_sweep_s": t_rev, "reverse_over_forward": t_rev / t_fwd,
+                  "adjoint_over_forward": t_adj / t_fwd, "loss": loss}
+        del calib, out, runs
+        torch.cuda.empty_cache()
+    k0 = ex["ckpt_every"]
+    record = res[1]
+    record["gradients_bitwise_equal_to_checkpointed"] = bool(
+        record["loss"] == res[k0]["loss"] and
+        all(torch.equal(a, b) for a, b in zip(grads[1], grads[k0])))
+    return {"n_cells": mesh.n_cells, "steps": steps, "forward_s": t_fwd, **res[k0],
+            "record_every_step": record,
             "timing": "best of 3 after one warm-up, HIP events on the stream. forward_s: swe_run "
                       "of the steps with the replayed dt. adjoint_s: the whole swe_adjoint call; "
-                      "its checkpointing forward pass and its reverse sweep (segment recompute "
-                      "and adjoint steps) from swe_adjoint_timings"}
+                      "its forward pass (checkpoints, or every state) and its reverse sweep "
+                      "(segment recompute, if any, and adjoint steps) from swe_adjoint_timings"}
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=10):
@@ -424,10 +438,15 @@ def main():
     adjoint = {}
     if args.adjoint_steps > 0 and args.size == "full":
         adjoint = bench_adjoint(stream, args.adjoint_steps)
+        rec = adjoint["record_every_step"]
         print(f"# adjoint: {adjoint['n_cells']} cells, {adjoint['steps']} steps: forward "
               f"{adjoint['forward_s']:.3f} s, adjoint {adjoint['adjoint_s']:.3f} s "
               f"(x{adjoint['adjoint_over_forward']:.2f}; reverse sweep "
-              f"x{adjoint['reverse_over_forward']:.2f})", file=sys.stderr, flush=True)
+              f"x{adjoint['reverse_over_forward']:.2f}); every step stored "
+              f"({rec['workspace_GB']:.1f} GB): {rec['adjoint_s']:.3f} s "
+              f"(x{rec['adjoint_over_forward']:.2f}; reverse sweep x{rec['reverse_over_forward']:.2f}), "
+              f"gradients bitwise equal {rec['gradients_bitwise_equal_to_checkpointed']}",
+              file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
     copy_gbps = copy_bandwidth()

@@ -332,8 +332,9 @@ typedef struct swe_grads {
     double *dh, *dhu, *dhv;  /* dJ/d(initial state) */
 } swe_grads;
 
-/* Workspace bytes of swe_adjoint: checkpoints, a recompute segment and the adjoint state.
- * Errors: SWE_EINVAL. */
+/* Workspace bytes of swe_adjoint: checkpoints, a recompute segment and the adjoint state;
+ * with ckpt_every = 1, every state and every step's U* instead (6 T doubles per step) and no
+ * segment.  Errors: SWE_EINVAL. */
 int32_t swe_adjoint_workspace_bytes(const swe_mesh *mesh, int64_t n_steps, int32_t ckpt_every,
                                     int64_t *bytes);
 
@@ -343,9 +344,10 @@ int32_t swe_adjoint_workspace_bytes(const swe_mesh *mesh, int64_t n_steps, int32
  * misfit J of `loss`, and the hand-written reverse sweep of the step (friction and clamp,
  * then the transposed interface fluxes with hydrostatic reconstruction, every branch frozen
  * to the forward run).  Forward states are checkpointed every ckpt_every steps and recomputed
- * segment by segment in the reverse pass.  The caller's state is not modified.  ws: device,
- * swe_adjoint_workspace_bytes bytes, 256-byte aligned.  *loss_out (host, may be NULL)
- * receives J; then the stream is synchronised.  Errors: SWE_EINVAL, SWE_EUNSUPPORTED (FP32),
+ * segment by segment in the reverse pass; ckpt_every = 1 stores every state and U* in the
+ * forward pass and recomputes nothing (the same gradients, bit for bit).  The caller's state
+ * is not modified.  ws: device, swe_adjoint_workspace_bytes bytes, 256-byte aligned.
+ * *loss_out (host, may be NULL) receives J; then the stream is synchronised.  Errors: SWE_EINVAL, SWE_EUNSUPPORTED (FP32),
  * SWE_EDEVICE.
  */
 int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
@@ -354,8 +356,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
                     void *ws, int64_t ws_bytes, void *stream);
 
 /* Device time of this thread's last completed swe_adjoint call, in milliseconds, from HIP
- * events on its stream: the checkpointing forward pass (with the loss) and the reverse sweep
- * (segment recompute and adjoint steps).  Waits for that call's work to finish.
+ * events on its stream: the forward pass (checkpoints or every state, with the loss) and the
+ * reverse sweep (segment recompute, unless every state was stored, and adjoint steps).  Waits for that call's work to finish.
  * Errors: SWE_EINVAL (no completed call on this thread), SWE_EDEVICE. */
 int32_t swe_adjoint_timings(double *forward_ms, double *reverse_ms);
 

@@ -13,8 +13,10 @@
 // the forward values and its derivative taken as is.  dt is replayed, not differentiated.
 //
 // Forward states are checkpointed every K steps; the reverse pass recomputes each segment
-// (storing U^n and the pre-friction U*) and then runs the adjoint through it backwards.  The
-// forward passes replay dt without the control block.  FP64 divisions and square roots of the
+// (storing U^n and the pre-friction U*) and then runs the adjoint through it backwards.  With
+// K = 1 the forward pass itself stores every U^n and U* (HBM holds them for the meshes and
+// step counts of a calibration run) and the reverse pass recomputes nothing.  The forward
+// passes replay dt without the control block.  FP64 divisions and square roots of the
 // adjoint use the Newton forms of swe_device_math.h (within an ulp).
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -462,6 +464,7 @@ struct AdjLayout {
     size_t ckpt, seg, segstar, lam, mu, area, loss, ctrl, work, total;
 };
 
+// K == 1 (every state stored): no recompute segment; U* of every step.
 AdjLayout adj_layout(int64_t T, int64_t n_steps, int64_t K)
 {
     AdjLayout L;
@@ -472,8 +475,8 @@ AdjLayout adj_layout(int64_t T, int64_t n_steps, int64_t K)
     size_t off = 0;
     const size_t st = 3 * static_cast<size_t>(T) * 8;
     L.ckpt = off; off += al(st * L.n_ckpt);
-    L.seg = off; off += al(st * (K + 1));
-    L.segstar = off; off += al(st * K);
+    L.seg = off; off += K == 1 ? 0 : al(st * (K + 1));
+    L.segstar = off; off += al(st * (K == 1 ? n_steps : K));
     L.lam = off; off += al(st);
     L.mu = off; off += al(st);
     L.area = off; off += al(static_cast<size_t>(T) * 8);
@@ -621,6 +624,23 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
 
     // forward pass: checkpoints and the loss (segment slots 0 and 1 serve as ping-pong)
     if (int32_t rc = copy3(ck(0, 0), ck(0, 1), ck(0, 2), s->h[s->cur], s->hu[s->cur], s->hv[s->cur])) return rc;
+    const bool record = K == 1;
+    if (record) {
+        // step n reads stored state n and writes state n + 1 and its U* in place
+        for (int64_t nstep = 0; nstep < n_steps; ++nstep) {
+            swe_state v = view(ck(nstep, 0), ck(nstep, 1), ck(nstep, 2), ck(nstep + 1, 0),
+                               ck(nstep + 1, 1), ck(nstep + 1, 2));
+            double *ustar[3] = {ss(nstep, 0), ss(nstep, 1), ss(nstep, 2)};
+            if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, v, 0, dt_seq,
+                                                                      n_steps, st, tl, nullptr, remap,
+                                                                      ustar, dt_seq + nstep)), W))
+                return rc;
+            if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
+                misfit_kernel<<<1, 64, 0, st>>>(ck(nstep + 1, 0), loss->gauges, loss->n_gauges,
+                                                loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges,
+                                                lossd, nullptr);
+        }
+    } else {
     if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(0, 0), ck(0, 1), ck(0, 2))) return rc;
     // the steps replay dt_seq directly: no control block, no dt reduction
     swe_state fw = view(sg(0, 0), sg(0, 1), sg(0, 2), sg(1, 0), sg(1, 1), sg(1, 2));
@@ -640,6 +660,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
             const int64_t c = (nstep + 1) / K;
             if (int32_t rc = copy3(ck(c, 0), ck(c, 1), ck(c, 2), fw.h[cur], fw.hu[cur], fw.hv[cur])) return rc;
         }
+    }
     }
 
     // reverse pass
@@ -682,7 +703,33 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     fill_kernel<<<(3 * S + 255) / 256, 256, 0, st>>>(lam, 3 * T, 0.0);
     fill_kernel<<<blocks, 256, 0, st>>>(out->dn, T, 0.0);
     fill_kernel<<<blocks, 256, 0, st>>>(out->dz, T, 0.0);
-    const int64_t n_seg = (n_steps + K - 1) / K;
+    // one adjoint step: lambda^{n+1} (plus the misfit at n + 1) -> lambda^n, from the state
+    // U^n and U* of step n
+    auto adjoint_step = [&](int64_t nstep, const double *const *un, const double *const *us1,
+                            const double *const *ustar) {
+        if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
+            misfit_kernel<<<(loss->n_gauges + 63) / 64, 64, 0, st>>>(
+                us1[0], loss->gauges, loss->n_gauges,
+                loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges, nullptr, lam);
+        a.step = nstep;
+        a.sh = ustar[0]; a.shu = ustar[1]; a.shv = ustar[2];
+        friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+        a.h = un[0]; a.hu = un[1]; a.hv = un[2];
+        if (adj_lds)
+            tile_flux_adjoint_kernel<<<dim3(static_cast<unsigned>(at.n_tiles)), 256, adj_lds, st>>>(a, at);
+        else
+            flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+    };
+    if (record) {
+        for (int64_t nstep = n_steps - 1; nstep >= 0; --nstep) {
+            const double *un[3] = {ck(nstep, 0), ck(nstep, 1), ck(nstep, 2)};
+            const double *u1[3] = {ck(nstep + 1, 0), ck(nstep + 1, 1), ck(nstep + 1, 2)};
+            const double *us[3] = {ss(nstep, 0), ss(nstep, 1), ss(nstep, 2)};
+            adjoint_step(nstep, un, u1, us);
+        }
+        if (int32_t rc = ahip(hipGetLastError(), W)) return rc;
+    }
+    const int64_t n_seg = record ? 0 : (n_steps + K - 1) / K;
     for (int64_t sgi = n_seg - 1; sgi >= 0; --sgi) {
         const int64_t s0 = sgi * K, s1 = std::min(n_steps, s0 + K);
         if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(sgi, 0), ck(sgi, 1), ck(sgi, 2))) return rc;
@@ -697,18 +744,10 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         }
         for (int64_t nstep = s1 - 1; nstep >= s0; --nstep) {
             const int64_t q = nstep - s0;
-            if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
-                misfit_kernel<<<(loss->n_gauges + 63) / 64, 64, 0, st>>>(
-                    sg(q + 1, 0), loss->gauges, loss->n_gauges,
-                    loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges, nullptr, lam);
-            a.step = nstep;
-            a.sh = ss(q, 0); a.shu = ss(q, 1); a.shv = ss(q, 2);
-            friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
-            a.h = sg(q, 0); a.hu = sg(q, 1); a.hv = sg(q, 2);
-            if (adj_lds)
-                tile_flux_adjoint_kernel<<<dim3(static_cast<unsigned>(at.n_tiles)), 256, adj_lds, st>>>(a, at);
-            else
-                flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+            const double *un[3] = {sg(q, 0), sg(q, 1), sg(q, 2)};
+            const double *u1[3] = {sg(q + 1, 0), sg(q + 1, 1), sg(q + 1, 2)};
+            const double *us[3] = {ss(q, 0), ss(q, 1), ss(q, 2)};
+            adjoint_step(nstep, un, u1, us);
         }
         if (int32_t rc = ahip(hipGetLastError(), W)) return rc;
     }

@@ -66,9 +66,11 @@ def test_central_differences_on_random_cells(setup):
     assert len(bad) == 0
 
 
-def test_checkpoint_interval_does_not_change_gradients(setup, gpu):
+@pytest.mark.parametrize("ckpt_every", [7, 1])
+def test_checkpoint_interval_does_not_change_gradients(setup, gpu, ckpt_every):
+    """Other checkpoint intervals, and every state stored (no recompute), give the same bits."""
     case, om, dts, obs, calib, j, grads = setup
-    c2 = gpu.Calibration(calib.mesh, dts, case.extra["gauges"], obs, every=10, ckpt_every=7)
+    c2 = gpu.Calibration(calib.mesh, dts, case.extra["gauges"], obs, every=10, ckpt_every=ckpt_every)
     j2, g2 = c2.run(case.n, case.z, case.h, case.hu, case.hv)
     assert j2 == j
     for a, b in zip(grads, g2):
