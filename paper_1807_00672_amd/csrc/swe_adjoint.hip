@@ -338,27 +338,46 @@ struct AdjTiles {
 
 // LDS of the tiled flux adjoint: 7 words per staged cell (h, hu, hv, z and the cotangent
 // -dt/A mu of its contribution), 8 per edge-list entry (both sides' cotangents and bed terms).
+// Tiles of at most 2 SWE_TILE entries use a shared layout: [8 rows of SWE_TILE for entries
+// 0..SWE_TILE-1 | staged cells], the later entries written in 8 rows of SWE_TILE over the
+// staged cells once every interface has been differentiated; others [cells | 8 rows of M].
+inline bool tile_adj_shared(int64_t max_edges) { return max_edges <= 2 * SWE_TILE; }
+
 inline size_t tile_adj_lds_bytes(int64_t max_halo, int64_t max_edges)
 {
-    return 8 * static_cast<size_t>(7 * (SWE_TILE + max_halo) + 8 * max_edges);
+    const size_t cells = 7 * static_cast<size_t>(SWE_TILE + max_halo);
+    if (tile_adj_shared(max_edges))
+        return 8 * (8 * static_cast<size_t>(SWE_TILE) + std::max(cells, 8 * static_cast<size_t>(SWE_TILE)));
+    return 8 * (cells + 8 * static_cast<size_t>(max_edges));
 }
 
 // The flux adjoint of flux_adjoint_kernel, tiled: each interface of a tile's edge list is
 // differentiated once (both sides' cotangents at once) into LDS, then each cell gathers its
 // three shares in local-edge order.  Same quantities as the per-cell kernel, up to rounding.
-__global__ __launch_bounds__(256) void tile_flux_adjoint_kernel(AdjArgs a, AdjTiles t)
+// Work-items take edge-list and halo positions as the tiled step does (the wave with one
+// round of interfaces stages the halo; which wave it is turns with the tile).  Four waves per
+// SIMD: 128 VGPRs, and the shared layout's LDS.
+template <bool Shared>
+__global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, AdjTiles t)
 {
     const int tile = blockIdx.x;
     if (tile >= t.n_tiles) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int ns = SWE_TILE + t.max_halo, M = t.max_edges;
-    double *s_h = reinterpret_cast<double *>(smem);
+    double *const lds = reinterpret_cast<double *>(smem);
+    const int ns = SWE_TILE + t.max_halo;
+    // staged cells at cbase; edge-list entry q of row j at ebase + j estride + q (+ bshift from
+    // entry SWE_TILE on)
+    const int cbase = Shared ? 8 * SWE_TILE : 0;
+    const int ebase = Shared ? 0 : 7 * ns;
+    const int estride = Shared ? SWE_TILE : t.max_edges;
+    const int bshift = Shared ? 7 * SWE_TILE : 0;
+    double *s_h = lds + cbase;
     double *s_hu = s_h + ns, *s_hv = s_hu + ns, *s_z = s_hv + ns;
     double *s_c0 = s_z + ns, *s_c1 = s_c0 + ns, *s_c2 = s_c1 + ns;
-    double *e_a = s_c2 + ns;        // [4][M]: side a's (h, hu, hv) cotangent and bed term
-    double *e_b = e_a + 4 * M;      // [4][M]: side b's, for interfaces inside the tile
     const int64_t T = a.T, s0 = static_cast<int64_t>(tile) * SWE_TILE;
     const int tid = threadIdx.x;
+    const int pt = (tid + 64 * (tile & 3)) & (SWE_TILE - 1);
+    const int ph = SWE_TILE - 1 - pt;
     const int64_t i = s0 + tid;
     const bool mine = i < T;
     const double dt = a.dt_seq[a.step], g = a.g, hd = a.hd;
@@ -374,11 +393,14 @@ __global__ __launch_bounds__(256) void tile_flux_adjoint_kernel(AdjArgs a, AdjTi
     };
     if (mine) stage(tid, i);
     const int hb = t.halo_off[tile], he = t.halo_off[tile + 1];
-    for (int j = hb + tid; j < he; j += SWE_TILE) stage(SWE_TILE + (j - hb), t.halo[j]);
+    for (int j = hb + ph; j < he; j += SWE_TILE) stage(SWE_TILE + (j - hb), t.halo[j]);
     __syncthreads();
 
-    const int eb = t.edge_off[tile], ee = t.edge_off[tile + 1];
-    for (int e = eb + tid; e < ee; e += SWE_TILE) {
+    // side a's (h, hu, hv) cotangent and bed term, then side b's for interfaces inside the tile
+    struct EdgeAdj {
+        double v[8];
+    };
+    auto diff = [&](int e, EdgeAdj &o) {
         const uint32_t w = t.edges[e];
         const int ca = static_cast<int>(w & 0xffu);
         const int k = static_cast<int>((w >> 8) & 3u);
@@ -391,28 +413,55 @@ __global__ __launch_bounds__(256) void tile_flux_adjoint_kernel(AdjArgs a, AdjTi
         const double ci[3] = {s_c0[ca], s_c1[ca], s_c2[ca]};
         Vjp3 u{0.0, 0.0, 0.0};
         double za_b = 0.0;
-        const int q = e - eb;
+        bool inner = false;
         if (cb >= 0) {
             const double cj[3] = {s_c0[cb], s_c1[cb], s_c2[cb]};
             Vjp3 ub;
             double zb_b;
             interface_vjp(g, hd, s_h[ca], s_hu[ca], s_hv[ca], s_z[ca], s_h[cb], s_hu[cb],
                           s_hv[cb], s_z[cb], nx, ny, l, ci, cj, u, za_b, ub, zb_b);
-            if (cb < SWE_TILE) {
-                e_b[q] = ub.h;
-                e_b[M + q] = ub.hu;
-                e_b[2 * M + q] = ub.hv;
-                e_b[3 * M + q] = zb_b;
-            }
+            inner = cb < SWE_TILE;
+            o.v[4] = ub.h;
+            o.v[5] = ub.hu;
+            o.v[6] = ub.hv;
+            o.v[7] = zb_b;
         } else if (cb == SWE_WALL) {
             wall_vjp(g, hd, s_h[ca], s_hu[ca], s_hv[ca], nx, ny, l, ci, u);
         } else {
             inflow_vjp(g, a.q[-2 - cb], s_h[ca], nx, ny, l, ci, u);
         }
-        e_a[q] = u.h;
-        e_a[M + q] = u.hu;
-        e_a[2 * M + q] = u.hv;
-        e_a[3 * M + q] = za_b;
+        o.v[0] = u.h;
+        o.v[1] = u.hu;
+        o.v[2] = u.hv;
+        o.v[3] = za_b;
+        return inner;
+    };
+    auto put = [&](int q, const EdgeAdj &o, bool inner) {
+        double *ed = lds + ebase + q + (q >= SWE_TILE ? bshift : 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ed[r * estride] = o.v[r];
+        if (inner) {
+#pragma unroll
+            for (int r = 4; r < 8; ++r) ed[r * estride] = o.v[r];
+        }
+    };
+    const int eb = t.edge_off[tile], ee = t.edge_off[tile + 1];
+    // one call site of diff: in the shared layout (two rounds at most) the second round's
+    // result waits for the barrier after which the staged cells may be overwritten
+    EdgeAdj o;
+    bool inner = false;
+    int held = -1;
+    for (int q = pt; eb + q < ee; q += SWE_TILE) {
+        inner = diff(eb + q, o);
+        if (Shared && q >= SWE_TILE) {
+            held = q;
+            break;
+        }
+        put(q, o, inner);
+    }
+    if constexpr (Shared) {
+        __syncthreads();   // every read of the staged cells is done
+        if (held >= 0) put(held, o, inner);
     }
     __syncthreads();
     if (!mine) return;
@@ -421,11 +470,11 @@ __global__ __launch_bounds__(256) void tile_flux_adjoint_kernel(AdjArgs a, AdjTi
     for (int k = 0; k < 3; ++k) {
         const uint32_t sl = t.slot[k * T + i];
         const int q = static_cast<int>(sl & 0x7fffu);
-        const double *ed = (sl & 0x8000u) ? e_b : e_a;
-        lh += ed[q];
-        lhu += ed[M + q];
-        lhv += ed[2 * M + q];
-        zb_sum += ed[3 * M + q];
+        const double *ed = lds + ebase + q + (q >= SWE_TILE ? bshift : 0) + ((sl & 0x8000u) ? 4 * estride : 0);
+        lh += ed[0];
+        lhu += ed[estride];
+        lhv += ed[2 * estride];
+        zb_sum += ed[3 * estride];
     }
     a.lh[i] = lh;
     a.lhu[i] = lhu;
@@ -433,7 +482,8 @@ __global__ __launch_bounds__(256) void tile_flux_adjoint_kernel(AdjArgs a, AdjTi
     a.gz[i] += zb_sum;
 }
 
-// Misfit at an observation: the loss gains sum (h_g - obs_g)^2 (one work-item, fixed order);
+// Misfit at an observation: the loss gains sum (h_g - obs_g)^2, summed in gauge order by one
+// work-item from squares the 64 work-items of the (single) workgroup form a chunk at a time;
 // with lam != nullptr the adjoint gains 2 (h_g - obs_g) at the gauges instead.
 __global__ void misfit_kernel(const double *h, const int32_t *gauges, int ng, const double *obs,
                               double *loss, double *lam)
@@ -443,13 +493,20 @@ __global__ void misfit_kernel(const double *h, const int32_t *gauges, int ng, co
         if (q < ng) lam[gauges[q]] += 2.0 * (h[gauges[q]] - obs[q]);
         return;
     }
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sq[64];
     double acc = 0.0;
-    for (int q = 0; q < ng; ++q) {
-        const double r = h[gauges[q]] - obs[q];
-        acc += r * r;
+    for (int base = 0; base < ng; base += 64) {
+        const int q = base + static_cast<int>(threadIdx.x);
+        if (q < ng) {
+            const double r = h[gauges[q]] - obs[q];
+            sq[threadIdx.x] = r * r;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 64 && base + k < ng; ++k) acc += sq[k];
+        __syncthreads();
     }
-    *loss += acc;
+    if (threadIdx.x == 0) *loss += acc;
 }
 
 __global__ void fill_kernel(double *p, int64_t n, double v)
@@ -686,8 +743,10 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     AdjTiles at;
     memset(&at, 0, sizeof(at));
     size_t adj_lds = 0;
+    bool adj_shared = false;
     if (tl && SWE_TILE_ADJOINT) {
         const size_t need = tile_adj_lds_bytes(tl->max_halo, tl->max_edges);
+        adj_shared = tile_adj_shared(tl->max_edges);
         if (need <= 65536) {
             adj_lds = need;
             at.halo_off = dm->halo_off;
@@ -716,7 +775,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
         a.h = un[0]; a.hu = un[1]; a.hv = un[2];
         if (adj_lds)
-            tile_flux_adjoint_kernel<<<dim3(static_cast<unsigned>(at.n_tiles)), 256, adj_lds, st>>>(a, at);
+            (adj_shared ? tile_flux_adjoint_kernel<true> : tile_flux_adjoint_kernel<false>)
+                <<<dim3(static_cast<unsigned>(at.n_tiles)), 256, adj_lds, st>>>(a, at);
         else
             flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
     };
