@@ -739,7 +739,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     a.g = p->g;
     a.hd = p->h_dry;
     for (int k = 0; k < p->n_inflow; ++k) a.q[k] = p->inflow_q[k];
-    // the tiled flux adjoint where the step is tiled and its LDS fits the default 64 KiB
+    // the tiled flux adjoint where the step is tiled and its LDS fits a workgroup
     AdjTiles at;
     memset(&at, 0, sizeof(at));
     size_t adj_lds = 0;
@@ -747,7 +747,19 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     if (tl && SWE_TILE_ADJOINT) {
         const size_t need = tile_adj_lds_bytes(tl->max_halo, tl->max_edges);
         adj_shared = tile_adj_shared(tl->max_edges);
-        if (need <= 65536) {
+        int dev = 0, max_lds = 65536;
+        if (int32_t rc = ahip(hipGetDevice(&dev), W)) return rc;
+        if (int32_t rc = ahip(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), W))
+            return rc;
+        bool fits = need <= static_cast<size_t>(max_lds);
+        if (fits && need > 65536) {   // beyond the default dynamic LDS limit
+            const void *k = adj_shared ? reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<true>)
+                                       : reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<false>);
+            fits = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(need)) == hipSuccess;
+            if (!fits) (void)hipGetLastError();   // the per-cell kernel then; clear the error
+        }
+        if (fits) {
             adj_lds = need;
             at.halo_off = dm->halo_off;
             at.halo = dm->halo;
