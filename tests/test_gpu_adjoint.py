@@ -99,3 +99,20 @@ def test_autograd_function(setup, gpu):
     assert loss.item() == j
     for t, g in zip(ts, grads):
         assert np.array_equal(t.grad.numpy(), 2.0 * g)
+
+
+@pytest.mark.parametrize("ckpt_every", [1, 2])
+def test_roughness_gradient_matches_friction_closed_form(gpu, ckpt_every):
+    """dJ/dn on the supersonic channel (two steps, one gauge) against the hand-derived closed
+    form: nonzero only at the gauge and its upwind neighbour."""
+    from test_oracle_adjoint import friction_closed_form_dn, supersonic_channel
+    xy, tri, st, gauge, dts, obs, consts = supersonic_channel()
+    mesh = gpu.Mesh(xy, tri)
+    j_want, want = friction_closed_form_dn(xy, tri, st["n"], gauge, consts)
+    calib = gpu.Calibration(mesh, dts, [gauge], obs, every=2, ckpt_every=ckpt_every)
+    j, grads = calib.run(st["n"], st["z"], st["h"], st["hu"], st["hv"])
+    dn = grads[0]
+    print(f"J {j!r} (closed form {j_want!r}); dn at the gauge {dn[gauge]!r} "
+          f"(closed form {want[gauge]!r}); max |dn - closed form| {np.abs(dn - want).max():.3e}")
+    assert j == pytest.approx(j_want, rel=1e-12)
+    assert np.abs(dn - want).max() <= 1e-10 * np.abs(want).max()

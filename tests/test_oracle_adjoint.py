@@ -50,3 +50,84 @@ def test_tangent_matches_central_differences(setup, which):
     fd = (loss(1) - loss(-1)) / (2 * eps)
     assert J == pytest.approx(loss(0), rel=1e-15)
     assert dJ == pytest.approx(fd, rel=1e-5)
+
+
+def supersonic_channel(nx=24, ny=12, h0=1.7, froude=2.0, dt=0.015, seed=3):
+    """Right triangles (fixed diagonals, 1 m squares), flat bed, uniform depth h0 and velocity
+    u0 = Froude * sqrt(g h0) along x, walls, Manning n random per cell.  Every edge that carries
+    mass is then supersonic (|q| >= u0 / sqrt(2) > c), so each HLLC mass flux is the upwind
+    side's h q; edges along the flow carry none.  Gauge: the lower triangle of the central square,
+    observed after two steps of length dt (observation h0 - 0.1)."""
+    g = 9.81
+    xs, ys = np.meshgrid(np.arange(nx + 1.0), np.arange(ny + 1.0))
+    xy = np.stack([xs.ravel(), ys.ravel()], 1)
+    node = lambda i, j: j * (nx + 1) + i
+    tri = []
+    for j in range(ny):
+        for i in range(nx):
+            tri.append((node(i, j), node(i + 1, j), node(i + 1, j + 1)))   # lower
+            tri.append((node(i, j), node(i + 1, j + 1), node(i, j + 1)))   # upper
+    tri = np.array(tri, np.int32)
+    t = tri.shape[0]
+    u0 = froude * np.sqrt(g * h0)
+    n = np.random.default_rng(seed).uniform(0.02, 0.05, t)
+    gauge = 2 * ((ny // 2) * nx + nx // 2)
+    state = dict(z=np.zeros(t), n=n, h=np.full(t, h0), hu=np.full(t, h0 * u0), hv=np.zeros(t))
+    return xy, tri, state, gauge, np.array([dt, dt]), np.array([[h0 - 0.1]]), (g, h0, u0, dt)
+
+
+def friction_closed_form_dn(xy, tri, n, gauge, consts):
+    """dJ/dn of the two-step misfit J = (h2[gauge] - obs)^2 in supersonic_channel, by hand.
+
+    Step 1 moves no mass in the uniform interior and its friction turns u0 into
+    u1 = u0 / D(n), D = 1 + dt g n^2 |q| / (h0^2 h0^(1/3)) with |q| = h0 u0.  Step 2's mass flux
+    through an edge of the gauge cell with outward normal (n_x, n_y) is h0 u1 n_x of the upwind
+    cell, so h2 = h0 - dt / A sum_k l_k n_x,k h0 u1(upwind_k), with l_k n_x,k = dy_k.  Outflow
+    edges (dy > 0) take the gauge's own n, inflow edges (dy < 0) the neighbour's; dt is not
+    differentiated.  Returns (J, dJ/dn)."""
+    g, h0, u0, dt = consts
+    p = xy[tri[gauge]]
+    area = 0.5 * ((p[1, 0] - p[0, 0]) * (p[2, 1] - p[0, 1]) - (p[1, 1] - p[0, 1]) * (p[2, 0] - p[0, 0]))
+    k_fric = dt * g * h0 * u0 / (h0 ** 2 * np.cbrt(h0))
+
+    def u1(nm):
+        return u0 / (1.0 + k_fric * nm * nm)
+
+    def du1(nm):   # d(u0 / D)/dn
+        d = 1.0 + k_fric * nm * nm
+        return -u0 * (2.0 * k_fric * nm) / d ** 2
+
+    keys = {}
+    for c, (a, b, e) in enumerate(tri):
+        for u, v in ((a, b), (b, e), (e, a)):
+            keys.setdefault((min(u, v), max(u, v)), []).append(c)
+    h2, dh2 = h0, np.zeros(tri.shape[0])
+    for k in range(3):
+        a, b = tri[gauge][k], tri[gauge][(k + 1) % 3]
+        dy = xy[b, 1] - xy[a, 1]
+        if dy == 0.0:
+            continue
+        cell = gauge if dy > 0 else [c for c in keys[(min(a, b), max(a, b))] if c != gauge][0]
+        h2 -= dt / area * h0 * dy * u1(n[cell])
+        dh2[cell] += -dt / area * h0 * dy * du1(n[cell])
+    r = h2 - (h0 - 0.1)
+    return r * r, 2.0 * r * dh2
+
+
+def test_tangent_matches_friction_closed_form():
+    """The tangent model's dJ/dn on the supersonic channel, cell by cell, against the
+    closed form: nonzero exactly at the gauge (outflow edge) and its upwind neighbour."""
+    xy, tri, st, gauge, dts, obs, consts = supersonic_channel()
+    mesh = oracle.Mesh(xy, tri)
+    j_want, want = friction_closed_form_dn(xy, tri, st["n"], gauge, consts)
+    nz = np.flatnonzero(want)
+    assert nz.size == 2
+    probe = list(nz) + [gauge + 5, gauge - 2 * 24]     # and two cells that must give zero
+    for c in probe:
+        e = np.zeros(tri.shape[0])
+        e[c] = 1.0
+        J, dJ = oracle.run_tl(mesh, st["z"], st["n"], st["h"], st["hu"], st["hv"], dts,
+                              [gauge], 2, obs, dn=e)
+        assert J == pytest.approx(j_want, rel=1e-12)
+        print(f"cell {c}: tangent {dJ!r}, closed form {want[c]!r}")
+        assert dJ == pytest.approx(want[c], rel=1e-10, abs=1e-12 * np.abs(want).max())
