@@ -42,9 +42,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(dtype: str, n_cells: int):
-    """HBM bytes per launch of the step kernel from committed counter runs, if they were taken
-    on the current kernel source for this workload; else None."""
+def load_counter(dtype: str, n_cells: int, what: str = "bytes_per_launch"):
+    """A per-launch counter figure of the step kernel (HBM bytes, VALU instructions) from
+    committed counter runs, if they were taken on the current kernel source for this
+    workload; else None."""
     p = os.path.join(ROOT, "profiles", "tile_step_kernel_traffic.json")
     if not os.path.exists(p):
         return None
@@ -52,7 +53,28 @@ def load_traffic(dtype: str, n_cells: int):
         d = json.load(f)
     if d.get("kernel_sha") != kernel_source_hash() or d.get("n_cells") != n_cells:
         return None
-    return d.get("bytes_per_launch", {}).get(dtype)
+    return d.get(what, {}).get(dtype)
+
+
+# VALU issue: one wave64 instruction takes 4 cycles of a 16-lane SIMD; 256 CUs x 4 SIMDs at
+# 2.4 GHz (MI355X).
+N_SIMD, CLOCK_HZ = 1024, 2.4e9
+
+
+def valu_issue_s(valu_insts):
+    return valu_insts * 4 / N_SIMD / CLOCK_HZ
+
+
+def alu_view(r):
+    """The step's second ceiling: its counted VALU instructions issued at full rate on every
+    SIMD, against the measured step time."""
+    v = r.get("valu_insts_per_launch")
+    if v is None:
+        return None
+    t = valu_issue_s(v)
+    return {"valu_insts_per_launch": v, "valu_issue_us_at_full_rate": t * 1e6,
+            "frac_of_step_time": t / (r["ms_per_step"] * 1e-3),
+            "source": "SQ_INSTS_VALU of the committed counter run (profiles/)"}
 
 
 def time_gpu(solver, steps, warmup, stream):
@@ -427,7 +449,9 @@ def main():
             "achieved_GBps": alg / per_step_s / 1e9,
             "kernel": kernel,
             "math": "correctly rounded" if exact else ("newton" if dt == "f64" else "hardware"),
-            "traffic": (load_traffic(key, case.n_cells) if kernel == PROFILED_KERNEL else None),
+            "traffic": (load_counter(key, case.n_cells) if kernel == PROFILED_KERNEL else None),
+            "valu_insts_per_launch": (load_counter(key, case.n_cells, "valu_insts_per_launch")
+                                      if kernel == PROFILED_KERNEL else None),
             "t_end_state": st["t"],
         }
         print(f"# {key}: {ms / args.steps:.4f} ms/step, {results[key]['value'] / 1e9:.2f} G "
@@ -504,7 +528,8 @@ def main():
                      "timed": "whole step (step kernel + dt fold kernel) per step",
                      "alg_bytes_per_launch": r["alg_bytes_per_step"],
                      "copy_GBps_measured": copy_gbps,
-                     "frac_of_measured_copy": r["achieved_GBps"] / copy_gbps},
+                     "frac_of_measured_copy": r["achieved_GBps"] / copy_gbps,
+                     "alu": alu_view(r)},
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "t_end_state"}
                      for k, v in results.items()},
         "tuning": tuning,
