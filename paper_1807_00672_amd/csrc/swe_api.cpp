@@ -97,8 +97,8 @@ struct DeviceLds {
 DeviceLds g_lds[64];
 
 
-// Two steps (even and odd buffer) captured once as a graph and replayed by swe_run; the
-// launch arguments it bakes in form its key.
+// kGraphSteps steps (an even number: the state ends in the buffer it started from) captured
+// once as a graph and replayed by swe_run; the launch arguments it bakes in form its key.
 struct GraphKey {
     swe_dev_mesh dm;
     double g, courant, h_dry;
