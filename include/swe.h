@@ -106,8 +106,16 @@ enum swe_mesh_array {
                               SWE_TILE + j, or a boundary code (SWE_WALL, -1 - s) */
     SWE_ARR_SLOT = 9,      /* uint16[3T], [k*T + i]: entry of cell i's local edge k in its
                               tile's edge list; bit 15 set when i is the edge's side b */
-    SWE_ARR_GLOBAL = 10    /* int32[T]: index of cell i in the mesh a shard was cut from
+    SWE_ARR_GLOBAL = 10,   /* int32[T]: index of cell i in the mesh a shard was cut from
                               (swe_mesh_create_shard); i for other meshes */
+    SWE_ARR_EDGE_VEC = 11, /* double[2 n_tile_edges]: (dx, dy) of each EDGES entry, node k+1
+                              minus node k of its owning cell (the outward normal of eq. 3
+                              is (dy, -dx) / l) */
+    SWE_ARR_CELL_GEO = 12, /* double[2T]: area A_i of cell i at [i] (eq. 4), inradius
+                              r_i = 2 A_i / P_i at [T + i] (the CFL bound); IEEE square root
+                              and division, l_k summed in local-edge order */
+    SWE_ARR_EDGE_VEC32 = 13, /* float[2 n_tile_edges]: SWE_ARR_EDGE_VEC rounded to float */
+    SWE_ARR_CELL_GEO32 = 14  /* float[2T]: SWE_ARR_CELL_GEO rounded to float */
 };
 
 /* Device view of a mesh: the arrays of swe_mesh_export copied to device memory. */
@@ -121,6 +129,12 @@ typedef struct swe_dev_mesh {
     const int32_t *edge_off;   /* device, as SWE_ARR_EDGE_OFF */
     const uint32_t *edges;     /* device, as SWE_ARR_EDGES */
     const uint16_t *slot;      /* device, as SWE_ARR_SLOT */
+    const double *edge_vec;    /* device, as SWE_ARR_EDGE_VEC, 16-byte aligned (FP64 tiled step) */
+    const double *cell_geo;    /* device, as SWE_ARR_CELL_GEO (FP64 steps and the adjoint) */
+    const float *edge_vec32;   /* device, as SWE_ARR_EDGE_VEC32, 8-byte aligned (FP32 tiled
+                                  step); may be NULL for FP64-only use */
+    const float *cell_geo32;   /* device, as SWE_ARR_CELL_GEO32 (FP32 steps); may be NULL for
+                                  FP64-only use */
 } swe_dev_mesh;
 
 /* Physical and numerical parameters (section 2.1-2.2). */

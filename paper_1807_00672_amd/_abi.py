@@ -40,7 +40,8 @@ SWE_EXACT = 8
 SWE_TILE = 256
 
 (SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,
- SWE_ARR_HALO, SWE_ARR_EDGE_OFF, SWE_ARR_EDGES, SWE_ARR_SLOT, SWE_ARR_GLOBAL) = range(11)
+ SWE_ARR_HALO, SWE_ARR_EDGE_OFF, SWE_ARR_EDGES, SWE_ARR_SLOT, SWE_ARR_GLOBAL, SWE_ARR_EDGE_VEC,
+ SWE_ARR_CELL_GEO, SWE_ARR_EDGE_VEC32, SWE_ARR_CELL_GEO32) = range(15)
 
 _NAMES = {0: "SWE_OK", -1: "SWE_EINVAL", -2: "SWE_EMESH", -3: "SWE_EDEVICE",
           -4: "SWE_ENONFINITE", -5: "SWE_EDRY", -6: "SWE_EUNSUPPORTED"}
@@ -67,7 +68,8 @@ class swe_dev_mesh(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("nbr", C.c_void_p),
                 ("c2n", C.c_void_p), ("xy", C.c_void_p), ("halo_off", C.c_void_p),
                 ("halo", C.c_void_p), ("edge_off", C.c_void_p), ("edges", C.c_void_p),
-                ("slot", C.c_void_p)]
+                ("slot", C.c_void_p), ("edge_vec", C.c_void_p), ("cell_geo", C.c_void_p),
+                ("edge_vec32", C.c_void_p), ("cell_geo32", C.c_void_p)]
 
 
 class swe_params(C.Structure):

@@ -237,15 +237,6 @@ struct AdjArgs {
     double q[SWE_MAX_INFLOW];
 };
 
-__global__ __launch_bounds__(256) void area_kernel(int64_t T, const int32_t *c2n, const double2 *xy,
-                                                   double *area)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= T) return;
-    const double2 p0 = xy[c2n[i]], p1 = xy[c2n[T + i]], p2 = xy[c2n[2 * T + i]];
-    area[i] = 0.5 * ((p1.x - p0.x) * (p2.y - p1.y) - (p1.y - p0.y) * (p2.x - p1.x));
-}
-
 // mu = (dU^{n+1}/dU*)^T lambda^{n+1}; the roughness gradient gains (dU^{n+1}/dn)^T lambda.
 __global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
 {
@@ -333,6 +324,7 @@ struct AdjTiles {
     const int32_t *halo_off, *halo, *edge_off;
     const uint32_t *edges;
     const uint16_t *slot;
+    const double2 *edge_vec;
     int32_t n_tiles, max_halo, max_edges, pad;
 };
 
@@ -403,11 +395,9 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     auto diff = [&](int e, EdgeAdj &o) {
         const uint32_t w = t.edges[e];
         const int ca = static_cast<int>(w & 0xffu);
-        const int k = static_cast<int>((w >> 8) & 3u);
         const int cb = static_cast<int16_t>(w >> 16);
-        const double2 p0 = a.xy[a.c2n[k * T + s0 + ca]];
-        const double2 p1 = a.xy[a.c2n[(k == 2 ? 0 : k + 1) * T + s0 + ca]];
-        const double dx = p1.x - p0.x, dy = p1.y - p0.y;
+        const double2 d = t.edge_vec[e];
+        const double dx = d.x, dy = d.y;
         const double l = sqrt_nr(dx * dx + dy * dy);
         const double nx = div_nr(dy, l), ny = div_nr(-dx, l);
         const double ci[3] = {s_c0[ca], s_c1[ca], s_c2[ca]};
@@ -518,7 +508,7 @@ __global__ void fill_kernel(double *p, int64_t n, double v)
 // Workspace layout of swe_adjoint (all double unless noted).
 struct AdjLayout {
     int64_t T, n_ckpt, K;
-    size_t ckpt, seg, segstar, lam, mu, area, loss, ctrl, work, total;
+    size_t ckpt, seg, segstar, lam, mu, loss, ctrl, work, total;
 };
 
 // K == 1 (every state stored): no recompute segment; U* of every step.
@@ -536,7 +526,6 @@ AdjLayout adj_layout(int64_t T, int64_t n_steps, int64_t K)
     L.segstar = off; off += al(st * (K == 1 ? n_steps : K));
     L.lam = off; off += al(st);
     L.mu = off; off += al(st);
-    L.area = off; off += al(static_cast<size_t>(T) * 8);
     L.loss = off; off += 256;
     L.ctrl = off; off += al(SWE_CTRL_BYTES);
     L.work = off; off += al(static_cast<size_t>(workspace_bytes(T)));
@@ -615,7 +604,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     if (!(p->g > 0.0) || !(p->h_dry >= 0.0) || p->n_inflow < 0 || p->n_inflow > SWE_MAX_INFLOW ||
         (p->n_inflow > 0 && !p->inflow_q) || mesh->info.n_inflow_segments > p->n_inflow)
         return afail(SWE_EINVAL, "swe_adjoint: bad parameters");
-    if (dm->n_cells != mesh->info.n_cells || !dm->nbr || !dm->c2n || !dm->xy)
+    if (dm->n_cells != mesh->info.n_cells || !dm->nbr || !dm->c2n || !dm->xy || !dm->cell_geo)
         return afail(SWE_EINVAL, "swe_adjoint: bad device mesh");
     if (mesh->info.n_owned != mesh->info.n_cells || (p->flags & SWE_SHARD))
         return afail(SWE_EUNSUPPORTED, "swe_adjoint: not for shards");
@@ -640,7 +629,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     auto ck = [&](int64_t c, int f) { return D(L.ckpt) + (static_cast<size_t>(c) * 3 + f) * S; };
     auto sg = [&](int64_t n, int f) { return D(L.seg) + (static_cast<size_t>(n) * 3 + f) * S; };
     auto ss = [&](int64_t n, int f) { return D(L.segstar) + (static_cast<size_t>(n) * 3 + f) * S; };
-    double *lam = D(L.lam), *mu = D(L.mu), *area = D(L.area), *lossd = D(L.loss);
+    double *lam = D(L.lam), *mu = D(L.mu), *lossd = D(L.loss);
     const unsigned blocks = static_cast<unsigned>((T + 255) / 256);
 
     StepConfig cfg;
@@ -676,7 +665,6 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         return ahip(hipMemcpyAsync(dhv, shv, bytes3, hipMemcpyDeviceToDevice, st), W);
     };
 
-    area_kernel<<<blocks, 256, 0, st>>>(T, dm->c2n, reinterpret_cast<const double2 *>(dm->xy), area);
     fill_kernel<<<1, 256, 0, st>>>(lossd, 1, 0.0);
 
     // forward pass: checkpoints and the loss (segment slots 0 and 1 serve as ping-pong)
@@ -730,7 +718,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     a.xy = reinterpret_cast<const double2 *>(dm->xy);
     a.z = static_cast<const double *>(s->z);
     a.n = static_cast<const double *>(s->n);
-    a.area = area;
+    a.area = dm->cell_geo;   // the cell areas A_i, first T entries
     a.lh = lam; a.lhu = lam + S; a.lhv = lam + 2 * S;
     a.mh = mu; a.mhu = mu + S; a.mhv = mu + 2 * S;
     a.gn = out->dn;
@@ -766,6 +754,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
             at.edge_off = dm->edge_off;
             at.edges = dm->edges;
             at.slot = dm->slot;
+            at.edge_vec = reinterpret_cast<const double2 *>(dm->edge_vec);
             at.n_tiles = static_cast<int32_t>(tl->n_tiles);
             at.max_halo = tl->max_halo;
             at.max_edges = tl->max_edges;

@@ -56,7 +56,8 @@ int32_t check_call(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_param
     if (int32_t rc = check_params(p, where)) return rc;
     if (dm->n_cells != mesh->info.n_cells || dm->n_nodes != mesh->info.n_nodes)
         return fail(SWE_EINVAL, w + ": device mesh sizes differ from the mesh");
-    if (!dm->nbr || !dm->c2n || !dm->xy) return fail(SWE_EINVAL, w + ": null device mesh array");
+    if (!dm->nbr || !dm->c2n || !dm->xy || !(p->dtype == SWE_F64 ? (const void *)dm->cell_geo : (const void *)dm->cell_geo32))
+        return fail(SWE_EINVAL, w + ": null device mesh array");
     if (!aligned(dm->xy, 16)) return fail(SWE_EINVAL, w + ": xy must be 16-byte aligned");
     if (mesh->info.n_inflow_segments > p->n_inflow)
         return fail(SWE_EINVAL, w + ": mesh has inflow segment " +
@@ -227,7 +228,10 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     }
     if (variant == SWE_CELL) return SWE_OK;
     const bool auto_ = variant == SWE_AUTO;
-    const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot;
+    const void *ev = p->dtype == SWE_F64 ? (const void *)dm->edge_vec : (const void *)dm->edge_vec32;
+    const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot && ev;
+    if (have && !aligned(ev, p->dtype == SWE_F64 ? 16 : 8))
+        return fail(SWE_EINVAL, w + ": edge vectors misaligned (16 bytes for FP64, 8 for FP32)");
     if (!have) return auto_ ? SWE_OK : fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
     int dev = 0;
     if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;

@@ -19,7 +19,7 @@ struct swe_batch {
     std::vector<int32_t> perm, nbr, c2n, halo_off, halo, edge_off;
     std::vector<uint32_t> edges;
     std::vector<uint16_t> slot;
-    std::vector<double> xy;
+    std::vector<double> xy, edge_vec, cell_geo;
     swe::TileLayout tiles;
     void *graph = nullptr;
     ~swe_batch();
@@ -74,10 +74,14 @@ int32_t check_batch_call(const swe_batch *b, const swe_batch_dev *d, const swe_b
     const swe_dev_mesh &m = d->mesh;
     if (m.n_cells != b->info.n_cells || m.n_nodes != b->info.n_nodes)
         return bfail(SWE_EINVAL, w + ": device arrays sized for another batch");
+    const bool f64 = p->dtype == SWE_F64;
+    const void *ev = f64 ? (const void *)m.edge_vec : (const void *)m.edge_vec32;
+    const void *cg = f64 ? (const void *)m.cell_geo : (const void *)m.cell_geo32;
     if (!m.nbr || !m.c2n || !m.xy || !m.halo_off || !m.halo || !m.edge_off || !m.edges ||
-        !m.slot || !d->tile_start || !d->tile_scen || !d->scen_tile_off)
+        !m.slot || !ev || !cg || !d->tile_start || !d->tile_scen || !d->scen_tile_off)
         return bfail(SWE_EINVAL, w + ": null device array");
-    if (reinterpret_cast<uintptr_t>(m.xy) % 16) return bfail(SWE_EINVAL, w + ": xy not 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(m.xy) % 16 || reinterpret_cast<uintptr_t>(ev) % (f64 ? 16 : 8))
+        return bfail(SWE_EINVAL, w + ": xy or edge vectors misaligned");
     for (int k = 0; k < 2; ++k)
         if (!s->h[k] || !s->hu[k] || !s->hv[k]) return bfail(SWE_EINVAL, w + ": null state buffer");
     if (!s->z || !s->n || !s->ctrl || !s->work) return bfail(SWE_EINVAL, w + ": null z, n, ctrl or work");
@@ -244,6 +248,8 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
         b->slot.resize(3 * T);
         b->perm.resize(T);
         b->xy.resize(2 * V);
+        b->cell_geo.resize(2 * T);
+        b->edge_vec.reserve(2 * ne);
         b->tile_start.reserve(nt_total + 1);
         b->tile_scen.reserve(nt_total);
         b->halo_off.assign(1, 0);
@@ -260,7 +266,11 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
                     b->c2n[k * T + c0 + i] = static_cast<int32_t>(m.c2n[k * Ts + i] + v0);
                     b->slot[k * T + c0 + i] = m.slot[k * Ts + i];
                 }
-            for (int64_t i = 0; i < Ts; ++i) b->perm[c0 + i] = m.perm[i];
+            for (int64_t i = 0; i < Ts; ++i) {
+                b->perm[c0 + i] = m.perm[i];
+                b->cell_geo[c0 + i] = m.cell_geo[i];
+                b->cell_geo[T + c0 + i] = m.cell_geo[Ts + i];
+            }
             memcpy(&b->xy[2 * v0], m.xy.data(), sizeof(double) * 2 * m.info.n_nodes);
             for (int64_t t = 0; t < m.info.n_tiles; ++t) {
                 b->tile_start.push_back(static_cast<int32_t>(c0 + t * SWE_TILE));
@@ -270,6 +280,8 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
                 b->halo_off.push_back(static_cast<int32_t>(b->halo.size()));
                 b->edges.insert(b->edges.end(), m.edges.begin() + m.edge_off[t],
                                 m.edges.begin() + m.edge_off[t + 1]);
+                b->edge_vec.insert(b->edge_vec.end(), m.edge_vec.begin() + 2 * m.edge_off[t],
+                                   m.edge_vec.begin() + 2 * m.edge_off[t + 1]);
                 b->edge_off.push_back(static_cast<int32_t>(b->edges.size()));
             }
             b->scen_tile_off[s + 1] = static_cast<int32_t>(b->tile_scen.size());
@@ -318,6 +330,10 @@ int32_t swe_batch_export(const swe_batch *b, int32_t which, void *dst, int64_t d
     case SWE_ARR_EDGE_OFF: pick(b->edge_off); break;
     case SWE_ARR_EDGES: pick(b->edges); break;
     case SWE_ARR_SLOT: pick(b->slot); break;
+    case SWE_ARR_EDGE_VEC: pick(b->edge_vec); break;
+    case SWE_ARR_CELL_GEO: pick(b->cell_geo); break;
+    case SWE_ARR_EDGE_VEC32: return export_as_float(b->edge_vec, dst, dst_bytes, "swe_batch_export");
+    case SWE_ARR_CELL_GEO32: return export_as_float(b->cell_geo, dst, dst_bytes, "swe_batch_export");
     case SWE_BARR_CELL_OFF: pick(b->cell_off); break;
     case SWE_BARR_NODE_OFF: pick(b->node_off); break;
     case SWE_BARR_TILE_START: pick(b->tile_start); break;

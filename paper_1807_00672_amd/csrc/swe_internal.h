@@ -172,6 +172,21 @@ bool tuned_choice(int device, int dtype, int64_t n_cells, int *variant, int *rem
 }  // namespace swe
 
 // The host-side mesh object behind the opaque swe_mesh handle.
+namespace swe {
+// Copy `v` rounded to float (round to nearest) into a host buffer of dst_bytes bytes.
+inline int32_t export_as_float(const std::vector<double> &v, void *dst, int64_t dst_bytes,
+                               const char *where)
+{
+    if (dst_bytes < static_cast<int64_t>(4 * v.size())) {
+        set_error(std::string(where) + ": destination too small");
+        return SWE_EINVAL;
+    }
+    float *d = static_cast<float *>(dst);
+    for (size_t k = 0; k < v.size(); ++k) d[k] = static_cast<float>(v[k]);
+    return SWE_OK;
+}
+}  // namespace swe
+
 struct swe_mesh {
     swe_mesh_info info;
     std::vector<int32_t> perm;       // mesh cell -> input cell
@@ -184,6 +199,8 @@ struct swe_mesh {
     std::vector<int32_t> edge_off;   // [n_tiles + 1]
     std::vector<uint32_t> edges;     // packed edge-list entries, per tile
     std::vector<uint16_t> slot;      // [3][T]
+    std::vector<double> edge_vec;    // [n_tile_edges][2]: edge vector of each edge-list entry
+    std::vector<double> cell_geo;    // [2][T]: area, inradius
     std::vector<int32_t> global;     // shards: cell index in the mesh cut from; else empty
     swe::TileLayout tiles;           // sizes the tiled step needs at launch
     void *graph = nullptr;           // cached two-step graph of swe_run (swe_api.cpp)

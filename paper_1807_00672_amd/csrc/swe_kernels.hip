@@ -252,11 +252,11 @@ __device__ __forceinline__ R inflow_speed(R g, R q_in, R h)
 
 // Local edge k of a counter-clockwise triangle runs from node k to node k+1; its outward
 // unit normal is (dy, -dx) / l (section 2.2, eq. 3, Fig. 1).  Coordinates are double for both
-// precisions; the edge vector is rounded to R after the subtraction.
+// precisions; the edge vector is rounded to R after the subtraction.  The cell's area and
+// inradius come from the mesh (SWE_ARR_CELL_GEO).
 template <typename R>
 struct CellGeom {
     R nx[3], ny[3], l[3];
-    R area, inradius;
 };
 
 template <typename R>
@@ -274,8 +274,6 @@ __device__ __forceinline__ void cell_geometry(const double2 *__restrict__ xy, in
         gm.ny[k] = div_(-dx, l);
         gm.l[k] = l;
     }
-    gm.area = static_cast<R>(0.5 * (ex[0] * ey[1] - ey[0] * ex[1]));
-    gm.inradius = div_(R(2) * gm.area, gm.l[0] + gm.l[1] + gm.l[2]);
 }
 
 // ------------------------------------------------------------------------ reductions
@@ -488,6 +486,7 @@ struct StepArgs {
     const int32_t *__restrict__ nbr;
     const int32_t *__restrict__ c2n;
     const double2 *__restrict__ xy;
+    const R *__restrict__ cell_geo;        // [2T]: area, inradius (mesh, in R)
     const R *__restrict__ z;
     const R *__restrict__ n;
     const R *__restrict__ h;
@@ -556,7 +555,8 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
             }
         }
         // explicit Euler update, positivity clamp, semi-implicit friction
-        const R r = div_(dt, gm.area);
+        const R area = a.cell_geo[i], inradius = a.cell_geo[T + i];
+        const R r = div_(dt, area);
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         a.huo[i] = hun;
         a.hvo[i] = hvn;
         if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
-        dtc = cell_dt<R>(g, hd, hs, hun, hvn, gm.inradius, nb, cfg, qtab);
+        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
         if (i >= cfg.n_owned) {   // a shard's halo cell: refreshed by its owner
             dtc = static_cast<R>(kInf);
             clamp = 0;
@@ -622,6 +622,18 @@ __device__ __forceinline__ void st(T *p, int64_t i, T v)
         p[i] = v;
 }
 
+// (dx, dy) pairs of the mesh's edge vectors in the step's precision.
+template <typename R>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+
 template <typename R>
 struct TileArgs {
     StepArgs<R> s;
@@ -630,6 +642,7 @@ struct TileArgs {
     const int32_t *__restrict__ edge_off;
     const uint32_t *__restrict__ edges;
     const uint16_t *__restrict__ slot;
+    const typename Vec2<R>::type *__restrict__ edge_vec;   // per edge-list entry (mesh, in R)
     int32_t n_tiles, max_halo, max_edges, pad;
 };
 
@@ -722,31 +735,25 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     const int ph = kBlock - 1 - pt;
 
     // global loads: own cell
-    R h = R(0), hu = R(0), hv = R(0), zc = R(0), nm = R(0);
-    double2 p0 = {0.0, 0.0}, p1 = {0.0, 0.0}, p2 = {0.0, 0.0};
+    R h = R(0), hu = R(0), hv = R(0), zc = R(0), nm = R(0), area = R(0), inradius = R(1);
     uint32_t sl0 = 0, sl1 = 0, sl2 = 0;
     if (mine) {
         h = ld<O32>(a.h, i); hu = ld<O32>(a.hu, i); hv = ld<O32>(a.hv, i);
         zc = ld<O32>(a.z, i); nm = ld<O32>(a.n, i);
         sl0 = ld<O32>(ta.slot, i); sl1 = ld<O32>(ta.slot, T + i); sl2 = ld<O32>(ta.slot, 2 * T + i);
-        p0 = ld<O32>(a.xy, ld<O32>(a.c2n, i));
-        p1 = ld<O32>(a.xy, ld<O32>(a.c2n, T + i));
-        p2 = ld<O32>(a.xy, ld<O32>(a.c2n, 2 * T + i));
+        area = ld<O32>(a.cell_geo, i);
+        inradius = ld<O32>(a.cell_geo, T + i);
     }
-    // global loads: the edge-list entries of the first two rounds and their end nodes
+    // global loads: the edge-list entries of the first two rounds and their edge vectors
     const int eb = ta.edge_off[tile], ee = ta.edge_off[tile + 1];
     uint32_t ew[2] = {0u, 0u};
-    double2 ep0[2] = {{0.0, 0.0}, {0.0, 0.0}}, ep1[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    typename Vec2<R>::type ev[2] = {{R(0), R(0)}, {R(0), R(0)}};
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
         const int e = eb + pt + it * kBlock;
         if (e < ee) {
-            const uint32_t w = ld<O32>(ta.edges, e);
-            const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
-            const int k = static_cast<int>((w >> 8) & 3u);
-            ew[it] = w;
-            ep0[it] = ld<O32>(a.xy, ld<O32>(a.c2n, k * T + ca));
-            ep1[it] = ld<O32>(a.xy, ld<O32>(a.c2n, (k == 2 ? 0 : k + 1) * T + ca));
+            ew[it] = ld<O32>(ta.edges, e);
+            ev[it] = ld<O32>(ta.edge_vec, e);
         }
     }
     // phase 1: halo and own cell into LDS
@@ -766,27 +773,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         s_v[tid] = velocity(h, hv, hd);
         s_z[tid] = zc;
     }
-    // the cell's area and inradius and the edges' vectors, formed here so that the node
-    // coordinates are not held through phase 2
-    R area = R(0), inradius = R(1);
-    if (mine) {
-        const double ex[3] = {p1.x - p0.x, p2.x - p1.x, p0.x - p2.x};
-        const double ey[3] = {p1.y - p0.y, p2.y - p1.y, p0.y - p2.y};
-        R l[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const R dx = static_cast<R>(ex[k]), dy = static_cast<R>(ey[k]);
-            l[k] = sqrt_(dx * dx + dy * dy);
-        }
-        area = static_cast<R>(0.5 * (ex[0] * ey[1] - ey[0] * ex[1]));
-        inradius = div_(R(2) * area, l[0] + l[1] + l[2]);
-    }
-    R edx[2], edy[2];
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        edx[it] = static_cast<R>(ep1[it].x - ep0[it].x);
-        edy[it] = static_cast<R>(ep1[it].y - ep0[it].y);
-    }
+    R edx[2] = {ev[0].x, ev[1].x}, edy[2] = {ev[0].y, ev[1].y};
     __syncthreads();
 
     // phase 2: the tile's interfaces, each once
@@ -841,12 +828,9 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     }
     for (int e = eb + pt + 2 * kBlock; e < ee; e += kBlock) {   // plain layout only
         const uint32_t w = ld<O32>(ta.edges, e);
-        const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
-        const int k = static_cast<int>((w >> 8) & 3u);
-        const double2 q0 = ld<O32>(a.xy, ld<O32>(a.c2n, k * T + ca));
-        const double2 q1 = ld<O32>(a.xy, ld<O32>(a.c2n, (k == 2 ? 0 : k + 1) * T + ca));
+        const auto d = ld<O32>(ta.edge_vec, e);
         EdgeOut o;
-        put(e - eb, o, flux(w, static_cast<R>(q1.x - q0.x), static_cast<R>(q1.y - q0.y), o));
+        put(e - eb, o, flux(w, d.x, d.y, o));
     }
     __syncthreads();
 
@@ -926,12 +910,10 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig 
     R dtc = static_cast<R>(kInf);
     int flag = 0;
     if (i < s1 && i < T) {
-        CellGeom<R> gm;
-        cell_geometry<R>(a.xy, a.c2n[i], a.c2n[T + i], a.c2n[2 * T + i], gm);
         const int32_t nb[3] = {a.nbr[i], a.nbr[T + i], a.nbr[2 * T + i]};
         const R h = a.h[i], hu = a.hu[i], hv = a.hv[i];
         if (!isfinite(h) || !isfinite(hu) || !isfinite(hv)) flag = kStatusNonFinite;
-        dtc = cell_dt<R>(g, hd, h, hu, hv, gm.inradius, nb, cfg, qtab);
+        dtc = cell_dt<R>(g, hd, h, hu, hv, a.cell_geo[T + i], nb, cfg, qtab);
         if (i >= cfg.n_owned) {
             dtc = static_cast<R>(kInf);
             flag = 0;
@@ -1225,6 +1207,10 @@ StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
     a.nbr = dm.nbr;
     a.c2n = dm.c2n;
     a.xy = reinterpret_cast<const double2 *>(dm.xy);
+    if constexpr (sizeof(R) == 8)
+        a.cell_geo = dm.cell_geo;
+    else
+        a.cell_geo = dm.cell_geo32;
     a.z = static_cast<const R *>(s.z);
     a.n = static_cast<const R *>(s.n);
     a.h = static_cast<const R *>(s.h[cur]);
@@ -1252,6 +1238,10 @@ TileArgs<R> make_tile_args(const swe_dev_mesh &dm, const swe_state &s, int cur,
     t.edge_off = dm.edge_off;
     t.edges = dm.edges;
     t.slot = dm.slot;
+    if constexpr (sizeof(R) == 8)
+        t.edge_vec = reinterpret_cast<const double2 *>(dm.edge_vec);
+    else
+        t.edge_vec = reinterpret_cast<const float2 *>(dm.edge_vec32);
     t.n_tiles = static_cast<int32_t>(tl.n_tiles);
     t.max_halo = tl.max_halo;
     t.max_edges = tl.max_edges;
@@ -1346,8 +1336,8 @@ namespace {
 bool offsets_fit_32(const swe_dev_mesh &dm, int64_t n_cells, const TileLayout &tl)
 {
     const int64_t lim = int64_t{1} << 32;
-    return SWE_OFF32 && 12 * n_cells < lim && 16 * dm.n_nodes < lim &&
-           4 * tl.n_tiles * static_cast<int64_t>(tl.max_edges) < lim &&
+    return SWE_OFF32 && 16 * n_cells < lim && 16 * dm.n_nodes < lim &&
+           16 * tl.n_tiles * static_cast<int64_t>(tl.max_edges) < lim &&
            4 * tl.n_tiles * static_cast<int64_t>(tl.max_halo) < lim;
 }
 

@@ -158,6 +158,19 @@ void build_tiles(swe_mesh &m)
     }
     if (m.edges.size() > static_cast<size_t>(INT32_MAX) || m.halo.size() > static_cast<size_t>(INT32_MAX))
         throw Fail{SWE_EINVAL, "mesh too large for int32 tile offsets"};
+    // each entry's edge vector, node k+1 minus node k of its owning cell (eq. 3's outward
+    // normal is (dy, -dx) / l), so that the step reads it instead of two node lookups
+    m.edge_vec.resize(2 * m.edges.size());
+    for (int64_t t = 0; t < nt; ++t)
+        for (int32_t e = m.edge_off[t]; e < m.edge_off[t + 1]; ++e) {
+            const uint32_t w = m.edges[e];
+            const int64_t ca = t * SWE_TILE + static_cast<int64_t>(w & 0xffu);
+            const int k = static_cast<int>((w >> 8) & 3u);
+            const int32_t n0 = m.c2n[k * T + ca], n1 = m.c2n[((k + 1) % 3) * T + ca];
+            m.edge_vec[2 * static_cast<size_t>(e)] = m.xy[2 * static_cast<size_t>(n1)] - m.xy[2 * static_cast<size_t>(n0)];
+            m.edge_vec[2 * static_cast<size_t>(e) + 1] =
+                m.xy[2 * static_cast<size_t>(n1) + 1] - m.xy[2 * static_cast<size_t>(n0) + 1];
+        }
     m.info.n_tiles = nt;
     m.info.n_halo = static_cast<int64_t>(m.halo.size());
     m.info.n_tile_edges = static_cast<int64_t>(m.edges.size());
@@ -356,6 +369,23 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
         m.xy[2 * j] = xy[2 * m.node_perm[j]];
         m.xy[2 * j + 1] = xy[2 * m.node_perm[j] + 1];
     }
+    // 7. area A = cross(e0, e1) / 2 and inradius r = 2A / P of every cell (eq. 4's A_i and the
+    // CFL bound's length), with the edge vectors of its local edges in their order; IEEE
+    // square root and division, evaluated in this order
+    m.cell_geo.resize(2 * T);
+    for (int64_t i = 0; i < T; ++i) {
+        double ex[3], ey[3];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t n0 = m.c2n[k * T + i], n1 = m.c2n[((k + 1) % 3) * T + i];
+            ex[k] = m.xy[2 * static_cast<size_t>(n1)] - m.xy[2 * static_cast<size_t>(n0)];
+            ey[k] = m.xy[2 * static_cast<size_t>(n1) + 1] - m.xy[2 * static_cast<size_t>(n0) + 1];
+        }
+        double l[3];
+        for (int k = 0; k < 3; ++k) l[k] = sqrt(ex[k] * ex[k] + ey[k] * ey[k]);
+        const double area = 0.5 * (ex[0] * ey[1] - ey[0] * ex[1]);
+        m.cell_geo[i] = area;
+        m.cell_geo[T + i] = (2.0 * area) / (l[0] + l[1] + l[2]);
+    }
     build_tiles(m);
 }
 
@@ -502,6 +532,10 @@ int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t 
         src = mesh->edge_off.data(); bytes = 4 * (int64_t)mesh->edge_off.size(); break;
     case SWE_ARR_EDGES: src = mesh->edges.data(); bytes = 4 * (int64_t)mesh->edges.size(); break;
     case SWE_ARR_SLOT: src = mesh->slot.data(); bytes = 2 * (int64_t)mesh->slot.size(); break;
+    case SWE_ARR_EDGE_VEC: src = mesh->edge_vec.data(); bytes = 8 * (int64_t)mesh->edge_vec.size(); break;
+    case SWE_ARR_CELL_GEO: src = mesh->cell_geo.data(); bytes = 8 * (int64_t)mesh->cell_geo.size(); break;
+    case SWE_ARR_EDGE_VEC32: return swe::export_as_float(mesh->edge_vec, dst, dst_bytes, "swe_mesh_export");
+    case SWE_ARR_CELL_GEO32: return swe::export_as_float(mesh->cell_geo, dst, dst_bytes, "swe_mesh_export");
     case SWE_ARR_GLOBAL:
         bytes = 4 * mesh->info.n_cells;
         if (!mesh->global.empty()) {

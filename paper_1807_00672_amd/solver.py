@@ -51,6 +51,12 @@ class Mesh:
         self.edges = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGES, int(self.info.n_tile_edges),
                                        np.uint32)
         self.slot = A.swe_mesh_export(self.handle, A.SWE_ARR_SLOT, 3 * t, np.uint16)
+        self.edge_vec = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGE_VEC,
+                                          2 * int(self.info.n_tile_edges), np.float64)
+        self.cell_geo = A.swe_mesh_export(self.handle, A.SWE_ARR_CELL_GEO, 2 * t, np.float64)
+        self.edge_vec32 = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGE_VEC32,
+                                            2 * int(self.info.n_tile_edges), np.float32)
+        self.cell_geo32 = A.swe_mesh_export(self.handle, A.SWE_ARR_CELL_GEO32, 2 * t, np.float32)
         self.n_owned = int(self.info.n_owned)
         self.global_ids = A.swe_mesh_export(self.handle, A.SWE_ARR_GLOBAL, t, np.int32)
         self.device = None
@@ -76,9 +82,15 @@ class Mesh:
         self.d_edge_off = torch.from_numpy(self.edge_off).to(self.device)
         self.d_edges = torch.from_numpy(self.edges.view(np.int32)).to(self.device)
         self.d_slot = torch.from_numpy(self.slot.view(np.int16)).to(self.device)
+        self.d_edge_vec = torch.from_numpy(self.edge_vec).to(self.device)
+        self.d_cell_geo = torch.from_numpy(self.cell_geo).to(self.device)
+        self.d_edge_vec32 = torch.from_numpy(self.edge_vec32).to(self.device)
+        self.d_cell_geo32 = torch.from_numpy(self.cell_geo32).to(self.device)
         self.dev = A.swe_dev_mesh(self.n_cells, self.n_nodes, _ptr(self.d_nbr), _ptr(self.d_c2n),
                                   _ptr(self.d_xy), _ptr(self.d_halo_off), _ptr(self.d_halo),
-                                  _ptr(self.d_edge_off), _ptr(self.d_edges), _ptr(self.d_slot))
+                                  _ptr(self.d_edge_off), _ptr(self.d_edges), _ptr(self.d_slot),
+                                  _ptr(self.d_edge_vec), _ptr(self.d_cell_geo),
+                                  _ptr(self.d_edge_vec32), _ptr(self.d_cell_geo32))
         return self
 
     def to_mesh_order(self, a):
@@ -200,6 +212,10 @@ class Batch:
             "edge_off": ex(A.SWE_ARR_EDGE_OFF, nt + 1, np.int32),
             "edges": ex(A.SWE_ARR_EDGES, int(i.n_tile_edges), np.uint32).view(np.int32),
             "slot": ex(A.SWE_ARR_SLOT, 3 * t, np.uint16).view(np.int16),
+            "edge_vec": ex(A.SWE_ARR_EDGE_VEC, 2 * int(i.n_tile_edges), np.float64),
+            "cell_geo": ex(A.SWE_ARR_CELL_GEO, 2 * t, np.float64),
+            "edge_vec32": ex(A.SWE_ARR_EDGE_VEC32, 2 * int(i.n_tile_edges), np.float32),
+            "cell_geo32": ex(A.SWE_ARR_CELL_GEO32, 2 * t, np.float32),
             "tile_start": ex(A.SWE_BARR_TILE_START, nt + 1, np.int32),
             "tile_scen": ex(A.SWE_BARR_TILE_SCEN, nt, np.int32),
             "scen_tile_off": ex(A.SWE_BARR_SCEN_TILE_OFF, n + 1, np.int32),
@@ -211,7 +227,8 @@ class Batch:
         self.d = {k: torch.from_numpy(a).to(d) for k, a in arrays.items()}
         P = lambda k: _ptr(self.d[k])
         mesh = A.swe_dev_mesh(t, v, P("nbr"), P("c2n"), P("xy"), P("halo_off"), P("halo"),
-                              P("edge_off"), P("edges"), P("slot"))
+                              P("edge_off"), P("edges"), P("slot"), P("edge_vec"), P("cell_geo"),
+                              P("edge_vec32"), P("cell_geo32"))
         self.dev = A.swe_batch_dev(mesh, P("tile_start"), P("tile_scen"), P("scen_tile_off"))
 
     def scenario_slice(self, s: int) -> slice:

@@ -70,6 +70,24 @@ def test_mesh_builder_agrees_with_oracle_connectivity(k, morton):
     mapped = np.where(inner, perm[np.where(inner, nbr, 0)], nbr)
     assert np.array_equal(mapped, onb[perm])
     assert info.total_area == pytest.approx(oarea.sum(), rel=1e-13)
+    # precomputed geometry: the oracle's areas and inradii bit for bit, and each edge-list
+    # entry's vector from its owning cell's node k to node k+1
+    _, _, _, oinr = om.arrays()
+    assert np.array_equal(m.cell_geo[:t], oarea[perm])
+    assert np.array_equal(m.cell_geo[t:], oinr[perm])
+    ev = m.edge_vec.reshape(-1, 2)
+    assert ev.shape[0] == info.n_tile_edges
+    for tile in range(int(info.n_tiles)):
+        e0, e1 = m.edge_off[tile], m.edge_off[tile + 1]
+        w = m.edges[e0:e1].astype(np.int64)
+        ca = tile * 256 + (w & 0xff)
+        k = (w >> 8) & 3
+        n0 = m.c2n.reshape(3, t)[k, ca]
+        n1 = m.c2n.reshape(3, t)[(k + 1) % 3, ca]
+        assert np.array_equal(ev[e0:e1], xy[n1] - xy[n0])
+    # the float copies the FP32 step reads: rounded to nearest
+    assert np.array_equal(m.edge_vec32, m.edge_vec.astype(np.float32))
+    assert np.array_equal(m.cell_geo32, m.cell_geo.astype(np.float32))
 
 
 def test_morton_order_brings_neighbours_closer():
