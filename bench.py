@@ -37,9 +37,16 @@ def algorithmic_bytes(n_cells: int, n_nodes: int, word: int) -> int:
 
 
 def kernel_source_hash() -> str:
+    """sha256[:16] of the step kernels' source with comments and blank lines removed: a
+    committed counter run stays valid across comment edits, not across code changes."""
+    import re
     p = os.path.join(ROOT, "paper_1807_00672_amd", "csrc", "swe_kernels.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(p) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    code = "\n".join(ln.rstrip() for ln in src.splitlines() if ln.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def load_counter(dtype: str, n_cells: int, what: str = "bytes_per_launch"):

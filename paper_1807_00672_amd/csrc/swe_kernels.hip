@@ -683,10 +683,10 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
 }
 
 // One explicit step, tiled.  Every global load of the workgroup is issued up front: the own
-// cell (state, bed, Manning, nodes, edge slots), the halo states, and the first two rounds of
-// edge-list entries with their node coordinates.  Phase 1 stages the tile's cells and its
-// halo in LDS as (h, u, v, z), each velocity computed once, and forms the cell's area and
-// inradius and the edge vectors, so that no node coordinate is held through phase 2.  Phase 2
+// cell (state, bed, Manning, area, inradius, edge slots), the halo states, and the first two
+// rounds of edge-list entries with their edge vectors, all from the mesh's arrays, so no load
+// waits on another's index but the halo list's.  Phase 1 stages the tile's cells and its halo
+// in LDS as (h, u, v, z), each velocity computed once.  Phase 2
 // evaluates every interface of the edge list once (section 2.3's interface loop, restricted
 // to the tile) and stores the contributions l (F + p n) to eq. 3 of both sides, computed
 // exactly as the per-cell form computes them; with the shared layout (Shared) the second
