@@ -188,6 +188,24 @@ def test_step_calls_reject_bad_arguments_without_touching_a_device():
     assert "null" in swe.swe_last_error()
     assert swe.lib.swe_run(None, None, None, None, 1, None, None, None) == swe.SWE_EINVAL
     assert swe.swe_workspace_bytes(10000) >= 40 * 16
+    # the mesh geometry the kernels read: the cell areas and inradii for either kernel, the
+    # edge vectors for the tiled one (stand-in addresses, never dereferenced on these paths)
+    buf = np.zeros(1 << 16, np.uint8)
+    a = (buf.ctypes.data + 255) // 256 * 256
+    full = [a] * 8
+    dm = swe.swe_dev_mesh(m.n_cells, m.n_nodes, *full, None, None, None, None)
+    assert swe.lib.swe_step(m.handle, C.byref(dm), C.byref(p), C.byref(s), None) == swe.SWE_EINVAL
+    assert "null device mesh array" in swe.swe_last_error()
+    st = swe.swe_state()
+    st.h[0] = st.h[1] = st.hu[0] = st.hu[1] = st.hv[0] = st.hv[1] = a
+    st.z = st.n = st.ctrl = st.work = a
+    tiled = swe.swe_params(9.81, 0.7, 1e-6, swe.SWE_F64, 0, None, swe.SWE_TILED, 0)
+    dm = swe.swe_dev_mesh(m.n_cells, m.n_nodes, *full, None, a, None, None)
+    assert swe.lib.swe_step(m.handle, C.byref(dm), C.byref(tiled), C.byref(st), None) == swe.SWE_EINVAL
+    assert "tile arrays" in swe.swe_last_error()
+    f32 = swe.swe_params(9.81, 0.7, 1e-6, swe.SWE_F32, 0, None, swe.SWE_TILED, 0)
+    dm = swe.swe_dev_mesh(m.n_cells, m.n_nodes, *full, a, a, None, None)   # FP64 arrays only
+    assert swe.lib.swe_step(m.handle, C.byref(dm), C.byref(f32), C.byref(st), None) == swe.SWE_EINVAL
 
 
 @pytest.mark.parametrize("k,morton", [(1, True), (2, True), (3, False)])
