@@ -102,6 +102,7 @@ enum swe_mesh_array {
     SWE_ARR_EDGE_OFF = 7,  /* int32[n_tiles+1]: tile t's edges are EDGES[off[t] .. off[t+1]) */
     SWE_ARR_EDGES = 8,     /* uint32[n_tile_edges]: one per interface a tile evaluates:
                               bits 0-7 owning cell a (tile-local), bits 8-9 a's local edge k,
+                              bits 10-11 b's local edge when b is a tile cell (else 0),
                               bits 16-31 int16 b: tile-local cell (< SWE_TILE), halo slot
                               SWE_TILE + j, or a boundary code (SWE_WALL, -1 - s) */
     SWE_ARR_SLOT = 9,      /* uint16[3T], [k*T + i]: entry of cell i's local edge k in its

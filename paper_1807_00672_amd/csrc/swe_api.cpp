@@ -241,14 +241,14 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
         int lim = 0;
         if (int32_t rc = check_hip(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), where))
             return rc;
-        d.limit = lim;
+        d.limit = lim - static_cast<int>(kTileStaticLdsMax);   // left for dynamic LDS
     }
     const size_t need = tile_lds_bytes_for(p->dtype, mesh->tiles);
     if (need > static_cast<size_t>(d.limit) && auto_) return SWE_OK;
     if (need > static_cast<size_t>(d.limit))
         return fail(SWE_EUNSUPPORTED, w + ": tile needs " + std::to_string(need) +
                                           " bytes of LDS, device allows " + std::to_string(d.limit));
-    if (need > 65536 && d.prepared < need) {
+    if (need + kTileStaticLdsMax > 65536 && d.prepared < need) {
         if (int32_t rc = check_hip(prepare_tile_kernels(static_cast<size_t>(d.limit)), where)) return rc;
         d.prepared = static_cast<size_t>(d.limit);
     }

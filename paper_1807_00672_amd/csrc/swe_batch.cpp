@@ -132,6 +132,7 @@ int32_t check_lds(const swe_batch *b, int dtype, int variant, bool *tiled, const
                                                           hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
                                     where))
             return rc;
+        g_blimit[dev] -= static_cast<int>(kTileStaticLdsMax);   // left for dynamic LDS
         g_blimit_known[dev] = true;
     }
     const size_t need = tile_lds_bytes_for(dtype, b->tiles);
@@ -139,7 +140,7 @@ int32_t check_lds(const swe_batch *b, int dtype, int variant, bool *tiled, const
     if (need > static_cast<size_t>(g_blimit[dev]))
         return bfail(SWE_EUNSUPPORTED, std::string(where) + ": a tile needs " + std::to_string(need) +
                                            " bytes of LDS");
-    if (need > 65536 && g_bprepared[dev] < need) {
+    if (need + kTileStaticLdsMax > 65536 && g_bprepared[dev] < need) {
         if (int32_t rc = bcheck_hip(prepare_tile_kernels(static_cast<size_t>(g_blimit[dev])), where))
             return rc;
         g_bprepared[dev] = static_cast<size_t>(g_blimit[dev]);

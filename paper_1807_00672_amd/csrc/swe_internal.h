@@ -95,6 +95,10 @@ struct StepConfig {
 };
 
 // Tile sizes of a mesh that the tiled step needs at launch.
+// Static LDS the tiled step kernels may use besides their dynamic LDS (the slot table and the
+// block reduction); the device's per-workgroup limit less this is what dynamic LDS may take.
+constexpr size_t kTileStaticLdsMax = 2048;
+
 struct TileLayout {
     int64_t n_tiles;
     int32_t max_halo, max_edges;

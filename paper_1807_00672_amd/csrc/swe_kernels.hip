@@ -641,7 +641,6 @@ struct TileArgs {
     const int32_t *__restrict__ halo;
     const int32_t *__restrict__ edge_off;
     const uint32_t *__restrict__ edges;
-    const uint16_t *__restrict__ slot;
     const typename Vec2<R>::type *__restrict__ edge_vec;   // per edge-list entry (mesh, in R)
     int32_t n_tiles, max_halo, max_edges, pad;
 };
@@ -667,12 +666,16 @@ inline size_t tile_lds_shared(size_t word, int64_t max_halo)
 // limits a CU (160 KiB of LDS, four waves per workgroup) to fewer than eight waves per SIMD
 // and the shared one fits more workgroups.  FP64 only: FP32 tiles of the meshes built here
 // reach eight waves in the plain layout.
+// Static LDS of the tiled step besides: its slot table and the block reduction's partials.
+constexpr size_t kTileStaticLds = 3 * kBlock * sizeof(uint16_t) + 64;
+static_assert(kTileStaticLds <= kTileStaticLdsMax, "static LDS beyond the allowance");
+
 inline bool tile_alias(size_t word, int64_t max_halo, int64_t max_edges)
 {
     if (!SWE_TILE_ALIAS || word != 8 || max_edges > 2 * kBlock) return false;
     constexpr size_t kLdsPerCu = 160 * 1024;
-    const size_t plain = kLdsPerCu / tile_lds_plain(word, max_halo, max_edges);
-    const size_t shared = kLdsPerCu / tile_lds_shared(word, max_halo);
+    const size_t plain = kLdsPerCu / (tile_lds_plain(word, max_halo, max_edges) + kTileStaticLds);
+    const size_t shared = kLdsPerCu / (tile_lds_shared(word, max_halo) + kTileStaticLds);
     return plain < 8 && shared > plain;
 }
 
@@ -683,10 +686,11 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
 }
 
 // One explicit step, tiled.  Every global load of the workgroup is issued up front: the own
-// cell (state, bed, Manning, area, inradius, edge slots), the halo states, and the first two
-// rounds of edge-list entries with their edge vectors, all from the mesh's arrays, so no load
-// waits on another's index but the halo list's.  Phase 1 stages the tile's cells and its halo
-// in LDS as (h, u, v, z), each velocity computed once.  Phase 2
+// cell (state, bed, Manning, area, inradius), the halo states, and the first two rounds of
+// edge-list entries with their edge vectors, all from the mesh's arrays, so no load waits on
+// another's index but the halo list's.  Phase 1 stages the tile's cells and its halo in LDS as
+// (h, u, v, z), each velocity computed once.  Phase 2 also records, for each tile cell's local
+// edge, its entry in the edge list (the entries carry both sides' local edges).  Phase 2
 // evaluates every interface of the edge list once (section 2.3's interface loop, restricted
 // to the tile) and stores the contributions l (F + p n) to eq. 3 of both sides, computed
 // exactly as the per-cell form computes them; with the shared layout (Shared) the second
@@ -719,6 +723,9 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     R *s_u = s_h + ns;
     R *s_v = s_u + ns;
     R *s_z = s_v + ns;
+    // each tile cell's local edge k -> its edge-list entry (bit 15: the cell is side b),
+    // filled from the edge list in phase 2
+    __shared__ uint16_t s_slot[3 * kBlock];
 
     const int64_t T = cfg.n_cells;
     const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
@@ -736,11 +743,9 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
 
     // global loads: own cell
     R h = R(0), hu = R(0), hv = R(0), zc = R(0), nm = R(0), area = R(0), inradius = R(1);
-    uint32_t sl0 = 0, sl1 = 0, sl2 = 0;
     if (mine) {
         h = ld<O32>(a.h, i); hu = ld<O32>(a.hu, i); hv = ld<O32>(a.hv, i);
         zc = ld<O32>(a.z, i); nm = ld<O32>(a.n, i);
-        sl0 = ld<O32>(ta.slot, i); sl1 = ld<O32>(ta.slot, T + i); sl2 = ld<O32>(ta.slot, 2 * T + i);
         area = ld<O32>(a.cell_geo, i);
         inradius = ld<O32>(a.cell_geo, T + i);
     }
@@ -807,7 +812,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         o.a2 = l * (fy + pa * ny);
         return cb >= 0;
     };
-    auto put = [&](int q, const EdgeOut &o, bool two) {
+    auto put = [&](int q, uint32_t w, const EdgeOut &o, bool two) {
         R *e = lds + ebase + q + (q >= kBlock ? bshift : 0);
         e[0] = o.a0;
         e[estride] = o.a1;
@@ -816,21 +821,24 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
             e[3 * estride] = o.b1;
             e[4 * estride] = o.b2;
         }
+        s_slot[3 * (w & 0xffu) + ((w >> 8) & 3u)] = static_cast<uint16_t>(q);
+        const int cb = static_cast<int16_t>(w >> 16);
+        if (cb >= 0 && cb < kBlock) s_slot[3 * cb + ((w >> 10) & 3u)] = static_cast<uint16_t>(q | 0x8000);
     };
     {
         EdgeOut o;
-        if (eb + pt < ee) put(pt, o, flux(ew[0], edx[0], edy[0], o));
+        if (eb + pt < ee) put(pt, ew[0], o, flux(ew[0], edx[0], edy[0], o));
         const bool has1 = eb + pt + kBlock < ee;
         bool two1 = false;
         if (has1) two1 = flux(ew[1], edx[1], edy[1], o);
         if constexpr (alias) __syncthreads();   // every read of the states is done
-        if (has1) put(pt + kBlock, o, two1);
+        if (has1) put(pt + kBlock, ew[1], o, two1);
     }
     for (int e = eb + pt + 2 * kBlock; e < ee; e += kBlock) {   // plain layout only
         const uint32_t w = ld<O32>(ta.edges, e);
         const auto d = ld<O32>(ta.edge_vec, e);
         EdgeOut o;
-        put(e - eb, o, flux(w, d.x, d.y, o));
+        put(e - eb, w, o, flux(w, d.x, d.y, o));
     }
     __syncthreads();
 
@@ -838,7 +846,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     R dtc = static_cast<R>(kInf);
     int clamp = 0, flag = 0;
     if (mine) {
-        const uint32_t sl[3] = {sl0, sl1, sl2};
+        const uint32_t sl[3] = {s_slot[3 * tid], s_slot[3 * tid + 1], s_slot[3 * tid + 2]};
         R acc0 = R(0), acc1 = R(0), acc2 = R(0);
         int32_t nb[3];
 #pragma unroll
@@ -1237,7 +1245,6 @@ TileArgs<R> make_tile_args(const swe_dev_mesh &dm, const swe_state &s, int cur,
     t.halo = dm.halo;
     t.edge_off = dm.edge_off;
     t.edges = dm.edges;
-    t.slot = dm.slot;
     if constexpr (sizeof(R) == 8)
         t.edge_vec = reinterpret_cast<const double2 *>(dm.edge_vec);
     else

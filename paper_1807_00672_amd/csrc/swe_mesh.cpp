@@ -140,6 +140,7 @@ void build_tiles(swe_mesh &m)
             const int k = ak % 4;
             m.slot[k * T + i] = static_cast<uint16_t>(e);
             const int32_t b = static_cast<int16_t>(w >> 16);
+            uint32_t wk = w;
             if (b >= 0 && b < SWE_TILE) {  // side b of an interior interface
                 const int64_t jb = s0 + b;
                 int kb = -1;
@@ -147,8 +148,9 @@ void build_tiles(swe_mesh &m)
                     if (m.nbr[q * T + jb] == i) kb = q;
                 if (kb < 0) throw Fail{SWE_EMESH, "neighbour relation is not mutual"};
                 m.slot[kb * T + jb] = static_cast<uint16_t>(e | 0x8000);
+                wk |= static_cast<uint32_t>(kb) << 10;   // b's local edge, for the tile's slots
             }
-            m.edges.push_back(w);
+            m.edges.push_back(wk);
         }
         m.halo.insert(m.halo.end(), hl.begin(), hl.end());
         m.halo_off[t + 1] = static_cast<int32_t>(m.halo.size());

@@ -233,6 +233,12 @@ def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton):
         kk = ((ent >> 8) & 3).astype(np.int64)
         b = (ent >> 16).astype(np.uint16).view(np.int16).astype(np.int64)
         assert (a < s1 - s0).all() and (kk < 3).all()
+        # side b's local edge (bits 10-11) for interfaces between two tile cells: b's
+        # neighbour across it is a; 0 for the others
+        kb = ((ent >> 10) & 3).astype(np.int64)
+        inner = (b >= 0) & (b < tile)
+        assert (kb[~inner] == 0).all() and (kb < 3).all()
+        assert (nbr[kb[inner], s0 + b[inner]] == s0 + a[inner]).all()
         bnd = b < 0
         assert not (bnd[:-1] & ~bnd[1:]).any()          # boundary entries last
         for e in range(len(ent)):
