@@ -119,7 +119,11 @@ enum swe_mesh_array {
     SWE_ARR_CELL_GEO32 = 14  /* float[2T]: SWE_ARR_CELL_GEO rounded to float */
 };
 
-/* Device view of a mesh: the arrays of swe_mesh_export copied to device memory. */
+/* Device view of a mesh: the arrays of swe_mesh_export copied to device memory.  nbr, c2n,
+ * xy and the cell geometry of the step's precision are required; halo_off, halo, edge_off,
+ * edges, slot and the edge vectors of the step's precision are the tiled kernels' (the tiled
+ * step reads all but slot, which the tiled adjoint reads): when one is NULL, SWE_AUTO runs the
+ * per-cell kernel and SWE_TILED is an error. */
 typedef struct swe_dev_mesh {
     int64_t n_cells, n_nodes;
     const int32_t *nbr;    /* device, as SWE_ARR_NBR */
