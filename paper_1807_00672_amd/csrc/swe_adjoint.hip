@@ -228,8 +228,9 @@ struct AdjArgs {
     const double *z, *n, *area;
     const double *h, *hu, *hv;          // U^n
     const double *sh, *shu, *shv;       // U*^n before the clamp
-    double *lh, *lhu, *lhv;             // lambda
-    double *mh, *mhu, *mhv;             // mu
+    const double *lh, *lhu, *lhv;       // lambda^{n+1}
+    double *lo, *lou, *lov;             // lambda^n
+    double *mh, *mhu, *mhv;             // mu (per-cell kernels)
     double *gn, *gz;
     const double *dt_seq;
     int64_t step;
@@ -237,17 +238,18 @@ struct AdjArgs {
     double q[SWE_MAX_INFLOW];
 };
 
-// mu = (dU^{n+1}/dU*)^T lambda^{n+1}; the roughness gradient gains (dU^{n+1}/dn)^T lambda.
-__global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
+// mu = (dU^{n+1}/dU*)^T lambda^{n+1} of cell i, and the roughness gradient's share
+// (dU^{n+1}/dn_i)^T lambda^{n+1}; returns whether the cell is wet (the share exists).
+__device__ __forceinline__ bool friction_vjp(const AdjArgs &a, int64_t i, double dt, Vjp3 &mu,
+                                             double &gn)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= a.T) return;
-    const double dt = a.dt_seq[a.step], g = a.g;
+    const double g = a.g;
     const double hraw = a.sh[i], hus = a.shu[i], hvs = a.shv[i];
     const bool clamped = hraw < 0.0;
     const double hs = clamped ? 0.0 : hraw;
     const double lh = a.lh[i], lhu = a.lhu[i], lhv = a.lhv[i];
     double mh = lh, mhu = 0.0, mhv = 0.0;
+    gn = 0.0;
     if (hs > a.hd) {
         const double nm = a.n[i];
         const double mag = sqrt_nr(hus * hus + hvs * hvs);
@@ -268,12 +270,24 @@ __global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
         }
         const double Pb = -div_nr(Db * K * mag, P * P);
         mh += Pb * (7.0 / 3.0) * hs * c;
-        a.gn[i] += div_nr(Db * mag, P) * 2.0 * dt * g * nm;
+        gn = div_nr(Db * mag, P) * 2.0 * dt * g * nm;
     }
     if (clamped) mh = 0.0;
-    a.mh[i] = mh;
-    a.mhu[i] = mhu;
-    a.mhv[i] = mhv;
+    mu = {mh, mhu, mhv};
+    return hs > a.hd;
+}
+
+// mu of every cell into a.mh (the per-cell flux adjoint reads it); roughness gradient.
+__global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= a.T) return;
+    Vjp3 mu;
+    double gn;
+    if (friction_vjp(a, i, a.dt_seq[a.step], mu, gn)) a.gn[i] += gn;
+    a.mh[i] = mu.h;
+    a.mhu[i] = mu.hu;
+    a.mhv[i] = mu.hv;
 }
 
 // lambda^n = mu + sum over the cell's edges of its share of the edge adjoints; bed gradient.
@@ -313,9 +327,9 @@ __global__ __launch_bounds__(256) void flux_adjoint_kernel(AdjArgs a)
         lhu += u.hu;
         lhv += u.hv;
     }
-    a.lh[i] = lh;
-    a.lhu[i] = lhu;
-    a.lhv[i] = lhv;
+    a.lo[i] = lh;
+    a.lou[i] = lhu;
+    a.lov[i] = lhv;
     a.gz[i] += zb_sum;
 }
 
@@ -373,19 +387,30 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     const int64_t i = s0 + tid;
     const bool mine = i < T;
     const double dt = a.dt_seq[a.step], g = a.g, hd = a.hd;
-    auto stage = [&](int q, int64_t c) {
+    // the friction adjoint of every staged cell (halo cells' redone here rather than read):
+    // mu and the contribution cotangent -dt/A mu; a tile cell keeps its mu and adds its
+    // roughness gradient
+    Vjp3 mu_own{0.0, 0.0, 0.0};
+    auto stage = [&](int q, int64_t c, bool own) {
         s_h[q] = a.h[c];
         s_hu[q] = a.hu[c];
         s_hv[q] = a.hv[c];
         s_z[q] = a.z[c];
+        Vjp3 mu;
+        double gn;
+        const bool wet = friction_vjp(a, c, dt, mu, gn);
+        if (own) {
+            mu_own = mu;
+            if (wet) a.gn[c] += gn;
+        }
         const double r = div_nr(dt, a.area[c]);
-        s_c0[q] = -r * a.mh[c];
-        s_c1[q] = -r * a.mhu[c];
-        s_c2[q] = -r * a.mhv[c];
+        s_c0[q] = -r * mu.h;
+        s_c1[q] = -r * mu.hu;
+        s_c2[q] = -r * mu.hv;
     };
-    if (mine) stage(tid, i);
+    if (mine) stage(tid, i, true);
     const int hb = t.halo_off[tile], he = t.halo_off[tile + 1];
-    for (int j = hb + ph; j < he; j += SWE_TILE) stage(SWE_TILE + (j - hb), t.halo[j]);
+    for (int j = hb + ph; j < he; j += SWE_TILE) stage(SWE_TILE + (j - hb), t.halo[j], false);
     __syncthreads();
 
     // side a's (h, hu, hv) cotangent and bed term, then side b's for interfaces inside the tile
@@ -455,7 +480,7 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     }
     __syncthreads();
     if (!mine) return;
-    double lh = a.mh[i], lhu = a.mhu[i], lhv = a.mhv[i], zb_sum = 0.0;
+    double lh = mu_own.h, lhu = mu_own.hu, lhv = mu_own.hv, zb_sum = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const uint32_t sl = t.slot[k * T + i];
@@ -466,9 +491,9 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
         lhv += ed[2 * estride];
         zb_sum += ed[3 * estride];
     }
-    a.lh[i] = lh;
-    a.lhu[i] = lhu;
-    a.lhv[i] = lhv;
+    a.lo[i] = lh;
+    a.lou[i] = lhu;
+    a.lov[i] = lhv;
     a.gz[i] += zb_sum;
 }
 
@@ -508,7 +533,7 @@ __global__ void fill_kernel(double *p, int64_t n, double v)
 // Workspace layout of swe_adjoint (all double unless noted).
 struct AdjLayout {
     int64_t T, n_ckpt, K;
-    size_t ckpt, seg, segstar, lam, mu, loss, ctrl, work, total;
+    size_t ckpt, seg, segstar, lam, lam2, mu, loss, ctrl, work, total;
 };
 
 // K == 1 (every state stored): no recompute segment; U* of every step.
@@ -525,6 +550,7 @@ AdjLayout adj_layout(int64_t T, int64_t n_steps, int64_t K)
     L.seg = off; off += K == 1 ? 0 : al(st * (K + 1));
     L.segstar = off; off += al(st * (K == 1 ? n_steps : K));
     L.lam = off; off += al(st);
+    L.lam2 = off; off += al(st);
     L.mu = off; off += al(st);
     L.loss = off; off += 256;
     L.ctrl = off; off += al(SWE_CTRL_BYTES);
@@ -629,7 +655,11 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     auto ck = [&](int64_t c, int f) { return D(L.ckpt) + (static_cast<size_t>(c) * 3 + f) * S; };
     auto sg = [&](int64_t n, int f) { return D(L.seg) + (static_cast<size_t>(n) * 3 + f) * S; };
     auto ss = [&](int64_t n, int f) { return D(L.segstar) + (static_cast<size_t>(n) * 3 + f) * S; };
-    double *lam = D(L.lam), *mu = D(L.mu), *lossd = D(L.loss);
+    // lambda alternates between two buffers: a step reads lambda^{n+1} from one and writes
+    // lambda^n to the other (neighbouring tiles still read the former)
+    double *lamb[2] = {D(L.lam), D(L.lam2)};
+    int lcur = 0;
+    double *mu = D(L.mu), *lossd = D(L.loss);
     const unsigned blocks = static_cast<unsigned>((T + 255) / 256);
 
     StepConfig cfg;
@@ -719,7 +749,6 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     a.z = static_cast<const double *>(s->z);
     a.n = static_cast<const double *>(s->n);
     a.area = dm->cell_geo;   // the cell areas A_i, first T entries
-    a.lh = lam; a.lhu = lam + S; a.lhv = lam + 2 * S;
     a.mh = mu; a.mhu = mu + S; a.mhv = mu + 2 * S;
     a.gn = out->dn;
     a.gz = out->dz;
@@ -760,26 +789,32 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
             at.max_edges = tl->max_edges;
         }
     }
-    fill_kernel<<<(3 * S + 255) / 256, 256, 0, st>>>(lam, 3 * T, 0.0);
+    fill_kernel<<<(3 * S + 255) / 256, 256, 0, st>>>(lamb[0], 3 * T, 0.0);
     fill_kernel<<<blocks, 256, 0, st>>>(out->dn, T, 0.0);
     fill_kernel<<<blocks, 256, 0, st>>>(out->dz, T, 0.0);
     // one adjoint step: lambda^{n+1} (plus the misfit at n + 1) -> lambda^n, from the state
     // U^n and U* of step n
+    // (the tiled kernel does the friction adjoint of the cells it stages itself)
     auto adjoint_step = [&](int64_t nstep, const double *const *un, const double *const *us1,
                             const double *const *ustar) {
+        double *lin = lamb[lcur], *lout = lamb[lcur ^ 1];
         if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
             misfit_kernel<<<(loss->n_gauges + 63) / 64, 64, 0, st>>>(
                 us1[0], loss->gauges, loss->n_gauges,
-                loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges, nullptr, lam);
+                loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges, nullptr, lin);
         a.step = nstep;
         a.sh = ustar[0]; a.shu = ustar[1]; a.shv = ustar[2];
-        friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+        a.lh = lin; a.lhu = lin + S; a.lhv = lin + 2 * S;
+        a.lo = lout; a.lou = lout + S; a.lov = lout + 2 * S;
         a.h = un[0]; a.hu = un[1]; a.hv = un[2];
-        if (adj_lds)
+        if (adj_lds) {
             (adj_shared ? tile_flux_adjoint_kernel<true> : tile_flux_adjoint_kernel<false>)
                 <<<dim3(static_cast<unsigned>(at.n_tiles)), 256, adj_lds, st>>>(a, at);
-        else
+        } else {
+            friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
             flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
+        }
+        lcur ^= 1;
     };
     if (record) {
         for (int64_t nstep = n_steps - 1; nstep >= 0; --nstep) {
@@ -812,6 +847,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         }
         if (int32_t rc = ahip(hipGetLastError(), W)) return rc;
     }
+    double *lam = lamb[lcur];   // lambda^0
     if (int32_t rc = copy3(out->dh, out->dhu, out->dhv, lam, lam + S, lam + 2 * S)) return rc;
     if (int32_t rc = ahip(hipEventRecord(tm.ev[2], st), W)) return rc;
     tm.recorded = true;
