@@ -238,12 +238,13 @@ int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
 /*
  * n_steps steps (the host time loop of section 2.3) with no host round trip between them:
  * groups of 8 steps are captured once as a hipGraph (cached on the mesh, keyed by the
- * launch's arguments) and replayed; runs shorter than 16 steps launch step by step.  dt_seq: NULL (CFL dt) or a device array of n_steps doubles
- * replayed as the steps' dt (the t_end clip still applies; not with SWE_SHARD).  out: NULL to
- * only queue the work, or a stats record: then the stream is synchronised, *out filled, and
- * s->cur set to the buffer holding the result; the return value is then also the state's
- * status (SWE_ENONFINITE, SWE_EDRY).  The graph cache makes calls on one mesh from several
- * threads at once unsafe; use one mesh object per thread.
+ * launch's arguments) and replayed; runs shorter than 16 steps launch step by step.  dt_seq:
+ * NULL (CFL dt) or a device array of n_steps doubles replayed as the steps' dt (the t_end
+ * clip still applies; not with SWE_SHARD).  out: NULL to only queue the work, or a stats
+ * record: then the stream is synchronised, *out filled, and s->cur set to the buffer holding
+ * the result; the return value is then also the state's status (SWE_ENONFINITE, SWE_EDRY).
+ * The graph cache makes calls on one mesh from several threads at once unsafe; use one mesh
+ * object per thread.
  * Errors: SWE_EINVAL, SWE_EDEVICE, and with out != NULL the state's status.
  */
 int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
@@ -275,8 +276,8 @@ typedef struct swe_batch_info {
 } swe_batch_info;
 
 /* Arrays of a batch besides the concatenated SWE_ARR_* ones (which swe_batch_export also
- * gives: NBR, C2N, XY, HALO_OFF, HALO, EDGE_OFF, EDGES, SLOT, and PERM = each scenario's
- * own SWE_ARR_PERM, concatenated). */
+ * gives: NBR, C2N, XY, HALO_OFF, HALO, EDGE_OFF, EDGES, SLOT, EDGE_VEC, CELL_GEO, EDGE_VEC32,
+ * CELL_GEO32, and PERM = each scenario's own SWE_ARR_PERM, concatenated). */
 enum swe_batch_array {
     SWE_BARR_CELL_OFF = 16,      /* int64[n+1]: scenario s owns cells [off[s], off[s+1]) */
     SWE_BARR_NODE_OFF = 17,      /* int64[n+1]: and nodes [off[s], off[s+1]) */
@@ -366,8 +367,8 @@ int32_t swe_adjoint_workspace_bytes(const swe_mesh *mesh, int64_t n_steps, int32
  * segment by segment in the reverse pass; ckpt_every = 1 stores every state and U* in the
  * forward pass and recomputes nothing (the same gradients, bit for bit).  The caller's state
  * is not modified.  ws: device, swe_adjoint_workspace_bytes bytes, 256-byte aligned.
- * *loss_out (host, may be NULL) receives J; then the stream is synchronised.  Errors: SWE_EINVAL, SWE_EUNSUPPORTED (FP32),
- * SWE_EDEVICE.
+ * *loss_out (host, may be NULL) receives J; then the stream is synchronised.
+ * Errors: SWE_EINVAL, SWE_EUNSUPPORTED (FP32), SWE_EDEVICE.
  */
 int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
                     const swe_state *s, int64_t n_steps, const double *dt_seq,
@@ -376,7 +377,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
 
 /* Device time of this thread's last completed swe_adjoint call, in milliseconds, from HIP
  * events on its stream: the forward pass (checkpoints or every state, with the loss) and the
- * reverse sweep (segment recompute, unless every state was stored, and adjoint steps).  Waits for that call's work to finish.
+ * reverse sweep (segment recompute, unless every state was stored, and adjoint steps).
+ * Waits for that call's work to finish.
  * Errors: SWE_EINVAL (no completed call on this thread), SWE_EDEVICE. */
 int32_t swe_adjoint_timings(double *forward_ms, double *reverse_ms);
 
