@@ -1,6 +1,8 @@
 """Hand-written adjoint of the step against the oracle: the loss, a dot-product test against
-the oracle's tangent-linear model in every input direction, central finite differences on 32
-random cells (eps = 1e-6), independence of the checkpoint interval, and torch.autograd."""
+the oracle's tangent-linear model in every input direction, every gradient entry of a small
+mesh against the tangent-linear derivative along its basis direction, central finite
+differences on 32 random cells (eps = 1e-6), independence of the checkpoint interval, and
+torch.autograd."""
 import numpy as np
 import pytest
 
@@ -116,3 +118,38 @@ def test_roughness_gradient_matches_friction_closed_form(gpu, ckpt_every):
           f"(closed form {want[gauge]!r}); max |dn - closed form| {np.abs(dn - want).max():.3e}")
     assert j == pytest.approx(j_want, rel=1e-12)
     assert np.abs(dn - want).max() <= 1e-10 * np.abs(want).max()
+
+
+@pytest.fixture(scope="module")
+def small_full_gradient():
+    """A 400-cell calibration (one full tile and a ragged one, 60 steps, 8 gauges) and every
+    entry of the oracle's gradient: the tangent-linear derivative along each entry's basis
+    direction, one oracle run per entry."""
+    case = gen.calibration(nx=20, ny=10, steps=60, n_gauges=8)
+    case.z = case.z + 1e-4 * gen.centroids(case.xy, case.tri)[:, 0]
+    om = oracle.Mesh(case.xy, case.tri)
+    dts, obs = oracle.observations(case, om, steps=60)
+    t = case.n_cells
+    ref = np.empty((5, t))
+    for k, which in enumerate(("n", "z", "h", "hu", "hv")):
+        for c in range(t):
+            e = np.zeros(t)
+            e[c] = 1.0
+            _, ref[k, c] = oracle.run_tl(om, case.z, case.n, case.h, case.hu, case.hv, dts,
+                                         case.extra["gauges"], 10, obs, **{"d" + which: e})
+    return case, dts, obs, ref
+
+
+@pytest.mark.parametrize("ckpt_every", [7, 1])
+def test_every_gradient_entry_matches_the_oracle(gpu, small_full_gradient, ckpt_every):
+    case, dts, obs, ref = small_full_gradient
+    mesh = gpu.Mesh(case.xy, case.tri)
+    calib = gpu.Calibration(mesh, dts, case.extra["gauges"], obs, every=10, ckpt_every=ckpt_every)
+    j, grads = calib.run(case.n, case.z, case.h, case.hu, case.hv)
+    for k, which in enumerate(("n", "z", "h", "hu", "hv")):
+        scale = np.abs(ref[k]).max()
+        err = np.abs(np.asarray(grads[k]) - ref[k]).max()
+        print(f"d{which}: {np.count_nonzero(ref[k])} nonzero entries, max |grad| {scale:.3e}, "
+              f"max difference {err:.3e}")
+        assert scale > 0
+        assert err <= 1e-12 * scale
