@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <new>
 #include <string>
 
 #include "swe_internal.h"
@@ -185,7 +186,12 @@ hipGraphExec_t step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const sw
         (void)hipGetLastError();
         return nullptr;
     }
-    gc = new GraphCache();
+    gc = new (std::nothrow) GraphCache();
+    if (!gc) {   // no host memory for the cache: the caller launches step by step
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return nullptr;
+    }
     gc->key = key;
     gc->graph = graph;
     gc->exec = exec;

@@ -7,6 +7,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <new>
 #include <string>
 #include <vector>
 
@@ -194,7 +195,12 @@ hipGraphExec_t batch_graph(const swe_batch *b, const swe_batch_dev *d, const swe
         (void)hipGetLastError();
         return nullptr;
     }
-    g = new BatchGraph();
+    g = new (std::nothrow) BatchGraph();
+    if (!g) {   // no host memory for the cache: the caller launches step by step
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return nullptr;
+    }
     memcpy(g->key, key, n);
     g->key_len = n;
     g->graph = graph;

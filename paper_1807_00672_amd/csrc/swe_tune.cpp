@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 
@@ -132,9 +133,11 @@ int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SWE_OK) return rc;
-    {
+    try {
         std::lock_guard<std::mutex> lk(g_mu);
         g_table[Key{dev, p->dtype, size_class(mesh->info.n_cells)}] = r;
+    } catch (const std::bad_alloc &) {
+        return tfail(SWE_EINVAL, "swe_tune: out of host memory");
     }
     *out = r;
     return SWE_OK;
@@ -163,10 +166,14 @@ int32_t swe_tune_set(int32_t device, int32_t dtype, int64_t n_cells, const swe_t
     if (r->xcd_remap != 0 && r->xcd_remap != 1) return tfail(SWE_EINVAL, "swe_tune_set: xcd_remap must be 0 or 1");
     std::lock_guard<std::mutex> lk(g_mu);
     const Key k{device, dtype, size_class(n_cells)};
-    if (r->variant == SWE_AUTO)
-        g_table.erase(k);
-    else
-        g_table[k] = *r;
+    try {
+        if (r->variant == SWE_AUTO)
+            g_table.erase(k);
+        else
+            g_table[k] = *r;
+    } catch (const std::bad_alloc &) {
+        return tfail(SWE_EINVAL, "swe_tune_set: out of host memory");
+    }
     return SWE_OK;
 }
 
