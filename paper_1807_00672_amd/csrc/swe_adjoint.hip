@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "swe_device_math.h"
@@ -566,6 +567,11 @@ using namespace swe;
 
 namespace {
 
+// Whether the tiled flux adjoint's dynamic LDS limit has been raised on a device (per layout:
+// 0 not yet, 1 raised, -1 refused).
+int g_adj_lds[64][2] = {};
+std::mutex g_adj_lds_mu;
+
 int32_t afail(int32_t code, const std::string &msg)
 {
     set_error(msg);
@@ -770,11 +776,24 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
             return rc;
         bool fits = need <= static_cast<size_t>(max_lds);
         if (fits && need > 65536) {   // beyond the default dynamic LDS limit
-            const void *k = adj_shared ? reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<true>)
-                                       : reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<false>);
-            fits = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(need)) == hipSuccess;
-            if (!fits) (void)hipGetLastError();   // the per-cell kernel then; clear the error
+            // raised once per device and layout to the device's limit (the kernel has no static
+            // LDS), so that calls on other meshes, from other threads too, never lower it
+            fits = false;
+            if (dev >= 0 && dev < 64) {
+                std::lock_guard<std::mutex> lk(g_adj_lds_mu);
+                int &state = g_adj_lds[dev][adj_shared ? 1 : 0];
+                if (state == 0) {
+                    const void *k = adj_shared
+                                        ? reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<true>)
+                                        : reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<false>);
+                    state = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) ==
+                                    hipSuccess
+                                ? 1
+                                : -1;
+                    if (state < 0) (void)hipGetLastError();   // the per-cell kernel then; clear it
+                }
+                fits = state > 0;
+            }
         }
         if (fits) {
             adj_lds = need;

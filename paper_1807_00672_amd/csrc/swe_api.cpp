@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -97,6 +98,7 @@ struct DeviceLds {
     size_t prepared = 0;
 };
 DeviceLds g_lds[64];
+std::mutex g_lds_mu;   // guards g_lds
 
 
 // kGraphSteps steps (an even number: the state ends in the buffer it started from) captured
@@ -126,7 +128,10 @@ struct GraphCache {
     }
 };
 
+// Per-device capture streams, created on first use; captures from several threads (on different
+// meshes) take turns.
 hipStream_t g_capture[64] = {};
+std::mutex g_capture_mu;
 
 GraphKey make_key(const swe_dev_mesh *dm, const swe_params *p, const swe_state *s,
                   const double *dt_seq, int64_t n_seq, const TileLayout *tl, int remap, int dev)
@@ -163,6 +168,7 @@ hipGraphExec_t step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const sw
     if (gc && memcmp(&gc->key, &key, sizeof(key)) == 0) return gc->exec;
     delete gc;
     m->graph = nullptr;
+    std::lock_guard<std::mutex> lk(g_capture_mu);
     if (!g_capture[dev] && hipStreamCreateWithFlags(&g_capture[dev], hipStreamNonBlocking) != hipSuccess) {
         g_capture[dev] = nullptr;
         return nullptr;
@@ -242,6 +248,7 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     int dev = 0;
     if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;
     if (dev < 0 || dev >= 64) return fail(SWE_EUNSUPPORTED, w + ": device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_lds_mu);
     DeviceLds &d = g_lds[dev];
     if (d.limit < 0) {
         int lim = 0;

@@ -7,6 +7,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,10 +55,14 @@ struct BatchGraph {
     }
 };
 
+// Per-device capture streams, created on first use; captures from several threads (on different
+// batches) take turns.
 hipStream_t g_bcapture[64] = {};
+std::mutex g_bcapture_mu;
 int g_blimit[64];
 bool g_blimit_known[64] = {};
 size_t g_bprepared[64] = {};
+std::mutex g_blimit_mu;   // guards g_blimit, g_blimit_known and g_bprepared
 
 int32_t check_batch_call(const swe_batch *b, const swe_batch_dev *d, const swe_batch_params *p,
                          const swe_state *s, const char *where)
@@ -128,12 +133,13 @@ int32_t check_lds(const swe_batch *b, int dtype, int variant, bool *tiled, const
     int dev = 0;
     if (int32_t rc = bcheck_hip(hipGetDevice(&dev), where)) return rc;
     if (dev < 0 || dev >= 64) return bfail(SWE_EUNSUPPORTED, std::string(where) + ": device index");
+    std::lock_guard<std::mutex> lk(g_blimit_mu);
     if (!g_blimit_known[dev]) {
-        if (int32_t rc = bcheck_hip(hipDeviceGetAttribute(&g_blimit[dev],
-                                                          hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+        int lim = 0;
+        if (int32_t rc = bcheck_hip(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
                                     where))
             return rc;
-        g_blimit[dev] -= static_cast<int>(kTileStaticLdsMax);   // left for dynamic LDS
+        g_blimit[dev] = lim - static_cast<int>(kTileStaticLdsMax);   // left for dynamic LDS
         g_blimit_known[dev] = true;
     }
     const size_t need = tile_lds_bytes_for(dtype, b->tiles);
@@ -170,6 +176,7 @@ hipGraphExec_t batch_graph(const swe_batch *b, const swe_batch_dev *d, const swe
     if (g && g->key_len == n && memcmp(g->key, key, n) == 0) return g->exec;
     delete g;
     mb->graph = nullptr;
+    std::lock_guard<std::mutex> lk(g_bcapture_mu);
     if (!g_bcapture[dev] && hipStreamCreateWithFlags(&g_bcapture[dev], hipStreamNonBlocking) != hipSuccess) {
         g_bcapture[dev] = nullptr;
         return nullptr;
