@@ -306,3 +306,34 @@ def test_ritter_dry_bed_strip_parity(gpu):
     assert rc_o == 0 and rc_g == 0 and st_g["steps"] == st_o["steps"] and st_g["t"] == 0.5
     assert max(errors(case, g, ora)) <= TOL_F64
     assert np.array_equal(g[0] > case.h_dry, ora[0] > case.h_dry)
+
+
+def _quarter_turn(case):
+    """The case turned a quarter about the origin: (x, y) -> (-y, x), exact in floating point,
+    with the initial momentum turned alike."""
+    import copy
+    c = copy.copy(case)
+    c.xy = np.ascontiguousarray(np.stack([-case.xy[:, 1], case.xy[:, 0]], axis=1))
+    c.hu, c.hv = -case.hv, case.hu.copy()
+    return c
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("k", [2, 3, "ensemble"])
+def test_quarter_turn_rotates_the_result_bitwise(gpu, k, dtype):
+    """Every operation of the step is either unchanged by the turn (the same two products
+    summed in the other order, lengths, |u|, areas) or odd in it (unit normals, momenta,
+    divisions), so the turned mesh gives h unchanged and (hu, hv) -> (-hv, hu) bit for bit,
+    although its cell order, tiles and halos all differ; "ensemble" has an inflow segment."""
+    case = gen.ensemble_scenario(3, steps=60) if k == "ensemble" else gen.small(k)
+    steps = 60
+    turned = _quarter_turn(case)
+    rc, st, h, hu, hv = run_gpu(case, dtype, steps=steps)
+    rc2, st2, h2, hu2, hv2 = run_gpu(turned, dtype, steps=steps)
+    assert rc == rc2 == 0 and st["steps"] == st2["steps"] == steps and st["t"] == st2["t"]
+    print(f"{case.name} {dtype}: {case.n_cells} cells, t = {st['t']:.6g}, "
+          f"max |hu| {np.abs(hu).max():.3e}")
+    assert np.abs(hu).max() > 0 and np.abs(hv).max() > 0
+    assert np.array_equal(h2, h)
+    assert np.array_equal(hu2, -hv)
+    assert np.array_equal(hv2, hu)

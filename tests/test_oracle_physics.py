@@ -242,6 +242,24 @@ def test_replaying_the_dt_sequence_is_bitwise():
     assert rc2 == 0 and np.array_equal(h, h2) and np.array_equal(hu, hu2)
 
 
+@pytest.mark.parametrize("which", ["wetdry", "inflow"])
+def test_a_quarter_turn_of_the_mesh_turns_the_result_bit_for_bit(which):
+    """(x, y) -> (-y, x) is exact, and the step (normals, rotation into the edge frame and
+    back, lengths, areas, |u|) is covariant under it operation by operation: h unchanged and
+    (hu, hv) -> (-hv, hu) exactly.  A sign or component slip in a normal or in a frame
+    rotation breaks this; the inflow case turns an inflow segment too."""
+    import copy
+    case = gen.small(2) if which == "wetdry" else gen.ensemble_scenario(3, steps=60)
+    turned = copy.copy(case)
+    turned.xy = np.ascontiguousarray(np.stack([-case.xy[:, 1], case.xy[:, 0]], axis=1))
+    turned.hu, turned.hv = -case.hv, case.hu.copy()
+    rc, h, hu, hv, _, st = oracle.run_case(case, steps=60)
+    rc2, h2, hu2, hv2, _, st2 = oracle.run_case(turned, steps=60)
+    assert rc == rc2 == 0 and st["steps"] == st2["steps"] == 60 and st["t"] == st2["t"]
+    assert np.abs(hu).max() > 0 and np.abs(hv).max() > 0
+    assert np.array_equal(h2, h) and np.array_equal(hu2, -hv) and np.array_equal(hv2, hu)
+
+
 def test_all_dry_and_nonfinite_states_are_reported():
     c = gen.small(1)
     m = oracle.Mesh(c.xy, c.tri)
