@@ -29,6 +29,16 @@ def run_gpu(case, dtype="f64", steps=None, morton=True, t_end=0.0, dt_seq=None, 
     return rc, st, h, hu, hv
 
 
+def quarter_turn(case):
+    """The case turned a quarter about the origin: (x, y) -> (-y, x), exact in floating point,
+    with the initial momentum turned alike."""
+    import copy
+    c = copy.copy(case)
+    c.xy = np.ascontiguousarray(np.stack([-case.xy[:, 1], case.xy[:, 0]], axis=1))
+    c.hu, c.hv = -case.hv, case.hu.copy()
+    return c
+
+
 def run_oracle(case, steps=None, t_end=0.0, dt_seq=None, mesh=None):
     return oracle.run_case(case, steps=steps, t_end=t_end, dt_seq=dt_seq, mesh=mesh)
 

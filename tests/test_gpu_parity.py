@@ -12,8 +12,8 @@ import pytest
 
 import gen
 import oracle
-from parity import (TOL_F32, TOL_F64, errors, fp32_momentum_tol, mask_mismatch, run_gpu,
-                    run_oracle)
+from parity import (TOL_F32, TOL_F64, errors, fp32_momentum_tol, mask_mismatch, quarter_turn,
+                    run_gpu, run_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -308,16 +308,6 @@ def test_ritter_dry_bed_strip_parity(gpu):
     assert np.array_equal(g[0] > case.h_dry, ora[0] > case.h_dry)
 
 
-def _quarter_turn(case):
-    """The case turned a quarter about the origin: (x, y) -> (-y, x), exact in floating point,
-    with the initial momentum turned alike."""
-    import copy
-    c = copy.copy(case)
-    c.xy = np.ascontiguousarray(np.stack([-case.xy[:, 1], case.xy[:, 0]], axis=1))
-    c.hu, c.hv = -case.hv, case.hu.copy()
-    return c
-
-
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("k", [2, 3, "ensemble"])
 def test_quarter_turn_rotates_the_result_bitwise(gpu, k, dtype):
@@ -327,7 +317,7 @@ def test_quarter_turn_rotates_the_result_bitwise(gpu, k, dtype):
     although its cell order, tiles and halos all differ; "ensemble" has an inflow segment."""
     case = gen.ensemble_scenario(3, steps=60) if k == "ensemble" else gen.small(k)
     steps = 60
-    turned = _quarter_turn(case)
+    turned = quarter_turn(case)
     rc, st, h, hu, hv = run_gpu(case, dtype, steps=steps)
     rc2, st2, h2, hu2, hv2 = run_gpu(turned, dtype, steps=steps)
     assert rc == rc2 == 0 and st["steps"] == st2["steps"] == steps and st["t"] == st2["t"]
