@@ -52,6 +52,13 @@ def test_final_state_matches_oracle_samples(gpu, cases, k, dtype):
     print(f"config {k} {dtype}: sampled errors h {e_h:.3e} hu {e_hu:.3e} hv {e_hv:.3e}; "
           f"t {st['t']!r} vs {gd['t']!r}; wet {wet} vs {gd['wet_cells']}")
     assert st["clamps"] == gd["clamps"]
+    # both workloads are walled: with no depth clamped, the volume stays put up to rounding
+    a, b, c = (case.xy[case.tri[:, j]] for j in range(3))
+    area = 0.5 * np.abs((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]))
+    m0 = float(np.dot(case.h, area))
+    drift = abs(float(np.dot(np.asarray(h, dtype=np.float64), area)) - m0) / m0
+    print(f"   volume drift over {st['steps']} steps {drift:.3e}")
+    assert gd["clamps"] > 0 or drift <= (1e-12 if dtype == "f64" else TOL_F32)
     if dtype == "f64":
         assert max(e_h, e_hu, e_hv) <= TOL_F64
         assert st["t"] == pytest.approx(gd["t"], rel=TOL_F64)
