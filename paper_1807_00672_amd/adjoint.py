@@ -21,11 +21,18 @@ class Calibration:
                  g=9.81, h_dry=1e-6, inflow_q=None):
         self.mesh = mesh
         dev = mesh.device
-        self.dt = torch.as_tensor(np.asarray(dt_seq, np.float64), device=dev)
+        dt_seq = np.asarray(dt_seq, np.float64)
+        if dt_seq.ndim != 1 or dt_seq.size < 1:
+            raise ValueError("dt_seq must be a non-empty 1-D sequence of time steps")
+        self.dt = torch.as_tensor(dt_seq, device=dev)
         self.n_steps = int(self.dt.numel())
+        gauges = np.asarray(gauges, np.int64)
+        if (gauges.ndim != 1 or gauges.size < 1 or gauges.min() < 0 or
+                gauges.max() >= mesh.n_cells or np.unique(gauges).size != gauges.size):
+            raise ValueError(f"gauges must be distinct cell ids in [0, {mesh.n_cells})")
         inv = np.empty(mesh.n_cells, np.int64)
         inv[mesh.perm] = np.arange(mesh.n_cells)
-        self.gauges = torch.as_tensor(inv[np.asarray(gauges)].astype(np.int32), device=dev)
+        self.gauges = torch.as_tensor(inv[gauges].astype(np.int32), device=dev)
         obs = np.asarray(obs, np.float64).reshape(-1, len(gauges))
         if obs.shape[0] != self.n_steps // every:
             raise ValueError("need one observation row per `every` steps")

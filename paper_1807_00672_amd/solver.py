@@ -21,6 +21,16 @@ def _ptr(t: torch.Tensor):
     return C.c_void_p(t.data_ptr())
 
 
+def _cell_field(mesh, a, name: str) -> np.ndarray:
+    """A per-cell input (one value per cell, input order) as float64 in mesh order; the kernels
+    index it by cell, so any other shape is refused here."""
+    a = np.asarray(a, np.float64)
+    if a.shape != (mesh.n_cells,):
+        raise ValueError(f"{name} must hold one value per cell: shape ({mesh.n_cells},), "
+                         f"got {a.shape}")
+    return mesh.to_mesh_order(a)
+
+
 class Mesh:
     """A triangle mesh built by swe_mesh_create, with its arrays copied to the device.
 
@@ -134,14 +144,14 @@ class Solver:
                                    (A.SWE_EXACT if exact else 0))
         t = mesh.n_cells
 
-        def field(a):
-            return torch.from_numpy(mesh.to_mesh_order(np.asarray(a, np.float64))).to(
+        def field(a, name):
+            return torch.from_numpy(_cell_field(mesh, a, name)).to(
                 device=dev, dtype=self.tdtype).contiguous()
 
-        self.z, self.n = field(z), field(n)
-        self.h = [field(h), torch.empty(t, dtype=self.tdtype, device=dev)]
-        self.hu = [field(hu), torch.empty(t, dtype=self.tdtype, device=dev)]
-        self.hv = [field(hv), torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.z, self.n = field(z, "z"), field(n, "n")
+        self.h = [field(h, "h"), torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.hu = [field(hu, "hu"), torch.empty(t, dtype=self.tdtype, device=dev)]
+        self.hv = [field(hv, "hv"), torch.empty(t, dtype=self.tdtype, device=dev)]
         self.ctrl = torch.zeros(A.SWE_CTRL_BYTES // 8, dtype=torch.float64, device=dev)
         self.work = torch.zeros(A.swe_workspace_bytes(t), dtype=torch.uint8, device=dev)
         self.state = A.swe_state(
@@ -165,7 +175,10 @@ class Solver:
         if dt_seq is not None:
             if dt_seq.dtype != torch.float64 or dt_seq.device != self.mesh.device:
                 raise ValueError("dt_seq must be a float64 tensor on the mesh device")
-            seq = _ptr(dt_seq.contiguous())
+            if dt_seq.numel() < n_steps:
+                raise ValueError(f"dt_seq holds {dt_seq.numel()} values for {n_steps} steps")
+            self._dt_seq = dt_seq.contiguous()   # alive while the queued steps read it
+            seq = _ptr(self._dt_seq)
         st = A.swe_run_stats() if sync else None
         rc = A.swe_run(self.mesh.handle, self.mesh.dev, self.params, self.state, n_steps, seq,
                        st, _stream_handle(stream))
@@ -249,11 +262,14 @@ class BatchSolver:
         self.batch = batch
         self.tdtype = torch.float64 if dtype == "f64" else torch.float32
         dev = batch.device
+        cases = list(cases)
+        if len(cases) != batch.n_scen:
+            raise ValueError(f"need one case per scenario: {batch.n_scen}, got {len(cases)}")
         q = np.zeros((batch.n_scen, A.SWE_MAX_INFLOW))
         cat = {k: [] for k in ("z", "n", "h", "hu", "hv")}
         for s, (m, c) in enumerate(zip(batch.meshes, cases)):
             for k in cat:
-                cat[k].append(m.to_mesh_order(np.asarray(getattr(c, k), np.float64)))
+                cat[k].append(_cell_field(m, getattr(c, k), f"scenario {s} {k}"))
             if c.inflow_q is not None:
                 q[s, : len(c.inflow_q)] = c.inflow_q
         f = {k: torch.from_numpy(np.concatenate(v)).to(device=dev, dtype=self.tdtype)

@@ -361,3 +361,30 @@ def test_shard_keeps_inflow_tags_and_rejects_bad_ranges():
     assert swe.lib.swe_shard_dt_combine(None, 1, None) == swe.SWE_EINVAL
     assert swe.lib.swe_halo_pack(0, 5, None, None, None, None, None, None) == swe.SWE_EINVAL
     assert swe.lib.swe_halo_pack(0, 0, None, None, None, None, None, None) == swe.SWE_OK
+
+
+def test_python_binding_refuses_inputs_the_kernels_would_read_out_of_bounds():
+    """The C calls take bare device pointers; the binding checks sizes before any of them:
+    per-cell fields of the wrong shape, a batch with fewer cases than scenarios, gauges out of
+    range or repeated, and a replayed dt sequence shorter than the run."""
+    import torch
+    case = gen.small(5)
+    m = swe.Mesh(case.xy, case.tri, device="cpu")
+    t = m.n_cells
+    for bad in (case.h[:-1], np.concatenate([case.h, case.h]), case.h.reshape(-1, 1)):
+        with pytest.raises(ValueError, match="one value per cell"):
+            swe.Solver(m, case.z, case.n, bad, case.hu, case.hv)
+    with pytest.raises(ValueError, match="one value per cell"):
+        swe.Solver(m, case.z[:10], case.n, case.h, case.hu, case.hv)
+    for g in ([-1, 3], [3, 3], [t], []):
+        with pytest.raises(ValueError, match="gauges"):
+            swe.Calibration(m, [0.1] * 20, g, np.zeros((2, max(len(g), 1))), every=10)
+    with pytest.raises(ValueError, match="dt_seq"):
+        swe.Calibration(m, [], [3], np.zeros((0, 1)), every=10)
+    b = swe.Batch([m, m], device="cpu")
+    with pytest.raises(ValueError, match="one case per scenario"):
+        swe.BatchSolver(b, [case])
+    s = swe.Solver.__new__(swe.Solver)   # only the dt_seq check of run, before any C call
+    s.mesh = m
+    with pytest.raises(ValueError, match="holds 5 values for 8 steps"):
+        s.run(8, dt_seq=torch.zeros(5, dtype=torch.float64))
