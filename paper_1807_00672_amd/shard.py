@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _abi as A
-from .solver import Mesh, Solver, _ptr, _stream_handle
+from .solver import Mesh, Solver, _cell_field, _ptr, _stream_handle
 
 
 class ShardedSolver:
@@ -29,7 +29,8 @@ class ShardedSolver:
         self.mesh = mesh
         self.parts = len(self.bounds) - 1
         dev = mesh.device
-        full = [mesh.to_mesh_order(np.asarray(a, np.float64)) for a in (z, n, h, hu, hv)]
+        full = [_cell_field(mesh, a, name) for a, name in zip((z, n, h, hu, hv),
+                                                               ("z", "n", "h", "hu", "hv"))]
         self.meshes, self.solvers = [], []
         for p in range(self.parts):
             m = Mesh.shard(mesh, int(self.bounds[p]), int(self.bounds[p + 1]), device=dev)
