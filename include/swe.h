@@ -85,6 +85,10 @@ typedef struct swe_mesh_info {
     int32_t max_tile_edges;    /* longest edge list of a tile */
     int64_t n_owned;           /* cells [0, n_owned) are owned: they alone enter the dt
                                   reduction and the counters (T except for shards) */
+    int64_t n_tile_nodes;      /* total node-list entries over all tiles; 0: no node lists
+                                  (a tile has more than 256 nodes) */
+    int32_t max_tile_nodes;    /* most distinct nodes of a tile's cells */
+    int32_t reserved;
 } swe_mesh_info;
 
 /* Arrays swe_mesh_export copies out (sizes in elements). */
@@ -116,14 +120,24 @@ enum swe_mesh_array {
                               r_i = 2 A_i / P_i at [T + i] (the CFL bound); IEEE square root
                               and division, l_k summed in local-edge order */
     SWE_ARR_EDGE_VEC32 = 13, /* float[2 n_tile_edges]: SWE_ARR_EDGE_VEC rounded to float */
-    SWE_ARR_CELL_GEO32 = 14  /* float[2T]: SWE_ARR_CELL_GEO rounded to float */
+    SWE_ARR_CELL_GEO32 = 14, /* float[2T]: SWE_ARR_CELL_GEO rounded to float */
+    /* (ids 16-20 are the batch arrays of enum swe_batch_array) */
+    SWE_ARR_TILE_NODE_OFF = 21, /* int32[n_tiles+1]: tile t's nodes are TILE_NODES entries
+                                   [off[t] .. off[t+1]); only where every tile has at most 256 */
+    SWE_ARR_TILE_NODES = 22,    /* double[2 n_tile_nodes]: (x, y) of each tile's nodes, the
+                                   nodes of its cells in first-use order (cell, then local node) */
+    SWE_ARR_EDGE_NODES = 23     /* uint16[n_tile_edges]: bits 0-7 and 8-15 the tile-local node
+                                   ids of node k and node k+1 of each EDGES entry's owning cell:
+                                   their difference is the entry's SWE_ARR_EDGE_VEC, bit for bit */
 };
 
 /* Device view of a mesh: the arrays of swe_mesh_export copied to device memory.  nbr, c2n,
  * xy and the cell geometry of the step's precision are required; halo_off, halo, edge_off,
  * edges, slot and the edge vectors of the step's precision are the tiled kernels' (the tiled
  * step reads all but slot, which the tiled adjoint reads): when one is NULL, SWE_AUTO runs the
- * per-cell kernel and SWE_TILED is an error. */
+ * per-cell kernel and SWE_TILED is an error.  tile_node_off, tile_nodes and edge_nodes are
+ * optional: with all three the FP64 tiled step forms each edge vector from its tile's node list
+ * instead of reading edge_vec (the same bits, fewer bytes). */
 typedef struct swe_dev_mesh {
     int64_t n_cells, n_nodes;
     const int32_t *nbr;    /* device, as SWE_ARR_NBR */
@@ -140,6 +154,9 @@ typedef struct swe_dev_mesh {
                                   step); may be NULL for FP64-only use */
     const float *cell_geo32;   /* device, as SWE_ARR_CELL_GEO32 (FP32 steps); may be NULL for
                                   FP64-only use */
+    const int32_t *tile_node_off;  /* device, as SWE_ARR_TILE_NODE_OFF, or NULL */
+    const double *tile_nodes;      /* device, as SWE_ARR_TILE_NODES, 16-byte aligned, or NULL */
+    const uint16_t *edge_nodes;    /* device, as SWE_ARR_EDGE_NODES, or NULL */
 } swe_dev_mesh;
 
 /* Physical and numerical parameters (section 2.1-2.2). */
@@ -273,11 +290,14 @@ typedef struct swe_batch_info {
     int32_t max_inflow_segments;   /* largest inflow tag over the scenarios */
     int64_t n_cells, n_nodes, n_tiles, n_halo, n_tile_edges;
     int32_t max_halo, max_tile_edges;
+    int64_t n_tile_nodes;          /* 0: a scenario has no node lists */
+    int32_t max_tile_nodes, reserved;
 } swe_batch_info;
 
 /* Arrays of a batch besides the concatenated SWE_ARR_* ones (which swe_batch_export also
  * gives: NBR, C2N, XY, HALO_OFF, HALO, EDGE_OFF, EDGES, SLOT, EDGE_VEC, CELL_GEO, EDGE_VEC32,
- * CELL_GEO32, and PERM = each scenario's own SWE_ARR_PERM, concatenated). */
+ * CELL_GEO32, TILE_NODE_OFF, TILE_NODES, EDGE_NODES, and PERM = each scenario's own
+ * SWE_ARR_PERM, concatenated). */
 enum swe_batch_array {
     SWE_BARR_CELL_OFF = 16,      /* int64[n+1]: scenario s owns cells [off[s], off[s+1]) */
     SWE_BARR_NODE_OFF = 17,      /* int64[n+1]: and nodes [off[s], off[s+1]) */

@@ -42,6 +42,7 @@ SWE_TILE = 256
 (SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,
  SWE_ARR_HALO, SWE_ARR_EDGE_OFF, SWE_ARR_EDGES, SWE_ARR_SLOT, SWE_ARR_GLOBAL, SWE_ARR_EDGE_VEC,
  SWE_ARR_CELL_GEO, SWE_ARR_EDGE_VEC32, SWE_ARR_CELL_GEO32) = range(15)
+SWE_ARR_TILE_NODE_OFF, SWE_ARR_TILE_NODES, SWE_ARR_EDGE_NODES = 21, 22, 23
 
 _NAMES = {0: "SWE_OK", -1: "SWE_EINVAL", -2: "SWE_EMESH", -3: "SWE_EDEVICE",
           -4: "SWE_ENONFINITE", -5: "SWE_EDRY", -6: "SWE_EUNSUPPORTED"}
@@ -61,7 +62,9 @@ class swe_mesh_info(C.Structure):
                 ("total_area", C.c_double), ("min_inradius", C.c_double),
                 ("bbox", C.c_double * 4), ("n_tiles", C.c_int64), ("n_halo", C.c_int64),
                 ("n_tile_edges", C.c_int64), ("max_halo", C.c_int32),
-                ("max_tile_edges", C.c_int32), ("n_owned", C.c_int64)]
+                ("max_tile_edges", C.c_int32), ("n_owned", C.c_int64),
+                ("n_tile_nodes", C.c_int64), ("max_tile_nodes", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class swe_dev_mesh(C.Structure):
@@ -69,7 +72,9 @@ class swe_dev_mesh(C.Structure):
                 ("c2n", C.c_void_p), ("xy", C.c_void_p), ("halo_off", C.c_void_p),
                 ("halo", C.c_void_p), ("edge_off", C.c_void_p), ("edges", C.c_void_p),
                 ("slot", C.c_void_p), ("edge_vec", C.c_void_p), ("cell_geo", C.c_void_p),
-                ("edge_vec32", C.c_void_p), ("cell_geo32", C.c_void_p)]
+                ("edge_vec32", C.c_void_p), ("cell_geo32", C.c_void_p),
+                ("tile_node_off", C.c_void_p), ("tile_nodes", C.c_void_p),
+                ("edge_nodes", C.c_void_p)]
 
 
 class swe_params(C.Structure):
@@ -113,7 +118,8 @@ class swe_batch_info(C.Structure):
     _fields_ = [("n_scenarios", C.c_int32), ("max_inflow_segments", C.c_int32),
                 ("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("n_tiles", C.c_int64),
                 ("n_halo", C.c_int64), ("n_tile_edges", C.c_int64), ("max_halo", C.c_int32),
-                ("max_tile_edges", C.c_int32)]
+                ("max_tile_edges", C.c_int32), ("n_tile_nodes", C.c_int64),
+                ("max_tile_nodes", C.c_int32), ("reserved", C.c_int32)]
 
 
 class swe_batch_dev(C.Structure):

@@ -244,6 +244,8 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
     const bool have = dm->halo_off && dm->halo && dm->edge_off && dm->edges && dm->slot && ev;
     if (have && !aligned(ev, p->dtype == SWE_F64 ? 16 : 8))
         return fail(SWE_EINVAL, w + ": edge vectors misaligned (16 bytes for FP64, 8 for FP32)");
+    if (have && dm->tile_nodes && !aligned(dm->tile_nodes, 16))
+        return fail(SWE_EINVAL, w + ": tile nodes misaligned (16 bytes)");
     if (!have) return auto_ ? SWE_OK : fail(SWE_EINVAL, w + ": device mesh has no tile arrays");
     int dev = 0;
     if (int32_t rc = check_hip(hipGetDevice(&dev), where)) return rc;

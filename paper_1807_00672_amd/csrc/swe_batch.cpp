@@ -18,10 +18,10 @@ struct swe_batch {
     swe_batch_info info;
     std::vector<int64_t> cell_off, node_off;
     std::vector<int32_t> tile_start, tile_scen, scen_tile_off;
-    std::vector<int32_t> perm, nbr, c2n, halo_off, halo, edge_off;
+    std::vector<int32_t> perm, nbr, c2n, halo_off, halo, edge_off, tile_node_off;
     std::vector<uint32_t> edges;
-    std::vector<uint16_t> slot;
-    std::vector<double> xy, edge_vec, cell_geo;
+    std::vector<uint16_t> slot, edge_nodes;
+    std::vector<double> xy, edge_vec, cell_geo, tile_nodes;
     swe::TileLayout tiles;
     void *graph = nullptr;
     ~swe_batch();
@@ -88,6 +88,8 @@ int32_t check_batch_call(const swe_batch *b, const swe_batch_dev *d, const swe_b
         return bfail(SWE_EINVAL, w + ": null device array");
     if (reinterpret_cast<uintptr_t>(m.xy) % 16 || reinterpret_cast<uintptr_t>(ev) % (f64 ? 16 : 8))
         return bfail(SWE_EINVAL, w + ": xy or edge vectors misaligned");
+    if (reinterpret_cast<uintptr_t>(m.tile_nodes) % 16)
+        return bfail(SWE_EINVAL, w + ": tile nodes misaligned");
     for (int k = 0; k < 2; ++k)
         if (!s->h[k] || !s->hu[k] || !s->hv[k]) return bfail(SWE_EINVAL, w + ": null state buffer");
     if (!s->z || !s->n || !s->ctrl || !s->work) return bfail(SWE_EINVAL, w + ": null z, n, ctrl or work");
@@ -239,7 +241,8 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
         b->cell_off.assign(n + 1, 0);
         b->node_off.assign(n + 1, 0);
         b->scen_tile_off.assign(n + 1, 0);
-        int64_t nt_total = 0, nh = 0, ne = 0;
+        int64_t nt_total = 0, nh = 0, ne = 0, nn = 0;
+        bool nodes = true;   // node lists only if every scenario has them
         for (int32_t s = 0; s < n; ++s) {
             const swe_mesh_info &mi = meshes[s]->info;
             b->cell_off[s + 1] = b->cell_off[s] + mi.n_cells;
@@ -250,10 +253,13 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
             b->info.max_inflow_segments = std::max(b->info.max_inflow_segments, mi.n_inflow_segments);
             b->tiles.max_halo = std::max(b->tiles.max_halo, mi.max_halo);
             b->tiles.max_edges = std::max(b->tiles.max_edges, mi.max_tile_edges);
+            b->info.max_tile_nodes = std::max(b->info.max_tile_nodes, mi.max_tile_nodes);
+            nn += mi.n_tile_nodes;
+            if (meshes[s]->tile_node_off.empty()) nodes = false;
         }
         const int64_t T = b->cell_off[n], V = b->node_off[n];
         if (T > INT32_MAX / 3 || V > INT32_MAX / 2 || nt_total >= INT32_MAX || nh >= INT32_MAX ||
-            ne >= INT32_MAX) {
+            ne >= INT32_MAX || nn >= INT32_MAX) {
             delete b;
             return bfail(SWE_EINVAL, "swe_batch_create: batch too large for int32 indices");
         }
@@ -270,6 +276,11 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
         b->edge_off.assign(1, 0);
         b->halo.reserve(nh);
         b->edges.reserve(ne);
+        if (nodes) {
+            b->tile_node_off.assign(1, 0);
+            b->tile_nodes.reserve(2 * nn);
+            b->edge_nodes.reserve(ne);
+        }
         for (int32_t s = 0; s < n; ++s) {
             const swe_mesh &m = *meshes[s];
             const int64_t Ts = m.info.n_cells, c0 = b->cell_off[s], v0 = b->node_off[s];
@@ -297,6 +308,13 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
                 b->edge_vec.insert(b->edge_vec.end(), m.edge_vec.begin() + 2 * m.edge_off[t],
                                    m.edge_vec.begin() + 2 * m.edge_off[t + 1]);
                 b->edge_off.push_back(static_cast<int32_t>(b->edges.size()));
+                if (nodes) {   // ids are tile-local: copied as they are
+                    b->edge_nodes.insert(b->edge_nodes.end(), m.edge_nodes.begin() + m.edge_off[t],
+                                         m.edge_nodes.begin() + m.edge_off[t + 1]);
+                    b->tile_nodes.insert(b->tile_nodes.end(), m.tile_nodes.begin() + 2 * m.tile_node_off[t],
+                                         m.tile_nodes.begin() + 2 * m.tile_node_off[t + 1]);
+                    b->tile_node_off.push_back(static_cast<int32_t>(b->tile_nodes.size() / 2));
+                }
             }
             b->scen_tile_off[s + 1] = static_cast<int32_t>(b->tile_scen.size());
         }
@@ -310,6 +328,9 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
         b->info.max_halo = b->tiles.max_halo;
         b->info.max_tile_edges = b->tiles.max_edges;
         b->tiles.n_tiles = nt_total;
+        b->info.n_tile_nodes = static_cast<int64_t>(b->tile_nodes.size() / 2);
+        b->tiles.max_nodes = nodes ? b->info.max_tile_nodes : 0;
+        b->tiles.pad = 0;
     } catch (...) {
         delete b;
         return bfail(SWE_EINVAL, "swe_batch_create: out of host memory");
@@ -348,6 +369,9 @@ int32_t swe_batch_export(const swe_batch *b, int32_t which, void *dst, int64_t d
     case SWE_ARR_CELL_GEO: pick(b->cell_geo); break;
     case SWE_ARR_EDGE_VEC32: return export_as_float(b->edge_vec, dst, dst_bytes, "swe_batch_export");
     case SWE_ARR_CELL_GEO32: return export_as_float(b->cell_geo, dst, dst_bytes, "swe_batch_export");
+    case SWE_ARR_TILE_NODE_OFF: pick(b->tile_node_off); break;
+    case SWE_ARR_TILE_NODES: pick(b->tile_nodes); break;
+    case SWE_ARR_EDGE_NODES: pick(b->edge_nodes); break;
     case SWE_BARR_CELL_OFF: pick(b->cell_off); break;
     case SWE_BARR_NODE_OFF: pick(b->node_off); break;
     case SWE_BARR_TILE_START: pick(b->tile_start); break;

@@ -102,6 +102,8 @@ constexpr size_t kTileStaticLdsMax = 2048;
 struct TileLayout {
     int64_t n_tiles;
     int32_t max_halo, max_edges;
+    int32_t max_nodes;   // largest node list of a tile; 0: the mesh has no node lists
+    int32_t pad;
 };
 
 // Device arrays of a batch of meshes stepped together (swe_batch_*).
@@ -204,6 +206,9 @@ struct swe_mesh {
     std::vector<uint32_t> edges;     // packed edge-list entries, per tile
     std::vector<uint16_t> slot;      // [3][T]
     std::vector<double> edge_vec;    // [n_tile_edges][2]: edge vector of each edge-list entry
+    std::vector<int32_t> tile_node_off;   // [n_tiles + 1]; empty: no node lists
+    std::vector<double> tile_nodes;  // [n_tile_nodes][2]: coordinates of each tile's nodes
+    std::vector<uint16_t> edge_nodes;     // [n_tile_edges]: tile-local ids of an entry's nodes
     std::vector<double> cell_geo;    // [2][T]: area, inradius
     std::vector<int32_t> global;     // shards: cell index in the mesh cut from; else empty
     swe::TileLayout tiles;           // sizes the tiled step needs at launch

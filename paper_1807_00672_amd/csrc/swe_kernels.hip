@@ -642,24 +642,38 @@ struct TileArgs {
     const int32_t *__restrict__ edge_off;
     const uint32_t *__restrict__ edges;
     const typename Vec2<R>::type *__restrict__ edge_vec;   // per edge-list entry (mesh, in R)
-    int32_t n_tiles, max_halo, max_edges, pad;
+    // FP64 with node lists (else null): each tile's node coordinates and, per edge-list entry,
+    // the tile-local ids of the two nodes whose difference is its edge vector
+    const int32_t *__restrict__ tile_node_off;
+    const double2 *__restrict__ tile_nodes;
+    const uint16_t *__restrict__ edge_nodes;
+    int32_t n_tiles, max_halo, max_edges, max_nodes;
 };
 
 // LDS of the tiled step: the tile + halo states (h, u, v, z) and five values per edge-list
 // entry (side a's contribution and side b's momentum part; side b's mass part is -a's).
 // Plain layout: [states | 5 rows of max_edges].  Shared layout (at most 2 kBlock entries):
 // [5 rows of kBlock for entries 0..kBlock-1 | states], the entries from kBlock on written in
-// 5 rows of kBlock over the states once every interface of the tile has been evaluated.
-inline size_t tile_lds_plain(size_t word, int64_t max_halo, int64_t max_edges)
+// 5 rows of kBlock over the states once every interface of the tile has been evaluated.  An
+// FP64 step with node lists appends the tile's nodes, (x, y) each, at a 16-byte boundary.
+inline size_t tile_lds_nodes(size_t word, int64_t max_nodes)
 {
-    return 4 * word * static_cast<size_t>(kBlock + max_halo) +
-           5 * word * static_cast<size_t>(max_edges);
+    return word == 8 && max_nodes > 0 ? 16 * static_cast<size_t>(max_nodes) : 0;
 }
 
-inline size_t tile_lds_shared(size_t word, int64_t max_halo)
+inline size_t tile_lds_plain(size_t word, int64_t max_halo, int64_t max_edges, int64_t max_nodes)
+{
+    const size_t b = 4 * word * static_cast<size_t>(kBlock + max_halo) +
+                     5 * word * static_cast<size_t>(max_edges);
+    const size_t nd = tile_lds_nodes(word, max_nodes);
+    return nd ? ((b + 15) & ~static_cast<size_t>(15)) + nd : b;
+}
+
+inline size_t tile_lds_shared(size_t word, int64_t max_halo, int64_t max_nodes)
 {
     return word * (5 * static_cast<size_t>(kBlock) +
-                   std::max(4 * static_cast<size_t>(kBlock + max_halo), 5 * static_cast<size_t>(kBlock)));
+                   std::max(4 * static_cast<size_t>(kBlock + max_halo), 5 * static_cast<size_t>(kBlock))) +
+           tile_lds_nodes(word, max_nodes);
 }
 
 // The shared layout costs one more barrier per tile; take it only where the plain layout
@@ -670,25 +684,28 @@ inline size_t tile_lds_shared(size_t word, int64_t max_halo)
 constexpr size_t kTileStaticLds = 3 * kBlock * sizeof(uint16_t) + 64;
 static_assert(kTileStaticLds <= kTileStaticLdsMax, "static LDS beyond the allowance");
 
-inline bool tile_alias(size_t word, int64_t max_halo, int64_t max_edges)
+inline bool tile_alias(size_t word, int64_t max_halo, int64_t max_edges, int64_t max_nodes)
 {
     if (!SWE_TILE_ALIAS || word != 8 || max_edges > 2 * kBlock) return false;
     constexpr size_t kLdsPerCu = 160 * 1024;
-    const size_t plain = kLdsPerCu / (tile_lds_plain(word, max_halo, max_edges) + kTileStaticLds);
-    const size_t shared = kLdsPerCu / (tile_lds_shared(word, max_halo) + kTileStaticLds);
+    const size_t plain =
+        kLdsPerCu / (tile_lds_plain(word, max_halo, max_edges, max_nodes) + kTileStaticLds);
+    const size_t shared = kLdsPerCu / (tile_lds_shared(word, max_halo, max_nodes) + kTileStaticLds);
     return plain < 8 && shared > plain;
 }
 
-inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
+inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges, int64_t max_nodes)
 {
-    return tile_alias(word, max_halo, max_edges) ? tile_lds_shared(word, max_halo)
-                                                 : tile_lds_plain(word, max_halo, max_edges);
+    return tile_alias(word, max_halo, max_edges, max_nodes)
+               ? tile_lds_shared(word, max_halo, max_nodes)
+               : tile_lds_plain(word, max_halo, max_edges, max_nodes);
 }
 
 // One explicit step, tiled.  Every global load of the workgroup is issued up front: the own
 // cell (state, bed, Manning, area, inradius), the halo states, and the first two rounds of
-// edge-list entries with their edge vectors, all from the mesh's arrays, so no load waits on
-// another's index but the halo list's.  Phase 1 stages the tile's cells and its halo in LDS as
+// edge-list entries with their edge vectors (Nodes: their node ids, and the tile's node
+// coordinates, one per work-item), all from the mesh's arrays, so no load waits on another's
+// index but the halo list's.  Phase 1 stages the tile's cells and its halo in LDS as
 // (h, u, v, z), each velocity computed once.  Phase 2 also records, for each tile cell's local
 // edge, its entry in the edge list (the entries carry both sides' local edges).  Phase 2
 // evaluates every interface of the edge list once (section 2.3's interface loop, restricted
@@ -697,10 +714,11 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges)
 // round's results wait in registers until every work-item has read the states they replace.
 // Phase 3 sums each cell's three contributions in local-edge order and applies the update of
 // eq. 4, the clamp, the friction and the next CFL bound, as the per-cell kernel does.
-template <typename R, bool O32, bool Fuse, bool Shared>
+template <typename R, bool O32, bool Fuse, bool Shared, bool Nodes>
 __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
                                                            Batch bt)
 {
+    static_assert(!Nodes || sizeof(R) == 8, "node lists serve the FP64 step");
     const StepArgs<R> &a = ta.s;
     const int tile = xcd_tile(blockIdx.x, ta.n_tiles, bt.remap);
     if (tile >= ta.n_tiles) return;
@@ -723,6 +741,11 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     R *s_u = s_h + ns;
     R *s_v = s_u + ns;
     R *s_z = s_v + ns;
+    // Nodes (FP64 with node lists): the tile's nodes after the layout's other words (16-byte
+    // aligned), each entry's edge vector formed from them
+    constexpr bool nodes = Nodes;
+    double2 *const s_nd = reinterpret_cast<double2 *>(
+        lds + (alias ? 5 * kBlock + max(4 * ns, 5 * kBlock) : ((4 * ns + 5 * ta.max_edges + 1) & ~1)));
     // each tile cell's local edge k -> its edge-list entry (bit 15: the cell is side b),
     // filled from the edge list in phase 2
     __shared__ uint16_t s_slot[3 * kBlock];
@@ -749,18 +772,26 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         area = ld<O32>(a.cell_geo, i);
         inradius = ld<O32>(a.cell_geo, T + i);
     }
-    // global loads: the edge-list entries of the first two rounds and their edge vectors
+    // global loads: the edge-list entries of the first two rounds and their edge vectors (or
+    // their node ids, and the tile's nodes, one per work-item)
     const int eb = ta.edge_off[tile], ee = ta.edge_off[tile + 1];
-    uint32_t ew[2] = {0u, 0u};
+    uint32_t ew[2] = {0u, 0u}, en[2] = {0u, 0u};
     typename Vec2<R>::type ev[2] = {{R(0), R(0)}, {R(0), R(0)}};
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
         const int e = eb + pt + it * kBlock;
         if (e < ee) {
             ew[it] = ld<O32>(ta.edges, e);
-            ev[it] = ld<O32>(ta.edge_vec, e);
+            if (nodes)
+                en[it] = ld<O32>(ta.edge_nodes, e);
+            else
+                ev[it] = ld<O32>(ta.edge_vec, e);
         }
     }
+    double2 nd = {0.0, 0.0};
+    const int nb0 = nodes ? ta.tile_node_off[tile] : 0;
+    const bool node_mine = nodes && tid < ta.tile_node_off[tile + 1] - nb0;
+    if (node_mine) nd = ld<O32>(ta.tile_nodes, nb0 + tid);
     // phase 1: halo and own cell into LDS
     const int hb = ta.halo_off[tile], he = ta.halo_off[tile + 1];
     for (int j = hb + ph; j < he; j += kBlock) {
@@ -778,8 +809,20 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         s_v[tid] = velocity(h, hv, hd);
         s_z[tid] = zc;
     }
-    R edx[2] = {ev[0].x, ev[1].x}, edy[2] = {ev[0].y, ev[1].y};
+    if (node_mine) s_nd[tid] = nd;
     __syncthreads();
+    // an entry's edge vector: node k+1 minus node k of its owning cell, the same subtraction
+    // (and bits) as the mesh's edge vectors
+    auto node_vec = [&](uint32_t p, R &dx, R &dy) {
+        const double2 p0 = s_nd[p & 0xffu], p1 = s_nd[(p >> 8) & 0xffu];
+        dx = static_cast<R>(p1.x - p0.x);
+        dy = static_cast<R>(p1.y - p0.y);
+    };
+    R edx[2] = {ev[0].x, ev[1].x}, edy[2] = {ev[0].y, ev[1].y};
+    if (nodes) {
+        node_vec(en[0], edx[0], edy[0]);
+        node_vec(en[1], edx[1], edy[1]);
+    }
 
     // phase 2: the tile's interfaces, each once
     struct EdgeOut {
@@ -836,9 +879,16 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     }
     for (int e = eb + pt + 2 * kBlock; e < ee; e += kBlock) {   // plain layout only
         const uint32_t w = ld<O32>(ta.edges, e);
-        const auto d = ld<O32>(ta.edge_vec, e);
+        R dx, dy;
+        if (nodes) {
+            node_vec(ld<O32>(ta.edge_nodes, e), dx, dy);
+        } else {
+            const auto d = ld<O32>(ta.edge_vec, e);
+            dx = d.x;
+            dy = d.y;
+        }
         EdgeOut o;
-        put(e - eb, w, o, flux(w, d.x, d.y, o));
+        put(e - eb, w, o, flux(w, dx, dy, o));
     }
     __syncthreads();
 
@@ -1245,14 +1295,24 @@ TileArgs<R> make_tile_args(const swe_dev_mesh &dm, const swe_state &s, int cur,
     t.halo = dm.halo;
     t.edge_off = dm.edge_off;
     t.edges = dm.edges;
-    if constexpr (sizeof(R) == 8)
+    t.tile_node_off = nullptr;
+    t.tile_nodes = nullptr;
+    t.edge_nodes = nullptr;
+    t.max_nodes = 0;
+    if constexpr (sizeof(R) == 8) {
         t.edge_vec = reinterpret_cast<const double2 *>(dm.edge_vec);
-    else
+        if (tl.max_nodes > 0 && dm.tile_node_off && dm.tile_nodes && dm.edge_nodes) {
+            t.tile_node_off = dm.tile_node_off;
+            t.tile_nodes = reinterpret_cast<const double2 *>(dm.tile_nodes);
+            t.edge_nodes = dm.edge_nodes;
+            t.max_nodes = tl.max_nodes;
+        }
+    } else {
         t.edge_vec = reinterpret_cast<const float2 *>(dm.edge_vec32);
+    }
     t.n_tiles = static_cast<int32_t>(tl.n_tiles);
     t.max_halo = tl.max_halo;
     t.max_edges = tl.max_edges;
-    t.pad = 0;
     return t;
 }
 
@@ -1298,36 +1358,45 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     return static_cast<int>(hipGetLastError());
 }
 
-// The tiled kernel for a launch (FP32 has no shared-layout instances).
+// The tiled kernel for a launch (FP32 has no shared-layout or node-list instances).
 template <typename R>
 using TileKernel = void (*)(TileArgs<R>, StepConfig, Batch);
 
+template <typename R, bool Shared, bool Nodes>
+TileKernel<R> tile_kernel_of(bool o32, bool fuse)
+{
+    return o32 ? (fuse ? tile_step_kernel<R, true, true, Shared, Nodes>
+                       : tile_step_kernel<R, true, false, Shared, Nodes>)
+               : (fuse ? tile_step_kernel<R, false, true, Shared, Nodes>
+                       : tile_step_kernel<R, false, false, Shared, Nodes>);
+}
+
 template <typename R>
-TileKernel<R> tile_kernel(bool o32, bool fuse, bool shared)
+TileKernel<R> tile_kernel(bool o32, bool fuse, bool shared, bool nodes)
 {
     if constexpr (sizeof(R) == 8) {
         if (shared)
-            return o32 ? (fuse ? tile_step_kernel<R, true, true, true> : tile_step_kernel<R, true, false, true>)
-                       : (fuse ? tile_step_kernel<R, false, true, true> : tile_step_kernel<R, false, false, true>);
+            return nodes ? tile_kernel_of<R, true, true>(o32, fuse) : tile_kernel_of<R, true, false>(o32, fuse);
+        if (nodes) return tile_kernel_of<R, false, true>(o32, fuse);
     }
-    return o32 ? (fuse ? tile_step_kernel<R, true, true, false> : tile_step_kernel<R, true, false, false>)
-               : (fuse ? tile_step_kernel<R, false, true, false> : tile_step_kernel<R, false, false, false>);
+    return tile_kernel_of<R, false, false>(o32, fuse);
 }
 
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
 {
-    return tile_lds_bytes(dtype == SWE_F64 ? 8 : 4, tl.max_halo, tl.max_edges);
+    return tile_lds_bytes(dtype == SWE_F64 ? 8 : 4, tl.max_halo, tl.max_edges, tl.max_nodes);
 }
 
 int prepare_tile_kernels(size_t max_lds)
 {
-    const void *k[12];
+    const void *k[20];
     int n = 0;
     for (int o32 = 0; o32 < 2; ++o32)
         for (int fuse = 0; fuse < 2; ++fuse) {
-            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, false));
-            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, true));
-            k[n++] = reinterpret_cast<const void *>(tile_kernel<float>(o32, fuse, false));
+            for (int shared = 0; shared < 2; ++shared)
+                for (int nodes = 0; nodes < 2; ++nodes)
+                    k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, shared, nodes));
+            k[n++] = reinterpret_cast<const void *>(tile_kernel<float>(o32, fuse, false, false));
         }
     for (const void *f : k) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1345,7 +1414,8 @@ bool offsets_fit_32(const swe_dev_mesh &dm, int64_t n_cells, const TileLayout &t
     const int64_t lim = int64_t{1} << 32;
     return SWE_OFF32 && 16 * n_cells < lim && 16 * dm.n_nodes < lim &&
            16 * tl.n_tiles * static_cast<int64_t>(tl.max_edges) < lim &&
-           4 * tl.n_tiles * static_cast<int64_t>(tl.max_halo) < lim;
+           4 * tl.n_tiles * static_cast<int64_t>(tl.max_halo) < lim &&
+           16 * tl.n_tiles * static_cast<int64_t>(tl.max_nodes) < lim;
 }
 
 }  // namespace
@@ -1378,14 +1448,15 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
                 ta.s.us_hu = ustar[1];
                 ta.s.us_hv = ustar[2];
             }
-            const bool shared = tile_alias(sizeof(double), tl->max_halo, tl->max_edges);
-            tile_kernel<double>(o32, fuse, shared)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            const bool shared = tile_alias(sizeof(double), tl->max_halo, tl->max_edges, tl->max_nodes);
+            const bool nodes = ta.edge_nodes != nullptr;
+            tile_kernel<double>(o32, fuse, shared, nodes)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         } else {
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
             ta.s.part = part;
             ta.s.dt_direct = dt_direct;
             ta.s.adv = adv;
-            tile_kernel<float>(o32, fuse, false)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            tile_kernel<float>(o32, fuse, false, false)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         }
     } else if (dtype == SWE_F64) {
         StepArgs<double> a = make_args<double>(dm, s, cur);

@@ -173,6 +173,51 @@ void build_tiles(swe_mesh &m)
             m.edge_vec[2 * static_cast<size_t>(e) + 1] =
                 m.xy[2 * static_cast<size_t>(n1) + 1] - m.xy[2 * static_cast<size_t>(n0) + 1];
         }
+    // each tile's nodes in first-use order and, per entry, the tile-local ids of the nodes
+    // whose difference is its edge vector: the FP64 tiled step stages a tile's nodes (about
+    // 0.7 per cell) once instead of reading an edge vector per entry (about 1.7 per cell);
+    // kept only where every tile's ids fit in 8 bits
+    std::vector<int32_t> local(static_cast<size_t>(m.info.n_nodes), -1);
+    std::vector<int32_t> used;
+    int32_t max_nodes = 0;
+    m.tile_node_off.assign(nt + 1, 0);
+    m.tile_nodes.clear();
+    m.edge_nodes.assign(m.edges.size(), 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t s0 = t * SWE_TILE, s1 = std::min<int64_t>(T, s0 + SWE_TILE);
+        used.clear();
+        for (int64_t i = s0; i < s1; ++i)
+            for (int k = 0; k < 3; ++k) {
+                const int32_t v = m.c2n[k * T + i];
+                if (local[v] < 0) {
+                    local[v] = static_cast<int32_t>(used.size());
+                    used.push_back(v);
+                }
+            }
+        max_nodes = std::max(max_nodes, static_cast<int32_t>(used.size()));
+        if (max_nodes <= 256) {
+            for (int32_t e = m.edge_off[t]; e < m.edge_off[t + 1]; ++e) {
+                const uint32_t w = m.edges[e];
+                const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
+                const int k = static_cast<int>((w >> 8) & 3u);
+                const int32_t n0 = local[m.c2n[k * T + ca]], n1 = local[m.c2n[((k + 1) % 3) * T + ca]];
+                m.edge_nodes[e] = static_cast<uint16_t>(n0 | (n1 << 8));
+            }
+            for (int32_t v : used) {
+                m.tile_nodes.push_back(m.xy[2 * static_cast<size_t>(v)]);
+                m.tile_nodes.push_back(m.xy[2 * static_cast<size_t>(v) + 1]);
+            }
+            m.tile_node_off[t + 1] = static_cast<int32_t>(m.tile_nodes.size() / 2);
+        }
+        for (int32_t v : used) local[v] = -1;
+    }
+    if (max_nodes > 256 || m.tile_nodes.size() / 2 > static_cast<size_t>(INT32_MAX)) {
+        m.tile_node_off.clear();
+        m.tile_nodes.clear();
+        m.edge_nodes.clear();
+    }
+    m.info.n_tile_nodes = static_cast<int64_t>(m.tile_nodes.size() / 2);
+    m.info.max_tile_nodes = max_nodes;
     m.info.n_tiles = nt;
     m.info.n_halo = static_cast<int64_t>(m.halo.size());
     m.info.n_tile_edges = static_cast<int64_t>(m.edges.size());
@@ -181,6 +226,8 @@ void build_tiles(swe_mesh &m)
     m.tiles.n_tiles = nt;
     m.tiles.max_halo = max_halo;
     m.tiles.max_edges = max_edges;
+    m.tiles.max_nodes = m.tile_nodes.empty() ? 0 : max_nodes;
+    m.tiles.pad = 0;
 }
 
 void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_t nt,
@@ -538,6 +585,12 @@ int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t 
     case SWE_ARR_CELL_GEO: src = mesh->cell_geo.data(); bytes = 8 * (int64_t)mesh->cell_geo.size(); break;
     case SWE_ARR_EDGE_VEC32: return swe::export_as_float(mesh->edge_vec, dst, dst_bytes, "swe_mesh_export");
     case SWE_ARR_CELL_GEO32: return swe::export_as_float(mesh->cell_geo, dst, dst_bytes, "swe_mesh_export");
+    case SWE_ARR_TILE_NODE_OFF:
+        src = mesh->tile_node_off.data(); bytes = 4 * (int64_t)mesh->tile_node_off.size(); break;
+    case SWE_ARR_TILE_NODES:
+        src = mesh->tile_nodes.data(); bytes = 8 * (int64_t)mesh->tile_nodes.size(); break;
+    case SWE_ARR_EDGE_NODES:
+        src = mesh->edge_nodes.data(); bytes = 2 * (int64_t)mesh->edge_nodes.size(); break;
     case SWE_ARR_GLOBAL:
         bytes = 4 * mesh->info.n_cells;
         if (!mesh->global.empty()) {
@@ -557,7 +610,7 @@ int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t 
                        " bytes, array needs " + std::to_string(bytes));
         return SWE_EINVAL;
     }
-    memcpy(dst, src, static_cast<size_t>(bytes));
+    if (bytes > 0) memcpy(dst, src, static_cast<size_t>(bytes));
     return SWE_OK;
 }
 

@@ -67,6 +67,15 @@ class Mesh:
         self.edge_vec32 = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGE_VEC32,
                                             2 * int(self.info.n_tile_edges), np.float32)
         self.cell_geo32 = A.swe_mesh_export(self.handle, A.SWE_ARR_CELL_GEO32, 2 * t, np.float32)
+        # tile node lists (none where a tile has more than 256 nodes)
+        self.tile_node_off = self.tile_nodes = self.edge_nodes = None
+        if int(self.info.n_tile_nodes) > 0:
+            self.tile_node_off = A.swe_mesh_export(self.handle, A.SWE_ARR_TILE_NODE_OFF, nt + 1,
+                                                   np.int32)
+            self.tile_nodes = A.swe_mesh_export(self.handle, A.SWE_ARR_TILE_NODES,
+                                                2 * int(self.info.n_tile_nodes), np.float64)
+            self.edge_nodes = A.swe_mesh_export(self.handle, A.SWE_ARR_EDGE_NODES,
+                                                int(self.info.n_tile_edges), np.uint16)
         self.n_owned = int(self.info.n_owned)
         self.global_ids = A.swe_mesh_export(self.handle, A.SWE_ARR_GLOBAL, t, np.int32)
         self.device = None
@@ -96,11 +105,19 @@ class Mesh:
         self.d_cell_geo = torch.from_numpy(self.cell_geo).to(self.device)
         self.d_edge_vec32 = torch.from_numpy(self.edge_vec32).to(self.device)
         self.d_cell_geo32 = torch.from_numpy(self.cell_geo32).to(self.device)
+        nodes = self.tile_nodes is not None
+        self.d_tile_node_off = torch.from_numpy(self.tile_node_off).to(self.device) if nodes else None
+        self.d_tile_nodes = torch.from_numpy(self.tile_nodes).to(self.device) if nodes else None
+        self.d_edge_nodes = (torch.from_numpy(self.edge_nodes.view(np.int16)).to(self.device)
+                             if nodes else None)
+        opt = lambda t: _ptr(t) if t is not None else None
         self.dev = A.swe_dev_mesh(self.n_cells, self.n_nodes, _ptr(self.d_nbr), _ptr(self.d_c2n),
                                   _ptr(self.d_xy), _ptr(self.d_halo_off), _ptr(self.d_halo),
                                   _ptr(self.d_edge_off), _ptr(self.d_edges), _ptr(self.d_slot),
                                   _ptr(self.d_edge_vec), _ptr(self.d_cell_geo),
-                                  _ptr(self.d_edge_vec32), _ptr(self.d_cell_geo32))
+                                  _ptr(self.d_edge_vec32), _ptr(self.d_cell_geo32),
+                                  opt(self.d_tile_node_off), opt(self.d_tile_nodes),
+                                  opt(self.d_edge_nodes))
         return self
 
     def to_mesh_order(self, a):
@@ -233,15 +250,21 @@ class Batch:
             "tile_scen": ex(A.SWE_BARR_TILE_SCEN, nt, np.int32),
             "scen_tile_off": ex(A.SWE_BARR_SCEN_TILE_OFF, n + 1, np.int32),
         }
+        if int(i.n_tile_nodes) > 0:   # every scenario has tile node lists
+            arrays["tile_node_off"] = ex(A.SWE_ARR_TILE_NODE_OFF, nt + 1, np.int32)
+            arrays["tile_nodes"] = ex(A.SWE_ARR_TILE_NODES, 2 * int(i.n_tile_nodes), np.float64)
+            arrays["edge_nodes"] = ex(A.SWE_ARR_EDGE_NODES, int(i.n_tile_edges),
+                                      np.uint16).view(np.int16)
         d = torch.device(device)
         if d.type == "cuda" and d.index is None:
             d = torch.device("cuda", torch.cuda.current_device())
         self.device = d
         self.d = {k: torch.from_numpy(a).to(d) for k, a in arrays.items()}
-        P = lambda k: _ptr(self.d[k])
+        P = lambda k: _ptr(self.d[k]) if k in self.d else None
         mesh = A.swe_dev_mesh(t, v, P("nbr"), P("c2n"), P("xy"), P("halo_off"), P("halo"),
                               P("edge_off"), P("edges"), P("slot"), P("edge_vec"), P("cell_geo"),
-                              P("edge_vec32"), P("cell_geo32"))
+                              P("edge_vec32"), P("cell_geo32"), P("tile_node_off"),
+                              P("tile_nodes"), P("edge_nodes"))
         self.dev = A.swe_batch_dev(mesh, P("tile_start"), P("tile_scen"), P("scen_tile_off"))
 
     def scenario_slice(self, s: int) -> slice:

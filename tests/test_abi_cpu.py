@@ -267,6 +267,62 @@ def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton):
     assert len(seen) == info.n_tile_edges
 
 
+@pytest.mark.parametrize("k,order", [(1, "morton"), (3, "hilbert"), (5, "morton")])
+def test_tile_node_lists_reproduce_the_edge_vectors_bitwise(k, order):
+    """Each tile's node list holds the distinct nodes of its cells, with their coordinates;
+    each edge-list entry's two node ids give back its edge vector, bit for bit."""
+    c = gen.small(k)
+    m = swe.Mesh(c.xy, c.tri, order=order, device=None)
+    t, tile = m.n_cells, swe.SWE_TILE
+    info = m.info
+    assert info.n_tile_nodes > 0 and 0 < info.max_tile_nodes <= 256
+    off, nodes, en = m.tile_node_off, m.tile_nodes.reshape(-1, 2), m.edge_nodes.astype(np.int64)
+    assert off[0] == 0 and off[-1] == info.n_tile_nodes and (np.diff(off) > 0).all()
+    assert np.diff(off).max() == info.max_tile_nodes
+    xy, c2n = m.xy.reshape(-1, 2), m.c2n.reshape(3, t)
+    ev = m.edge_vec.reshape(-1, 2)
+    for tt in range(info.n_tiles):
+        s0, s1 = tt * tile, min(t, (tt + 1) * tile)
+        want = np.unique(c2n[:, s0:s1])
+        tn = nodes[off[tt]:off[tt + 1]]
+        assert len(tn) == len(want)
+        assert np.array_equal(np.unique(tn, axis=0), np.unique(xy[want], axis=0))
+        e0, e1 = m.edge_off[tt], m.edge_off[tt + 1]
+        p0, p1 = tn[en[e0:e1] & 0xFF], tn[en[e0:e1] >> 8]
+        assert np.array_equal(p1 - p0, ev[e0:e1])
+
+
+def test_scattered_tiles_get_no_node_lists_and_batches_concatenate_them():
+    """Tiles of 256 cells in random order touch far more than 256 nodes: no node lists (the
+    FP64 tiled step then reads the edge vectors).  A batch keeps the lists of its scenarios,
+    with their tile-local ids, when every scenario has them."""
+    c = gen.small(5)
+    perm = np.random.default_rng(3).permutation(c.n_cells)
+    sc = swe.Mesh(c.xy, c.tri[perm], morton=False, device="cpu")
+    assert sc.info.n_tile_nodes == 0 and sc.info.max_tile_nodes > 256
+    assert sc.tile_nodes is None and sc.dev.tile_nodes is None
+    cases = [gen.ensemble_scenario(s) for s in range(3)]
+    meshes = [swe.Mesh(x.xy, x.tri, x.edge_tag, device=None) for x in cases]
+    b = swe.Batch(meshes, device="cpu")
+    i = b.info
+    assert i.n_tile_nodes == sum(m.info.n_tile_nodes for m in meshes)
+    assert i.max_tile_nodes == max(m.info.max_tile_nodes for m in meshes)
+    off = swe.swe_batch_export(b.handle, swe._abi.SWE_ARR_TILE_NODE_OFF, int(i.n_tiles) + 1, np.int32)
+    nodes = swe.swe_batch_export(b.handle, swe._abi.SWE_ARR_TILE_NODES, 2 * int(i.n_tile_nodes),
+                                 np.float64).reshape(-1, 2)
+    en = swe.swe_batch_export(b.handle, swe._abi.SWE_ARR_EDGE_NODES, int(i.n_tile_edges),
+                              np.uint16).astype(np.int64)
+    eoff = swe.swe_batch_export(b.handle, swe._abi.SWE_ARR_EDGE_OFF, int(i.n_tiles) + 1, np.int32)
+    ev = swe.swe_batch_export(b.handle, swe._abi.SWE_ARR_EDGE_VEC, 2 * int(i.n_tile_edges),
+                              np.float64).reshape(-1, 2)
+    for tt in range(int(i.n_tiles)):
+        tn = nodes[off[tt]:off[tt + 1]]
+        e = slice(eoff[tt], eoff[tt + 1])
+        assert np.array_equal(tn[en[e] >> 8] - tn[en[e] & 0xFF], ev[e])
+    mixed = swe.Batch([meshes[0], sc], device="cpu")
+    assert mixed.info.n_tile_nodes == 0 and "tile_nodes" not in mixed.d
+
+
 def test_batch_concatenates_scenarios_without_straddling_tiles():
     cases = [gen.ensemble_scenario(s) for s in range(5)]
     meshes = [swe.Mesh(c.xy, c.tri, c.edge_tag, device=None) for c in cases]
