@@ -655,18 +655,17 @@ struct TileArgs {
 // Plain layout: [states | 5 rows of max_edges].  Shared layout (at most 2 kBlock entries):
 // [5 rows of kBlock for entries 0..kBlock-1 | states], the entries from kBlock on written in
 // 5 rows of kBlock over the states once every interface of the tile has been evaluated.  An
-// FP64 step with node lists appends the tile's nodes, (x, y) each, at a 16-byte boundary.
+// FP64 step with node lists (shared layout only: a tile of at most 256 nodes has at most 511
+// interfaces) appends the tile's nodes, (x, y) each; the layout's words before them are even.
 inline size_t tile_lds_nodes(size_t word, int64_t max_nodes)
 {
     return word == 8 && max_nodes > 0 ? 16 * static_cast<size_t>(max_nodes) : 0;
 }
 
-inline size_t tile_lds_plain(size_t word, int64_t max_halo, int64_t max_edges, int64_t max_nodes)
+inline size_t tile_lds_plain(size_t word, int64_t max_halo, int64_t max_edges)
 {
-    const size_t b = 4 * word * static_cast<size_t>(kBlock + max_halo) +
-                     5 * word * static_cast<size_t>(max_edges);
-    const size_t nd = tile_lds_nodes(word, max_nodes);
-    return nd ? ((b + 15) & ~static_cast<size_t>(15)) + nd : b;
+    return 4 * word * static_cast<size_t>(kBlock + max_halo) +
+           5 * word * static_cast<size_t>(max_edges);
 }
 
 inline size_t tile_lds_shared(size_t word, int64_t max_halo, int64_t max_nodes)
@@ -688,8 +687,7 @@ inline bool tile_alias(size_t word, int64_t max_halo, int64_t max_edges, int64_t
 {
     if (!SWE_TILE_ALIAS || word != 8 || max_edges > 2 * kBlock) return false;
     constexpr size_t kLdsPerCu = 160 * 1024;
-    const size_t plain =
-        kLdsPerCu / (tile_lds_plain(word, max_halo, max_edges, max_nodes) + kTileStaticLds);
+    const size_t plain = kLdsPerCu / (tile_lds_plain(word, max_halo, max_edges) + kTileStaticLds);
     const size_t shared = kLdsPerCu / (tile_lds_shared(word, max_halo, max_nodes) + kTileStaticLds);
     return plain < 8 && shared > plain;
 }
@@ -698,7 +696,7 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges, i
 {
     return tile_alias(word, max_halo, max_edges, max_nodes)
                ? tile_lds_shared(word, max_halo, max_nodes)
-               : tile_lds_plain(word, max_halo, max_edges, max_nodes);
+               : tile_lds_plain(word, max_halo, max_edges);
 }
 
 // One explicit step, tiled.  Every global load of the workgroup is issued up front: the own
@@ -718,7 +716,7 @@ template <typename R, bool O32, bool Fuse, bool Shared, bool Nodes>
 __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
                                                            Batch bt)
 {
-    static_assert(!Nodes || sizeof(R) == 8, "node lists serve the FP64 step");
+    static_assert(!Nodes || (sizeof(R) == 8 && Shared), "node lists serve the shared FP64 layout");
     const StepArgs<R> &a = ta.s;
     const int tile = xcd_tile(blockIdx.x, ta.n_tiles, bt.remap);
     if (tile >= ta.n_tiles) return;
@@ -741,11 +739,10 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     R *s_u = s_h + ns;
     R *s_v = s_u + ns;
     R *s_z = s_v + ns;
-    // Nodes (FP64 with node lists): the tile's nodes after the layout's other words (16-byte
-    // aligned), each entry's edge vector formed from them
+    // Nodes (FP64 with node lists): the tile's nodes after the layout's other words (an even
+    // count, so 16-byte aligned), each entry's edge vector formed from them
     constexpr bool nodes = Nodes;
-    double2 *const s_nd = reinterpret_cast<double2 *>(
-        lds + (alias ? 5 * kBlock + max(4 * ns, 5 * kBlock) : ((4 * ns + 5 * ta.max_edges + 1) & ~1)));
+    double2 *const s_nd = reinterpret_cast<double2 *>(lds + 5 * kBlock + max(4 * ns, 5 * kBlock));
     // each tile cell's local edge k -> its edge-list entry (bit 15: the cell is side b),
     // filled from the edge list in phase 2
     __shared__ uint16_t s_slot[3 * kBlock];
@@ -879,16 +876,9 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     }
     for (int e = eb + pt + 2 * kBlock; e < ee; e += kBlock) {   // plain layout only
         const uint32_t w = ld<O32>(ta.edges, e);
-        R dx, dy;
-        if (nodes) {
-            node_vec(ld<O32>(ta.edge_nodes, e), dx, dy);
-        } else {
-            const auto d = ld<O32>(ta.edge_vec, e);
-            dx = d.x;
-            dy = d.y;
-        }
+        const auto d = ld<O32>(ta.edge_vec, e);
         EdgeOut o;
-        put(e - eb, w, o, flux(w, dx, dy, o));
+        put(e - eb, w, o, flux(w, d.x, d.y, o));
     }
     __syncthreads();
 
@@ -1377,7 +1367,6 @@ TileKernel<R> tile_kernel(bool o32, bool fuse, bool shared, bool nodes)
     if constexpr (sizeof(R) == 8) {
         if (shared)
             return nodes ? tile_kernel_of<R, true, true>(o32, fuse) : tile_kernel_of<R, true, false>(o32, fuse);
-        if (nodes) return tile_kernel_of<R, false, true>(o32, fuse);
     }
     return tile_kernel_of<R, false, false>(o32, fuse);
 }
@@ -1389,13 +1378,13 @@ size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
 
 int prepare_tile_kernels(size_t max_lds)
 {
-    const void *k[20];
+    const void *k[16];
     int n = 0;
     for (int o32 = 0; o32 < 2; ++o32)
         for (int fuse = 0; fuse < 2; ++fuse) {
-            for (int shared = 0; shared < 2; ++shared)
-                for (int nodes = 0; nodes < 2; ++nodes)
-                    k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, shared, nodes));
+            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, false, false));
+            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, true, false));
+            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, true, true));
             k[n++] = reinterpret_cast<const void *>(tile_kernel<float>(o32, fuse, false, false));
         }
     for (const void *f : k) {
@@ -1449,7 +1438,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
                 ta.s.us_hv = ustar[2];
             }
             const bool shared = tile_alias(sizeof(double), tl->max_halo, tl->max_edges, tl->max_nodes);
-            const bool nodes = ta.edge_nodes != nullptr;
+            const bool nodes = shared && ta.edge_nodes != nullptr;
             tile_kernel<double>(o32, fuse, shared, nodes)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
         } else {
             TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
