@@ -136,8 +136,9 @@ enum swe_mesh_array {
  * edges, slot and the edge vectors of the step's precision are the tiled kernels' (the tiled
  * step reads all but slot, which the tiled adjoint reads): when one is NULL, SWE_AUTO runs the
  * per-cell kernel and SWE_TILED is an error.  tile_node_off, tile_nodes and edge_nodes are
- * optional: with all three the FP64 tiled step forms each edge vector from its tile's node list
- * instead of reading edge_vec (the same bits, fewer bytes). */
+ * optional: with all three the FP64 tiled step, in its shared LDS layout (the one it takes
+ * unless the plain one fits as many tiles per CU), forms each edge vector from its tile's node
+ * list instead of reading edge_vec (the same bits, fewer bytes). */
 typedef struct swe_dev_mesh {
     int64_t n_cells, n_nodes;
     const int32_t *nbr;    /* device, as SWE_ARR_NBR */
