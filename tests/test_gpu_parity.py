@@ -327,3 +327,25 @@ def test_quarter_turn_rotates_the_result_bitwise(gpu, k, dtype):
     assert np.array_equal(h2, h)
     assert np.array_equal(hu2, -hv)
     assert np.array_equal(hv2, hu)
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_tile_node_lists_and_edge_vectors_give_the_same_bits(gpu, exact):
+    """The FP64 tiled step forms each edge vector from its tile's node list by the mesh
+    builder's own subtraction; without the node arrays it reads the stored edge vectors: the
+    same run, bit for bit, in both FP64 math modes."""
+    case = gen.small(3)
+    m = gpu.Mesh(case.xy, case.tri)
+    assert m.info.n_tile_nodes > 0 and m.dev.tile_nodes is not None
+
+    def run():
+        s = gpu.Solver(m, case.z, case.n, case.h, case.hu, case.hv, dtype="f64",
+                       variant="tiled", exact=exact)
+        rc, st = s.run(60)
+        return rc, st, s.numpy_state()
+
+    rc, st, (h, hu, hv) = run()
+    m.dev.tile_node_off = m.dev.tile_nodes = m.dev.edge_nodes = None
+    rc2, st2, (h2, hu2, hv2) = run()
+    assert rc == rc2 == 0 and st["steps"] == st2["steps"] == 60 and st["t"] == st2["t"]
+    assert np.array_equal(h, h2) and np.array_equal(hu, hu2) and np.array_equal(hv, hv2)
