@@ -14,14 +14,14 @@ TOL_F32 = 1e-5
 
 
 def run_gpu(case, dtype="f64", steps=None, morton=True, t_end=0.0, dt_seq=None, mesh=None,
-            variant="auto"):
+            variant="auto", exact=False):
     import torch
 
     import paper_1807_00672_amd as swe
     m = mesh or swe.Mesh(case.xy, case.tri, case.edge_tag, morton=morton)
     s = swe.Solver(m, case.z, case.n, case.h, case.hu, case.hv, dtype=dtype, g=case.g,
                    courant=case.courant, h_dry=case.h_dry, inflow_q=case.inflow_q, t_end=t_end,
-                   variant=variant)
+                   variant=variant, exact=exact)
     seq = None if dt_seq is None else torch.as_tensor(dt_seq, dtype=torch.float64,
                                                       device=m.device)
     rc, st = s.run(case.steps if steps is None else steps, dt_seq=seq)

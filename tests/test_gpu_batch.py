@@ -11,11 +11,11 @@ from parity import TOL_F64, errors, run_gpu
 pytestmark = pytest.mark.gpu
 
 
-def _batch(swe, cases, dtype, steps, t_end=0.0, variant="auto", xcd_remap=True):
+def _batch(swe, cases, dtype, steps, t_end=0.0, variant="auto", xcd_remap=True, exact=False):
     meshes = [swe.Mesh(c.xy, c.tri, c.edge_tag) for c in cases]
     b = swe.Batch(meshes)
     bs = swe.BatchSolver(b, cases, dtype=dtype, t_end=t_end, variant=variant,
-                         xcd_remap=xcd_remap)
+                         xcd_remap=xcd_remap, exact=exact)
     rc, st = bs.run(steps)
     return rc, st, bs
 
@@ -34,6 +34,19 @@ def test_batch_equals_single_runs_bitwise(gpu, dtype, variant, remap):
         assert np.array_equal(hb, h) and np.array_equal(hub, hu) and np.array_equal(hvb, hv)
     ts = [x["t"] for x in st]
     assert len(set(ts)) == len(ts)            # every scenario kept its own dt
+
+
+@pytest.mark.parametrize("variant", ["tiled", "cell"])
+def test_exact_batch_equals_single_exact_runs_bitwise(gpu, variant):
+    """Correctly rounded FP64 (SWE_EXACT) in a batch: each scenario as its own exact run."""
+    cases = [gen.ensemble_scenario(s) for s in (1, 4, 8)]
+    rc, st, bs = _batch(gpu, cases, "f64", 80, variant=variant, exact=True)
+    assert rc == 0
+    for s, c in enumerate(cases):
+        rc1, st1, h, hu, hv = run_gpu(c, "f64", steps=80, exact=True)
+        assert rc1 == 0 and st[s]["steps"] == st1["steps"] == 80 and st[s]["t"] == st1["t"]
+        hb, hub, hvb = bs.numpy_state(s)
+        assert np.array_equal(hb, h) and np.array_equal(hub, hu) and np.array_equal(hvb, hv)
 
 
 def test_batch_matches_oracle_and_stops_each_scenario_at_t_end(gpu):
