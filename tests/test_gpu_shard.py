@@ -39,6 +39,22 @@ def test_sharded_run_equals_single_domain_bitwise(gpu, dtype, variant, parts):
         assert np.array_equal(a, b)
 
 
+def test_exact_sharded_run_equals_single_domain_bitwise(gpu):
+    """Correctly rounded FP64 (SWE_EXACT): five shards give the single-domain exact run."""
+    swe = gpu
+    case = gen.small(3)
+    mesh = swe.Mesh(case.xy, case.tri)
+    rc0, st0, ref = _single(swe, case, mesh, "f64", 60, variant="tiled", exact=True)
+    sh = swe.ShardedSolver(mesh, 5, case.z, case.n, case.h, case.hu, case.hv, dtype="f64",
+                           variant="tiled", exact=True)
+    sh.step(60)
+    rc1, st1 = sh.stats()
+    assert rc0 == rc1 == swe.SWE_OK and st1["steps"] == st0["steps"] == 60
+    assert st1["t"] == st0["t"]
+    for a, b in zip(ref, sh.numpy_state()):
+        assert np.array_equal(a, b)
+
+
 def test_sharded_inflow_and_t_end_match_single_domain(gpu):
     swe = gpu
     case = gen.ensemble_scenario(3, t_min=8e3, t_max=9e3)
