@@ -153,3 +153,37 @@ def test_every_gradient_entry_matches_the_oracle(gpu, small_full_gradient, ckpt_
               f"max difference {err:.3e}")
         assert scale > 0
         assert err <= 1e-12 * scale
+
+
+def test_adjoint_with_an_inflow_segment_matches_the_oracle_tangent(gpu):
+    """An ensemble scenario with its inflow segment (discharge through the boundary, the depth
+    there from max(h, critical depth)): the loss and the dot product of each gradient with a
+    random direction against the oracle's tangent model, gauges near the inflow."""
+    case = gen.ensemble_scenario(3, steps=60)
+    om = oracle.Mesh(case.xy, case.tri, case.edge_tag)
+    q = case.inflow_q
+    rc, _, _, _, dts, _ = oracle.run(om, case.z, case.n, case.h, case.hu, case.hv, 60, inflow_q=q)
+    assert rc == 0 and len(dts) == 60
+    rng = np.random.default_rng(5)
+    near = np.argsort(gen.centroids(case.xy, case.tri)[:, 0])[:200]
+    gauges = np.sort(rng.choice(near, 12, replace=False)).astype(np.int32)
+    h, hu, hv, obs = case.h.copy(), case.hu.copy(), case.hv.copy(), []
+    for s in range(60):   # observations of a rougher run
+        rc, h, hu, hv, _, _ = oracle.run(om, case.z, 1.3 * case.n, h, hu, hv, 1,
+                                         dt_seq=dts[s:s + 1], inflow_q=q)
+        if (s + 1) % 10 == 0:
+            obs.append(h[gauges].copy())
+    obs = np.array(obs)
+    mesh = gpu.Mesh(case.xy, case.tri, case.edge_tag)
+    calib = gpu.Calibration(mesh, dts, gauges, obs, every=10, ckpt_every=7, inflow_q=q)
+    j, grads = calib.run(case.n, case.z, case.h, case.hu, case.hv)
+    jo = oracle.run_loss(om, case.z, case.n, case.h, case.hu, case.hv, dts, gauges, 10, obs,
+                         inflow_q=q)
+    assert j == pytest.approx(jo, rel=1e-12) and j > 0
+    for k, which in enumerate(("n", "z", "h", "hu", "hv")):
+        v = rng.normal(size=case.n_cells)
+        _, djo = oracle.run_tl(om, case.z, case.n, case.h, case.hu, case.hv, dts, gauges, 10,
+                               obs, inflow_q=q, **{"d" + which: v})
+        adj = float(np.dot(grads[k], v))
+        print(f"inflow d{which}: adjoint {adj!r}, tangent {djo!r}")
+        assert adj == pytest.approx(djo, rel=1e-9, abs=1e-14 * abs(jo))
