@@ -9,6 +9,9 @@ Oracle functions and the passages of the paper they follow (section 2 of Zaoui 2
   ``Mesh``          triangles, interfaces and geometry (section 2.2, eq. 3, Fig. 1)
   ``hllc``          HLLC interface flux (section 2.2, ref. [6])
   ``interface``     hydrostatic reconstruction of the bed around the flux (section 2.2)
+  ``wall``          reflective wall as a mirror ghost (section 3)
+  ``inflow``        prescribed unit discharge through a boundary edge (not in the paper: the
+                    ensemble's inflow segments; boundary state read as critical or deeper flow)
   ``run``           explicit Euler steps of eq. 4 with CFL dt (Courant 0.7), friction
                     (S_f of eq. 1) and the host time loop of section 2.3
 """
@@ -84,6 +87,7 @@ def _bind(L):
     L.om_interface_batch.argtypes = [C.c_long, C.c_double, C.c_double] + [_dp] * 13
     L.om_wall_batch.argtypes = [C.c_long, C.c_double, C.c_double] + [_dp] * 7
     L.om_wave_speeds_batch.argtypes = [C.c_long, C.c_double] + [_dp] * 6
+    L.om_inflow_batch.argtypes = [C.c_long, C.c_double] + [_dp] * 6
     L.om_run_tl.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                             C.POINTER(_Params), C.c_long, _dp, _ip, C.c_int, C.c_int, _dp, _dp,
                             _dp]
@@ -214,6 +218,17 @@ def wall(h, hu, hv, nx, ny, g=9.81, h_dry=1e-6):
     p = np.empty(nn)
     lib().om_wall_batch(nn, g, h_dry, *[_ptr(v) for v in a], _ptr(f), _ptr(p))
     return f, p
+
+
+def inflow(q_in, h, nx, ny, g=9.81):
+    """Flux through an inflow edge carrying unit discharge q_in into a cell of depth h (outward
+    unit normal (nx, ny)) and the boundary wave speed; (F [N,3], speed [N])."""
+    a = [_d(v).ravel() for v in (q_in, h, nx, ny)]
+    nn = a[0].size
+    f = np.empty((nn, 3))
+    s = np.empty(nn)
+    lib().om_inflow_batch(nn, g, *[_ptr(v) for v in a], _ptr(f), _ptr(s))
+    return f, s
 
 
 def wave_speeds(hl, ql, hr, qr, g=9.81):

@@ -556,6 +556,13 @@ void om_wave_speeds_batch(long n, double g, const double *hl, const double *ql,
     for (long i = 0; i < n; ++i) om_wave_speeds(g, hl[i], ql[i], hr[i], qr[i], sl + i, sr + i);
 }
 
+/* Inflow flux (3 values per edge) and boundary wave speed of n independent inflow edges. */
+void om_inflow_batch(long n, double g, const double *q_in, const double *h, const double *nx,
+                     const double *ny, double *f, double *speed)
+{
+    for (long i = 0; i < n; ++i) speed[i] = om_inflow(g, q_in[i], h[i], nx[i], ny[i], f + 3 * i);
+}
+
 /* ----------------------------------------------------------------- tangent-linear model
  *
  * Forward-mode derivative of om_run with the dt sequence replayed (dt is not differentiated),

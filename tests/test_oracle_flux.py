@@ -185,3 +185,57 @@ def test_reconstruction_step_is_well_balanced_pointwise():
     assert np.abs(f[:, 0]).max() < 1e-12
     tot_x = f[:, 1] + pl * nx
     np.testing.assert_allclose(tot_x, 0.5 * G * hl * hl * nx, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ inflow boundary
+def critical_depth(q, g=G):
+    """Depth at which the unit discharge q flows critically, Froude number one (q / h equal to
+    sqrt(g h)), by bisection on that condition (q / h - sqrt(g h) falls as h grows)."""
+    q = np.asarray(q, dtype=np.float64)
+    lo = np.full(q.shape, 1e-6)
+    hi = np.full(q.shape, 1e3)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        sub = q / mid - np.sqrt(g * mid) > 0.0
+        lo = np.where(sub, mid, lo)
+        hi = np.where(sub, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+def test_inflow_flux_of_deep_water_is_the_physical_flux_of_the_boundary_state():
+    """At depths h >= h_c the boundary state is the cell's depth carrying the discharge
+    inwards, (h, -q n / h): the edge flux is eq. 1's physical normal flux of that state and the
+    boundary wave speed is |u_b| + sqrt(g h)."""
+    rng = np.random.default_rng(31)
+    n = 100000
+    q = rng.uniform(5.0, 50.0, n)
+    hc = critical_depth(q)
+    h = hc * rng.uniform(1.0 + 1e-9, 4.0, n)
+    nx, ny = unit_normals(rng, n)
+    f, speed = oracle.inflow(q, h, nx, ny)
+    ub, vb = -q * nx / h, -q * ny / h
+    ref = physical_normal_flux(h, ub, vb, nx, ny)
+    scale = np.abs(ref).max(axis=1)
+    assert (np.abs(f - ref).max(axis=1) / scale).max() < 1e-14
+    ref_speed = np.hypot(ub, vb) + np.sqrt(G * h)
+    np.testing.assert_allclose(speed, ref_speed, rtol=1e-14)
+
+
+def test_inflow_into_shallow_or_dry_cells_runs_at_critical_depth():
+    """Below the critical depth (dry cells included) the boundary carries the discharge at
+    critical flow: h_b^3 = q^2 / g, so the normal momentum flux q^2 / h_b + g h_b^2 / 2 is
+    exactly 3/2 g h_c^2, the mass flux is -q and the boundary wave speed q / h_b + sqrt(g h_b) is
+    2 sqrt(g h_c)."""
+    rng = np.random.default_rng(32)
+    n = 100000
+    q = rng.uniform(5.0, 50.0, n)
+    hc = critical_depth(q)
+    h = hc * rng.uniform(0.0, 1.0 - 1e-9, n)
+    h[: n // 10] = 0.0
+    nx, ny = unit_normals(rng, n)
+    f, speed = oracle.inflow(q, h, nx, ny)
+    mom = 1.5 * G * hc * hc
+    np.testing.assert_array_equal(f[:, 0], -q)
+    np.testing.assert_allclose(f[:, 1], mom * nx, rtol=1e-13, atol=1e-13 * mom.max())
+    np.testing.assert_allclose(f[:, 2], mom * ny, rtol=1e-13, atol=1e-13 * mom.max())
+    np.testing.assert_allclose(speed, 2.0 * np.sqrt(G * hc), rtol=1e-13)

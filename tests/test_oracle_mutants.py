@@ -42,6 +42,11 @@ MUTANTS = [
     ("normal points inward", "*nx = dy / l;\n    *ny = -dx / l;", "*nx = -dy / l;\n    *ny = dx / l;"),
     ("dry cells keep momentum", "hu[c] = 0.0;\n            hv[c] = 0.0;", "hu[c] = hus;\n            hv[c] = hvs;"),
     ("inflow sign", "f[0] = -q_in;", "f[0] = q_in;"),
+    ("inflow momentum without the half", "const double mom = q_in * q_in / hb + 0.5 * g * hb * hb;",
+     "const double mom = q_in * q_in / hb + g * hb * hb;"),
+    ("inflow boundary depth is the cell depth", "const double hb = fmax(h, hc);", "const double hb = h;"),
+    ("inflow speed without the flow term", "return q_in / hb + sqrt(g * hb);", "return sqrt(g * hb);"),
+    ("CFL ignores the inflow speed", "if (sb > s) s = sb;", "(void)sb;"),
     ("t_end clip ignored", "if (t_end > 0.0 && dt >= t_end - st->t) { dt = t_end - st->t; last = 1; }",
      "if (t_end > 0.0 && dt >= t_end - st->t) { last = 1; }"),
 ]

@@ -82,6 +82,32 @@ def test_right_triangle_cfl_dt_by_hand():
     assert dt == pytest.approx(0.7 * r / (math.hypot(u, v) + math.sqrt(G * h)), rel=1e-14)
 
 
+def test_inflow_cells_bound_the_cfl_dt_with_the_boundary_wave_speed():
+    """Uniform still water on right isosceles triangles (one inradius r for every cell) with
+    an inflow segment along x = 0: when the boundary wave speed of the inflow cells exceeds
+    sqrt(g h), dt = 0.7 r / (|u_b| + sqrt(g h_b)) of that boundary state.  Shallow water takes
+    the critical state (speed 2 sqrt(g h_c)), deep water the cell depth (q / h + sqrt(g h))."""
+    from test_oracle_flux import critical_depth
+    c = gen.dam_break(nx=20, ny=10, lx=20.0, ly=10.0, jitter=0.0)
+    tag = np.zeros((c.n_cells, 3), dtype=np.int32)
+    for k in range(3):
+        a, b = c.xy[c.tri[:, k]], c.xy[c.tri[:, (k + 1) % 3]]
+        tag[(a[:, 0] == 0.0) & (b[:, 0] == 0.0), k] = 1
+    assert tag.sum() == 10
+    m = oracle.Mesh(c.xy, c.tri, tag)
+    t = m.n_cells
+    r = 1.0 * (2.0 - math.sqrt(2.0)) / 2.0
+    q = 10.0
+    hc = float(critical_depth(q))
+    for h, speed in ((0.5, 2.0 * math.sqrt(G * hc)), (4.0, q / 4.0 + math.sqrt(G * 4.0))):
+        assert speed > math.sqrt(G * h)
+        dt = oracle.cfl_dt(m, np.full(t, h), np.zeros(t), np.zeros(t), inflow_q=[q])
+        assert dt == pytest.approx(0.7 * r / speed, rel=1e-13)
+        dt_walls = oracle.cfl_dt(oracle.Mesh(c.xy, c.tri), np.full(t, h), np.zeros(t),
+                                 np.zeros(t))
+        assert dt_walls == pytest.approx(0.7 * r / math.sqrt(G * h), rel=1e-14)
+
+
 # --------------------------------------------------------------------- invariants
 def test_lake_at_rest_with_dry_islands_is_held_to_round_off():
     c = gen.lake_at_rest()
