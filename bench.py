@@ -84,20 +84,51 @@ def alu_view(r):
             "source": "SQ_INSTS_VALU of the committed counter run (profiles/)"}
 
 
-def time_gpu(solver, steps, warmup, stream):
+# swe_run replays groups of 8 steps from one captured graph once a run has at least 16 steps:
+# a warm-up of that length captures it, so no timed window pays for the capture.
+GRAPH_WARMUP = 16
+# Device time the warm-up keeps the GPU stepping before the first timed window: a short
+# warm-up leaves the first windows several per cent slow while the device's clocks settle.
+SETTLE_S = 0.25
+
+
+def time_gpu(solver, steps, warmup, stream, windows=5):
+    """Median over `windows` timed windows of exactly `steps` steps each.  Before them, an
+    untimed warm-up on the same stream: max(warmup, GRAPH_WARMUP) steps, then more untimed
+    windows of `steps` steps until the warm-up has kept the device busy for SETTLE_S.  HIP
+    events on the stream that runs the steps bracket each window.  Returns (ms of the median
+    window, rc, stats, warm-up steps run, every timed window's ms)."""
     import torch
-    solver.run(warmup, sync=True)
-    torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    warm = max(warmup, GRAPH_WARMUP)
     with torch.cuda.stream(stream):
         ev0.record(stream)
-        solver.run(steps, sync=False, stream=stream)
+        solver.run(warm, sync=False, stream=stream)
         ev1.record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    busy = ev0.elapsed_time(ev1) * 1e-3
+    chunk = max(steps, GRAPH_WARMUP)
+    while busy < SETTLE_S:
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            solver.run(chunk, sync=False, stream=stream)
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        busy += ev0.elapsed_time(ev1) * 1e-3
+        warm += chunk
+    times = []
+    for _ in range(windows):
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            solver.run(steps, sync=False, stream=stream)
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    ms = float(np.median(times))
     rc, st = solver.stats(stream=stream)
-    return ms, rc, st
+    return ms, rc, st, warm, times
 
 
 def bench_ensemble(dtype: str, steps: int, warmup: int, stream) -> dict:
@@ -111,7 +142,7 @@ def bench_ensemble(dtype: str, steps: int, warmup: int, stream) -> dict:
     meshes = [swe.Mesh(c.xy, c.tri, c.edge_tag) for c in cases]
     batch = swe.Batch(meshes)
     bs = swe.BatchSolver(batch, cases, dtype=dtype)
-    bs.run(warmup)
+    bs.run(warmup)   # at least 16 steps: captures the batch's graph
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(stream):
@@ -190,7 +221,7 @@ def bench_shards(mesh, case, stream, parts: int = 8, steps: int = 100) -> dict:
     m = sh.meshes[q]
     one = swe.Solver(m, *[np.asarray(a, np.float64)[mesh.perm][m.global_ids]
                           for a in (case.z, case.n, case.h, case.hu, case.hv)], dtype="f64")
-    ms_one, rc, st = time_gpu(one, steps, 10, stream)
+    ms_one, rc, st, _, _ = time_gpu(one, steps, 10, stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     sh.step(5)
     torch.cuda.synchronize()
@@ -225,8 +256,8 @@ def bench_configs(stream, dtypes) -> dict:
         r = {"n_cells": case.n_cells, "steps": case.steps}
         for dt in dtypes:
             solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt)
-            ms, rc, st = time_gpu(solver, case.steps, 0, stream)
-            if rc != swe.SWE_OK or st["steps"] != case.steps:
+            ms, rc, st, warm, _ = time_gpu(solver, case.steps, 0, stream)
+            if rc != swe.SWE_OK or st["steps"] != warm + 5 * case.steps:
                 raise RuntimeError(f"config {k} {dt}: rc={rc} stats={st}")
             r[dt] = {"cell_updates_per_s": case.n_cells * case.steps / (ms * 1e-3),
                      "ms_per_step": ms / case.steps}
@@ -336,6 +367,22 @@ def copy_bandwidth(nbytes=2 << 30, reps=10):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), and how many logical CPUs it lists."""
+    names, n = [], 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    n += 1
+                    nm = ln.split(":", 1)[1].strip()
+                    if nm not in names:
+                        names.append(nm)
+    except OSError:
+        return "unknown"
+    return f"{' / '.join(names) or 'unknown'} ({n} logical CPUs listed)"
+
+
 def cpu_baseline(case, budget_s=12.0, single_budget_s=8.0, config_ks=()):
     """The oracle, as it is, on this host: a bounded number of steps of the same workload, on
     all its OpenMP threads (`value`) and on one thread (`single_thread`, the paper's one-core
@@ -375,7 +422,7 @@ def cpu_baseline(case, budget_s=12.0, single_budget_s=8.0, config_ks=()):
         configs[f"config{k}"] = {"value": c.n_cells * c.steps / ek, "cores": nth,
                                  "sample": f"{c.n_cells} cells, all {c.steps} steps ({ek:.1f} s)"}
     return {"value": case.n_cells * steps / el, "unit": "cell-updates/s", "cores": nth,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{case.n_cells} cells, {steps} steps from the initial state "
                       f"({el:.1f} s on {nth} OpenMP threads; mesh build {build_s:.1f} s untimed)",
             "single_thread": {"value": case.n_cells * steps1 / el1, "cores": 1,
@@ -442,8 +489,8 @@ def main():
             print(f"# tuned {dt}: {tuning[dt]}", file=sys.stderr, flush=True)
         solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt,
                             exact=exact)
-        ms, rc, st = time_gpu(solver, args.steps, args.warmup, stream)
-        if rc != swe.SWE_OK or st["steps"] != args.warmup + args.steps:
+        ms, rc, st, warm, windows = time_gpu(solver, args.steps, args.warmup, stream)
+        if rc != swe.SWE_OK or st["steps"] != warm + 5 * args.steps:
             raise RuntimeError(f"{key}: run failed rc={rc} stats={st}")
         word = 8 if dt == "f64" else 4
         per_step_s = ms * 1e-3 / args.steps
@@ -452,6 +499,8 @@ def main():
         results[key] = {
             "value": case.n_cells * args.steps / (ms * 1e-3),
             "ms_per_step": ms / args.steps,
+            "window_ms_per_step": [w / args.steps for w in windows],
+            "warmup_steps_run": warm,
             "alg_bytes_per_step": alg,
             "achieved_GBps": alg / per_step_s / 1e9,
             "kernel": kernel,
@@ -470,7 +519,7 @@ def main():
     ensemble = {}
     if args.ensemble_steps > 0 and args.size == "full":
         for dt in args.dtypes.split(","):
-            ensemble[dt] = bench_ensemble(dt, args.ensemble_steps, 10, stream)
+            ensemble[dt] = bench_ensemble(dt, args.ensemble_steps, 16, stream)
             e = ensemble[dt]
             print(f"# ensemble {dt}: {e['n_cells']} cells in {e['scenarios']} scenarios, batched "
                   f"{e['batched_cell_updates_per_s'] / 1e9:.2f} G/s vs separate "

@@ -255,8 +255,10 @@ int32_t swe_step(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
 
 /*
  * n_steps steps (the host time loop of section 2.3) with no host round trip between them:
- * groups of 8 steps are captured once as a hipGraph (cached on the mesh, keyed by the
- * launch's arguments) and replayed; runs shorter than 16 steps launch step by step.  dt_seq:
+ * groups of 8 steps are captured once as a hipGraph (cached on the mesh, up to 8 graphs keyed
+ * by the launch's arguments, the least recently used replaced) and replayed, starting from
+ * buffer 0 (a state in buffer 1 takes one step on its own first); runs shorter than 16 steps
+ * launch step by step.  dt_seq:
  * NULL (CFL dt) or a device array of n_steps doubles replayed as the steps' dt (the t_end
  * clip still applies; not with SWE_SHARD).  out: NULL to only queue the work, or a stats
  * record: then the stream is synchronised, *out filled, and s->cur set to the buffer holding
@@ -454,8 +456,9 @@ typedef struct swe_tune_result {
 /*
  * Autotuning of the step launch (section 2.3's loops as GPU launches; the paper leaves the
  * mapping to the hardware open).  Times each variant x workgroup order for n_steps >= 2 steps
- * (graph replay, after 4 warm-up steps each) in three interleaved rounds, keeping each one's
- * best, on the initialised state s, which it advances by 16 + 12 n_steps steps at most (pass a
+ * (graph replay, after a warm-up of 16 steps each that captures its graph) in three
+ * interleaved rounds, keeping each one's best, on the initialised state s, which it advances by
+ * 64 + 12 n_steps steps at most (pass a
  * scratch state, or re-initialise afterwards).  Records the fastest for this device, the
  * params' dtype and the size class floor(log2 n_cells) in a process-wide table, keeping the
  * XCD-contiguous order unless the hardware order is more than 2 % faster (it moves fewer HBM

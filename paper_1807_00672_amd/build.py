@@ -33,19 +33,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(out: str = LIB, verbose: bool = False, extra=()) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc(), *FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-o", out + ".tmp", *srcs]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError(f"hipcc failed ({r.returncode})")
+        raise RuntimeError(f"hipcc failed ({r.returncode}): {' '.join(cmd[-3:])}")
     noise = [ln for ln in (r.stdout + r.stderr).splitlines()
              if ln.strip() and "packed-fp32-ops" not in ln and "target-feature" not in ln]
     if verbose and noise:
         sys.stderr.write("\n".join(noise) + "\n")
+
+
+def build(out: str = LIB, verbose: bool = False, extra=(), jobs: int = 8) -> str:
+    """Compile every source to an object (in parallel, in a temporary folder), then link."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    cc = hipcc()
+    flags = [f for f in FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="swe_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[cc, *flags, *extra, "-I", INCLUDE, "-I", CSRC, "-c", "-o", o,
+                 os.path.join(CSRC, s)] for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(cmds)))) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out + ".tmp", *objs], verbose)
     os.replace(out + ".tmp", out)
     return out
 

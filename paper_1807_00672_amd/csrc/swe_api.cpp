@@ -117,14 +117,32 @@ struct GraphKey {
     int device;
 };
 
-struct GraphCache {
+struct GraphEntry {
     GraphKey key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    ~GraphCache()
+    uint64_t used = 0;   // last use (GraphCache::tick); 0: empty
+    void clear()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        used = 0;
+    }
+};
+
+// A mesh's captured graphs, one per launch key (a state, a precision, a variant, a dt
+// sequence...), so that runs alternating between a few keys (several states on one mesh, the
+// tuner's candidates) replay their graphs instead of capturing again; the least recently used
+// entry gives way when all are taken.
+struct GraphCache {
+    static constexpr int kEntries = 8;
+    GraphEntry e[kEntries];
+    uint64_t tick = 0;
+    ~GraphCache()
+    {
+        for (GraphEntry &x : e) x.clear();
     }
 };
 
@@ -165,9 +183,20 @@ hipGraphExec_t step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const sw
     const GraphKey key = make_key(dm, p, s, dt_seq, n_seq, tl, remap, dev);
     swe_mesh *m = const_cast<swe_mesh *>(mesh);
     GraphCache *gc = static_cast<GraphCache *>(m->graph);
-    if (gc && memcmp(&gc->key, &key, sizeof(key)) == 0) return gc->exec;
-    delete gc;
-    m->graph = nullptr;
+    if (!gc) {
+        gc = new (std::nothrow) GraphCache();
+        if (!gc) return nullptr;   // no host memory for the cache: the caller launches step by step
+        m->graph = gc;
+    }
+    GraphEntry *slot = &gc->e[0];
+    for (GraphEntry &x : gc->e) {
+        if (x.used && memcmp(&x.key, &key, sizeof(key)) == 0) {
+            x.used = ++gc->tick;
+            return x.exec;
+        }
+        if (x.used < slot->used) slot = &x;   // an empty entry, else the least recently used
+    }
+    slot->clear();
     std::lock_guard<std::mutex> lk(g_capture_mu);
     if (!g_capture[dev] && hipStreamCreateWithFlags(&g_capture[dev], hipStreamNonBlocking) != hipSuccess) {
         g_capture[dev] = nullptr;
@@ -192,16 +221,10 @@ hipGraphExec_t step_graph(const swe_mesh *mesh, const swe_dev_mesh *dm, const sw
         (void)hipGetLastError();
         return nullptr;
     }
-    gc = new (std::nothrow) GraphCache();
-    if (!gc) {   // no host memory for the cache: the caller launches step by step
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        return nullptr;
-    }
-    gc->key = key;
-    gc->graph = graph;
-    gc->exec = exec;
-    m->graph = gc;
+    slot->key = key;
+    slot->graph = graph;
+    slot->exec = exec;
+    slot->used = ++gc->tick;
     return exec;
 }
 
@@ -268,6 +291,52 @@ int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_p
         d.prepared = static_cast<size_t>(d.limit);
     }
     *out = &mesh->tiles;
+    return SWE_OK;
+}
+
+}  // namespace swe
+
+namespace swe {
+
+int32_t run_steps(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                  swe_state *s, int64_t n_steps, const double *dt_seq, bool graphs, void *stream)
+{
+    if (int32_t rc = check_call(mesh, dm, p, s, "swe_run")) return rc;
+    if (n_steps < 0) return fail(SWE_EINVAL, "swe_run: n_steps < 0");
+    if (dt_seq && n_steps < 1) return fail(SWE_EINVAL, "swe_run: dt_seq needs n_steps >= 1");
+    if (dt_seq && (p->flags & SWE_SHARD))
+        return fail(SWE_EINVAL, "swe_run: a shard takes its dt from swe_shard_dt_combine");
+    const StepConfig cfg = make_config(mesh, p);
+    const TileLayout *tl = nullptr;
+    int remap = 1;
+    if (int32_t rc = choose_variant(mesh, dm, p, &tl, &remap, "swe_run")) return rc;
+    if (int32_t rc = check_hip(launch_run_begin(*s, dt_seq, stream), "swe_run")) return rc;
+    int64_t k = 0;
+    if (graphs && n_steps >= 2 * kGraphSteps) {
+        // graphs start from buffer 0, so one capture serves every run with these arguments: a
+        // state in buffer 1 takes one step on its own first
+        if (s->cur == 1) {
+            if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_steps,
+                                                   stream, tl, nullptr, remap),
+                                       "swe_run"))
+                return rc;
+            s->cur ^= 1;
+            k = 1;
+        }
+        if (hipGraphExec_t ex = step_graph(mesh, dm, p, cfg, s, dt_seq, n_steps, tl, remap)) {
+            for (; k + kGraphSteps <= n_steps; k += kGraphSteps)
+                if (int32_t rc = check_hip(hipGraphLaunch(ex, static_cast<hipStream_t>(stream)),
+                                           "swe_run"))
+                    return rc;
+        }
+    }
+    for (; k < n_steps; ++k) {
+        if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_steps,
+                                               stream, tl, nullptr, remap),
+                                   "swe_run"))
+            return rc;
+        s->cur ^= 1;
+    }
     return SWE_OK;
 }
 
@@ -344,32 +413,7 @@ int32_t swe_run(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *
                 swe_state *s, int64_t n_steps, const double *dt_seq, swe_run_stats *out,
                 void *stream)
 {
-    if (int32_t rc = check_call(mesh, dm, p, s, "swe_run")) return rc;
-    if (n_steps < 0) return fail(SWE_EINVAL, "swe_run: n_steps < 0");
-    if (dt_seq && n_steps < 1) return fail(SWE_EINVAL, "swe_run: dt_seq needs n_steps >= 1");
-    if (dt_seq && (p->flags & SWE_SHARD))
-        return fail(SWE_EINVAL, "swe_run: a shard takes its dt from swe_shard_dt_combine");
-    const StepConfig cfg = make_config(mesh, p);
-    const TileLayout *tl = nullptr;
-    int remap = 1;
-    if (int32_t rc = choose_variant(mesh, dm, p, &tl, &remap, "swe_run")) return rc;
-    if (int32_t rc = check_hip(launch_run_begin(*s, dt_seq, stream), "swe_run")) return rc;
-    int64_t k = 0;
-    if (n_steps >= 2 * kGraphSteps) {
-        if (hipGraphExec_t ex = step_graph(mesh, dm, p, cfg, s, dt_seq, n_steps, tl, remap)) {
-            for (; k + kGraphSteps <= n_steps; k += kGraphSteps)
-                if (int32_t rc = check_hip(hipGraphLaunch(ex, static_cast<hipStream_t>(stream)),
-                                           "swe_run"))
-                    return rc;
-        }
-    }
-    for (; k < n_steps; ++k) {
-        if (int32_t rc = check_hip(launch_step(p->dtype, *dm, cfg, *s, s->cur, dt_seq, n_steps,
-                                               stream, tl, nullptr, remap),
-                                   "swe_run"))
-            return rc;
-        s->cur ^= 1;
-    }
+    if (int32_t rc = run_steps(mesh, dm, p, s, n_steps, dt_seq, true, stream)) return rc;
     if (!out) return SWE_OK;
     return swe_read_stats(s, out, stream);
 }

@@ -418,6 +418,17 @@ int32_t swe_batch_run(const swe_batch *batch, const swe_batch_dev *dev,
     hipStream_t st = static_cast<hipStream_t>(stream);
     int64_t k = 0;
     if (n_steps >= 2 * kGraphSteps) {
+        // the graph starts from buffer 0 (one capture serves every run): a state in buffer 1
+        // takes one step on its own first
+        if (s->cur == 1) {
+            if (int32_t rc = bcheck_hip(launch_step(p->dtype, dev->mesh, cfg, *s, s->cur, nullptr,
+                                                    0, stream, tiled ? &batch->tiles : nullptr,
+                                                    &bl, (p->flags & SWE_NO_XCD_REMAP) ? 0 : 1),
+                                        "swe_batch_run"))
+                return rc;
+            s->cur ^= 1;
+            k = 1;
+        }
         if (hipGraphExec_t ex = batch_graph(batch, dev, p, cfg, s, tiled)) {
             for (; k + kGraphSteps <= n_steps; k += kGraphSteps)
                 if (int32_t rc = bcheck_hip(hipGraphLaunch(ex, st), "swe_batch_run")) return rc;

@@ -166,6 +166,11 @@ int launch_flux_eval(int dtype, bool fast_math, int64_t n, double g, double h_dr
 
 void set_error(const std::string &msg);
 
+// swe_run without the stats read: queue n_steps steps, replaying captured graphs where
+// `graphs` allows it (swe_api.cpp).
+int32_t run_steps(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                  swe_state *s, int64_t n_steps, const double *dt_seq, bool graphs, void *stream);
+
 // The step kernel a launch uses (swe_api.cpp): *tl = the mesh's tile layout for the tiled
 // kernel, nullptr for the per-cell one; *remap = 1 for the XCD-contiguous workgroup order.
 int32_t choose_variant(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,

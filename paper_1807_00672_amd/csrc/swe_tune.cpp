@@ -76,15 +76,16 @@ int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
     swe_params q[4];
     bool runs[4] = {false, false, false, false};
     // candidates in the order of ms_per_step: cell + remap, cell, tiled + remap, tiled; each
-    // warmed up (graph capture, first launches), then timed in kRounds interleaved rounds
-    // (best round kept) so that drift of the state or the clock favours none of them
+    // warmed up by a run that captures its graph (the mesh keeps one per candidate), then
+    // timed in kRounds interleaved rounds (best round kept) so that drift of the state or the
+    // clock favours none of them
     constexpr int kRounds = 3;
     for (int c = 0; c < 4 && rc == SWE_OK; ++c) {
         q[c] = *p;
         q[c].variant = c < 2 ? SWE_CELL : SWE_TILED;
         q[c].flags = (p->flags & ~SWE_NO_XCD_REMAP) | ((c & 1) ? SWE_NO_XCD_REMAP : 0);
         swe_run_stats stats;
-        const int32_t w = swe_run(mesh, dm, &q[c], s, 4, nullptr, &stats, stream);
+        const int32_t w = swe_run(mesh, dm, &q[c], s, 2 * kGraphSteps, nullptr, &stats, stream);
         if ((w == SWE_EUNSUPPORTED || w == SWE_EINVAL) && q[c].variant == SWE_TILED)
             continue;   // no tile arrays, or its LDS does not fit
         if (w != SWE_OK) rc = w;
