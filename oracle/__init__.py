@@ -14,6 +14,9 @@ Oracle functions and the passages of the paper they follow (section 2 of Zaoui 2
                     ensemble's inflow segments; boundary state read as critical or deeper flow)
   ``run``           explicit Euler steps of eq. 4 with CFL dt (Courant 0.7), friction
                     (S_f of eq. 1) and the host time loop of section 2.3
+  ``run_loss_sig``  the same steps with a replayed dt, the gauge misfit and a signature of
+                    the branches taken (finite differences are compared only between runs
+                    that took the same branches)
 """
 from __future__ import annotations
 
@@ -95,6 +98,10 @@ def _bind(L):
     L.om_run_loss.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.POINTER(_Params), C.c_long,
                               _dp, _ip, C.c_int, C.c_int, _dp, _dp]
     L.om_run_loss.restype = C.c_int
+    L.om_run_loss_sig.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.POINTER(_Params),
+                                  C.c_long, _dp, _ip, C.c_int, C.c_int, _dp, _dp,
+                                  C.POINTER(C.c_ulong)]
+    L.om_run_loss_sig.restype = C.c_int
     L.om_set_threads.argtypes = [C.c_int]
     L.om_get_threads.restype = C.c_int
     return L
@@ -278,6 +285,27 @@ def run_loss(mesh: Mesh, z, n, h, hu, hv, dt_seq, gauges, every, obs, g=9.81, h_
     if rc != OK:
         raise RuntimeError(f"oracle loss run failed: {rc}")
     return J.value
+
+
+def run_loss_sig(mesh: Mesh, z, n, h, hu, hv, dt_seq, gauges, every, obs, g=9.81, h_dry=1e-6,
+                 inflow_q=None) -> tuple[float, int]:
+    """The gauge misfit of a plain run with the replayed dt sequence and the run's branch
+    signature (a 64-bit hash of every branch every edge and cell took at every step): equal
+    signatures mark runs that took the same branches, between which the misfit is smooth."""
+    z, n = _d(z), _d(n)
+    h, hu, hv = _d(h).copy(), _d(hu).copy(), _d(hv).copy()
+    seq = _d(dt_seq)
+    gg = np.ascontiguousarray(gauges, dtype=np.int32)
+    ob = _d(obs)
+    p, _keep = _params(g, 0.7, h_dry, inflow_q)
+    J = C.c_double()
+    sig = C.c_ulong()
+    rc = lib().om_run_loss_sig(mesh._h, _ptr(z), _ptr(n), _ptr(h), _ptr(hu), _ptr(hv),
+                               C.byref(p), seq.size, _ptr(seq), gg.ctypes.data_as(_ip), gg.size,
+                               int(every), _ptr(ob), C.byref(J), C.byref(sig))
+    if rc != OK:
+        raise RuntimeError(f"oracle signature run failed: {rc}")
+    return J.value, int(sig.value)
 
 
 def observations(case, mesh: Mesh | None = None, steps=None):

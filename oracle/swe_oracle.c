@@ -232,23 +232,32 @@ void om_mesh_arrays(const om_mesh *m, int *cell_node, int *cell_nbr, double *are
 
 /* ------------------------------------------------------------------------- Riemann flux */
 
+/* The branches the last flux evaluation of this thread took (wave-speed case and min/max
+ * choices, flux region and contact side, reconstruction cases).  Recorded only: nothing reads
+ * them but the branch signature of a run (om_run_loss_sig), which tells whether two runs
+ * took the same branches everywhere. */
+static __thread unsigned om_branch;
+
 /* Wave-speed estimates S_L < S_R of the HLLC solver (section 2.2, ref. [6]) from the
  * reconstructed depths and normal velocities.  Returns 0 when both sides are dry. */
 int om_wave_speeds(double g, double hl, double ql, double hr, double qr, double *sl, double *sr)
 {
-    if (hl == 0.0 && hr == 0.0) { *sl = 0.0; *sr = 0.0; return 0; }
+    if (hl == 0.0 && hr == 0.0) { *sl = 0.0; *sr = 0.0; om_branch = 0u; return 0; }
     const double cl = sqrt(g * hl), cr = sqrt(g * hr);
     if (hl == 0.0) {            /* dry left: the right state's rarefaction reaches the dry bed */
         *sl = qr - 2.0 * cr;
         *sr = qr + cr;
+        om_branch = 1u;
     } else if (hr == 0.0) {     /* dry right */
         *sl = ql - cl;
         *sr = ql + 2.0 * cl;
+        om_branch = 2u;
     } else {                    /* two-rarefaction estimate of the star state */
         const double us = (ql + qr) / 2.0 + (cl - cr);
         const double cs = (cl + cr) / 2.0 + (ql - qr) / 4.0;
         *sl = fmin(ql - cl, us - cs);
         *sr = fmax(qr + cr, us + cs);
+        om_branch = 3u + (ql - cl <= us - cs ? 0u : 4u) + (qr + cr >= us + cs ? 0u : 8u);
     }
     return 1;
 }
@@ -273,8 +282,10 @@ void om_hllc_normal(double g, double hl, double ql, double wl, double hr, double
     double fh, fq, fw;
     if (sl >= 0.0) {
         fh = fhl; fq = fql; fw = fh * wl;
+        om_branch |= 16u;
     } else if (sr <= 0.0) {
         fh = fhr; fq = fqr; fw = fh * wr;
+        om_branch |= 32u;
     } else {
         const double den = sr - sl;
         fh = ((sr * fhl - sl * fhr) + sl * sr * (hr - hl)) / den;
@@ -283,6 +294,7 @@ void om_hllc_normal(double g, double hl, double ql, double wl, double hr, double
                              (hr * (qr - sr) - hl * (ql - sl));
         const double wup = sstar > 0.0 ? wl : (sstar < 0.0 ? wr : (wl + wr) / 2.0);
         fw = fh * wup;
+        om_branch |= sstar > 0.0 ? 64u : (sstar < 0.0 ? 128u : 192u);
     }
     *fh_out = fh; *fq_out = fq; *fw_out = fw;
 }
@@ -319,10 +331,15 @@ void om_interface(double g, double h_dry, double hl, double hul, double hvl, dou
     const double zs = fmax(zl, zr);
     double hsl = fmax(0.0, hl - (zs - zl));
     double hsr = fmax(0.0, hr - (zs - zr));
+    const unsigned rec = (zl > zr ? 1u : (zr > zl ? 2u : 3u)) |
+                         (hl - (zs - zl) < 0.0 ? 4u : 0u) | (hsl <= h_dry ? 8u : 0u) |
+                         (hr - (zs - zr) < 0.0 ? 16u : 0u) | (hsr <= h_dry ? 32u : 0u) |
+                         (hl > h_dry ? 64u : 0u) | (hr > h_dry ? 128u : 0u);
     if (hsl <= h_dry) hsl = 0.0;
     if (hsr <= h_dry) hsr = 0.0;
     om_hllc(g, hsl, om_vel(hl, hul, h_dry), om_vel(hl, hvl, h_dry), hsr,
             om_vel(hr, hur, h_dry), om_vel(hr, hvr, h_dry), nx, ny, f);
+    om_branch |= rec << 8;
     *pl = 0.5 * g * (hl * hl - hsl * hsl);
     *pr = 0.5 * g * (hr * hr - hsr * hsr);
 }
@@ -391,7 +408,10 @@ double om_cfl_dt(const om_mesh *m, const double *h, const double *hu, const doub
 }
 
 /* Workspace of one step: per-edge flux and side pressures. */
-typedef struct { double *f, *pl, *pr; } om_work;
+typedef struct {
+    double *f, *pl, *pr;
+    unsigned *ecode, *ccode;   /* NULL, or each edge's and cell's branches (om_run_loss_sig) */
+} om_work;
 
 /*
  * One explicit Euler step (eq. 4) of length dt: fluxes over all interfaces (section 2.3,
@@ -413,11 +433,15 @@ static void om_step(const om_mesh *m, const double *z, const double *n, double *
         } else if (r == OM_WALL) {
             om_wall(g, hd, h[l], hu[l], hv[l], m->edge_nx[e], m->edge_ny[e], f, &w->pl[e]);
             w->pr[e] = 0.0;
+            om_branch |= (h[l] > hd ? 1u : 2u) << 16;
         } else {
             om_inflow(g, p->inflow_q[-1 - r - 1], h[l], m->edge_nx[e], m->edge_ny[e], f);
             w->pl[e] = 0.0;
             w->pr[e] = 0.0;
+            om_branch = (h[l] >= cbrt(p->inflow_q[-1 - r - 1] * p->inflow_q[-1 - r - 1] / g)
+                             ? 4u : 8u) << 16;
         }
+        if (w->ecode) w->ecode[e] = om_branch;
     }
     long clamps = 0;
     double clamped = 0.0;
@@ -440,6 +464,7 @@ static void om_step(const om_mesh *m, const double *z, const double *n, double *
         double hs = h[c] - r * acc[0];
         const double hus = hu[c] - r * acc[1];
         const double hvs = hv[c] - r * acc[2];
+        if (w->ccode) w->ccode[c] = (hs < 0.0 ? 1u : 0u) | (hs > hd ? 2u : 0u);
         if (hs < 0.0) { ++clamps; clamped += -hs * m->area[c]; hs = 0.0; }
         if (hs > hd) {
             const double mag = sqrt(hus * hus + hvs * hvs);
@@ -474,6 +499,7 @@ int om_run(const om_mesh *m, const double *z, const double *n, double *h, double
     if (!(p->g > 0.0) || !(p->courant > 0.0) || !(p->courant <= 1.0) || !(p->h_dry >= 0.0))
         return OM_EINVAL;
     om_work w;
+    w.ecode = w.ccode = NULL;
     w.f = (double *)malloc(sizeof(double) * 3 * m->ne);
     w.pl = (double *)malloc(sizeof(double) * m->ne);
     w.pr = (double *)malloc(sizeof(double) * m->ne);
@@ -793,6 +819,58 @@ int om_run_tl(const om_mesh *m, const double *z, const double *zd, const double 
     *J = jv;
     *dJ = jd;
     free(Z); free(N); free(H); free(HU); free(HV); free(f); free(pl); free(pr);
+    return OM_OK;
+}
+
+/* A 64-bit mix of (step, index, branch code), summed by exclusive or over every edge and cell
+ * of every step: equal signatures mean, barring a collision, runs that took the same branches
+ * everywhere (the splitmix64 finaliser). */
+static unsigned long om_mix(unsigned long x)
+{
+    x ^= x >> 30; x *= 0xbf58476d1ce4e5b9ul;
+    x ^= x >> 27; x *= 0x94d049bb133111ebul;
+    return x ^ (x >> 31);
+}
+
+/* om_run_loss with the replayed dt sequence, plus the branch signature of the run: finite
+ * differences of the loss are compared with the adjoint only where the perturbed runs keep the
+ * base run's signature, i.e. away from switches. */
+int om_run_loss_sig(const om_mesh *m, const double *z, const double *n, double *h, double *hu,
+                    double *hv, const om_params *p, long nsteps, const double *dt_seq,
+                    const int *gauges, int ng, int every, const double *obs, double *J,
+                    unsigned long *sig)
+{
+    if (!(p->g > 0.0) || !(p->h_dry >= 0.0) || every < 1) return OM_EINVAL;
+    om_work w;
+    w.f = (double *)malloc(sizeof(double) * 3 * m->ne);
+    w.pl = (double *)malloc(sizeof(double) * m->ne);
+    w.pr = (double *)malloc(sizeof(double) * m->ne);
+    w.ecode = (unsigned *)malloc(sizeof(unsigned) * m->ne);
+    w.ccode = (unsigned *)malloc(sizeof(unsigned) * m->nt);
+    om_stats st;
+    memset(&st, 0, sizeof(st));
+    double jv = 0.0;
+    unsigned long sg = 0;
+    for (long s = 0; s < nsteps; ++s) {
+        om_step(m, z, n, h, hu, hv, p, dt_seq[s], &w, &st);
+        const unsigned long base = om_mix((unsigned long)s);
+#pragma omp parallel for reduction(^ : sg) schedule(static)
+        for (long e = 0; e < m->ne; ++e)
+            sg ^= om_mix(base ^ ((unsigned long)e << 24) ^ w.ecode[e]);
+#pragma omp parallel for reduction(^ : sg) schedule(static)
+        for (long c = 0; c < m->nt; ++c)
+            sg ^= om_mix(~base ^ ((unsigned long)c << 24) ^ w.ccode[c]);
+        if ((s + 1) % every == 0) {
+            const double *o = obs + ((s + 1) / every - 1) * (long)ng;
+            for (int q = 0; q < ng; ++q) {
+                const double r = h[gauges[q]] - o[q];
+                jv += r * r;
+            }
+        }
+    }
+    free(w.f); free(w.pl); free(w.pr); free(w.ecode); free(w.ccode);
+    *J = jv;
+    *sig = sg;
     return OM_OK;
 }
 

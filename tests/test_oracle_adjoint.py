@@ -131,3 +131,29 @@ def test_tangent_matches_friction_closed_form():
         assert J == pytest.approx(j_want, rel=1e-12)
         print(f"cell {c}: tangent {dJ!r}, closed form {want[c]!r}")
         assert dJ == pytest.approx(want[c], rel=1e-10, abs=1e-12 * np.abs(want).max())
+
+
+def test_branch_signature_marks_switches(setup):
+    """The signature of run_loss_sig is the same for repeated runs and for a perturbation too
+    small to flip any branch; it changes when a perturbation flips a branch (a dry cell raised
+    above the dry threshold, the bed tilted by more than the neighbouring beds' differences),
+    and it leaves the misfit of run_loss unchanged."""
+    case, mesh, dts, obs = setup
+    g = case.extra["gauges"]
+    base = (case.z, case.n, case.h, case.hu, case.hv)
+    j0, s0 = oracle.run_loss_sig(mesh, *base, dts, g, 10, obs)
+    assert j0 == oracle.run_loss(mesh, *base, dts, g, 10, obs)
+    assert oracle.run_loss_sig(mesh, *base, dts, g, 10, obs) == (j0, s0)
+    # a smooth perturbation: a gauge cell's roughness by 1e-8
+    n1 = case.n.copy()
+    n1[g[0]] += 1e-8
+    j1, s1 = oracle.run_loss_sig(mesh, case.z, n1, case.h, case.hu, case.hv, dts, g, 10, obs)
+    assert s1 == s0 and j1 != j0
+    # a dry cell made wet: its dry tests flip
+    dry = int(np.flatnonzero(case.h == 0.0)[0])
+    h2 = case.h.copy()
+    h2[dry] = 1e-3
+    assert oracle.run_loss_sig(mesh, case.z, case.n, h2, case.hu, case.hv, dts, g, 10, obs)[1] != s0
+    # a bed turned by more than its local differences: which side's bed is the higher flips
+    z3 = case.z - 2e-3 * gen.centroids(case.xy, case.tri)[:, 0]
+    assert oracle.run_loss_sig(mesh, z3, case.n, case.h, case.hu, case.hv, dts, g, 10, obs)[1] != s0
