@@ -478,6 +478,32 @@ int32_t swe_tune_get(int32_t device, int32_t dtype, int64_t n_cells, swe_tune_re
  * Errors: SWE_EINVAL (unknown variant, xcd_remap not 0 or 1). */
 int32_t swe_tune_set(int32_t device, int32_t dtype, int64_t n_cells, const swe_tune_result *r);
 
+/* ------------------------------------------------------------------ without allocation */
+
+/* Bytes of the device array that swe_run_static keeps per GPU in place of a workspace: enough
+ * for meshes with swe_workspace_bytes(n_cells) up to this size (about 67 million cells). */
+#define SWE_STATIC_WORK_BYTES 4194304
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture into a graph,
+ * serving loops that forbid allocation): swe_state_init (when init != 0, at t0 with t_end)
+ * followed by swe_run, in one call that uses no workspace.  s->work is ignored and may be NULL;
+ * the step partials and arrival counters live in a library-owned device array of
+ * SWE_STATIC_WORK_BYTES, one per GPU, looked up on the first call on each device and kept until
+ * the process ends.  The call allocates nothing: no hipMalloc, no graph instantiation (steps are
+ * launched one by one), no host-side device allocation by any library routine.  The caller still
+ * provides the state's buffers and control block.  Every call on one GPU shares its array, which
+ * keeps the last call's contents: the call clears what must start at zero, and calls whose work
+ * overlaps on one GPU (several streams or threads at once) race and give undefined results.
+ * The results are those of swe_state_init + swe_run with a workspace, bit for bit.  With
+ * out != NULL the stream is synchronised and the state's status returned, as by swe_run.
+ * Errors: SWE_EINVAL (as swe_state_init and swe_run, or a mesh whose partials exceed
+ * SWE_STATIC_WORK_BYTES), SWE_EDEVICE.
+ */
+int32_t swe_run_static(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
+                       swe_state *s, int32_t init, double t0, double t_end, int64_t n_steps,
+                       const double *dt_seq, swe_run_stats *out, void *stream);
+
 /* ------------------------------------------------------------------ test hook */
 
 /*

@@ -150,7 +150,7 @@ EXPORTS = [
     "swe_batch_export", "swe_batch_destroy", "swe_batch_workspace_bytes", "swe_batch_state_init",
     "swe_batch_run", "swe_adjoint_workspace_bytes", "swe_adjoint", "swe_adjoint_timings", "swe_tune", "swe_tune_get",
     "swe_tune_set", "swe_mesh_create_shard", "swe_halo_pack", "swe_halo_unpack",
-    "swe_shard_dt_combine",
+    "swe_shard_dt_combine", "swe_run_static",
 ]
 
 
@@ -173,6 +173,9 @@ def _load():
     L.swe_run.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
                           C.POINTER(swe_state), i64, vp, C.POINTER(swe_run_stats), vp]
     L.swe_read_stats.argtypes = [C.POINTER(swe_state), C.POINTER(swe_run_stats), vp]
+    L.swe_run_static.argtypes = [vp, C.POINTER(swe_dev_mesh), C.POINTER(swe_params),
+                                 C.POINTER(swe_state), i32, dbl, dbl, i64, vp,
+                                 C.POINTER(swe_run_stats), vp]
     L.swe_last_error.argtypes = []
     L.swe_last_error.restype = C.c_char_p
     L.swe_flux_eval.argtypes = [i32, i32, i64, dbl, dbl] + [vp] * 12 + [vp]
@@ -270,6 +273,17 @@ def swe_run(mesh, dm, params, state, n_steps: int, dt_seq=None, stats=None, stre
                      None if stats is None else C.byref(stats), stream)
     if rc in (SWE_EINVAL, SWE_EDEVICE, SWE_EMESH, SWE_EUNSUPPORTED):
         _check(rc, "swe_run")
+    return rc
+
+
+def swe_run_static(mesh, dm, params, state, n_steps: int, init: bool = False, t0=0.0,
+                   t_end=0.0, dt_seq=None, stats=None, stream=None) -> int:
+    """swe_state_init (init) and swe_run without a workspace; as swe_run otherwise."""
+    rc = lib.swe_run_static(mesh, C.byref(dm), C.byref(params), C.byref(state), 1 if init else 0,
+                            t0, t_end, n_steps, dt_seq, None if stats is None else C.byref(stats),
+                            stream)
+    if rc in (SWE_EINVAL, SWE_EDEVICE, SWE_EMESH, SWE_EUNSUPPORTED):
+        _check(rc, "swe_run_static")
     return rc
 
 

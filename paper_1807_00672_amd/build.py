@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libswe.so")
 
 SOURCES = ["swe_mesh.cpp", "swe_api.cpp", "swe_batch.cpp", "swe_tune.cpp", "swe_launch.cpp",
-           "swe_kernels.hip", "swe_kernels_fast.hip", "swe_adjoint.hip"]
+           "swe_kernels.hip", "swe_kernels_fast.hip", "swe_adjoint.hip", "swe_static.hip"]
 HEADERS = ["swe_internal.h", "swe_device_math.h"]
 
 # Contraction off: every product and sum rounds on its own, in the order the sources write
