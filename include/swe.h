@@ -63,8 +63,14 @@ extern "C" {
 #define SWE_EXACT 8u           /* flag: FP64 division and square root correctly rounded, the
                                   same bits as the host's IEEE operations in the same order;
                                   default: hardware-seeded Newton forms, within an ulp */
-#define SWE_TILE 256           /* cells per tile: consecutive mesh-order cells stepped by one
-                                  workgroup, which stages them and their neighbours in LDS */
+#define SWE_TILE 256           /* default cells per tile: consecutive mesh-order cells stepped
+                                  by one workgroup, which stages them and their neighbours in
+                                  LDS (the workgroup size of the step kernels) */
+#define SWE_TILE_64 16u        /* swe_mesh_create flag: tiles of 64 cells */
+#define SWE_TILE_128 32u       /* swe_mesh_create flag: tiles of 128 cells */
+#define SWE_TILE_512 64u       /* swe_mesh_create flag: tiles of 512 cells (none of the three
+                                  flags: SWE_TILE cells); swe_tune times a mesh's own size,
+                                  tune.tune_tiles builds one mesh per size and keeps the fastest */
 
 typedef struct swe_mesh swe_mesh;   /* host-side mesh object, owned by the library */
 
@@ -78,7 +84,7 @@ typedef struct swe_mesh_info {
     uint32_t flags;            /* flags given to swe_mesh_create */
     double min_area, max_area, total_area, min_inradius;
     double bbox[4];            /* xmin, ymin, xmax, ymax */
-    int64_t n_tiles;           /* ceil(T / SWE_TILE) */
+    int64_t n_tiles;           /* ceil(T / tile_cells) */
     int64_t n_halo;            /* total halo entries over all tiles */
     int64_t n_tile_edges;      /* total edge-list entries over all tiles */
     int32_t max_halo;          /* largest halo of a tile */
@@ -88,7 +94,7 @@ typedef struct swe_mesh_info {
     int64_t n_tile_nodes;      /* total node-list entries over all tiles; 0: no node lists
                                   (a tile has more than 256 nodes) */
     int32_t max_tile_nodes;    /* most distinct nodes of a tile's cells */
-    int32_t reserved;
+    int32_t tile_cells;        /* cells per tile: 64, 128, 256 or 512 (swe_mesh_create flags) */
 } swe_mesh_info;
 
 /* Arrays swe_mesh_export copies out (sizes in elements). */
@@ -105,10 +111,10 @@ enum swe_mesh_array {
     SWE_ARR_HALO = 6,      /* int32[n_halo]: cells outside a tile that neighbour it, ascending */
     SWE_ARR_EDGE_OFF = 7,  /* int32[n_tiles+1]: tile t's edges are EDGES[off[t] .. off[t+1]) */
     SWE_ARR_EDGES = 8,     /* uint32[n_tile_edges]: one per interface a tile evaluates:
-                              bits 0-7 owning cell a (tile-local), bits 8-9 a's local edge k,
-                              bits 10-11 b's local edge when b is a tile cell (else 0),
-                              bits 16-31 int16 b: tile-local cell (< SWE_TILE), halo slot
-                              SWE_TILE + j, or a boundary code (SWE_WALL, -1 - s) */
+                              bits 0-8 owning cell a (tile-local), bits 9-10 a's local edge k,
+                              bits 11-12 b's local edge when b is a tile cell (else 0),
+                              bits 16-31 int16 b: tile-local cell (< tile_cells), halo slot
+                              tile_cells + j, or a boundary code (SWE_WALL, -1 - s) */
     SWE_ARR_SLOT = 9,      /* uint16[3T], [k*T + i]: entry of cell i's local edge k in its
                               tile's edge list; bit 15 set when i is the edge's side b */
     SWE_ARR_GLOBAL = 10,   /* int32[T]: index of cell i in the mesh a shard was cut from
@@ -207,7 +213,9 @@ typedef struct swe_run_stats {
  * (v0, v2, v1)); edge_tag: host int32[3*nt] or NULL (all walls): for a boundary edge k of
  * triangle t (nodes k, k+1 of the input triangle), 0 = wall, s >= 1 = inflow segment s.
  * flags: SWE_MORTON, SWE_HILBERT or 0 (keep the input order); the curves run through the
- * centroids quantised to 16 bits per axis over the bounding box, ties keep the input order.
+ * centroids quantised to 16 bits per axis over the bounding box, ties keep the input order;
+ * plus at most one of SWE_TILE_64, SWE_TILE_128, SWE_TILE_512 (else tiles of SWE_TILE cells):
+ * the workgroup size of the step kernels, with the tile lists built for it.
  * On success *out owns a new mesh.
  * Errors: SWE_EINVAL (null pointer, nv < 3, nt < 1, sizes beyond int32, non-finite
  * coordinates, tag out of range), SWE_EMESH (repeated or out-of-range node, zero-area
@@ -226,7 +234,8 @@ int32_t swe_mesh_export(const swe_mesh *mesh, int32_t which, void *dst, int64_t 
 /* Free a mesh (NULL is ignored). */
 void swe_mesh_destroy(swe_mesh *mesh);
 
-/* Bytes of the device workspace a state of n_cells cells needs.  Errors: SWE_EINVAL. */
+/* Bytes of the device workspace a state of n_cells cells needs, whatever its mesh's tile size
+ * (it holds one partial result per tile of the smallest size).  Errors: SWE_EINVAL. */
 int32_t swe_workspace_bytes(int64_t n_cells, int64_t *bytes);
 
 /* ------------------------------------------------------------------ stepping (device) */
@@ -294,7 +303,7 @@ typedef struct swe_batch_info {
     int64_t n_cells, n_nodes, n_tiles, n_halo, n_tile_edges;
     int32_t max_halo, max_tile_edges;
     int64_t n_tile_nodes;          /* 0: a scenario has no node lists */
-    int32_t max_tile_nodes, reserved;
+    int32_t max_tile_nodes, tile_cells;   /* the scenarios' common tile size */
 } swe_batch_info;
 
 /* Arrays of a batch besides the concatenated SWE_ARR_* ones (which swe_batch_export also
@@ -326,8 +335,8 @@ typedef struct swe_batch_params {
     int32_t reserved;
 } swe_batch_params;
 
-/* Concatenate n built meshes (each keeps its own cell and node order).  The meshes may be
- * destroyed afterwards.  Errors: SWE_EINVAL. */
+/* Concatenate n built meshes (each keeps its own cell and node order), all of one tile size.
+ * The meshes may be destroyed afterwards.  Errors: SWE_EINVAL. */
 int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **out);
 int32_t swe_batch_info_get(const swe_batch *batch, swe_batch_info *out);
 /* Copy a SWE_ARR_* or SWE_BARR_* array of the batch to host memory.  Errors: SWE_EINVAL. */
@@ -451,6 +460,8 @@ typedef struct swe_tune_result {
     int32_t variant;         /* SWE_CELL or SWE_TILED; SWE_AUTO: nothing recorded */
     int32_t xcd_remap;       /* 1: XCD-contiguous tile order, 0: hardware order */
     double ms_per_step[4];
+    int32_t tile_cells;      /* tile size of the mesh timed (64, 128, 256 or 512); 0: unknown */
+    int32_t reserved;
 } swe_tune_result;
 
 /*
@@ -458,9 +469,11 @@ typedef struct swe_tune_result {
  * mapping to the hardware open).  Times each variant x workgroup order for n_steps >= 2 steps
  * (graph replay, after a warm-up of 16 steps each that captures its graph) in three
  * interleaved rounds, keeping each one's best, on the initialised state s, which it advances by
- * 64 + 12 n_steps steps at most (pass a
- * scratch state, or re-initialise afterwards).  Records the fastest for this device, the
- * params' dtype and the size class floor(log2 n_cells) in a process-wide table, keeping the
+ * 64 + 12 n_steps steps at most (pass a scratch state, or re-initialise afterwards).  The tile
+ * size is the mesh's (a mesh is built for one); comparing tile sizes takes one mesh per size,
+ * each tuned, and swe_tune_set of the fastest (tune.tune_tiles does that).  Records the fastest
+ * for this device, the params' dtype and the size class floor(log2 n_cells) in a process-wide
+ * table, with the mesh's tile size, keeping the
  * XCD-contiguous order unless the hardware order is more than 2 % faster (it moves fewer HBM
  * bytes at equal time).  SWE_AUTO then launches that choice (SWE_NO_XCD_REMAP still forces
  * the hardware order).  All candidates compute the same bits.  Synchronises the stream.
@@ -475,13 +488,15 @@ int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
 int32_t swe_tune_get(int32_t device, int32_t dtype, int64_t n_cells, swe_tune_result *out);
 
 /* Record a choice (e.g. one saved from an earlier process); variant SWE_AUTO erases it.
- * Errors: SWE_EINVAL (unknown variant, xcd_remap not 0 or 1). */
+ * Errors: SWE_EINVAL (unknown variant, xcd_remap not 0 or 1, tile_cells not 0, 64, 128, 256
+ * or 512). */
 int32_t swe_tune_set(int32_t device, int32_t dtype, int64_t n_cells, const swe_tune_result *r);
 
 /* ------------------------------------------------------------------ without allocation */
 
 /* Bytes of the device array that swe_run_static keeps per GPU in place of a workspace: enough
- * for meshes with swe_workspace_bytes(n_cells) up to this size (about 67 million cells). */
+ * for the step partials of about 262,000 tiles (67 million cells in tiles of 256, 16.7 million
+ * in tiles of 64). */
 #define SWE_STATIC_WORK_BYTES 4194304
 
 /*
@@ -497,8 +512,8 @@ int32_t swe_tune_set(int32_t device, int32_t dtype, int64_t n_cells, const swe_t
  * overlaps on one GPU (several streams or threads at once) race and give undefined results.
  * The results are those of swe_state_init + swe_run with a workspace, bit for bit.  With
  * out != NULL the stream is synchronised and the state's status returned, as by swe_run.
- * Errors: SWE_EINVAL (as swe_state_init and swe_run, or a mesh whose partials exceed
- * SWE_STATIC_WORK_BYTES), SWE_EDEVICE.
+ * Errors: SWE_EINVAL (as swe_state_init and swe_run, or a mesh whose partials, for its tile
+ * count, exceed SWE_STATIC_WORK_BYTES), SWE_EDEVICE.
  */
 int32_t swe_run_static(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params *p,
                        swe_state *s, int32_t init, double t0, double t_end, int64_t n_steps,

@@ -14,7 +14,8 @@ from ._abi import (  # noqa: F401
     swe_batch_state_init, swe_batch_workspace_bytes, swe_adjoint, swe_adjoint_timings, swe_adjoint_workspace_bytes,
     swe_grads, swe_loss, swe_tune, swe_tune_get, swe_tune_result, swe_tune_set,
     swe_mesh_create_shard, swe_halo_pack, swe_halo_unpack, swe_shard_dt_combine, SWE_SHARD,
-    SWE_ARR_GLOBAL, SWE_INDEX64, SWE_EXACT, SWE_HILBERT, swe_run_static)
+    SWE_ARR_GLOBAL, SWE_INDEX64, SWE_EXACT, SWE_HILBERT, SWE_TILE_64, SWE_TILE_128, SWE_TILE_512,
+    swe_run_static)
 from .solver import Batch, BatchSolver, Mesh, Solver  # noqa: F401
 from .adjoint import AdjointLoss, Calibration  # noqa: F401
 from . import tune  # noqa: F401

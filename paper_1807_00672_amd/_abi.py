@@ -38,6 +38,10 @@ SWE_SHARD = 2
 SWE_INDEX64 = 4
 SWE_EXACT = 8
 SWE_TILE = 256
+SWE_TILE_64, SWE_TILE_128, SWE_TILE_512 = 16, 32, 64
+TILE_FLAGS = {64: SWE_TILE_64, 128: SWE_TILE_128, 256: 0, 512: SWE_TILE_512}
+# packed edge-list entry: side a, a's local edge, b's local edge, side b (int16)
+EDGE_A_MASK, EDGE_KA_SHIFT, EDGE_KB_SHIFT = 0x1FF, 9, 11
 
 (SWE_ARR_PERM, SWE_ARR_NBR, SWE_ARR_C2N, SWE_ARR_XY, SWE_ARR_NODE_PERM, SWE_ARR_HALO_OFF,
  SWE_ARR_HALO, SWE_ARR_EDGE_OFF, SWE_ARR_EDGES, SWE_ARR_SLOT, SWE_ARR_GLOBAL, SWE_ARR_EDGE_VEC,
@@ -64,7 +68,7 @@ class swe_mesh_info(C.Structure):
                 ("n_tile_edges", C.c_int64), ("max_halo", C.c_int32),
                 ("max_tile_edges", C.c_int32), ("n_owned", C.c_int64),
                 ("n_tile_nodes", C.c_int64), ("max_tile_nodes", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("tile_cells", C.c_int32)]
 
 
 class swe_dev_mesh(C.Structure):
@@ -106,11 +110,12 @@ SWE_BARR_CELL_OFF, SWE_BARR_NODE_OFF, SWE_BARR_TILE_START, SWE_BARR_TILE_SCEN, \
 
 class swe_tune_result(C.Structure):
     _fields_ = [("variant", C.c_int32), ("xcd_remap", C.c_int32),
-                ("ms_per_step", C.c_double * 4)]
+                ("ms_per_step", C.c_double * 4), ("tile_cells", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {"variant": {SWE_AUTO: "auto", SWE_CELL: "cell", SWE_TILED: "tiled"}[self.variant],
-                "xcd_remap": bool(self.xcd_remap),
+                "xcd_remap": bool(self.xcd_remap), "tile": int(self.tile_cells),
                 "ms_per_step": {k: self.ms_per_step[i] for i, k in
                                 enumerate(("cell+remap", "cell", "tiled+remap", "tiled"))}}
 
@@ -119,7 +124,7 @@ class swe_batch_info(C.Structure):
                 ("n_cells", C.c_int64), ("n_nodes", C.c_int64), ("n_tiles", C.c_int64),
                 ("n_halo", C.c_int64), ("n_tile_edges", C.c_int64), ("max_halo", C.c_int32),
                 ("max_tile_edges", C.c_int32), ("n_tile_nodes", C.c_int64),
-                ("max_tile_nodes", C.c_int32), ("reserved", C.c_int32)]
+                ("max_tile_nodes", C.c_int32), ("tile_cells", C.c_int32)]
 
 
 class swe_batch_dev(C.Structure):

@@ -41,7 +41,23 @@ struct Vjp3 {
     double h, hu, hv;
 };
 
-__device__ __forceinline__ double vel(double h, double hq, double hd) { return h > hd ? div_nr(hq, h) : 0.0; }
+// Forward values are recomputed in the forms of the default FP64 step (one reciprocal per
+// divisor, lengths and unit normals from one reciprocal square root), so the branches taken
+// here are the forward run's.
+__device__ __forceinline__ double vel(double h, double hq, double hd)
+{
+    return h > hd ? hq * rcp_nr(h) : 0.0;
+}
+
+// Length and outward unit normal of an edge vector, as the step forms them.
+__device__ __forceinline__ void edge_normal_nr(double dx, double dy, double &nx, double &ny,
+                                               double &l)
+{
+    double il;
+    len_rcp_nr(dx * dx + dy * dy, l, il);
+    nx = quot_nr(dy, il, l);
+    ny = quot_nr(-dx, il, l);
+}
 
 // Cotangents of (hl, ql, wl, hr, qr, wr) from those of the edge-frame HLLC flux (fh, fq, fw).
 __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, double hr, double qr,
@@ -81,8 +97,9 @@ __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, doubl
     } else {
         const double den = sr - sl;
         const double dh = hr - hl, dq = hr * qr - hl * ql;
-        const double fh = div_nr((sr * fhl - sl * fhr) + sl * sr * dh, den);
-        const double fq = div_nr((sr * fql - sl * fqr) + sl * sr * dq, den);
+        const double rden = rcp_nr(den);
+        const double fh = quot_nr((sr * fhl - sl * fhr) + sl * sr * dh, rden, den);
+        const double fq = quot_nr((sr * fql - sl * fqr) + sl * sr * dq, rden, den);
         const double sstar = div_nr(sl * hr * (qr - sr) - sr * hl * (ql - sl),
                                     hr * (qr - sr) - hl * (ql - sl));
         const int sel = sstar > 0.0 ? 1 : (sstar < 0.0 ? 2 : 3);
@@ -307,8 +324,8 @@ __global__ __launch_bounds__(256) void flux_adjoint_kernel(AdjArgs a)
     for (int k = 0; k < 3; ++k) {
         const double2 p0 = p[k], p1 = p[k == 2 ? 0 : k + 1];
         const double dx = p1.x - p0.x, dy = p1.y - p0.y;
-        const double l = sqrt_nr(dx * dx + dy * dy);
-        const double nx = div_nr(dy, l), ny = div_nr(-dx, l);
+        double nx, ny, l;
+        edge_normal_nr(dx, dy, nx, ny, l);
         const int32_t j = a.nbr[k * T + i];
         Vjp3 u{0.0, 0.0, 0.0};
         if (j >= 0) {
@@ -345,16 +362,16 @@ struct AdjTiles {
 
 // LDS of the tiled flux adjoint: 7 words per staged cell (h, hu, hv, z and the cotangent
 // -dt/A mu of its contribution), 8 per edge-list entry (both sides' cotangents and bed terms).
-// Tiles of at most 2 SWE_TILE entries use a shared layout: [8 rows of SWE_TILE for entries
-// 0..SWE_TILE-1 | staged cells], the later entries written in 8 rows of SWE_TILE over the
-// staged cells once every interface has been differentiated; others [cells | 8 rows of M].
-inline bool tile_adj_shared(int64_t max_edges) { return max_edges <= 2 * SWE_TILE; }
+// Tiles of TB cells with at most 2 TB entries use a shared layout: [8 rows of TB for entries
+// 0..TB-1 | staged cells], the later entries written in 8 rows of TB over the staged cells
+// once every interface has been differentiated; others [cells | 8 rows of M].
+inline bool tile_adj_shared(int64_t tb, int64_t max_edges) { return max_edges <= 2 * tb; }
 
-inline size_t tile_adj_lds_bytes(int64_t max_halo, int64_t max_edges)
+inline size_t tile_adj_lds_bytes(int64_t tb, int64_t max_halo, int64_t max_edges)
 {
-    const size_t cells = 7 * static_cast<size_t>(SWE_TILE + max_halo);
-    if (tile_adj_shared(max_edges))
-        return 8 * (8 * static_cast<size_t>(SWE_TILE) + std::max(cells, 8 * static_cast<size_t>(SWE_TILE)));
+    const size_t cells = 7 * static_cast<size_t>(tb + max_halo);
+    if (tile_adj_shared(tb, max_edges))
+        return 8 * (8 * static_cast<size_t>(tb) + std::max(cells, 8 * static_cast<size_t>(tb)));
     return 8 * (cells + 8 * static_cast<size_t>(max_edges));
 }
 
@@ -364,27 +381,27 @@ inline size_t tile_adj_lds_bytes(int64_t max_halo, int64_t max_edges)
 // Work-items take edge-list and halo positions as the tiled step does (the wave with one
 // round of interfaces stages the halo; which wave it is turns with the tile).  Four waves per
 // SIMD: 128 VGPRs, and the shared layout's LDS.
-template <bool Shared>
-__global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, AdjTiles t)
+template <int TB, bool Shared>
+__global__ __launch_bounds__(TB, 4) void tile_flux_adjoint_kernel(AdjArgs a, AdjTiles t)
 {
     const int tile = blockIdx.x;
     if (tile >= t.n_tiles) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double *const lds = reinterpret_cast<double *>(smem);
-    const int ns = SWE_TILE + t.max_halo;
+    const int ns = TB + t.max_halo;
     // staged cells at cbase; edge-list entry q of row j at ebase + j estride + q (+ bshift from
-    // entry SWE_TILE on)
-    const int cbase = Shared ? 8 * SWE_TILE : 0;
+    // entry TB on)
+    const int cbase = Shared ? 8 * TB : 0;
     const int ebase = Shared ? 0 : 7 * ns;
-    const int estride = Shared ? SWE_TILE : t.max_edges;
-    const int bshift = Shared ? 7 * SWE_TILE : 0;
+    const int estride = Shared ? TB : t.max_edges;
+    const int bshift = Shared ? 7 * TB : 0;
     double *s_h = lds + cbase;
     double *s_hu = s_h + ns, *s_hv = s_hu + ns, *s_z = s_hv + ns;
     double *s_c0 = s_z + ns, *s_c1 = s_c0 + ns, *s_c2 = s_c1 + ns;
-    const int64_t T = a.T, s0 = static_cast<int64_t>(tile) * SWE_TILE;
+    const int64_t T = a.T, s0 = static_cast<int64_t>(tile) * TB;
     const int tid = threadIdx.x;
-    const int pt = (tid + 64 * (tile & 3)) & (SWE_TILE - 1);
-    const int ph = SWE_TILE - 1 - pt;
+    const int pt = (tid + 64 * (tile % (TB / 64))) & (TB - 1);
+    const int ph = TB - 1 - pt;
     const int64_t i = s0 + tid;
     const bool mine = i < T;
     const double dt = a.dt_seq[a.step], g = a.g, hd = a.hd;
@@ -411,7 +428,7 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     };
     if (mine) stage(tid, i, true);
     const int hb = t.halo_off[tile], he = t.halo_off[tile + 1];
-    for (int j = hb + ph; j < he; j += SWE_TILE) stage(SWE_TILE + (j - hb), t.halo[j], false);
+    for (int j = hb + ph; j < he; j += TB) stage(TB + (j - hb), t.halo[j], false);
     __syncthreads();
 
     // side a's (h, hu, hv) cotangent and bed term, then side b's for interfaces inside the tile
@@ -420,12 +437,12 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     };
     auto diff = [&](int e, EdgeAdj &o) {
         const uint32_t w = t.edges[e];
-        const int ca = static_cast<int>(w & 0xffu);
+        const int ca = static_cast<int>(w & kEdgeA);
         const int cb = static_cast<int16_t>(w >> 16);
         const double2 d = t.edge_vec[e];
         const double dx = d.x, dy = d.y;
-        const double l = sqrt_nr(dx * dx + dy * dy);
-        const double nx = div_nr(dy, l), ny = div_nr(-dx, l);
+        double nx, ny, l;
+        edge_normal_nr(dx, dy, nx, ny, l);
         const double ci[3] = {s_c0[ca], s_c1[ca], s_c2[ca]};
         Vjp3 u{0.0, 0.0, 0.0};
         double za_b = 0.0;
@@ -436,7 +453,7 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
             double zb_b;
             interface_vjp(g, hd, s_h[ca], s_hu[ca], s_hv[ca], s_z[ca], s_h[cb], s_hu[cb],
                           s_hv[cb], s_z[cb], nx, ny, l, ci, cj, u, za_b, ub, zb_b);
-            inner = cb < SWE_TILE;
+            inner = cb < TB;
             o.v[4] = ub.h;
             o.v[5] = ub.hu;
             o.v[6] = ub.hv;
@@ -453,7 +470,7 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
         return inner;
     };
     auto put = [&](int q, const EdgeAdj &o, bool inner) {
-        double *ed = lds + ebase + q + (q >= SWE_TILE ? bshift : 0);
+        double *ed = lds + ebase + q + (q >= TB ? bshift : 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) ed[r * estride] = o.v[r];
         if (inner) {
@@ -467,9 +484,9 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     EdgeAdj o;
     bool inner = false;
     int held = -1;
-    for (int q = pt; eb + q < ee; q += SWE_TILE) {
+    for (int q = pt; eb + q < ee; q += TB) {
         inner = diff(eb + q, o);
-        if (Shared && q >= SWE_TILE) {
+        if (Shared && q >= TB) {
             held = q;
             break;
         }
@@ -486,7 +503,7 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     for (int k = 0; k < 3; ++k) {
         const uint32_t sl = t.slot[k * T + i];
         const int q = static_cast<int>(sl & 0x7fffu);
-        const double *ed = lds + ebase + q + (q >= SWE_TILE ? bshift : 0) + ((sl & 0x8000u) ? 4 * estride : 0);
+        const double *ed = lds + ebase + q + (q >= TB ? bshift : 0) + ((sl & 0x8000u) ? 4 * estride : 0);
         lh += ed[0];
         lhu += ed[estride];
         lhv += ed[2 * estride];
@@ -496,6 +513,19 @@ __global__ __launch_bounds__(256, 4) void tile_flux_adjoint_kernel(AdjArgs a, Ad
     a.lou[i] = lhu;
     a.lov[i] = lhv;
     a.gz[i] += zb_sum;
+}
+
+// The tiled flux adjoint of a tile size and layout.
+using AdjKernel = void (*)(AdjArgs, AdjTiles);
+
+AdjKernel tile_adj_kernel(int tb, bool shared)
+{
+    switch (tb) {
+    case 64: return shared ? tile_flux_adjoint_kernel<64, true> : tile_flux_adjoint_kernel<64, false>;
+    case 128: return shared ? tile_flux_adjoint_kernel<128, true> : tile_flux_adjoint_kernel<128, false>;
+    case 512: return shared ? tile_flux_adjoint_kernel<512, true> : tile_flux_adjoint_kernel<512, false>;
+    default: return shared ? tile_flux_adjoint_kernel<256, true> : tile_flux_adjoint_kernel<256, false>;
+    }
 }
 
 // Misfit at an observation: the loss gains sum (h_g - obs_g)^2, summed in gauge order by one
@@ -569,7 +599,7 @@ namespace {
 
 // Whether the tiled flux adjoint's dynamic LDS limit has been raised on a device (per layout:
 // 0 not yet, 1 raised, -1 refused).
-int g_adj_lds[64][2] = {};
+int g_adj_lds[64][4][2] = {};   // device, tile size (64 << index), layout
 std::mutex g_adj_lds_mu;
 
 int32_t afail(int32_t code, const std::string &msg)
@@ -673,6 +703,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     cfg.n_cells = T;
     cfg.n_owned = T;
     cfg.fast = (p->flags & SWE_EXACT) ? 0 : 1;
+    cfg.tile = mesh->info.tile_cells;
     cfg.g = p->g;
     cfg.courant = p->courant > 0.0 && p->courant <= 1.0 ? p->courant : 0.7;
     cfg.h_dry = p->h_dry;
@@ -767,9 +798,10 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     memset(&at, 0, sizeof(at));
     size_t adj_lds = 0;
     bool adj_shared = false;
+    const int adj_tb = tl ? tl->tile : 0;
     if (tl && SWE_TILE_ADJOINT) {
-        const size_t need = tile_adj_lds_bytes(tl->max_halo, tl->max_edges);
-        adj_shared = tile_adj_shared(tl->max_edges);
+        const size_t need = tile_adj_lds_bytes(adj_tb, tl->max_halo, tl->max_edges);
+        adj_shared = tile_adj_shared(adj_tb, tl->max_edges);
         int dev = 0, max_lds = 65536;
         if (int32_t rc = ahip(hipGetDevice(&dev), W)) return rc;
         if (int32_t rc = ahip(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), W))
@@ -781,11 +813,10 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
             fits = false;
             if (dev >= 0 && dev < 64) {
                 std::lock_guard<std::mutex> lk(g_adj_lds_mu);
-                int &state = g_adj_lds[dev][adj_shared ? 1 : 0];
+                const int ti = adj_tb == 64 ? 0 : adj_tb == 128 ? 1 : adj_tb == 256 ? 2 : 3;
+                int &state = g_adj_lds[dev][ti][adj_shared ? 1 : 0];
                 if (state == 0) {
-                    const void *k = adj_shared
-                                        ? reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<true>)
-                                        : reinterpret_cast<const void *>(&tile_flux_adjoint_kernel<false>);
+                    const void *k = reinterpret_cast<const void *>(tile_adj_kernel(adj_tb, adj_shared));
                     state = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) ==
                                     hipSuccess
                                 ? 1
@@ -827,8 +858,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         a.lo = lout; a.lou = lout + S; a.lov = lout + 2 * S;
         a.h = un[0]; a.hu = un[1]; a.hv = un[2];
         if (adj_lds) {
-            (adj_shared ? tile_flux_adjoint_kernel<true> : tile_flux_adjoint_kernel<false>)
-                <<<dim3(static_cast<unsigned>(at.n_tiles)), 256, adj_lds, st>>>(a, at);
+            tile_adj_kernel(adj_tb, adj_shared)
+                <<<dim3(static_cast<unsigned>(at.n_tiles)), dim3(adj_tb), adj_lds, st>>>(a, at);
         } else {
             friction_adjoint_kernel<<<blocks, 256, 0, st>>>(a);
             flux_adjoint_kernel<<<blocks, 256, 0, st>>>(a);

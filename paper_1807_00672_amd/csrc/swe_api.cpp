@@ -83,6 +83,7 @@ StepConfig make_config(const swe_mesh *mesh, const swe_params *p)
     c.shard = (p->flags & SWE_SHARD) ? 1 : 0;
     c.index64 = (p->flags & SWE_INDEX64) ? 1 : 0;
     c.fast = (p->dtype == SWE_F64 && !(p->flags & SWE_EXACT)) ? 1 : 0;
+    c.tile = mesh->info.tile_cells;
     c.g = p->g;
     c.courant = p->courant;
     c.h_dry = p->h_dry;

@@ -106,6 +106,7 @@ StepConfig batch_config(const swe_batch *b, const swe_batch_params *p)
     c.n_cells = b->info.n_cells;
     c.n_owned = b->info.n_cells;
     c.fast = (p->dtype == SWE_F64 && !(p->flags & SWE_EXACT)) ? 1 : 0;
+    c.tile = b->tiles.tile;
     c.g = p->g;
     c.courant = p->courant;
     c.h_dry = p->h_dry;
@@ -243,8 +244,13 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
         b->scen_tile_off.assign(n + 1, 0);
         int64_t nt_total = 0, nh = 0, ne = 0, nn = 0;
         bool nodes = true;   // node lists only if every scenario has them
+        const int32_t tile = meshes[0]->info.tile_cells;
         for (int32_t s = 0; s < n; ++s) {
             const swe_mesh_info &mi = meshes[s]->info;
+            if (mi.tile_cells != tile) {
+                delete b;
+                return bfail(SWE_EINVAL, "swe_batch_create: the meshes have different tile sizes");
+            }
             b->cell_off[s + 1] = b->cell_off[s] + mi.n_cells;
             b->node_off[s + 1] = b->node_off[s] + mi.n_nodes;
             nt_total += mi.n_tiles;
@@ -298,7 +304,7 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
             }
             memcpy(&b->xy[2 * v0], m.xy.data(), sizeof(double) * 2 * m.info.n_nodes);
             for (int64_t t = 0; t < m.info.n_tiles; ++t) {
-                b->tile_start.push_back(static_cast<int32_t>(c0 + t * SWE_TILE));
+                b->tile_start.push_back(static_cast<int32_t>(c0 + t * tile));
                 b->tile_scen.push_back(s);
                 for (int32_t q = m.halo_off[t]; q < m.halo_off[t + 1]; ++q)
                     b->halo.push_back(static_cast<int32_t>(m.halo[q] + c0));
@@ -330,7 +336,8 @@ int32_t swe_batch_create(const swe_mesh *const *meshes, int32_t n, swe_batch **o
         b->tiles.n_tiles = nt_total;
         b->info.n_tile_nodes = static_cast<int64_t>(b->tile_nodes.size() / 2);
         b->tiles.max_nodes = nodes ? b->info.max_tile_nodes : 0;
-        b->tiles.pad = 0;
+        b->tiles.tile = tile;
+        b->info.tile_cells = tile;
     } catch (...) {
         delete b;
         return bfail(SWE_EINVAL, "swe_batch_create: out of host memory");

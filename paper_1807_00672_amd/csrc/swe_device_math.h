@@ -20,6 +20,43 @@ __device__ __forceinline__ double div_nr(double a, double b)
     return fma(rem, r, q);
 }
 
+// FP64 reciprocal by the hardware reciprocal refined by two Newton steps, for several
+// quotients by one divisor (each then a single product, within about an ulp); odd in b.
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+
+// a / b from ir = rcp_nr(b): the product refined by one residual step, within an ulp of the
+// quotient (nearly always the correctly rounded one); odd in a, and in b with ir.
+__device__ __forceinline__ double quot_nr(double a, double ir, double b)
+{
+    const double q = a * ir;
+    return fma(fma(-b, q, a), ir, q);
+}
+
+// Length l = sqrt(s) (within an ulp, residual-corrected as sqrt_nr) and its reciprocal
+// il = 1/l (within about an ulp) of a positive normal s, both from one hardware reciprocal
+// square root refined by Goldschmidt's iteration, g -> sqrt(s) and h -> 1/(2 sqrt(s)), and one
+// more step of h against the corrected root.
+__device__ __forceinline__ void len_rcp_nr(double s, double &l, double &il)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, s);
+    l = fma(d, h, g);
+    const double r2 = fma(-l, h, 0.5);
+    h = fma(h, r2, h);
+    il = h + h;
+}
+
 // FP64 square root by the hardware reciprocal square root refined by Goldschmidt's iteration
 // and one residual correction: within an ulp of the correctly rounded root; sqrt(0) = 0.
 __device__ __forceinline__ double sqrt_nr(double a)

@@ -29,7 +29,17 @@ static_assert(sizeof(Ctrl) <= SWE_CTRL_BYTES, "control block too large");
 
 enum : int32_t { kStatusNonFinite = 1, kStatusDry = 2, kStatusBadDt = 4 };
 
-constexpr int kBlock = SWE_TILE;     // cells per workgroup of the step kernels
+// Cells per tile (the workgroup size of the step kernels): a mesh's own choice among these.
+constexpr int kTileMin = 64, kTileMax = 512;
+inline bool valid_tile(int64_t tile)
+{
+    return tile == 64 || tile == 128 || tile == 256 || tile == 512;
+}
+
+// Packed edge-list entry (SWE_ARR_EDGES): bits 0-8 side a (tile-local), bits 9-10 a's local
+// edge, bits 11-12 b's local edge (b a tile cell), bits 16-31 side b as an int16.
+constexpr uint32_t kEdgeA = 0x1ffu;
+constexpr int kEdgeKa = 9, kEdgeKb = 11;
 
 constexpr int kGroup = 256;          // tiles whose partials one workgroup folds together
 
@@ -47,7 +57,7 @@ struct Partials {
     uint32_t *count;    // [n_groups(nb) + 1] arrivals per group, then of the groups
 };
 
-inline int64_t n_blocks(int64_t n_cells) { return (n_cells + kBlock - 1) / kBlock; }
+inline int64_t n_tiles_of(int64_t n_cells, int64_t tile) { return (n_cells + tile - 1) / tile; }
 inline int64_t n_groups(int64_t nb) { return (nb + kGroup - 1) / kGroup; }
 inline int64_t round256(int64_t b) { return ((b + 255) / 256) * 256; }
 
@@ -80,7 +90,11 @@ inline int64_t workspace_bytes_for_tiles(int64_t nb)
            round256((ng + 1) * 4);
 }
 
-inline int64_t workspace_bytes(int64_t n_cells) { return workspace_bytes_for_tiles(n_blocks(n_cells)); }
+// A state's workspace: room for the partials of the smallest tiles, so any mesh of n_cells fits.
+inline int64_t workspace_bytes(int64_t n_cells)
+{
+    return workspace_bytes_for_tiles(n_tiles_of(n_cells, kTileMin));
+}
 
 // Everything a launch needs besides the state: plain values, passed by value to kernels.
 struct StepConfig {
@@ -91,19 +105,21 @@ struct StepConfig {
     int32_t shard;     // 1: leave the next dt to swe_shard_dt_combine (SWE_SHARD)
     int32_t index64;   // 1: 64-bit index arithmetic in the tiled kernel (SWE_INDEX64)
     int32_t fast;      // 1: FP64 division and square root by Newton forms (not SWE_EXACT)
+    int32_t tile;      // cells per tile (the workgroup size of the step kernels)
+    int32_t pad;
     double inflow_q[SWE_MAX_INFLOW];
 };
 
 // Tile sizes of a mesh that the tiled step needs at launch.
 // Static LDS the tiled step kernels may use besides their dynamic LDS (the slot table and the
 // block reduction); the device's per-workgroup limit less this is what dynamic LDS may take.
-constexpr size_t kTileStaticLdsMax = 2048;
+constexpr size_t kTileStaticLdsMax = 4096;
 
 struct TileLayout {
     int64_t n_tiles;
     int32_t max_halo, max_edges;
     int32_t max_nodes;   // largest node list of a tile; 0: the mesh has no node lists
-    int32_t pad;
+    int32_t tile;        // cells per tile
 };
 
 // Device arrays of a batch of meshes stepped together (swe_batch_*).

@@ -19,6 +19,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "swe_device_math.h"
 #include "swe_internal.h"
@@ -111,13 +112,62 @@ __device__ __forceinline__ float sqrt_<float>(float a)
 }
 #endif
 
+// Fast forms (FP32, and FP64 outside SWE_EXACT): quotients by one divisor share its
+// reciprocal; an edge's length and reciprocal length come from one reciprocal square root; the
+// friction factor and the CFL bound are rearranged to one quotient each.  A velocity is the
+// momentum times the depth's reciprocal (within 1.5 ulp); the HLL fluxes and the unit normals,
+// where cancellation would magnify that, refine each product by one residual step (quot,
+// within an ulp, nearly always the correctly rounded quotient).  Every form is odd in the
+// arguments whose sign a mirrored interface flips, so the two sides of an interface still give
+// exact negatives.  SWE_EXACT keeps the plain definitions with correctly rounded division and
+// square root (the oracle's bits).
+template <typename R>
+constexpr bool kFastForms = sizeof(R) == 4 || SWE_F64_FAST;
+
+template <typename R>
+__device__ __forceinline__ R rcp_(R b);
+template <>
+__device__ __forceinline__ double rcp_<double>(double b)
+{
+    return rcp_nr(b);
+}
+template <>
+__device__ __forceinline__ float rcp_<float>(float b)
+{
+    return __builtin_amdgcn_rcpf(b);
+}
+
+// a / b from ir, the reciprocal of b: the product and, in FP64, one residual correction;
+// odd in a, and in b with ir.
+template <typename R>
+__device__ __forceinline__ R quot(R a, R ir, R b)
+{
+    if constexpr (sizeof(R) == 8) {
+        return quot_nr(a, ir, b);
+    } else {
+        return a * ir;   // as div_<float>
+    }
+}
+
 // ------------------------------------------------------------------------ flux pieces
 
-// Velocity of a cell: zero at or below the dry threshold.
+// Velocities of a cell: zero at or below the dry threshold.
 template <typename R>
-__device__ __forceinline__ R velocity(R h, R hq, R h_dry)
+__device__ __forceinline__ void velocities(R h, R hu, R hv, R h_dry, R &u, R &v)
 {
-    return h > h_dry ? div_(hq, h) : R(0);
+    if (h > h_dry) {
+        if constexpr (kFastForms<R>) {
+            const R ih = rcp_(h);
+            u = hu * ih;
+            v = hv * ih;
+        } else {
+            u = div_(hu, h);
+            v = div_(hv, h);
+        }
+    } else {
+        u = R(0);
+        v = R(0);
+    }
 }
 
 // Quotients with |num| below this fraction of |den| may round to zero; larger ones keep the
@@ -164,8 +214,16 @@ __device__ __forceinline__ void hllc_normal(R g, R hl, R ql, R wl, R hr, R qr, R
         fh = fhr; fq = fqr; fw = fh * wr;
     } else {
         const R den = sr - sl;
-        fh = div_((sr * fhl - sl * fhr) + sl * sr * (hr - hl), den);
-        fq = div_((sr * fql - sl * fqr) + sl * sr * (hr * qr - hl * ql), den);
+        const R nh = (sr * fhl - sl * fhr) + sl * sr * (hr - hl);
+        const R nq = (sr * fql - sl * fqr) + sl * sr * (hr * qr - hl * ql);
+        if constexpr (kFastForms<R>) {
+            const R rden = rcp_(den);
+            fh = quot(nh, rden, den);
+            fq = quot(nq, rden, den);
+        } else {
+            fh = div_(nh, den);
+            fq = div_(nq, den);
+        }
         // Only the sign of the contact speed S* = num / den is used.  In this branch a side is
         // wet, S_L < q_L and S_R > q_R, so den < 0 and S* has the sign of -num; the quotient
         // is formed only where it could underflow to zero.
@@ -206,9 +264,9 @@ __device__ __forceinline__ void interface_flux(R g, R hd, R hl, R ul, R vl, R zl
                                                R hvr, R zr, R nx, R ny, R &fh, R &fx, R &fy,
                                                R &p)
 {
-    R pr;
-    interface_flux_uv(g, hd, hl, ul, vl, zl, hr, velocity(hr, hur, hd), velocity(hr, hvr, hd),
-                      zr, nx, ny, fh, fx, fy, p, pr);
+    R pr, ur, vr;
+    velocities(hr, hur, hvr, hd, ur, vr);
+    interface_flux_uv(g, hd, hl, ul, vl, zl, hr, ur, vr, zr, nx, ny, fh, fx, fy, p, pr);
 }
 
 // Reflective wall (section 3): mirror ghost built in the edge frame (q -> -q, w kept), so the
@@ -240,6 +298,26 @@ __device__ __forceinline__ R inflow_flux(R g, R q_in, R h, R nx, R ny, R &fh, R 
     return div_(q_in, hb) + sqrt_(g * hb);
 }
 
+// Semi-implicit Manning friction (eq. 1's S_f, section 2.2) of a wet cell after the flux
+// update: D = 1 + dt g n^2 |q*| / (h*^2 cbrt(h*)), q = q* / D.
+template <typename R>
+__device__ __forceinline__ void friction(R g, R dt, R nm, R hs, R hus, R hvs, R &hun, R &hvn)
+{
+    const R mag = sqrt_(hus * hus + hvs * hvs);
+    const R x = dt * g * nm * nm * mag;
+    const R y = hs * hs * cbrt_(hs);
+    if constexpr (kFastForms<R>) {
+        // 1 / D = y / (y + x): one quotient for both components; D = 1 exactly when x = 0
+        const R rd = x > R(0) ? div_(y, y + x) : R(1);
+        hun = hus * rd;
+        hvn = hvs * rd;
+    } else {
+        const R d = R(1) + div_(x, y);
+        hun = div_(hus, d);
+        hvn = div_(hvs, d);
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ R inflow_speed(R g, R q_in, R h)
 {
@@ -259,6 +337,22 @@ struct CellGeom {
     R nx[3], ny[3], l[3];
 };
 
+// Length and outward unit normal (dy, -dx) / l of an edge vector; odd in (dx, dy).
+template <typename R>
+__device__ __forceinline__ void edge_normal(R dx, R dy, R &nx, R &ny, R &l)
+{
+    if constexpr (sizeof(R) == 8 && kFastForms<R>) {
+        R il;
+        len_rcp_nr(dx * dx + dy * dy, l, il);
+        nx = quot(dy, il, l);
+        ny = quot(-dx, il, l);
+    } else {
+        l = sqrt_(dx * dx + dy * dy);
+        nx = div_(dy, l);
+        ny = div_(-dx, l);
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void cell_geometry(const double2 *__restrict__ xy, int32_t n0,
                                               int32_t n1, int32_t n2, CellGeom<R> &gm)
@@ -268,11 +362,8 @@ __device__ __forceinline__ void cell_geometry(const double2 *__restrict__ xy, in
     const double ey[3] = {p1.y - p0.y, p2.y - p1.y, p0.y - p2.y};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const R dx = static_cast<R>(ex[k]), dy = static_cast<R>(ey[k]);
-        const R l = sqrt_(dx * dx + dy * dy);
-        gm.nx[k] = div_(dy, l);
-        gm.ny[k] = div_(-dx, l);
-        gm.l[k] = l;
+        edge_normal<R>(static_cast<R>(ex[k]), static_cast<R>(ey[k]), gm.nx[k], gm.ny[k],
+                       gm.l[k]);
     }
 }
 
@@ -300,38 +391,41 @@ __device__ __forceinline__ int wave_or(int v)
     return v;
 }
 
-// Block-wide (kBlock work-items) min / sum / or; thread 0 writes them as partials[slot].
+// Block-wide (TB work-items) min of the CFL bounds, count of clamps and status of a
+// step; thread 0 writes them as partials[slot].  A work-item's flag is 0 or
+// kStatusNonFinite and its clamp 0 or 1, so one integer sum carries both: clamps in the low
+// 16 bits, flagged work-items above them.
+template <int TB>
 __device__ __forceinline__ void block_partials_at(double dtc, int clamp, int flag,
                                                   const Partials &part, int slot)
 {
-    __shared__ double s_dt[kBlock / 64];
-    __shared__ int s_cl[kBlock / 64], s_fl[kBlock / 64];
+    static_assert(TB < (1 << 16), "clamp count must fit 16 bits");
+    __shared__ double s_dt[TB / 64];
+    __shared__ int s_cf[TB / 64];
     dtc = wave_min(dtc);
-    clamp = wave_sum(clamp);
-    flag = wave_or(flag);
+    int cf = wave_sum(clamp + (flag ? (1 << 16) : 0));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
         s_dt[wv] = dtc;
-        s_cl[wv] = clamp;
-        s_fl[wv] = flag;
+        s_cf[wv] = cf;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / 64; ++w) {
+        for (int w = 1; w < TB / 64; ++w) {
             dtc = fmin(dtc, s_dt[w]);
-            clamp += s_cl[w];
-            flag |= s_fl[w];
+            cf += s_cf[w];
         }
         part.dt[slot] = dtc;
-        part.clamps[slot] = clamp;
-        part.flags[slot] = flag;
+        part.clamps[slot] = cf & 0xffff;
+        part.flags[slot] = (cf >> 16) != 0 ? kStatusNonFinite : 0;
     }
 }
 
+template <int TB>
 __device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
                                                const Partials &part)
 {
-    block_partials_at(dtc, clamp, flag, part, blockIdx.x);
+    block_partials_at<TB>(dtc, clamp, flag, part, blockIdx.x);
 }
 
 // Account for the step just taken (m: min CFL bound over the cells, cl: clamps, fl: status
@@ -394,11 +488,11 @@ struct Advance {
 // arrived.
 // Fuse selects this at compile time: the kernels without it run measurably faster on large
 // grids even though the branch is never taken there.
-template <bool Fuse>
+template <int TB, bool Fuse>
 __device__ __forceinline__ void finish_step(double dtc, int clamp, int flag, const Partials &part,
                                             int slot, int n_tiles, const Advance &adv)
 {
-    block_partials_at(dtc, clamp, flag, part, slot);
+    block_partials_at<TB>(dtc, clamp, flag, part, slot);
     if constexpr (Fuse) {
     if (!adv.ctrl || threadIdx.x >= 64) return;
     // wave 0 only; work-item 0 wrote the partial
@@ -433,19 +527,39 @@ template <typename R>
 __device__ __forceinline__ R cell_dt(R g, R hd, R h, R hu, R hv, R inradius, const int32_t *nb,
                                      const StepConfig &cfg, const double *qtab = nullptr)
 {
-    R s = R(0);
-    if (h > hd) {
-        const R u = div_(hu, h), v = div_(hv, h);
-        s = sqrt_(u * u + v * v) + sqrt_(g * h);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (nb[k] < SWE_WALL) {
-            const double q = qtab ? qtab[-2 - nb[k]] : cfg.inflow_q[-2 - nb[k]];
-            const R sb = inflow_speed(g, static_cast<R>(q), h);
-            if (sb > s) s = sb;
+    if constexpr (kFastForms<R>) {
+        // r / (|u| + sqrt(g h)) as r h / (|(hu, hv)| + h sqrt(g h)): one quotient; the
+        // inflow speeds compare scaled by h alike
+        const bool wet = h > hd;
+        R num = inradius, s = R(0);
+        if (wet) {
+            num = inradius * h;
+            s = sqrt_(hu * hu + hv * hv) + h * sqrt_(g * h);
         }
-    return s > R(0) ? div_(inradius, s) : static_cast<R>(kInf);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (nb[k] < SWE_WALL) {
+                const double q = qtab ? qtab[-2 - nb[k]] : cfg.inflow_q[-2 - nb[k]];
+                R sb = inflow_speed(g, static_cast<R>(q), h);
+                if (wet) sb = sb * h;
+                if (sb > s) s = sb;
+            }
+        return s > R(0) ? div_(num, s) : static_cast<R>(kInf);
+    } else {
+        R s = R(0);
+        if (h > hd) {
+            const R u = div_(hu, h), v = div_(hv, h);
+            s = sqrt_(u * u + v * v) + sqrt_(g * h);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (nb[k] < SWE_WALL) {
+                const double q = qtab ? qtab[-2 - nb[k]] : cfg.inflow_q[-2 - nb[k]];
+                const R sb = inflow_speed(g, static_cast<R>(q), h);
+                if (sb > s) s = sb;
+            }
+        return s > R(0) ? div_(inradius, s) : static_cast<R>(kInf);
+    }
 }
 
 // Where a workgroup's cells live when several meshes (scenarios) are stepped together: tile t
@@ -503,8 +617,8 @@ struct StepArgs {
 };
 
 // One explicit step for every cell (eq. 4 with the source treatments of section 2.2).
-template <typename R, bool Fuse>
-__global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a, StepConfig cfg,
+template <typename R, int TB, bool Fuse>
+__global__ __launch_bounds__(TB, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a, StepConfig cfg,
                                                                    Batch bt)
 {
     const int tile = xcd_tile(blockIdx.x, bt.n_tiles, bt.remap);
@@ -515,8 +629,8 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
     const double *qtab = batched ? bt.q_table + scen * SWE_MAX_INFLOW : nullptr;
     if (!a.dt_direct && ctrl->done) return;   // uniform over the workgroup: its state stopped
     const int64_t T = cfg.n_cells;
-    const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
-    const int64_t s1 = batched ? bt.tile_start[tile + 1] : s0 + kBlock;
+    const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * TB;
+    const int64_t s1 = batched ? bt.tile_start[tile + 1] : s0 + TB;
     const int64_t i = s0 + threadIdx.x;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
     const R dt = static_cast<R>(a.dt_direct ? *a.dt_direct : ctrl->dt);
@@ -526,7 +640,8 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         CellGeom<R> gm;
         cell_geometry<R>(a.xy, a.c2n[i], a.c2n[T + i], a.c2n[2 * T + i], gm);
         const R h = a.h[i], hu = a.hu[i], hv = a.hv[i], z = a.z[i];
-        const R u = velocity(h, hu, hd), v = velocity(h, hv, hd);
+        R u, v;
+        velocities(h, hu, hv, hd, u, v);
         int32_t nb[3];
         R acc0 = R(0), acc1 = R(0), acc2 = R(0);
 #pragma unroll
@@ -571,11 +686,7 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         }
         R hun, hvn;
         if (hs > hd) {
-            const R nm = a.n[i];
-            const R mag = sqrt_(hus * hus + hvs * hvs);
-            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt_(hs));
-            hun = div_(hus, d);
-            hvn = div_(hvs, d);
+            friction(g, dt, a.n[i], hs, hus, hvs, hun, hvn);
         } else {
             hun = R(0);
             hvn = R(0);
@@ -592,7 +703,7 @@ __global__ __launch_bounds__(kBlock, SWE_CELL_WAVES) void step_kernel(StepArgs<R
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step<Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv);
+    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv);
 }
 
 // ------------------------------------------------------------------------ tiled step
@@ -651,52 +762,57 @@ struct TileArgs {
 };
 
 // LDS of the tiled step: the tile + halo states (h, u, v, z) and five values per edge-list
-// entry (side a's contribution and side b's momentum part; side b's mass part is -a's).
-// Plain layout: [states | 5 rows of max_edges].  Shared layout (at most 2 kBlock entries):
-// [5 rows of kBlock for entries 0..kBlock-1 | states], the entries from kBlock on written in
-// 5 rows of kBlock over the states once every interface of the tile has been evaluated.  An
-// FP64 step with node lists (shared layout only: a tile of at most 256 nodes has at most 511
+// entry (side a's contribution and side b's momentum contribution; side b's mass part is
+// -a's).
+// Plain layout: [states | 5 rows of max_edges].  Shared layout (at most 2 TB entries, TB the
+// tile's cells): [5 rows of TB for entries 0..TB-1 | states], the entries from TB on written in
+// 5 rows of TB over the states once every interface of the tile has been evaluated.  An FP64
+// step with node lists (shared layout only: a tile of at most 256 nodes has at most 511
 // interfaces) appends the tile's nodes, (x, y) each; the layout's words before them are even.
 inline size_t tile_lds_nodes(size_t word, int64_t max_nodes)
 {
     return word == 8 && max_nodes > 0 ? 16 * static_cast<size_t>(max_nodes) : 0;
 }
 
-inline size_t tile_lds_plain(size_t word, int64_t max_halo, int64_t max_edges)
+inline size_t tile_lds_plain(size_t word, int64_t tb, int64_t max_halo, int64_t max_edges)
 {
-    return 4 * word * static_cast<size_t>(kBlock + max_halo) +
+    return 4 * word * static_cast<size_t>(tb + max_halo) +
            5 * word * static_cast<size_t>(max_edges);
 }
 
-inline size_t tile_lds_shared(size_t word, int64_t max_halo, int64_t max_nodes)
+inline size_t tile_lds_shared(size_t word, int64_t tb, int64_t max_halo, int64_t max_nodes)
 {
-    return word * (5 * static_cast<size_t>(kBlock) +
-                   std::max(4 * static_cast<size_t>(kBlock + max_halo), 5 * static_cast<size_t>(kBlock))) +
+    return word * (5 * static_cast<size_t>(tb) +
+                   std::max(4 * static_cast<size_t>(tb + max_halo), 5 * static_cast<size_t>(tb))) +
            tile_lds_nodes(word, max_nodes);
 }
 
-// The shared layout costs one more barrier per tile; take it only where the plain layout
-// limits a CU (160 KiB of LDS, four waves per workgroup) to fewer than eight waves per SIMD
-// and the shared one fits more workgroups.  FP64 only: FP32 tiles of the meshes built here
-// reach eight waves in the plain layout.
 // Static LDS of the tiled step besides: its slot table and the block reduction's partials.
-constexpr size_t kTileStaticLds = 3 * kBlock * sizeof(uint16_t) + 64;
-static_assert(kTileStaticLds <= kTileStaticLdsMax, "static LDS beyond the allowance");
+constexpr size_t tile_static_lds(int64_t tb) { return 3 * static_cast<size_t>(tb) * sizeof(uint16_t) + 64; }
+static_assert(tile_static_lds(kTileMax) <= kTileStaticLdsMax, "static LDS beyond the allowance");
 
-inline bool tile_alias(size_t word, int64_t max_halo, int64_t max_edges, int64_t max_nodes)
+// The shared layout costs one more barrier per tile; take it only where the plain layout
+// limits a CU (160 KiB of LDS) to fewer than eight waves per SIMD and the shared one fits
+// more workgroups.  FP64 only: FP32 tiles of the meshes built here reach eight waves in the
+// plain layout.
+inline bool tile_alias(size_t word, int64_t tb, int64_t max_halo, int64_t max_edges,
+                       int64_t max_nodes)
 {
-    if (!SWE_TILE_ALIAS || word != 8 || max_edges > 2 * kBlock) return false;
+    if (!SWE_TILE_ALIAS || word != 8 || max_edges > 2 * tb) return false;
     constexpr size_t kLdsPerCu = 160 * 1024;
-    const size_t plain = kLdsPerCu / (tile_lds_plain(word, max_halo, max_edges) + kTileStaticLds);
-    const size_t shared = kLdsPerCu / (tile_lds_shared(word, max_halo, max_nodes) + kTileStaticLds);
-    return plain < 8 && shared > plain;
+    const size_t st = tile_static_lds(tb);
+    const size_t plain = kLdsPerCu / (tile_lds_plain(word, tb, max_halo, max_edges) + st);
+    const size_t shared = kLdsPerCu / (tile_lds_shared(word, tb, max_halo, max_nodes) + st);
+    // waves per SIMD: workgroups per CU x (tb / 64) waves over 4 SIMDs
+    return plain * static_cast<size_t>(tb) < 8 * 256 && shared > plain;
 }
 
-inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges, int64_t max_nodes)
+inline size_t tile_lds_bytes(size_t word, int64_t tb, int64_t max_halo, int64_t max_edges,
+                             int64_t max_nodes)
 {
-    return tile_alias(word, max_halo, max_edges, max_nodes)
-               ? tile_lds_shared(word, max_halo, max_nodes)
-               : tile_lds_plain(word, max_halo, max_edges);
+    return tile_alias(word, tb, max_halo, max_edges, max_nodes)
+               ? tile_lds_shared(word, tb, max_halo, max_nodes)
+               : tile_lds_plain(word, tb, max_halo, max_edges);
 }
 
 // One explicit step, tiled.  Every global load of the workgroup is issued up front: the own
@@ -712,9 +828,9 @@ inline size_t tile_lds_bytes(size_t word, int64_t max_halo, int64_t max_edges, i
 // round's results wait in registers until every work-item has read the states they replace.
 // Phase 3 sums each cell's three contributions in local-edge order and applies the update of
 // eq. 4, the clamp, the friction and the next CFL bound, as the per-cell kernel does.
-template <typename R, bool O32, bool Fuse, bool Shared, bool Nodes>
-__global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
-                                                           Batch bt)
+template <typename R, int TB, bool O32, bool Fuse, bool Shared, bool Nodes>
+__global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
+                                                                       Batch bt)
 {
     static_assert(!Nodes || (sizeof(R) == 8 && Shared), "node lists serve the shared FP64 layout");
     const StepArgs<R> &a = ta.s;
@@ -727,14 +843,14 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     if (!a.dt_direct && ctrl->done) return;   // uniform over the workgroup: its scenario stopped
     extern __shared__ __align__(16) unsigned char smem[];
     R *const lds = reinterpret_cast<R *>(smem);
-    const int ns = kBlock + ta.max_halo;
+    const int ns = TB + ta.max_halo;
     // word offsets: states, and edge-list entry q of row j at ebase + j estride + q (+ bshift
-    // from entry kBlock on)
+    // from entry TB on)
     constexpr bool alias = Shared;
-    const int sbase = alias ? 5 * kBlock : 0;
+    const int sbase = alias ? 5 * TB : 0;
     const int ebase = alias ? 0 : 4 * ns;
-    const int estride = alias ? kBlock : ta.max_edges;
-    const int bshift = alias ? 4 * kBlock : 0;
+    const int estride = alias ? TB : ta.max_edges;
+    const int bshift = alias ? 4 * TB : 0;
     R *s_h = lds + sbase;
     R *s_u = s_h + ns;
     R *s_v = s_u + ns;
@@ -742,24 +858,24 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     // Nodes (FP64 with node lists): the tile's nodes after the layout's other words (an even
     // count, so 16-byte aligned), each entry's edge vector formed from them
     constexpr bool nodes = Nodes;
-    double2 *const s_nd = reinterpret_cast<double2 *>(lds + 5 * kBlock + max(4 * ns, 5 * kBlock));
+    double2 *const s_nd = reinterpret_cast<double2 *>(lds + 5 * TB + max(4 * ns, 5 * TB));
     // each tile cell's local edge k -> its edge-list entry (bit 15: the cell is side b),
     // filled from the edge list in phase 2
-    __shared__ uint16_t s_slot[3 * kBlock];
+    __shared__ uint16_t s_slot[3 * TB];
 
     const int64_t T = cfg.n_cells;
-    const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * kBlock;
-    const int64_t s1 = batched ? bt.tile_start[tile + 1] : s0 + kBlock;
+    const int64_t s0 = batched ? bt.tile_start[tile] : static_cast<int64_t>(tile) * TB;
+    const int64_t s1 = batched ? bt.tile_start[tile + 1] : s0 + TB;
     const int tid = threadIdx.x;
     const int64_t i = s0 + tid;
     const bool mine = i < s1 && i < T;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
     const R dt = static_cast<R>(a.dt_direct ? *a.dt_direct : ctrl->dt);
     // Work-item positions in the edge list (pt) and the halo list (ph).  About 1.7 interfaces
-    // per cell leave one wave of four a single round of phase 2; the halo loads go to that
-    // wave, and which wave it is turns with the tile, so that no SIMD idles through a round.
-    const int pt = (tid + 64 * (tile & 3)) & (kBlock - 1);
-    const int ph = kBlock - 1 - pt;
+    // per cell leave some waves a single round of phase 2; the halo loads go to those waves,
+    // and which waves they are turns with the tile, so that no SIMD idles through a round.
+    const int pt = (tid + 64 * (tile % (TB / 64))) & (TB - 1);
+    const int ph = TB - 1 - pt;
 
     // global loads: own cell
     R h = R(0), hu = R(0), hv = R(0), zc = R(0), nm = R(0), area = R(0), inradius = R(1);
@@ -776,7 +892,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     typename Vec2<R>::type ev[2] = {{R(0), R(0)}, {R(0), R(0)}};
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-        const int e = eb + pt + it * kBlock;
+        const int e = eb + pt + it * TB;
         if (e < ee) {
             ew[it] = ld<O32>(ta.edges, e);
             if (nodes)
@@ -791,19 +907,23 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     if (node_mine) nd = ld<O32>(ta.tile_nodes, nb0 + tid);
     // phase 1: halo and own cell into LDS
     const int hb = ta.halo_off[tile], he = ta.halo_off[tile + 1];
-    for (int j = hb + ph; j < he; j += kBlock) {
+    for (int j = hb + ph; j < he; j += TB) {
         const int32_t c = ld<O32>(ta.halo, j);
         const R hh = ld<O32>(a.h, c);
-        const int q = kBlock + (j - hb);
+        const int q = TB + (j - hb);
         s_h[q] = hh;
-        s_u[q] = velocity(hh, ld<O32>(a.hu, c), hd);
-        s_v[q] = velocity(hh, ld<O32>(a.hv, c), hd);
+        R uu, vv;
+        velocities(hh, ld<O32>(a.hu, c), ld<O32>(a.hv, c), hd, uu, vv);
+        s_u[q] = uu;
+        s_v[q] = vv;
         s_z[q] = ld<O32>(a.z, c);
     }
     if (mine) {
         s_h[tid] = h;
-        s_u[tid] = velocity(h, hu, hd);
-        s_v[tid] = velocity(h, hv, hd);
+        R uu, vv;
+        velocities(h, hu, hv, hd, uu, vv);
+        s_u[tid] = uu;
+        s_v[tid] = vv;
         s_z[tid] = zc;
     }
     if (node_mine) s_nd[tid] = nd;
@@ -827,19 +947,19 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
     };
     // returns whether side b is a cell (its momentum parts b1, b2 set)
     auto flux = [&](uint32_t w, R dx, R dy, EdgeOut &o) {
-        const int ca = static_cast<int>(w & 0xffu);
+        const int ca = static_cast<int>(w & kEdgeA);
         const int cb = static_cast<int16_t>(w >> 16);
-        const R l = sqrt_(dx * dx + dy * dy);
-        const R nx = div_(dy, l), ny = div_(-dx, l);
+        R nx, ny, l;
+        edge_normal<R>(dx, dy, nx, ny, l);
         const R ha = s_h[ca], ua = s_u[ca], va = s_v[ca];
         R fh, fx, fy, pa, pb;
         if (cb >= 0) {
             interface_flux_uv<R>(g, hd, ha, ua, va, s_z[ca], s_h[cb], s_u[cb], s_v[cb], s_z[cb],
                                  nx, ny, fh, fx, fy, pa, pb);
             // side b's contributions are l (-f_h) = -(l f_h) and l (-f + p_b (-n)) =
-            // -(l (f + p_b n)), exactly
-            o.b1 = l * (fx + pb * nx);
-            o.b2 = l * (fy + pb * ny);
+            // -(l (f + p_b n)), exactly; its momentum parts are stored as they are added
+            o.b1 = -(l * (fx + pb * nx));
+            o.b2 = -(l * (fy + pb * ny));
         } else if (cb == SWE_WALL) {
             wall_flux<R>(g, hd, ha, ua, va, nx, ny, fh, fx, fy, pa);
         } else {
@@ -853,7 +973,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         return cb >= 0;
     };
     auto put = [&](int q, uint32_t w, const EdgeOut &o, bool two) {
-        R *e = lds + ebase + q + (q >= kBlock ? bshift : 0);
+        R *e = lds + ebase + q + (q >= TB ? bshift : 0);
         e[0] = o.a0;
         e[estride] = o.a1;
         e[2 * estride] = o.a2;
@@ -861,20 +981,20 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
             e[3 * estride] = o.b1;
             e[4 * estride] = o.b2;
         }
-        s_slot[3 * (w & 0xffu) + ((w >> 8) & 3u)] = static_cast<uint16_t>(q);
+        s_slot[3 * (w & kEdgeA) + ((w >> kEdgeKa) & 3u)] = static_cast<uint16_t>(q);
         const int cb = static_cast<int16_t>(w >> 16);
-        if (cb >= 0 && cb < kBlock) s_slot[3 * cb + ((w >> 10) & 3u)] = static_cast<uint16_t>(q | 0x8000);
+        if (cb >= 0 && cb < TB) s_slot[3 * cb + ((w >> kEdgeKb) & 3u)] = static_cast<uint16_t>(q | 0x8000);
     };
     {
         EdgeOut o;
         if (eb + pt < ee) put(pt, ew[0], o, flux(ew[0], edx[0], edy[0], o));
-        const bool has1 = eb + pt + kBlock < ee;
+        const bool has1 = eb + pt + TB < ee;
         bool two1 = false;
         if (has1) two1 = flux(ew[1], edx[1], edy[1], o);
         if constexpr (alias) __syncthreads();   // every read of the states is done
-        if (has1) put(pt + kBlock, ew[1], o, two1);
+        if (has1) put(pt + TB, ew[1], o, two1);
     }
-    for (int e = eb + pt + 2 * kBlock; e < ee; e += kBlock) {   // plain layout only
+    for (int e = eb + pt + 2 * TB; e < ee; e += TB) {   // plain layout only
         const uint32_t w = ld<O32>(ta.edges, e);
         const auto d = ld<O32>(ta.edge_vec, e);
         EdgeOut o;
@@ -893,10 +1013,11 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         for (int k = 0; k < 3; ++k) {
             const int q = static_cast<int>(sl[k] & 0x7fffu);
             const bool side_b = (sl[k] & 0x8000u) != 0;
-            const R *e = lds + ebase + q + (q >= kBlock ? bshift : 0);
+            const R *e = lds + ebase + q + (q >= TB ? bshift : 0);
+            const R *m = e + (side_b ? 3 * estride : estride);   // the side's momentum rows
             const R c0 = side_b ? -e[0] : e[0];
-            const R c1 = side_b ? -e[3 * estride] : e[estride];
-            const R c2 = side_b ? -e[4 * estride] : e[2 * estride];
+            const R c1 = m[0];
+            const R c2 = m[estride];
             nb[k] = 0;
             if ((cfg.n_inflow > 0 || batched) && !side_b)
                 nb[k] = static_cast<int16_t>(ld<O32>(ta.edges, eb + q) >> 16);
@@ -921,10 +1042,7 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         }
         R hun, hvn;
         if (hs > hd) {
-            const R mag = sqrt_(hus * hus + hvs * hvs);
-            const R d = R(1) + div_(dt * g * nm * nm * mag, hs * hs * cbrt_(hs));
-            hun = div_(hus, d);
-            hvn = div_(hvs, d);
+            friction(g, dt, nm, hs, hus, hvs, hun, hvn);
         } else {
             hun = R(0);
             hvn = R(0);
@@ -941,17 +1059,17 @@ __global__ __launch_bounds__(kBlock, SWE_TILE_WAVES) void tile_step_kernel(TileA
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step<Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv);
+    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv);
 }
 
 // CFL bounds of the initial state.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig cfg, Batch bt)
+template <typename R, int TB>
+__global__ __launch_bounds__(TB) void init_kernel(StepArgs<R> a, StepConfig cfg, Batch bt)
 {
     const int64_t T = cfg.n_cells;
     const bool batched = bt.tile_start != nullptr;
-    const int64_t s0 = batched ? bt.tile_start[blockIdx.x] : static_cast<int64_t>(blockIdx.x) * kBlock;
-    const int64_t s1 = batched ? bt.tile_start[blockIdx.x + 1] : s0 + kBlock;
+    const int64_t s0 = batched ? bt.tile_start[blockIdx.x] : static_cast<int64_t>(blockIdx.x) * TB;
+    const int64_t s1 = batched ? bt.tile_start[blockIdx.x + 1] : s0 + TB;
     const double *qtab = batched ? bt.q_table + bt.tile_scen[blockIdx.x] * SWE_MAX_INFLOW : nullptr;
     const int64_t i = s0 + threadIdx.x;
     const R g = static_cast<R>(cfg.g), hd = static_cast<R>(cfg.h_dry);
@@ -967,7 +1085,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs<R> a, StepConfig 
             flag = 0;
         }
     }
-    block_partials(static_cast<double>(dtc), 0, flag, a.part);
+    block_partials<TB>(static_cast<double>(dtc), 0, flag, a.part);
 }
 
 constexpr int kPassThreads = 1024;
@@ -1235,7 +1353,8 @@ __global__ void flux_eval_kernel(int64_t n, R g, R hd, const R *hl, const R *hul
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const R h = hl[i];
-    const R u = velocity(h, hul[i], hd), v = velocity(h, hvl[i], hd);
+    R u, v;
+    velocities(h, hul[i], hvl[i], hd, u, v);
     R fh, fx, fy, pp;
     if (hr)
         interface_flux<R>(g, hd, h, u, v, zl[i], hr[i], hur[i], hvr[i], zr[i], nx[i], ny[i], fh,
@@ -1268,7 +1387,7 @@ StepArgs<R> make_args(const swe_dev_mesh &dm, const swe_state &s, int cur)
     a.huo = static_cast<R *>(s.hu[1 - cur]);
     a.hvo = static_cast<R *>(s.hv[1 - cur]);
     a.ctrl = static_cast<const Ctrl *>(s.ctrl);
-    a.part = partials_for(s.work, n_blocks(dm.n_cells));
+    a.part = Partials{};   // set by the launcher, for the launch's tiles
     a.us_h = a.us_hu = a.us_hv = nullptr;
     a.dt_direct = nullptr;
     a.adv = Advance{nullptr, nullptr, 0, 0.0, 0, 0};
@@ -1326,22 +1445,41 @@ Batch batch_view(const BatchLaunch *b)
 
 }  // namespace
 
+// Kernels are instantiated for every tile size; with_tile(tile, f) calls f with it as a
+// compile-time constant.
+template <typename F>
+int with_tile(int tile, F &&f)
+{
+    switch (tile) {
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    case 512: return f(std::integral_constant<int, 512>{});
+    default: return static_cast<int>(hipErrorInvalidValue);
+    }
+}
+
 int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const swe_state &s,
                 double t0, double t_end, void *stream, const BatchLaunch *batch)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t nb = batch ? batch->n_tiles : n_blocks(cfg.n_cells);
+    const int64_t nb = batch ? batch->n_tiles : n_tiles_of(cfg.n_cells, cfg.tile);
     const Batch bv = batch_view(batch);
     const Partials part = partials_for(s.work, nb);
-    if (dtype == SWE_F64) {
-        StepArgs<double> a = make_args<double>(dm, s, s.cur);
-        a.part = part;
-        init_kernel<double><<<dim3(nb), dim3(kBlock), 0, st>>>(a, cfg, bv);
-    } else {
-        StepArgs<float> a = make_args<float>(dm, s, s.cur);
-        a.part = part;
-        init_kernel<float><<<dim3(nb), dim3(kBlock), 0, st>>>(a, cfg, bv);
-    }
+    const int e = with_tile(cfg.tile, [&](auto tb) {
+        constexpr int TB = decltype(tb)::value;
+        if (dtype == SWE_F64) {
+            StepArgs<double> a = make_args<double>(dm, s, s.cur);
+            a.part = part;
+            init_kernel<double, TB><<<dim3(nb), dim3(TB), 0, st>>>(a, cfg, bv);
+        } else {
+            StepArgs<float> a = make_args<float>(dm, s, s.cur);
+            a.part = part;
+            init_kernel<float, TB><<<dim3(nb), dim3(TB), 0, st>>>(a, cfg, bv);
+        }
+        return static_cast<int>(hipGetLastError());
+    });
+    if (e != hipSuccess) return e;
     dt_pass_kernel<<<dim3(bv.n_scen), kPassThreads, 0, st>>>(
         static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, nullptr, 0, 0, t0, t_end, s.cur, bv,
         cfg.shard);
@@ -1352,45 +1490,54 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
 template <typename R>
 using TileKernel = void (*)(TileArgs<R>, StepConfig, Batch);
 
-template <typename R, bool Shared, bool Nodes>
+template <typename R, int TB, bool Shared, bool Nodes>
 TileKernel<R> tile_kernel_of(bool o32, bool fuse)
 {
-    return o32 ? (fuse ? tile_step_kernel<R, true, true, Shared, Nodes>
-                       : tile_step_kernel<R, true, false, Shared, Nodes>)
-               : (fuse ? tile_step_kernel<R, false, true, Shared, Nodes>
-                       : tile_step_kernel<R, false, false, Shared, Nodes>);
+    return o32 ? (fuse ? tile_step_kernel<R, TB, true, true, Shared, Nodes>
+                       : tile_step_kernel<R, TB, true, false, Shared, Nodes>)
+               : (fuse ? tile_step_kernel<R, TB, false, true, Shared, Nodes>
+                       : tile_step_kernel<R, TB, false, false, Shared, Nodes>);
 }
 
-template <typename R>
+template <typename R, int TB>
 TileKernel<R> tile_kernel(bool o32, bool fuse, bool shared, bool nodes)
 {
     if constexpr (sizeof(R) == 8) {
         if (shared)
-            return nodes ? tile_kernel_of<R, true, true>(o32, fuse) : tile_kernel_of<R, true, false>(o32, fuse);
+            return nodes ? tile_kernel_of<R, TB, true, true>(o32, fuse)
+                         : tile_kernel_of<R, TB, true, false>(o32, fuse);
     }
-    return tile_kernel_of<R, false, false>(o32, fuse);
+    return tile_kernel_of<R, TB, false, false>(o32, fuse);
 }
 
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
 {
-    return tile_lds_bytes(dtype == SWE_F64 ? 8 : 4, tl.max_halo, tl.max_edges, tl.max_nodes);
+    return tile_lds_bytes(dtype == SWE_F64 ? 8 : 4, tl.tile, tl.max_halo, tl.max_edges,
+                          tl.max_nodes);
 }
 
 int prepare_tile_kernels(size_t max_lds)
 {
-    const void *k[16];
-    int n = 0;
-    for (int o32 = 0; o32 < 2; ++o32)
-        for (int fuse = 0; fuse < 2; ++fuse) {
-            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, false, false));
-            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, true, false));
-            k[n++] = reinterpret_cast<const void *>(tile_kernel<double>(o32, fuse, true, true));
-            k[n++] = reinterpret_cast<const void *>(tile_kernel<float>(o32, fuse, false, false));
-        }
-    for (const void *f : k) {
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 static_cast<int>(max_lds));
-        if (e != hipSuccess) return static_cast<int>(e);
+    for (int tile = kTileMin; tile <= kTileMax; tile *= 2) {
+        const int e = with_tile(tile, [&](auto tb) {
+            constexpr int TB = decltype(tb)::value;
+            const void *k[16];
+            int n = 0;
+            for (int o32 = 0; o32 < 2; ++o32)
+                for (int fuse = 0; fuse < 2; ++fuse) {
+                    k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, fuse, false, false));
+                    k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, fuse, true, false));
+                    k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, fuse, true, true));
+                    k[n++] = reinterpret_cast<const void *>(tile_kernel<float, TB>(o32, fuse, false, false));
+                }
+            for (const void *f : k) {
+                const hipError_t e = hipFuncSetAttribute(
+                    f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(max_lds));
+                if (e != hipSuccess) return static_cast<int>(e);
+            }
+            return static_cast<int>(hipSuccess);
+        });
+        if (e != hipSuccess) return e;
     }
     return static_cast<int>(hipSuccess);
 }
@@ -1415,7 +1562,7 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
                 const double *dt_direct)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t nb = batch ? batch->n_tiles : n_blocks(cfg.n_cells);
+    const int64_t nb = batch ? batch->n_tiles : n_tiles_of(cfg.n_cells, cfg.tile);
     Batch bv = batch_view(batch);
     bv.remap = remap;
     bv.n_tiles = static_cast<int32_t>(nb);
@@ -1424,50 +1571,58 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     const bool fuse = batch == nullptr && dt_direct == nullptr && nb <= SWE_FUSE_TILES;
     const Advance adv{fuse ? static_cast<Ctrl *>(s.ctrl) : nullptr, dt_seq, n_seq, cfg.courant,
                       cfg.shard, 0};
-    if (tl) {
-        const size_t lds = SWE_MATH_NS::tile_lds_bytes_for(dtype, *tl);
-        const bool o32 = !cfg.index64 && offsets_fit_32(dm, dm.n_cells, *tl);
-        if (dtype == SWE_F64) {
-            TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
-            ta.s.part = part;
-            ta.s.dt_direct = dt_direct;
-            ta.s.adv = adv;
-            if (ustar) {
-                ta.s.us_h = ustar[0];
-                ta.s.us_hu = ustar[1];
-                ta.s.us_hv = ustar[2];
+    const int e = with_tile(cfg.tile, [&](auto tb) {
+        constexpr int TB = decltype(tb)::value;
+        if (tl) {
+            const size_t lds = SWE_MATH_NS::tile_lds_bytes_for(dtype, *tl);
+            const bool o32 = !cfg.index64 && offsets_fit_32(dm, dm.n_cells, *tl);
+            if (dtype == SWE_F64) {
+                TileArgs<double> ta = make_tile_args<double>(dm, s, cur, *tl);
+                ta.s.part = part;
+                ta.s.dt_direct = dt_direct;
+                ta.s.adv = adv;
+                if (ustar) {
+                    ta.s.us_h = ustar[0];
+                    ta.s.us_hu = ustar[1];
+                    ta.s.us_hv = ustar[2];
+                }
+                const bool shared = tile_alias(sizeof(double), TB, tl->max_halo, tl->max_edges,
+                                               tl->max_nodes);
+                const bool nodes = shared && ta.edge_nodes != nullptr;
+                tile_kernel<double, TB>(o32, fuse, shared, nodes)<<<dim3(grid), dim3(TB), lds, st>>>(
+                    ta, cfg, bv);
+            } else {
+                TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
+                ta.s.part = part;
+                ta.s.dt_direct = dt_direct;
+                ta.s.adv = adv;
+                tile_kernel<float, TB>(o32, fuse, false, false)<<<dim3(grid), dim3(TB), lds, st>>>(
+                    ta, cfg, bv);
             }
-            const bool shared = tile_alias(sizeof(double), tl->max_halo, tl->max_edges, tl->max_nodes);
-            const bool nodes = shared && ta.edge_nodes != nullptr;
-            tile_kernel<double>(o32, fuse, shared, nodes)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+        } else if (dtype == SWE_F64) {
+            StepArgs<double> a = make_args<double>(dm, s, cur);
+            a.part = part;
+            a.dt_direct = dt_direct;
+            a.adv = adv;
+            if (ustar) {
+                a.us_h = ustar[0];
+                a.us_hu = ustar[1];
+                a.us_hv = ustar[2];
+            }
+            (fuse ? step_kernel<double, TB, true> : step_kernel<double, TB, false>)<<<dim3(grid), dim3(TB), 0, st>>>(
+                a, cfg, bv);
         } else {
-            TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
-            ta.s.part = part;
-            ta.s.dt_direct = dt_direct;
-            ta.s.adv = adv;
-            tile_kernel<float>(o32, fuse, false, false)<<<dim3(grid), dim3(kBlock), lds, st>>>(ta, cfg, bv);
+            StepArgs<float> a = make_args<float>(dm, s, cur);
+            a.part = part;
+            a.dt_direct = dt_direct;
+            a.adv = adv;
+            (fuse ? step_kernel<float, TB, true> : step_kernel<float, TB, false>)<<<dim3(grid), dim3(TB), 0, st>>>(
+                a, cfg, bv);
         }
-    } else if (dtype == SWE_F64) {
-        StepArgs<double> a = make_args<double>(dm, s, cur);
-        a.part = part;
-        a.dt_direct = dt_direct;
-        a.adv = adv;
-        if (ustar) {
-            a.us_h = ustar[0];
-            a.us_hu = ustar[1];
-            a.us_hv = ustar[2];
-        }
-        (fuse ? step_kernel<double, true> : step_kernel<double, false>)<<<dim3(grid), dim3(kBlock), 0, st>>>(
-            a, cfg, bv);
-    } else {
-        StepArgs<float> a = make_args<float>(dm, s, cur);
-        a.part = part;
-        a.dt_direct = dt_direct;
-        a.adv = adv;
-        (fuse ? step_kernel<float, true> : step_kernel<float, false>)<<<dim3(grid), dim3(kBlock), 0, st>>>(
-            a, cfg, bv);
-    }
-    if (dt_direct || fuse) return static_cast<int>(hipGetLastError());   // nothing to launch
+        return static_cast<int>(hipGetLastError());
+    });
+    if (e != hipSuccess) return e;
+    if (dt_direct || fuse) return static_cast<int>(hipSuccess);   // nothing more to launch
     if (SWE_DT_FOLD && batch == nullptr)
         dt_fold_kernel<<<dim3(n_groups(nb)), dim3(kGroup), 0, st>>>(
             static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, cfg.shard);

@@ -18,6 +18,12 @@
 
 namespace {
 
+using swe::kEdgeA;
+using swe::kEdgeKa;
+using swe::kEdgeKb;
+using swe::n_tiles_of;
+using swe::valid_tile;
+
 struct Fail {
     int32_t code;
     std::string msg;
@@ -75,7 +81,7 @@ void radix_sort_by_key(std::vector<uint32_t> &key, std::vector<int32_t> &idx)
     }
 }
 
-// Tiles of SWE_TILE consecutive mesh-order cells.  Per tile: the halo (cells outside it that
+// Tiles of tile_cells consecutive mesh-order cells.  Per tile: the halo (cells outside it that
 // share an edge with it, ascending) and the edge list: every interface between two tile
 // cells once (owned by the lower local index), every interface to a halo cell or the
 // boundary once (owned by the tile cell).  Interior and halo entries come first, boundary
@@ -84,7 +90,9 @@ void radix_sort_by_key(std::vector<uint32_t> &key, std::vector<int32_t> &idx)
 void build_tiles(swe_mesh &m)
 {
     const int64_t T = m.info.n_cells;
-    const int64_t nt = (T + SWE_TILE - 1) / SWE_TILE;
+    const int64_t TB = m.info.tile_cells;
+    if (!valid_tile(TB)) throw Fail{SWE_EINVAL, "tile size must be 64, 128, 256 or 512"};
+    const int64_t nt = n_tiles_of(T, TB);
     m.halo_off.assign(nt + 1, 0);
     m.edge_off.assign(nt + 1, 0);
     m.halo.clear();
@@ -95,7 +103,7 @@ void build_tiles(swe_mesh &m)
     std::vector<uint32_t> inner, bnd;
     std::vector<int32_t> inner_cell, bnd_cell;  // (local cell * 4 + k) of each entry
     for (int64_t t = 0; t < nt; ++t) {
-        const int64_t s0 = t * SWE_TILE, s1 = std::min<int64_t>(T, s0 + SWE_TILE);
+        const int64_t s0 = t * TB, s1 = std::min<int64_t>(T, s0 + TB);
         hl.clear();
         for (int64_t i = s0; i < s1; ++i)
             for (int k = 0; k < 3; ++k) {
@@ -104,7 +112,7 @@ void build_tiles(swe_mesh &m)
             }
         std::sort(hl.begin(), hl.end());
         hl.erase(std::unique(hl.begin(), hl.end()), hl.end());
-        if (static_cast<int64_t>(hl.size()) > 32767 - SWE_TILE)
+        if (static_cast<int64_t>(hl.size()) > 32767 - TB)
             throw Fail{SWE_EMESH, "tile halo too large"};
         inner.clear(); bnd.clear(); inner_cell.clear(); bnd_cell.clear();
         for (int64_t i = s0; i < s1; ++i) {
@@ -116,12 +124,12 @@ void build_tiles(swe_mesh &m)
                     if (j < i) continue;  // owned by the lower local index
                     b = static_cast<int32_t>(j - s0);
                 } else if (j >= 0) {
-                    b = SWE_TILE + static_cast<int32_t>(
+                    b = static_cast<int32_t>(TB) + static_cast<int32_t>(
                                        std::lower_bound(hl.begin(), hl.end(), j) - hl.begin());
                 } else {
                     b = j;
                 }
-                const uint32_t w = a | (static_cast<uint32_t>(k) << 8) |
+                const uint32_t w = a | (static_cast<uint32_t>(k) << kEdgeKa) |
                                    (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(b))) << 16);
                 if (b >= 0) {
                     inner.push_back(w);
@@ -141,14 +149,14 @@ void build_tiles(swe_mesh &m)
             m.slot[k * T + i] = static_cast<uint16_t>(e);
             const int32_t b = static_cast<int16_t>(w >> 16);
             uint32_t wk = w;
-            if (b >= 0 && b < SWE_TILE) {  // side b of an interior interface
+            if (b >= 0 && b < TB) {  // side b of an interior interface
                 const int64_t jb = s0 + b;
                 int kb = -1;
                 for (int q = 0; q < 3; ++q)
                     if (m.nbr[q * T + jb] == i) kb = q;
                 if (kb < 0) throw Fail{SWE_EMESH, "neighbour relation is not mutual"};
                 m.slot[kb * T + jb] = static_cast<uint16_t>(e | 0x8000);
-                wk |= static_cast<uint32_t>(kb) << 10;   // b's local edge, for the tile's slots
+                wk |= static_cast<uint32_t>(kb) << kEdgeKb;   // b's local edge, for the tile's slots
             }
             m.edges.push_back(wk);
         }
@@ -166,8 +174,8 @@ void build_tiles(swe_mesh &m)
     for (int64_t t = 0; t < nt; ++t)
         for (int32_t e = m.edge_off[t]; e < m.edge_off[t + 1]; ++e) {
             const uint32_t w = m.edges[e];
-            const int64_t ca = t * SWE_TILE + static_cast<int64_t>(w & 0xffu);
-            const int k = static_cast<int>((w >> 8) & 3u);
+            const int64_t ca = t * TB + static_cast<int64_t>(w & kEdgeA);
+            const int k = static_cast<int>((w >> kEdgeKa) & 3u);
             const int32_t n0 = m.c2n[k * T + ca], n1 = m.c2n[((k + 1) % 3) * T + ca];
             m.edge_vec[2 * static_cast<size_t>(e)] = m.xy[2 * static_cast<size_t>(n1)] - m.xy[2 * static_cast<size_t>(n0)];
             m.edge_vec[2 * static_cast<size_t>(e) + 1] =
@@ -176,7 +184,9 @@ void build_tiles(swe_mesh &m)
     // each tile's nodes in first-use order and, per entry, the tile-local ids of the nodes
     // whose difference is its edge vector: the FP64 tiled step stages a tile's nodes (about
     // 0.7 per cell) once instead of reading an edge vector per entry (about 1.7 per cell);
-    // kept only where every tile's ids fit in 8 bits
+    // kept only where every tile's ids fit in 8 bits and its nodes number at most its cells
+    // (one per work-item)
+    const int32_t node_cap = static_cast<int32_t>(std::min<int64_t>(256, TB));
     std::vector<int32_t> local(static_cast<size_t>(m.info.n_nodes), -1);
     std::vector<int32_t> used;
     int32_t max_nodes = 0;
@@ -184,7 +194,7 @@ void build_tiles(swe_mesh &m)
     m.tile_nodes.clear();
     m.edge_nodes.assign(m.edges.size(), 0);
     for (int64_t t = 0; t < nt; ++t) {
-        const int64_t s0 = t * SWE_TILE, s1 = std::min<int64_t>(T, s0 + SWE_TILE);
+        const int64_t s0 = t * TB, s1 = std::min<int64_t>(T, s0 + TB);
         used.clear();
         for (int64_t i = s0; i < s1; ++i)
             for (int k = 0; k < 3; ++k) {
@@ -195,11 +205,11 @@ void build_tiles(swe_mesh &m)
                 }
             }
         max_nodes = std::max(max_nodes, static_cast<int32_t>(used.size()));
-        if (max_nodes <= 256) {
+        if (max_nodes <= node_cap) {
             for (int32_t e = m.edge_off[t]; e < m.edge_off[t + 1]; ++e) {
                 const uint32_t w = m.edges[e];
-                const int64_t ca = s0 + static_cast<int64_t>(w & 0xffu);
-                const int k = static_cast<int>((w >> 8) & 3u);
+                const int64_t ca = s0 + static_cast<int64_t>(w & kEdgeA);
+                const int k = static_cast<int>((w >> kEdgeKa) & 3u);
                 const int32_t n0 = local[m.c2n[k * T + ca]], n1 = local[m.c2n[((k + 1) % 3) * T + ca]];
                 m.edge_nodes[e] = static_cast<uint16_t>(n0 | (n1 << 8));
             }
@@ -211,7 +221,7 @@ void build_tiles(swe_mesh &m)
         }
         for (int32_t v : used) local[v] = -1;
     }
-    if (max_nodes > 256 || m.tile_nodes.size() / 2 > static_cast<size_t>(INT32_MAX)) {
+    if (max_nodes > node_cap || m.tile_nodes.size() / 2 > static_cast<size_t>(INT32_MAX)) {
         m.tile_node_off.clear();
         m.tile_nodes.clear();
         m.edge_nodes.clear();
@@ -227,7 +237,7 @@ void build_tiles(swe_mesh &m)
     m.tiles.max_halo = max_halo;
     m.tiles.max_edges = max_edges;
     m.tiles.max_nodes = m.tile_nodes.empty() ? 0 : max_nodes;
-    m.tiles.pad = 0;
+    m.tiles.tile = static_cast<int32_t>(TB);
 }
 
 void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_t nt,
@@ -237,7 +247,11 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
     if (nv < 3 || nt < 1) throw Fail{SWE_EINVAL, "need at least 3 nodes and 1 triangle"};
     if (nv > INT32_MAX / 2 || nt > INT32_MAX / 3)
         throw Fail{SWE_EINVAL, "mesh too large for int32 indices"};
-    if (flags & ~(SWE_MORTON | SWE_HILBERT)) throw Fail{SWE_EINVAL, "unknown flags"};
+    if (flags & ~(SWE_MORTON | SWE_HILBERT | SWE_TILE_64 | SWE_TILE_128 | SWE_TILE_512))
+        throw Fail{SWE_EINVAL, "unknown flags"};
+    const uint32_t tf = flags & (SWE_TILE_64 | SWE_TILE_128 | SWE_TILE_512);
+    if (tf & (tf - 1)) throw Fail{SWE_EINVAL, "more than one tile size flag"};
+    const int32_t tile = tf == SWE_TILE_64 ? 64 : tf == SWE_TILE_128 ? 128 : tf == SWE_TILE_512 ? 512 : SWE_TILE;
     if ((flags & SWE_MORTON) && (flags & SWE_HILBERT))
         throw Fail{SWE_EINVAL, "SWE_MORTON and SWE_HILBERT exclude each other"};
     for (int64_t j = 0; j < 2 * nv; ++j)
@@ -340,6 +354,7 @@ void build(swe_mesh &m, const double *xy, int64_t nv, const int32_t *tri, int64_
     inf.n_inflow_edges = ninflow;
     inf.n_inflow_segments = max_tag;
     inf.flags = flags;
+    inf.tile_cells = tile;
     inf.min_area = INFINITY;
     inf.min_inradius = INFINITY;
     inf.bbox[0] = inf.bbox[1] = INFINITY;
@@ -483,7 +498,9 @@ void build_shard(swe_mesh &m, const swe_mesh &full, int64_t c0, int64_t c1)
             const int32_t code = full.nbr[k * T + c];
             if (code < SWE_WALL) tag[3 * q + k] = -1 - code;
         }
-    build(m, xy.data(), static_cast<int64_t>(nodes.size()), tri.data(), n, tag.data(), 0);
+    // the full mesh's tile size; no renumbering
+    build(m, xy.data(), static_cast<int64_t>(nodes.size()), tri.data(), n, tag.data(),
+          full.info.flags & (SWE_TILE_64 | SWE_TILE_128 | SWE_TILE_512));
     m.info.n_owned = c1 - c0;
     m.global = std::move(cells);
 }

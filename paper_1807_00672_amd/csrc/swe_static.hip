@@ -50,7 +50,8 @@ extern "C" int32_t swe_run_static(const swe_mesh *mesh, const swe_dev_mesh *dm,
     if (dt_seq && n_steps < 1) return sfail(SWE_EINVAL, "swe_run_static: dt_seq needs n_steps >= 1");
     if (init && (!isfinite(t0) || !isfinite(t_end)))
         return sfail(SWE_EINVAL, "swe_run_static: t0 and t_end must be finite");
-    const int64_t need = workspace_bytes(mesh->info.n_cells);
+    const int64_t nb = n_tiles_of(mesh->info.n_cells, mesh->info.tile_cells);
+    const int64_t need = workspace_bytes_for_tiles(nb);
     if (need > static_cast<int64_t>(SWE_STATIC_WORK_BYTES))
         return sfail(SWE_EINVAL, "swe_run_static: the mesh needs " + std::to_string(need) +
                                      " bytes of step partials, beyond the static " +
@@ -77,7 +78,6 @@ extern "C" int32_t swe_run_static(const swe_mesh *mesh, const swe_dev_mesh *dm,
     swe_state st = *s;
     st.work = work;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const int64_t nb = n_blocks(mesh->info.n_cells);
     const Partials part = partials_for(work, nb);
     const int64_t n_count = n_groups(nb) + 1;
     clear_counters_kernel<<<dim3(static_cast<unsigned>((n_count + 255) / 256)), 256, 0, hs>>>(

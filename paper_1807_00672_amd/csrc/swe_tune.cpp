@@ -131,6 +131,7 @@ int32_t swe_tune(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_params 
         r.variant = q[pick].variant;
         r.xcd_remap = (pick & 1) ? 0 : 1;
     }
+    r.tile_cells = mesh->info.tile_cells;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SWE_OK) return rc;
@@ -165,6 +166,8 @@ int32_t swe_tune_set(int32_t device, int32_t dtype, int64_t n_cells, const swe_t
     if (r->variant != SWE_AUTO && r->variant != SWE_CELL && r->variant != SWE_TILED)
         return tfail(SWE_EINVAL, "swe_tune_set: unknown variant");
     if (r->xcd_remap != 0 && r->xcd_remap != 1) return tfail(SWE_EINVAL, "swe_tune_set: xcd_remap must be 0 or 1");
+    if (r->tile_cells != 0 && !valid_tile(r->tile_cells))
+        return tfail(SWE_EINVAL, "swe_tune_set: tile_cells must be 0, 64, 128, 256 or 512");
     std::lock_guard<std::mutex> lk(g_mu);
     const Key k{device, dtype, size_class(n_cells)};
     try {

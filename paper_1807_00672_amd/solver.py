@@ -31,6 +31,13 @@ def _cell_field(mesh, a, name: str) -> np.ndarray:
     return mesh.to_mesh_order(a)
 
 
+def _tuned_tile(n_cells: int, dtype: str) -> int:
+    """The tile size swe_tune's table holds for this device, precision and size class."""
+    dev = torch.cuda.current_device() if torch.cuda.is_available() else 0
+    r = A.swe_tune_get(dev, {"f64": A.SWE_F64, "f32": A.SWE_F32}[dtype], n_cells)
+    return int(r.tile_cells) if r.variant != A.SWE_AUTO and r.tile_cells in A.TILE_FLAGS else A.SWE_TILE
+
+
 class Mesh:
     """A triangle mesh built by swe_mesh_create, with its arrays copied to the device.
 
@@ -41,13 +48,21 @@ class Mesh:
     ORDERS = {"morton": A.SWE_MORTON, "hilbert": A.SWE_HILBERT, "input": 0}
 
     def __init__(self, xy, tri, edge_tag=None, morton: bool = True, device="cuda", handle=None,
-                 order: str | None = None):
-        """order: "morton", "hilbert" or "input" cell order (default: morton unless morton=False)."""
+                 order: str | None = None, tile: int | str = A.SWE_TILE, dtype: str = "f64"):
+        """order: "morton", "hilbert" or "input" cell order (default: morton unless morton=False).
+        tile: cells per tile (64, 128, 256 or 512), or "auto": the size swe_tune recorded as
+        fastest for this device, `dtype` and size class (tune.tune_tiles), else SWE_TILE."""
         flags = self.ORDERS[order or ("morton" if morton else "input")]
+        if tile == "auto":
+            tile = _tuned_tile(len(tri), dtype)
+        if tile not in A.TILE_FLAGS:
+            raise ValueError(f"tile must be 64, 128, 256 or 512, not {tile!r}")
+        flags |= A.TILE_FLAGS[tile]
         self.handle = handle if handle is not None else A.swe_mesh_create(xy, tri, edge_tag, flags)
         self.info = A.swe_mesh_info_get(self.handle)
         t, v = int(self.info.n_cells), int(self.info.n_nodes)
         self.n_cells, self.n_nodes = t, v
+        self.tile = int(self.info.tile_cells)
         self.perm = A.swe_mesh_export(self.handle, A.SWE_ARR_PERM, t, np.int32)
         self.nbr = A.swe_mesh_export(self.handle, A.SWE_ARR_NBR, 3 * t, np.int32)
         self.c2n = A.swe_mesh_export(self.handle, A.SWE_ARR_C2N, 3 * t, np.int32)

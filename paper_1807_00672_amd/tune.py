@@ -1,6 +1,8 @@
 """Launch autotuning (swe_tune): which step kernel variant and workgroup order run fastest for
-a mesh size class on this device, remembered for SWE_AUTO; optional persistence as JSON keyed by
-device name, precision and size class, and a choice among Morton, Hilbert and input cell order."""
+a mesh size class on this device, remembered for SWE_AUTO; which tile size (the step kernels'
+workgroup size, a property of the mesh: one mesh per size) is fastest, remembered for
+Mesh(tile="auto"); optional persistence as JSON keyed by device name, precision and size class,
+and a choice among Morton, Hilbert and input cell order."""
 from __future__ import annotations
 
 import json
@@ -56,6 +58,7 @@ def save(path: str) -> None:
     entries = data.setdefault(name, {})
     for (dt, cls), r in _recorded.items():
         entries[f"{dt}:{cls}"] = {"variant": r["variant"], "xcd_remap": r["xcd_remap"],
+                                  "tile": r.get("tile", A.SWE_TILE),
                                   "ms_per_step": r["ms_per_step"]}
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
@@ -72,6 +75,7 @@ def load(path: str) -> int:
         r = A.swe_tune_result()
         r.variant = _VAR[e["variant"]]
         r.xcd_remap = 1 if e["xcd_remap"] else 0
+        r.tile_cells = int(e.get("tile", A.SWE_TILE))
         A.swe_tune_set(dev, _DT[dt], 1 << int(cls), r)
     return len(entries)
 
@@ -85,13 +89,37 @@ def tune_order(xy, tri, z, n, h, hu, hv, edge_tag=None, dtype: str = "f64",
     for order in orders:
         m = Mesh(xy, tri, edge_tag, order=order)
         res[order] = tune(m, z, n, h, hu, hv, dtype, steps, **solver_kw)
-    best = {k: min(v["ms_per_step"][x] for x in v["ms_per_step"] if v["ms_per_step"][x] > 0)
-            for k, v in res.items()}
-    order = min(best, key=best.get)
-    r = res[order]   # the order tuned last may not be the fastest: record the fastest again
+    order = min(res, key=lambda k: _best_ms(res[k]))
+    _record(res[order], dtype, len(tri))   # the order tuned last may not be the fastest
+    return order, res
+
+
+def _best_ms(r: dict) -> float:
+    return min(v for v in r["ms_per_step"].values() if v > 0)
+
+
+def _record(r: dict, dtype: str, n_cells: int) -> None:
     rr = A.swe_tune_result()
     rr.variant = _VAR[r["variant"]]
     rr.xcd_remap = 1 if r["xcd_remap"] else 0
-    A.swe_tune_set(torch.cuda.current_device(), _DT[dtype], len(tri), rr)
-    _recorded[(dtype, size_class(len(tri)))] = r
-    return order, res
+    rr.tile_cells = int(r.get("tile", A.SWE_TILE))
+    A.swe_tune_set(torch.cuda.current_device(), _DT[dtype], n_cells, rr)
+    _recorded[(dtype, size_class(n_cells))] = r
+
+
+def tune_tiles(xy, tri, z, n, h, hu, hv, edge_tag=None, dtype: str = "f64", steps: int = 20,
+               tiles=(64, 128, 256, 512), order: str = "morton", **solver_kw) -> tuple[int, dict]:
+    """Build the mesh with each tile size (cells per workgroup of the step kernels), tune each
+    (variant x workgroup order, swe_tune), and record the fastest tile size with its variant
+    and order for this device, precision and size class: Mesh(..., tile="auto") then builds
+    with it and SWE_AUTO launches its variant.  Returns (the fastest tile size, the timings of
+    every size)."""
+    res = {}
+    for tile in tiles:
+        m = Mesh(xy, tri, edge_tag, order=order, tile=tile)
+        res[tile] = tune(m, z, n, h, hu, hv, dtype, steps, **solver_kw)
+        del m
+        torch.cuda.empty_cache()
+    best = min(res, key=lambda t: _best_ms(res[t]))
+    _record(res[best], dtype, len(tri))
+    return best, res

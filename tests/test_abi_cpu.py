@@ -80,8 +80,8 @@ def test_mesh_builder_agrees_with_oracle_connectivity(k, morton):
     for tile in range(int(info.n_tiles)):
         e0, e1 = m.edge_off[tile], m.edge_off[tile + 1]
         w = m.edges[e0:e1].astype(np.int64)
-        ca = tile * 256 + (w & 0xff)
-        k = (w >> 8) & 3
+        ca = tile * m.tile + (w & swe._abi.EDGE_A_MASK)
+        k = (w >> swe._abi.EDGE_KA_SHIFT) & 3
         n0 = m.c2n.reshape(3, t)[k, ca]
         n1 = m.c2n.reshape(3, t)[(k + 1) % 3, ca]
         assert np.array_equal(ev[e0:e1], xy[n1] - xy[n0])
@@ -208,14 +208,17 @@ def test_step_calls_reject_bad_arguments_without_touching_a_device():
     assert swe.lib.swe_step(m.handle, C.byref(dm), C.byref(f32), C.byref(st), None) == swe.SWE_EINVAL
 
 
-@pytest.mark.parametrize("k,morton", [(1, True), (2, True), (3, False)])
-def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton):
-    """The tiled step evaluates, per tile of 256 mesh-order cells, each interface between two
-    tile cells once, each interface to a halo cell or to the boundary once, and each cell
+@pytest.mark.parametrize("k,morton,tile", [(1, True, 256), (2, True, 256), (3, False, 256),
+                                            (1, True, 64), (2, True, 128), (3, True, 512),
+                                            (3, False, 512)])
+def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton, tile):
+    """The tiled step evaluates, per tile of `tile` mesh-order cells, each interface between
+    two tile cells once, each interface to a halo cell or to the boundary once, and each cell
     finds its three local edges through its slots."""
     c = gen.small(k)
-    m = swe.Mesh(c.xy, c.tri, morton=morton, device=None)
-    t, tile = m.n_cells, swe.SWE_TILE
+    m = swe.Mesh(c.xy, c.tri, morton=morton, device=None, tile=tile)
+    t = m.n_cells
+    assert m.tile == m.info.tile_cells == tile
     nbr = m.nbr.reshape(3, t)
     slot = m.slot.reshape(3, t)
     info = m.info
@@ -229,13 +232,14 @@ def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton):
         expect = np.unique(nb[(nb >= 0) & ((nb < s0) | (nb >= s1))])
         assert np.array_equal(halo, expect)
         ent = m.edges[m.edge_off[tt]:m.edge_off[tt + 1]]
-        a = (ent & 0xFF).astype(np.int64)
-        kk = ((ent >> 8) & 3).astype(np.int64)
+        a = (ent & swe._abi.EDGE_A_MASK).astype(np.int64)
+        kk = ((ent >> swe._abi.EDGE_KA_SHIFT) & 3).astype(np.int64)
         b = (ent >> 16).astype(np.uint16).view(np.int16).astype(np.int64)
         assert (a < s1 - s0).all() and (kk < 3).all()
-        # side b's local edge (bits 10-11) for interfaces between two tile cells: b's
+        # side b's local edge (bits 11-12) for interfaces between two tile cells: b's
         # neighbour across it is a; 0 for the others
-        kb = ((ent >> 10) & 3).astype(np.int64)
+        kb = ((ent >> swe._abi.EDGE_KB_SHIFT) & 3).astype(np.int64)
+        assert ((ent >> 13) & 7 == 0).all()
         inner = (b >= 0) & (b < tile)
         assert (kb[~inner] == 0).all() and (kb < 3).all()
         assert (nbr[kb[inner], s0 + b[inner]] == s0 + a[inner]).all()
@@ -267,15 +271,18 @@ def test_tile_lists_cover_every_interface_exactly_once_per_tile(k, morton):
     assert len(seen) == info.n_tile_edges
 
 
-@pytest.mark.parametrize("k,order", [(1, "morton"), (3, "hilbert"), (5, "morton")])
-def test_tile_node_lists_reproduce_the_edge_vectors_bitwise(k, order):
+@pytest.mark.parametrize("k,order,tile", [(1, "morton", 256), (3, "hilbert", 256),
+                                          (5, "morton", 256), (1, "morton", 128),
+                                          (5, "morton", 64)])
+def test_tile_node_lists_reproduce_the_edge_vectors_bitwise(k, order, tile):
     """Each tile's node list holds the distinct nodes of its cells, with their coordinates;
-    each edge-list entry's two node ids give back its edge vector, bit for bit."""
+    each edge-list entry's two node ids give back its edge vector, bit for bit.  Lists are
+    kept where every tile has at most min(256, tile) nodes (one per work-item)."""
     c = gen.small(k)
-    m = swe.Mesh(c.xy, c.tri, order=order, device=None)
-    t, tile = m.n_cells, swe.SWE_TILE
+    m = swe.Mesh(c.xy, c.tri, order=order, device=None, tile=tile)
+    t = m.n_cells
     info = m.info
-    assert info.n_tile_nodes > 0 and 0 < info.max_tile_nodes <= 256
+    assert info.n_tile_nodes > 0 and 0 < info.max_tile_nodes <= min(256, tile)
     off, nodes, en = m.tile_node_off, m.tile_nodes.reshape(-1, 2), m.edge_nodes.astype(np.int64)
     assert off[0] == 0 and off[-1] == info.n_tile_nodes and (np.diff(off) > 0).all()
     assert np.diff(off).max() == info.max_tile_nodes
@@ -444,3 +451,29 @@ def test_python_binding_refuses_inputs_the_kernels_would_read_out_of_bounds():
     s.mesh = m
     with pytest.raises(ValueError, match="holds 5 values for 8 steps"):
         s.run(8, dt_seq=torch.zeros(5, dtype=torch.float64))
+
+
+def test_tile_size_is_a_mesh_property():
+    """swe_mesh_create takes at most one tile-size flag; shards keep their mesh's size and a
+    batch takes meshes of one size only."""
+    c = gen.small(1)
+    for tile in (64, 128, 256, 512):
+        m = swe.Mesh(c.xy, c.tri, device=None, tile=tile)
+        assert m.info.tile_cells == tile and m.info.n_tiles == -(-c.n_cells // tile)
+        sh = swe.Mesh.shard(m, 100, 3000, device=None)
+        assert sh.info.tile_cells == tile
+    out = C.c_void_p()
+    xy = np.ascontiguousarray(c.xy, np.float64)
+    tri = np.ascontiguousarray(c.tri, np.int32)
+    two = swe.SWE_MORTON | swe._abi.SWE_TILE_64 | swe._abi.SWE_TILE_512
+    assert swe.lib.swe_mesh_create(xy.ctypes.data, len(xy), tri.ctypes.data, len(tri), None,
+                                   two, C.byref(out)) == swe.SWE_EINVAL
+    with pytest.raises(ValueError):
+        swe.Mesh(c.xy, c.tri, device=None, tile=100)
+    a = swe.Mesh(c.xy, c.tri, device=None, tile=64)
+    b = swe.Mesh(c.xy, c.tri, device=None, tile=128)
+    h = (C.c_void_p * 2)(a.handle.value, b.handle.value)
+    assert swe.lib.swe_batch_create(h, 2, C.byref(out)) == swe.SWE_EINVAL
+    assert "tile sizes" in swe.swe_last_error()
+    # workspace: room for the partials of the smallest tiles
+    assert swe.swe_workspace_bytes(c.n_cells) >= 16 * (-(-c.n_cells // 64))
