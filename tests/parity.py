@@ -54,18 +54,43 @@ def errors(case, gpu_fields, ora_fields):
     return e_h, e_hu, e_hv
 
 
-def fp32_momentum_tol(case, h_o):
-    """Absolute momentum tolerance of the FP32 path.
+def float_rounded(case):
+    """The case with bed, roughness, initial state and inflow discharges rounded to float32
+    (and held in float64): the inputs an FP32 run actually starts from.  The mesh is kept."""
+    import copy
+    c = copy.copy(case)
+    r = lambda a: None if a is None else np.asarray(a, np.float32).astype(np.float64)
+    c.z, c.n, c.h, c.hu, c.hv = r(case.z), r(case.n), r(case.h), r(case.hu), r(case.hv)
+    c.inflow_q = r(case.inflow_q)
+    return c
 
-    Storing the bed and the depth in float moves the free surface eta = h + z by up to
-    eps32 * max|eta|, which the hydrostatic reconstruction sees as a surface slope: the
-    discrete lake at rest is lost and velocities of order sqrt(g * eps32 * max|eta|) appear
-    (gravity-wave speed of that surface error).  Momentum errors of that velocity times the
-    largest depth are inherent to the FP32 state, not to the kernels."""
-    eps32 = float(np.finfo(np.float32).eps)
+
+def fp32_momentum_bound(case, ora_fields):
+    """Absolute bound on the momentum error of an FP32 run against the FP64 oracle started
+    from the same float-rounded inputs (`float_rounded`).
+
+    The FP32 target holds depth errors to delta = 1e-5 max h.  A depth (free-surface) error
+    moves as gravity waves, whose momentum perturbation is c times their surface perturbation
+    (c = sqrt(g h), from the Riemann invariants q +- c eta of the linearised equations); a
+    left- and a right-going part, each within delta, give momentum errors up to
+    2 c_max delta, c_max = sqrt(g max h).  Rounding of the momentum's own arithmetic adds
+    1e-5 of its magnitude (the same relative target as the depth)."""
+    h_o, hu_o, hv_o = ora_fields
     hmax = float(np.abs(h_o).max())
-    eta_max = float(np.abs(case.z).max()) + hmax
-    return hmax * math.sqrt(case.g * eps32 * eta_max)
+    delta = TOL_F32 * hmax
+    qmax = float(np.sqrt(hu_o * hu_o + hv_o * hv_o).max())
+    return 2.0 * math.sqrt(case.g * hmax) * delta + TOL_F32 * qmax
+
+
+def fp32_errors(case, gpu_fields, ora_fields):
+    """FP32 errors against the oracle of the float-rounded inputs: the depth error relative to
+    max h (target 1e-5) and the largest momentum error, as a vector (hu, hv), over its bound
+    `fp32_momentum_bound` (target 1)."""
+    h_g, hu_g, hv_g = gpu_fields
+    h_o, hu_o, hv_o = ora_fields
+    e_h = float(np.abs(h_g - h_o).max()) / float(np.abs(h_o).max())
+    e_q = float(np.sqrt((hu_g - hu_o) ** 2 + (hv_g - hv_o) ** 2).max())
+    return e_h, e_q / fp32_momentum_bound(case, ora_fields)
 
 
 def mask_mismatch(case, h_g, h_o, band=0.0):

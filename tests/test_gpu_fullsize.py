@@ -1,8 +1,9 @@
 """Full-size parity: configurations 2 (1,000,000 triangles, 1,000 steps) and 3 (10,000,000
 triangles, 500 steps, the benchmark workload) in the launch configuration the benchmark
 times.  Final states are compared on a seeded sample of cells against values the oracle wrote
-(tests/golden/make_golden.py); the first steps are compared on every cell against the oracle
-run here.  Tolerances as in the small-size parity tests."""
+(tests/golden/make_golden.py), a fixture that pins this host's oracle build too; the first
+steps are compared on every cell against the oracle run here.  Every cell of the final states
+is compared in test_gpu_configured.py."""
 import json
 import math
 import os
@@ -12,7 +13,7 @@ import pytest
 
 import gen
 import oracle
-from parity import TOL_F32, TOL_F64, errors, fp32_momentum_tol, quarter_turn, run_gpu
+from parity import TOL_F32, TOL_F64, errors, quarter_turn, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -65,11 +66,9 @@ def test_final_state_matches_oracle_samples(gpu, cases, k, dtype):
         assert wet == gd["wet_cells"]
         assert np.abs(h).max() == pytest.approx(hmax, rel=TOL_F64)
     else:
-        e_q = max(np.abs(hu[ids] - np.asarray(gd["hu"])).max(),
-                  np.abs(hv[ids] - np.asarray(gd["hv"])).max())
-        bound = fp32_momentum_tol(case, np.array([hmax]))
-        print(f"   momentum abs error {e_q:.3e}, bound {bound:.3e}")
-        assert e_h <= TOL_F32 and e_q <= bound
+        # depth and volume here; the momentum of the FP32 run is compared on every cell with
+        # the oracle of the float-rounded inputs (test_gpu_configured.py)
+        assert e_h <= TOL_F32
         assert st["t"] == pytest.approx(gd["t"], rel=1e-5)
         band = TOL_F32 * hmax
         assert abs(wet - gd["wet_cells"]) <= int((np.abs(h - case.h_dry) <= band).sum())
