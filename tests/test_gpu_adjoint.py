@@ -93,6 +93,8 @@ def test_tiled_and_per_cell_adjoints_agree(setup, gpu):
 
 
 def test_autograd_function(setup, gpu):
+    """AdjointLoss on host tensors and on device tensors: the same loss and gradients bit for
+    bit as Calibration.run; device inputs get device gradients (permuted on the device)."""
     import torch
     case, om, dts, obs, calib, j, grads = setup
     ts = [torch.tensor(a, requires_grad=True) for a in (case.n, case.z, case.h, case.hu, case.hv)]
@@ -101,6 +103,16 @@ def test_autograd_function(setup, gpu):
     assert loss.item() == j
     for t, g in zip(ts, grads):
         assert np.array_equal(t.grad.numpy(), 2.0 * g)
+    dev = calib.mesh.device
+    td = [torch.tensor(a, device=dev, requires_grad=True)
+          for a in (case.n, case.z, case.h, case.hu, case.hv)]
+    loss = gpu.AdjointLoss.apply(calib, *td)
+    loss.backward()
+    assert loss.device == dev and loss.item() == j
+    for t, g in zip(td, grads):
+        assert t.grad.device == dev and np.array_equal(t.grad.cpu().numpy(), g)
+    jd, gd = calib.run_device(*[t.detach() for t in td])
+    assert jd == j and all(x.device == dev for x in gd)
 
 
 @pytest.mark.parametrize("ckpt_every", [1, 2])
