@@ -336,6 +336,43 @@ def bench_adjoint(stream, steps: int = 2000) -> dict:
                   "adjoint_over_forward": t_adj / t_fwd, "loss": loss}
         del calib, out, runs
         torch.cuda.empty_cache()
+    # the same adjoint through torch.autograd with device tensors (AdjointLoss: inputs permuted
+    # to mesh order and gradients back on the device), against swe_adjoint alone
+    calib = swe.Calibration(mesh, np.array(dts), ex["gauges"], np.array(obs), ex["obs_every"],
+                            ckpt_every=ex["ckpt_every"])
+    ins = [torch.tensor(np.asarray(a, np.float64), device=mesh.device, requires_grad=True)
+           for a in (case.n, case.z, case.h, case.hu, case.hv)]
+
+    def autograd_once():
+        for t in ins:
+            t.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = swe.AdjointLoss.apply(calib, *ins)
+        loss.backward()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    sa = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64")
+    outs = [torch.empty(mesh.n_cells, dtype=torch.float64, device=mesh.device) for _ in range(5)]
+    g_raw = A.swe_grads(*[_ptr(o) for o in outs])
+
+    def raw_once():   # the C call alone on prepared device arrays; it synchronises (loss out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A.swe_adjoint(mesh.handle, mesh.dev, sa.params, sa.state, steps, _ptr(calib.dt),
+                      calib.loss, calib.ckpt_every, g_raw, _ptr(calib.ws), calib.ws.numel(),
+                      _stream_handle(None))
+        return time.perf_counter() - t0
+
+    autograd_once()
+    raw_once()
+    t_auto = min(autograd_once() for _ in range(3))
+    t_raw = min(raw_once() for _ in range(3))
+    res[ex["ckpt_every"]]["autograd_s"] = t_auto
+    res[ex["ckpt_every"]]["autograd_over_swe_adjoint"] = t_auto / t_raw
+    del calib, ins, sa, outs
+    torch.cuda.empty_cache()
     k0 = ex["ckpt_every"]
     record = res[1]
     record["gradients_bitwise_equal_to_checkpointed"] = bool(
@@ -346,7 +383,9 @@ def bench_adjoint(stream, steps: int = 2000) -> dict:
             "timing": "best of 3 after one warm-up, HIP events on the stream. forward_s: swe_run "
                       "of the steps with the replayed dt. adjoint_s: the whole swe_adjoint call; "
                       "its forward pass (checkpoints, or every state) and its reverse sweep "
-                      "(segment recompute, if any, and adjoint steps) from swe_adjoint_timings"}
+                      "(segment recompute, if any, and adjoint steps) from swe_adjoint_timings. "
+                      "autograd_s: AdjointLoss.apply and backward on device tensors, host wall "
+                      "clock between synchronisations, against the swe_adjoint call alone"}
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=10):
@@ -438,6 +477,8 @@ def main():
     ap.add_argument("--size", default="full", choices=["full", "small"],
                     help="small: the same recipe at 1e5 cells (quick checks)")
     ap.add_argument("--dtypes", default="f64,f32")
+    ap.add_argument("--tiles", default="64,128,256,512",
+                    help="tile sizes the autotuner compares (one mesh each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the 256-scenario ensemble (0: skip it)")
@@ -470,10 +511,16 @@ def main():
                                                                     lx=2000.0, ly=1600.0)
     t_gen = time.perf_counter() - t_gen
     t_mesh = time.perf_counter()
-    mesh = swe.Mesh(case.xy, case.tri, morton=True)
+    meshes = {swe.SWE_TILE: swe.Mesh(case.xy, case.tri, morton=True)}
     t_mesh = time.perf_counter() - t_mesh
     print(f"# {case.name}: {case.n_cells} cells, {case.n_nodes} nodes; generate {t_gen:.1f} s, "
           f"mesh build {t_mesh:.1f} s", file=sys.stderr, flush=True)
+    tiles = tuple(int(x) for x in args.tiles.split(","))
+
+    def mesh_of(tile):
+        if tile not in meshes:
+            meshes[tile] = swe.Mesh(case.xy, case.tri, morton=True, tile=tile)
+        return meshes[tile]
 
     stream = torch.cuda.Stream()
     results = {}
@@ -483,10 +530,20 @@ def main():
         runs.append(("f64_exact", "f64", True))   # correctly rounded FP64 division and sqrt
     for key, dt, exact in runs:
         if dt not in tuning:
-            # the autotuner picks the step variant and workgroup order that SWE_AUTO then runs
-            tuning[dt] = swe.tune.tune(mesh, case.z, case.n, case.h, case.hu, case.hv,
-                                       dtype=dt, steps=20)
-            print(f"# tuned {dt}: {tuning[dt]}", file=sys.stderr, flush=True)
+            # the autotuner picks the tile size (one mesh per size), then the step variant and
+            # workgroup order that SWE_AUTO runs on it
+            best, per_tile = swe.tune.tune_tiles(case.xy, case.tri, case.z, case.n, case.h,
+                                                 case.hu, case.hv, dtype=dt, steps=20,
+                                                 tiles=tiles)
+            tuning[dt] = {"tile": best, **per_tile[best],
+                          "ms_per_step_by_tile": {
+                              str(t): min(v for v in r["ms_per_step"].values() if v > 0)
+                              for t, r in per_tile.items()},
+                          "by_tile": {str(t): r for t, r in per_tile.items()}}
+            print(f"# tuned {dt}: tile {best}; best ms/step by tile "
+                  f"{tuning[dt]['ms_per_step_by_tile']}", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        mesh = mesh_of(tuning[dt]["tile"])
         solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt,
                             exact=exact)
         ms, rc, st, warm, windows = time_gpu(solver, args.steps, args.warmup, stream)
@@ -529,7 +586,8 @@ def main():
 
     shards = {}
     if args.size == "full" and not args.no_configs:
-        shards = bench_shards(mesh, case, stream)
+        shards = bench_shards(mesh_of(tuning.get("f64", {}).get("tile", swe.SWE_TILE)), case,
+                              stream)
         print(f"# shard {shards['shard']} of {shards['parts']}: {shards['n_owned']} owned + "
               f"{shards['n_halo']} halo cells, {shards['shard_ms_per_step']:.4f} ms/step alone; "
               f"all shards in turn {shards['all_shards_on_one_gpu_ms_per_step']:.4f} ms/step, "
@@ -555,7 +613,8 @@ def main():
               f"x{adjoint['reverse_over_forward']:.2f}); every step stored "
               f"({rec['workspace_GB']:.1f} GB): {rec['adjoint_s']:.3f} s "
               f"(x{rec['adjoint_over_forward']:.2f}; reverse sweep x{rec['reverse_over_forward']:.2f}), "
-              f"gradients bitwise equal {rec['gradients_bitwise_equal_to_checkpointed']}",
+              f"gradients bitwise equal {rec['gradients_bitwise_equal_to_checkpointed']}; "
+              f"through AdjointLoss x{adjoint['autograd_over_swe_adjoint']:.3f} of swe_adjoint",
               file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
