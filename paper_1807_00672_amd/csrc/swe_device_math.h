@@ -73,18 +73,17 @@ __device__ __forceinline__ double sqrt_nr(double a)
 
 // Cube root of a positive normal argument by Newton's iteration for r = x^(-1/3), which needs
 // no division: r <- r + r (1 - x r^3) / 3, from the single-precision seed 2^(-log2(x) / 3) (the
-// hardware log2 and exp2, relative error a few 1e-6 over the range taken here).  Two steps
-// reach double precision (the error squares each step); cbrt(x) = x r^2 with one residual
-// correction c <- c - (c^3 - x) r^2 / 3.  Zero, tiny, huge and non-finite arguments take the
-// library cbrt.
+// hardware log2 and exp2, relative error a few 1e-6 over the range taken here).  A seed error
+// e becomes -2 e^2 (about 1e-10) after one step; cbrt(x) = x r^2 with one residual correction
+// c <- c - (c^3 - x) r^2 / 3, which squares the error again, below the double rounding.  Zero,
+// tiny, huge and non-finite arguments take the library cbrt.
 __device__ __forceinline__ double cbrt_(double x)
 {
     if (!(x > 0x1p-120 && x < 0x1p120)) return cbrt(x);
     double r = static_cast<double>(
         __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(static_cast<float>(x)) * (-1.0f / 3.0f)));
     const double third = 1.0 / 3.0;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    {
         const double e = fma(-x * r, r * r, 1.0);
         r = fma(r * third, e, r);
     }

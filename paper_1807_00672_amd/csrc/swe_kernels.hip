@@ -299,23 +299,17 @@ __device__ __forceinline__ R inflow_flux(R g, R q_in, R h, R nx, R ny, R &fh, R 
 }
 
 // Semi-implicit Manning friction (eq. 1's S_f, section 2.2) of a wet cell after the flux
-// update: D = 1 + dt g n^2 |q*| / (h*^2 cbrt(h*)), q = q* / D.
+// update: D = 1 + dt g n^2 |q*| / (h*^2 cbrt(h*)), q = q* / D (the plain form; the fast forms
+// take it inside cell_finish).
 template <typename R>
 __device__ __forceinline__ void friction(R g, R dt, R nm, R hs, R hus, R hvs, R &hun, R &hvn)
 {
     const R mag = sqrt_(hus * hus + hvs * hvs);
     const R x = dt * g * nm * nm * mag;
     const R y = hs * hs * cbrt_(hs);
-    if constexpr (kFastForms<R>) {
-        // 1 / D = y / (y + x): one quotient for both components; D = 1 exactly when x = 0
-        const R rd = x > R(0) ? div_(y, y + x) : R(1);
-        hun = hus * rd;
-        hvn = hvs * rd;
-    } else {
-        const R d = R(1) + div_(x, y);
-        hun = div_(hus, d);
-        hvn = div_(hvs, d);
-    }
+    const R d = R(1) + div_(x, y);
+    hun = div_(hus, d);
+    hvn = div_(hvs, d);
 }
 
 template <typename R>
@@ -562,6 +556,60 @@ __device__ __forceinline__ R cell_dt(R g, R hd, R h, R hu, R hv, R inradius, con
     }
 }
 
+// The positivity clamp, the semi-implicit friction and the next CFL bound of one cell after its
+// flux update U* = (hs, hus, hvs) (eq. 4 and the source treatments of section 2.2).  Outputs
+// U^{n+1} = (hs, hun, hvn) (hs clamped in place), the cell's CFL bound and whether it clamped.
+template <typename R>
+__device__ __forceinline__ void cell_finish(R g, R hd, R dt, R nm, R inradius, R &hs, R hus,
+                                            R hvs, const int32_t *nb, const StepConfig &cfg,
+                                            const double *qtab, R &hun, R &hvn, R &dtc,
+                                            int &clamp)
+{
+    clamp = 0;
+    if (hs < R(0)) {
+        clamp = 1;
+        hs = R(0);
+    }
+    if constexpr (kFastForms<R>) {
+        // The CFL bound r / (|u| + sqrt(g h)) is formed as r h / (|q| + h sqrt(g h)) with
+        // |q| = |q*| / D, the magnitude the friction already took; the inflow speeds compare
+        // scaled by h alike.
+        const bool wet = hs > hd;
+        R num = inradius, sp = R(0);
+        if (wet) {
+            const R mag = sqrt_(hus * hus + hvs * hvs);
+            const R x = dt * g * nm * nm * mag;
+            const R y = hs * hs * cbrt_(hs);
+            // 1 / D = y / (y + x): one quotient for both components; D = 1 exactly when x = 0
+            const R rd = x > R(0) ? div_(y, y + x) : R(1);
+            hun = hus * rd;
+            hvn = hvs * rd;
+            num = inradius * hs;
+            sp = mag * rd + hs * sqrt_(g * hs);
+        } else {
+            hun = R(0);
+            hvn = R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (nb[k] < SWE_WALL) {
+                const double q = qtab ? qtab[-2 - nb[k]] : cfg.inflow_q[-2 - nb[k]];
+                R sb = inflow_speed(g, static_cast<R>(q), hs);
+                if (wet) sb = sb * hs;
+                if (sb > sp) sp = sb;
+            }
+        dtc = sp > R(0) ? div_(num, sp) : static_cast<R>(kInf);
+    } else {
+        if (hs > hd) {
+            friction(g, dt, nm, hs, hus, hvs, hun, hvn);
+        } else {
+            hun = R(0);
+            hvn = R(0);
+        }
+        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
+    }
+}
+
 // Where a workgroup's cells live when several meshes (scenarios) are stepped together: tile t
 // holds cells [tile_start[t], tile_start[t+1]) of scenario tile_scen[t], whose control block
 // is ctrl + tile_scen[t] * SWE_CTRL_BYTES and inflow discharges q_table[16 s ..].  A single
@@ -680,22 +728,13 @@ __global__ __launch_bounds__(TB, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a,
             a.us_hu[i] = hus;
             a.us_hv[i] = hvs;
         }
-        if (hs < R(0)) {
-            clamp = 1;
-            hs = R(0);
-        }
         R hun, hvn;
-        if (hs > hd) {
-            friction(g, dt, a.n[i], hs, hus, hvs, hun, hvn);
-        } else {
-            hun = R(0);
-            hvn = R(0);
-        }
+        cell_finish<R>(g, hd, dt, a.n[i], inradius, hs, hus, hvs, nb, cfg, qtab, hun, hvn, dtc,
+                       clamp);
         a.ho[i] = hs;
         a.huo[i] = hun;
         a.hvo[i] = hvn;
         if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
-        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
         if (i >= cfg.n_owned) {   // a shard's halo cell: refreshed by its owner
             dtc = static_cast<R>(kInf);
             clamp = 0;
@@ -1036,22 +1075,12 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
             st<O32>(a.us_hu, i, hus);
             st<O32>(a.us_hv, i, hvs);
         }
-        if (hs < R(0)) {
-            clamp = 1;
-            hs = R(0);
-        }
         R hun, hvn;
-        if (hs > hd) {
-            friction(g, dt, nm, hs, hus, hvs, hun, hvn);
-        } else {
-            hun = R(0);
-            hvn = R(0);
-        }
+        cell_finish<R>(g, hd, dt, nm, inradius, hs, hus, hvs, nb, cfg, qtab, hun, hvn, dtc, clamp);
         st<O32>(a.ho, i, hs);
         st<O32>(a.huo, i, hun);
         st<O32>(a.hvo, i, hvn);
         if (!isfinite(hs) || !isfinite(hun) || !isfinite(hvn)) flag = kStatusNonFinite;
-        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
         if (i >= cfg.n_owned) {   // a shard's halo cell: refreshed by its owner
             dtc = static_cast<R>(kInf);
             clamp = 0;
