@@ -57,6 +57,14 @@ struct Partials {
     uint32_t *count;    // [n_groups(nb) + 1] arrivals per group, then of the groups
 };
 
+// A single mesh's step merges the partials of every kSlotTiles consecutive tiles into one slot
+// of the per-tile arrays (slot q at index q, q < n_slots(nb)) with device-scope atomics; the bit
+// pattern of +inf is the reset value of a slot's bound, which the workgroups lower by an
+// unsigned min of their bounds' bits.
+constexpr int kSlotTiles = 16;
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
+constexpr int64_t n_slots(int64_t nb) { return (nb + kSlotTiles - 1) / kSlotTiles; }
+
 inline int64_t n_tiles_of(int64_t n_cells, int64_t tile) { return (n_cells + tile - 1) / tile; }
 inline int64_t n_groups(int64_t nb) { return (nb + kGroup - 1) / kGroup; }
 inline int64_t round256(int64_t b) { return ((b + 255) / 256) * 256; }

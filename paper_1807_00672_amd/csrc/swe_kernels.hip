@@ -51,10 +51,12 @@ constexpr double kInf = __builtin_huge_val();
 #ifndef SWE_F32_FAST
 #define SWE_F32_FAST 1
 #endif
-// 1: a single mesh's step partials are folded by many workgroups (dt_fold_kernel); 0: by the
-// one-workgroup dt pass that batches use per scenario.
-#ifndef SWE_DT_FOLD
-#define SWE_DT_FOLD 1
+// 1: the workgroups of a single mesh's step merge their dt partials into one slot per
+// kSlotTiles tiles with relaxed device-scope atomics (min of the bound's bits, clamp count,
+// status bits), and one workgroup folds the slots after the step (dt_group_fold_kernel); 0:
+// they write per-tile partials, which dt_fold_kernel folds over many workgroups.
+#ifndef SWE_GROUP_ATOMIC
+#define SWE_GROUP_ATOMIC 1
 #endif
 // Single-mesh steps of at most this many tiles finish their dt reduction themselves (the last
 // workgroup to arrive folds the partials) instead of launching the fold kernel.  Each
@@ -385,19 +387,17 @@ __device__ __forceinline__ int wave_or(int v)
     return v;
 }
 
-// Block-wide (TB work-items) min of the CFL bounds, count of clamps and status of a
-// step; thread 0 writes them as partials[slot].  A work-item's flag is 0 or
-// kStatusNonFinite and its clamp 0 or 1, so one integer sum carries both: clamps in the low
-// 16 bits, flagged work-items above them.
+// Block-wide (TB work-items) min of the CFL bounds, count of clamps and status of a step, on
+// thread 0.  A work-item's flag is 0 or kStatusNonFinite and its clamp 0 or 1, so one integer
+// sum carries both: clamps in the low 16 bits, flagged work-items above them.
 template <int TB>
-__device__ __forceinline__ void block_partials_at(double dtc, int clamp, int flag,
-                                                  const Partials &part, int slot)
+__device__ __forceinline__ void block_reduce(double &dtc, int clamp, int flag, int &cf)
 {
     static_assert(TB < (1 << 16), "clamp count must fit 16 bits");
     __shared__ double s_dt[TB / 64];
     __shared__ int s_cf[TB / 64];
     dtc = wave_min(dtc);
-    int cf = wave_sum(clamp + (flag ? (1 << 16) : 0));
+    cf = wave_sum(clamp + (flag ? (1 << 16) : 0));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
         s_dt[wv] = dtc;
@@ -409,9 +409,45 @@ __device__ __forceinline__ void block_partials_at(double dtc, int clamp, int fla
             dtc = fmin(dtc, s_dt[w]);
             cf += s_cf[w];
         }
+    }
+}
+
+// The block's partials written as partials[slot] (thread 0).
+template <int TB>
+__device__ __forceinline__ void block_partials_at(double dtc, int clamp, int flag,
+                                                  const Partials &part, int slot)
+{
+    int cf;
+    block_reduce<TB>(dtc, clamp, flag, cf);
+    if (threadIdx.x == 0) {
         part.dt[slot] = dtc;
         part.clamps[slot] = cf & 0xffff;
         part.flags[slot] = (cf >> 16) != 0 ? kStatusNonFinite : 0;
+    }
+}
+
+// The block's partials merged into slot tile / kSlotTiles (thread 0): the bound by an unsigned
+// min of its bits (the order of non-negative doubles, with +inf and the NaNs above every
+// number, as fmin ignores a NaN), the clamps by an add and the status by an or (both only when
+// non-zero); relaxed device-scope atomics, read after the step by dt_group_fold_kernel.  A
+// slot takes few workgroups' atomics: one address taking hundreds per step serialises them.
+template <int TB>
+__device__ __forceinline__ void block_partials_group(double dtc, int clamp, int flag,
+                                                     const Partials &part, int slot)
+{
+    int cf;
+    block_reduce<TB>(dtc, clamp, flag, cf);
+    if (threadIdx.x == 0) {
+        const int q = slot / kSlotTiles;
+        __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(part.dt) + q,
+                               static_cast<unsigned long long>(__double_as_longlong(dtc)),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cf & 0xffff)
+            __hip_atomic_fetch_add(part.clamps + q, cf & 0xffff, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (cf >> 16)
+            __hip_atomic_fetch_or(part.flags + q, static_cast<int32_t>(kStatusNonFinite),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -476,16 +512,21 @@ struct Advance {
     int32_t pad;
 };
 
-// Block partials of tile `slot`; with adv.ctrl, the last workgroup to arrive (a release
-// increment by each, an acquire before reading) folds all n_tiles partials and advances the
-// control block.  No workgroup waits for another; every one read the control block before it
-// arrived.
+// Block partials of tile `slot`: merged into its slot (group: a single mesh's step with a fold
+// kernel after it) or written as the tile's partials; with Fuse and adv.ctrl, the last
+// workgroup to arrive (a release increment by each, an acquire before reading) folds all
+// n_tiles partials and advances the control block.  No workgroup waits for another; every one
+// read the control block before it arrived.
 // Fuse selects this at compile time: the kernels without it run measurably faster on large
 // grids even though the branch is never taken there.
 template <int TB, bool Fuse>
 __device__ __forceinline__ void finish_step(double dtc, int clamp, int flag, const Partials &part,
-                                            int slot, int n_tiles, const Advance &adv)
+                                            int slot, int n_tiles, const Advance &adv, bool group)
 {
+    if (!Fuse && group) {
+        block_partials_group<TB>(dtc, clamp, flag, part, slot);
+        return;
+    }
     block_partials_at<TB>(dtc, clamp, flag, part, slot);
     if constexpr (Fuse) {
     if (!adv.ctrl || threadIdx.x >= 64) return;
@@ -742,7 +783,8 @@ __global__ __launch_bounds__(TB, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a,
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv);
+    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv,
+                          SWE_GROUP_ATOMIC && !batched);
 }
 
 // ------------------------------------------------------------------------ tiled step
@@ -1088,7 +1130,8 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv);
+    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv,
+                          SWE_GROUP_ATOMIC && !batched);
 }
 
 // CFL bounds of the initial state.
@@ -1119,6 +1162,32 @@ __global__ __launch_bounds__(TB) void init_kernel(StepArgs<R> a, StepConfig cfg,
 
 constexpr int kPassThreads = 1024;
 
+// Min, sum and or over the kPassThreads work-items of a workgroup, the result on work-item 0;
+// every work-item calls it (one barrier).
+__device__ __forceinline__ void pass_reduce(double &m, long long &cl, int &fl)
+{
+    __shared__ double s_dt[kPassThreads / 64];
+    __shared__ long long s_cl[kPassThreads / 64];
+    __shared__ int s_fl[kPassThreads / 64];
+    m = wave_min(m);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cl += __shfl_xor(cl, off, 64);
+    fl = wave_or(fl);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_dt[wv] = m;
+        s_cl[wv] = cl;
+        s_fl[wv] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < kPassThreads / 64; ++w) {
+            m = fmin(m, s_dt[w]);
+            cl += s_cl[w];
+            fl |= s_fl[w];
+        }
+}
+
 // Reduce the per-block partials into the control block: account for the step just taken
 // (mode 1) or start the state (mode 0, which also clears the arrival counter of
 // dt_fold_kernel), then set the next step's dt (CFL, replayed, or cut at t_end).
@@ -1133,9 +1202,6 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
     Ctrl *ctrl = const_cast<Ctrl *>(ctrl_of(ctrl_base, blockIdx.x));
     const int64_t b_lo = bt.scen_tile_off ? bt.scen_tile_off[blockIdx.x] : 0;
     const int64_t b_hi = bt.scen_tile_off ? bt.scen_tile_off[blockIdx.x + 1] : nb;
-    __shared__ double s_dt[kPassThreads / 64];
-    __shared__ long long s_cl[kPassThreads / 64];
-    __shared__ int s_fl[kPassThreads / 64];
     if (mode == 0 && blockIdx.x == 0)
         for (int64_t q = threadIdx.x; q <= (nb + kGroup - 1) / kGroup; q += kPassThreads)
             part.count[q] = 0;
@@ -1164,23 +1230,17 @@ __global__ __launch_bounds__(kPassThreads) void dt_pass_kernel(Ctrl *ctrl_base, 
             fl |= f[u];
         }
     }
-    m = wave_min(m);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) cl += __shfl_xor(cl, off, 64);
-    fl = wave_or(fl);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-        s_dt[wv] = m;
-        s_cl[wv] = cl;
-        s_fl[wv] = fl;
+    pass_reduce(m, cl, fl);
+    if (mode == 0 && !bt.scen_tile_off) {
+        // a single mesh's first step merges its partials into the slots (dt_group_fold_kernel
+        // resets them after each step): they start reset, now that the partials are read
+        for (int64_t q = threadIdx.x; q < n_slots(nb); q += kPassThreads) {
+            reinterpret_cast<unsigned long long *>(part.dt)[q] = kInfBits;
+            part.clamps[q] = 0;
+            part.flags[q] = 0;
+        }
     }
-    __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int w = 1; w < kPassThreads / 64; ++w) {
-        m = fmin(m, s_dt[w]);
-        cl += s_cl[w];
-        fl |= s_fl[w];
-    }
     if (mode == 1) {
         advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq, shard);
         return;
@@ -1242,6 +1302,49 @@ __device__ __forceinline__ void fold_group(double &m, long long &cl, int &fl)
             fl |= s_fl[w];
         }
     __syncthreads();
+}
+
+// The dt pass of a single mesh after a step whose workgroups merged their partials into the
+// slots: one workgroup folds the ns slots, resets them for the next step (+inf, 0, 0) and
+// advances the control block.  A step skipped as done merged nothing: the slots stay reset.
+__global__ __launch_bounds__(kPassThreads) void dt_group_fold_kernel(Ctrl *ctrl, Partials part,
+                                                                    int64_t ns, double courant,
+                                                                    const double *dt_seq,
+                                                                    int64_t n_seq, int shard)
+{
+    if (ctrl->done) return;   // uniform
+    unsigned long long *const bits = reinterpret_cast<unsigned long long *>(part.dt);
+    double m = kInf;
+    long long cl = 0;
+    int fl = 0;
+    // kUnroll independent loads per work-item in flight: latency, not bandwidth, bounds this
+    constexpr int kUnroll = 4;
+    for (int64_t q0 = threadIdx.x; q0 < ns; q0 += kPassThreads * kUnroll) {
+        unsigned long long v[kUnroll];
+        int c[kUnroll], f[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t q = q0 + static_cast<int64_t>(u) * kPassThreads;
+            const bool in = q < ns;
+            v[u] = in ? bits[q] : kInfBits;
+            c[u] = in ? part.clamps[q] : 0;
+            f[u] = in ? part.flags[q] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t q = q0 + static_cast<int64_t>(u) * kPassThreads;
+            if (q < ns) {
+                bits[q] = kInfBits;
+                part.clamps[q] = 0;
+                part.flags[q] = 0;
+            }
+            m = fmin(m, __longlong_as_double(static_cast<long long>(v[u])));
+            cl += c[u];
+            fl |= f[u];
+        }
+    }
+    pass_reduce(m, cl, fl);
+    if (threadIdx.x == 0) advance_ctrl(ctrl, m, cl, fl, courant, dt_seq, n_seq, shard);
 }
 
 // The dt pass of a single mesh, spread over the chip: workgroup q folds the partials of tiles
@@ -1652,7 +1755,10 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     });
     if (e != hipSuccess) return e;
     if (dt_direct || fuse) return static_cast<int>(hipSuccess);   // nothing more to launch
-    if (SWE_DT_FOLD && batch == nullptr)
+    if (batch == nullptr && SWE_GROUP_ATOMIC)
+        dt_group_fold_kernel<<<1, dim3(kPassThreads), 0, st>>>(
+            static_cast<Ctrl *>(s.ctrl), part, n_slots(nb), cfg.courant, dt_seq, n_seq, cfg.shard);
+    else if (batch == nullptr)
         dt_fold_kernel<<<dim3(n_groups(nb)), dim3(kGroup), 0, st>>>(
             static_cast<Ctrl *>(s.ctrl), part, nb, cfg.courant, dt_seq, n_seq, cfg.shard);
     else

@@ -28,11 +28,17 @@ int32_t sfail(int32_t code, const std::string &msg)
     return code;
 }
 
-// Arrival counters must read zero when a state's steps begin.
-__global__ void clear_counters_kernel(uint32_t *count, int64_t n)
+// Arrival counters must read zero, and the step's slots +inf (the bound's bits), 0 and 0, when
+// a state's steps begin: n_count counters, n_slot slots.
+__global__ void clear_counters_kernel(Partials part, int64_t n_count, int64_t n_slot)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) count[i] = 0u;
+    if (i < n_count) part.count[i] = 0u;
+    if (i < n_slot) {
+        reinterpret_cast<unsigned long long *>(part.dt)[i] = kInfBits;
+        part.clamps[i] = 0;
+        part.flags[i] = 0;
+    }
 }
 
 }  // namespace
@@ -79,9 +85,10 @@ extern "C" int32_t swe_run_static(const swe_mesh *mesh, const swe_dev_mesh *dm,
     st.work = work;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const Partials part = partials_for(work, nb);
-    const int64_t n_count = n_groups(nb) + 1;
-    clear_counters_kernel<<<dim3(static_cast<unsigned>((n_count + 255) / 256)), 256, 0, hs>>>(
-        part.count, n_count);
+    const int64_t n_count = n_groups(nb) + 1, n_slot = n_slots(nb);
+    const int64_t n_clear = n_count > n_slot ? n_count : n_slot;
+    clear_counters_kernel<<<dim3(static_cast<unsigned>((n_clear + 255) / 256)), 256, 0, hs>>>(
+        part, n_count, n_slot);
     if (hipGetLastError() != hipSuccess)
         return sfail(SWE_EDEVICE, "swe_run_static: counter clear failed to launch");
     if (init) {
