@@ -503,7 +503,14 @@ def main():
 
     if args.probe == "copy":
         gbps = copy_bandwidth()
-        print(json.dumps({"probe": "copy", "bytes_per_copy": 2 << 30, "GBps": gbps}), flush=True)
+        # two more kernels of known traffic for the counter calibration: a read-only sum and a
+        # write-only fill of the same 2 GiB
+        a = torch.ones((2 << 30) // 8, dtype=torch.float64, device="cuda")
+        total = float(a.sum())
+        a.fill_(2.0)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_per_copy": 2 << 30, "GBps": gbps,
+                          "sum_of_ones": total}), flush=True)
         return
 
     t_gen = time.perf_counter()
