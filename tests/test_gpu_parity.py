@@ -275,9 +275,12 @@ def test_tiny_meshes(gpu):
     assert max(errors(two, g, ora)) <= TOL_F64
 
 
-def test_dry_and_nonfinite_states_are_reported(gpu):
+@pytest.mark.parametrize("large", [False, True])
+def test_dry_and_nonfinite_states_are_reported(gpu, large):
+    """Up to 128 tiles the step folds its dt partials itself; the 40,000-cell mesh (157 tiles)
+    merges them into atomic slots that a fold kernel reads."""
     import paper_1807_00672_amd as swe
-    case = gen.small(1)
+    case = gen.dam_break(nx=200, ny=100, lx=40.0, ly=20.0) if large else gen.small(1)
     z = np.zeros(case.n_cells)
     dry = gen.Case("dry", case.xy, case.tri, z, z, z, z, z, 5)
     rc, st, *_ = run_gpu(dry, "f64")
@@ -294,9 +297,30 @@ def test_dry_and_nonfinite_states_are_reported(gpu):
     assert rc == swe.SWE_ENONFINITE
 
 
+def test_clamps_counted_through_the_atomic_slots(gpu):
+    """A thin moving sheet stepped with a replayed dt about 2.5 times its CFL bound: a few cells
+    drain below zero and are clamped.  On 40,000 cells (157 tiles) the step merges its clamp
+    counts through the atomic slots; count, steps and fields against the oracle."""
+    import copy
+    case = copy.copy(gen.dam_break(nx=200, ny=100, lx=40.0, ly=20.0, h_right=0.0))
+    case.h = np.full(case.n_cells, 0.01)
+    case.hu = np.full(case.n_cells, 0.05)
+    seq = np.full(6, 0.015)
+    rc_o, *ora, dts, st_o = run_oracle(case, steps=6, dt_seq=seq)
+    rc_g, st_g, *g = run_gpu(case, "f64", steps=6, dt_seq=seq)
+    e = errors(case, g, ora)
+    print(f"clamps {st_g['clamps']} vs {st_o['clamps']}; errors {e}")
+    assert rc_o == 0 and rc_g == 0 and st_o["clamps"] > 0
+    assert st_g["clamps"] == st_o["clamps"] and st_g["steps"] == st_o["steps"] == 6
+    assert max(e) <= TOL_F64
+
+
+@pytest.mark.parametrize("nx", [120, 360])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_three_mound_wet_dry_parity(gpu, dtype):
-    case = gen.three_mounds()
+def test_three_mound_wet_dry_parity(gpu, dtype, nx):
+    """11,520 cells (45 tiles: the step folds its dt partials itself) and 103,680 (405 tiles:
+    atomic slots and a fold kernel), 600 steps with clamps and wet/dry fronts."""
+    case = gen.three_mounds(nx=nx, ny=nx * 2 // 5)
     rc_o, *ora, dts, st_o = run_oracle(case if dtype == "f64" else float_rounded(case))
     rc_g, st_g, *g = run_gpu(case, dtype)
     assert rc_o == 0 and rc_g == 0 and st_g["steps"] == st_o["steps"] == case.steps
