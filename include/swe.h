@@ -185,8 +185,9 @@ typedef struct swe_state {
     const void *n;               /* Manning coefficient, T values, >= 0 */
     void *ctrl;                  /* SWE_CTRL_BYTES, 16-byte aligned: time, dt, counters */
     void *work;                  /* swe_workspace_bytes(T) bytes, 256-byte aligned: step
-                                    partials and arrival counters that swe_state_init clears;
-                                    never shared by two states */
+                                    partials (a single mesh's steps merge them into atomic
+                                    slots) and arrival counters, which swe_state_init resets
+                                    and every step leaves reset; never shared by two states */
     int32_t cur;                 /* host: buffer holding the current state */
     int32_t reserved;
 } swe_state;
