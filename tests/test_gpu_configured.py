@@ -5,7 +5,8 @@ Table 2's scale.  Here the FP64 oracle runs on this host inside the test (once p
 configuration) and the HIP path runs in the launch configuration the benchmark times:
 
 - configurations 2 (1,000,000 triangles, 1,000 steps) and 3 (10,000,000 triangles, 500 steps):
-  FP64 every field within 1e-12 of its scale, identical wet/dry masks, clamp and step counts;
+  FP64 (both arithmetic modes) every field within 1e-12 of its scale, identical wet/dry masks,
+  clamp and step counts;
   FP32 against the oracle started from the same float-rounded inputs (bed, roughness and state
   rounded to float32 and back), h within 1e-5 of max h, momentum within the bound of
   tests/parity.py (fp32_momentum_bound), masks identical outside the band of 1e-5 max h
@@ -59,14 +60,18 @@ def _oracle(store, k, rounded):
     return store[key]
 
 
+@pytest.mark.parametrize("exact", [False, True])
 @pytest.mark.parametrize("k", [2, 3])
-def test_fp64_every_cell_at_the_configured_size(gpu, store, k):
+def test_fp64_every_cell_at_the_configured_size(gpu, store, k, exact):
+    """Both FP64 arithmetic modes: the fast forms and SWE_EXACT (correctly rounded division and
+    square root)."""
     case = _case(store, k)
     h_o, hu_o, hv_o, st_o = _oracle(store, k, False)
-    rc, st, h, hu, hv = run_gpu(case, "f64")
+    rc, st, h, hu, hv = run_gpu(case, "f64", exact=exact)
     e = errors(case, (h, hu, hv), (h_o, hu_o, hv_o))
     mism, _ = mask_mismatch(case, h, h_o)
-    print(f"config {k} f64, {case.n_cells} cells x {case.steps} steps: errors h {e[0]:.2e} "
+    mode = "f64 exact" if exact else "f64"
+    print(f"config {k} {mode}, {case.n_cells} cells x {case.steps} steps: errors h {e[0]:.2e} "
           f"hu {e[1]:.2e} hv {e[2]:.2e}; wet/dry mismatches {mism}; t {st['t']!r} vs "
           f"{st_o['t']!r}; clamps {st['clamps']} vs {st_o['clamps']}", flush=True)
     assert rc == 0 and st["steps"] == st_o["steps"] == case.steps
