@@ -117,8 +117,9 @@ __device__ __forceinline__ float sqrt_<float>(float a)
 // Fast forms (FP32, and FP64 outside SWE_EXACT): quotients by one divisor share its
 // reciprocal; an edge's length and reciprocal length come from one reciprocal square root; the
 // friction factor and the CFL bound are rearranged to one quotient each.  A velocity is the
-// momentum times the depth's reciprocal (within 1.5 ulp); the HLL fluxes and the unit normals,
-// where cancellation would magnify that, refine each product by one residual step (quot,
+// momentum times the depth's reciprocal (within 1.5 ulp), and so are a cell's dt/A, friction
+// factor and CFL bound; the HLL fluxes and the unit normals, where cancellation would magnify
+// that, refine each product by one residual step (quot,
 // within an ulp, nearly always the correctly rounded quotient).  Every form is odd in the
 // arguments whose sign a mirrored interface flips, so the two sides of an interface still give
 // exact negatives.  SWE_EXACT keeps the plain definitions with correctly rounded division and
@@ -301,17 +302,24 @@ __device__ __forceinline__ R inflow_flux(R g, R q_in, R h, R nx, R ny, R &fh, R 
 }
 
 // Semi-implicit Manning friction (eq. 1's S_f, section 2.2) of a wet cell after the flux
-// update: D = 1 + dt g n^2 |q*| / (h*^2 cbrt(h*)), q = q* / D (the plain form; the fast forms
-// take it inside cell_finish).
+// update: D = 1 + dt g n^2 |q*| / (h*^2 cbrt(h*)), q = q* / D.
 template <typename R>
 __device__ __forceinline__ void friction(R g, R dt, R nm, R hs, R hus, R hvs, R &hun, R &hvn)
 {
     const R mag = sqrt_(hus * hus + hvs * hvs);
     const R x = dt * g * nm * nm * mag;
     const R y = hs * hs * cbrt_(hs);
-    const R d = R(1) + div_(x, y);
-    hun = div_(hus, d);
-    hvn = div_(hvs, d);
+    if constexpr (kFastForms<R>) {
+        // 1 / D = y / (y + x) as y times the reciprocal (within 1.5 ulp), for both
+        // components; D = 1 exactly when x = 0
+        const R rd = x > R(0) ? y * rcp_(y + x) : R(1);
+        hun = hus * rd;
+        hvn = hvs * rd;
+    } else {
+        const R d = R(1) + div_(x, y);
+        hun = div_(hus, d);
+        hvn = div_(hvs, d);
+    }
 }
 
 template <typename R>
@@ -365,12 +373,39 @@ __device__ __forceinline__ void cell_geometry(const double2 *__restrict__ xy, in
 
 // ------------------------------------------------------------------------ reductions
 
-template <typename T>
-__device__ __forceinline__ T wave_min(T v)
+// A lane's double from another lane of its row of 16 by a DPP move (Ctrl: a quad permutation
+// or a row mirror), as two 32-bit moves; every lane of the wave active.
+template <int Ctrl>
+__device__ __forceinline__ double dpp_double(double v)
 {
+    const long long b = __double_as_longlong(v);
+    const int lo = static_cast<int>(b), hi = static_cast<int>(b >> 32);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, Ctrl, 0xF, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, Ctrl, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(static_cast<unsigned>(hi2)) << 32) |
+                                static_cast<unsigned>(lo2));
+}
+
+// Minimum over the wave (fmin: a NaN counts only where every value is one), on every lane and
+// with every lane active: within each row of 16 lanes by DPP moves (lane xor 1, lane xor 2,
+// the half-row mirror, the row mirror), then the four rows' minima read from one lane each.
+// No LDS traffic, unlike a shuffle through ds_bpermute.
+__device__ __forceinline__ double wave_min(double v)
+{
+    v = fmin(v, dpp_double<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+    v = fmin(v, dpp_double<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+    v = fmin(v, dpp_double<0x141>(v));   // row_half_mirror
+    v = fmin(v, dpp_double<0x140>(v));   // row_mirror
+    const long long b = __double_as_longlong(v);
+    const int lo = static_cast<int>(b), hi = static_cast<int>(b >> 32);
+    double r[4];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-    return v;
+    for (int q = 0; q < 4; ++q) {
+        const unsigned l = static_cast<unsigned>(__builtin_amdgcn_readlane(lo, 16 * q));
+        const unsigned h = static_cast<unsigned>(__builtin_amdgcn_readlane(hi, 16 * q));
+        r[q] = __longlong_as_double((static_cast<long long>(h) << 32) | l);
+    }
+    return fmin(fmin(r[0], r[1]), fmin(r[2], r[3]));
 }
 
 __device__ __forceinline__ int wave_sum(int v)
@@ -388,8 +423,9 @@ __device__ __forceinline__ int wave_or(int v)
 }
 
 // Block-wide (TB work-items) min of the CFL bounds, count of clamps and status of a step, on
-// thread 0.  A work-item's flag is 0 or kStatusNonFinite and its clamp 0 or 1, so one integer
-// sum carries both: clamps in the low 16 bits, flagged work-items above them.
+// thread 0.  A work-item's flag is 0 or kStatusNonFinite and its clamp 0 or 1: a wave counts
+// its clamps and flags from ballots, and one integer sum across the waves carries both, clamps
+// in the low 16 bits, flagged waves above them.
 template <int TB>
 __device__ __forceinline__ void block_reduce(double &dtc, int clamp, int flag, int &cf)
 {
@@ -397,7 +433,7 @@ __device__ __forceinline__ void block_reduce(double &dtc, int clamp, int flag, i
     __shared__ double s_dt[TB / 64];
     __shared__ int s_cf[TB / 64];
     dtc = wave_min(dtc);
-    cf = wave_sum(clamp + (flag ? (1 << 16) : 0));
+    cf = __popcll(__ballot(clamp != 0)) + (__ballot(flag != 0) ? (1 << 16) : 0);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
         s_dt[wv] = dtc;
@@ -558,6 +594,8 @@ __device__ __forceinline__ void finish_step(double dtc, int clamp, int flag, con
 
 // CFL bound r / (|u| + sqrt(g h)) of a cell (inflow edges add their boundary speed);
 // +inf for a dry cell without inflow.  qtab: the scenario's inflow discharges (nullptr: cfg's).
+// A function of the cell's state alone, the same in a step's epilogue and in the initial pass,
+// so that a run restarted from a saved state takes the uninterrupted run's dt.
 template <typename R>
 __device__ __forceinline__ R cell_dt(R g, R hd, R h, R hu, R hv, R inradius, const int32_t *nb,
                                      const StepConfig &cfg, const double *qtab = nullptr)
@@ -579,7 +617,7 @@ __device__ __forceinline__ R cell_dt(R g, R hd, R h, R hu, R hv, R inradius, con
                 if (wet) sb = sb * h;
                 if (sb > s) s = sb;
             }
-        return s > R(0) ? div_(num, s) : static_cast<R>(kInf);
+        return s > R(0) ? num * rcp_(s) : static_cast<R>(kInf);   // within 1.5 ulp
     } else {
         R s = R(0);
         if (h > hd) {
@@ -611,44 +649,13 @@ __device__ __forceinline__ void cell_finish(R g, R hd, R dt, R nm, R inradius, R
         clamp = 1;
         hs = R(0);
     }
-    if constexpr (kFastForms<R>) {
-        // The CFL bound r / (|u| + sqrt(g h)) is formed as r h / (|q| + h sqrt(g h)) with
-        // |q| = |q*| / D, the magnitude the friction already took; the inflow speeds compare
-        // scaled by h alike.
-        const bool wet = hs > hd;
-        R num = inradius, sp = R(0);
-        if (wet) {
-            const R mag = sqrt_(hus * hus + hvs * hvs);
-            const R x = dt * g * nm * nm * mag;
-            const R y = hs * hs * cbrt_(hs);
-            // 1 / D = y / (y + x): one quotient for both components; D = 1 exactly when x = 0
-            const R rd = x > R(0) ? div_(y, y + x) : R(1);
-            hun = hus * rd;
-            hvn = hvs * rd;
-            num = inradius * hs;
-            sp = mag * rd + hs * sqrt_(g * hs);
-        } else {
-            hun = R(0);
-            hvn = R(0);
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            if (nb[k] < SWE_WALL) {
-                const double q = qtab ? qtab[-2 - nb[k]] : cfg.inflow_q[-2 - nb[k]];
-                R sb = inflow_speed(g, static_cast<R>(q), hs);
-                if (wet) sb = sb * hs;
-                if (sb > sp) sp = sb;
-            }
-        dtc = sp > R(0) ? div_(num, sp) : static_cast<R>(kInf);
+    if (hs > hd) {
+        friction(g, dt, nm, hs, hus, hvs, hun, hvn);
     } else {
-        if (hs > hd) {
-            friction(g, dt, nm, hs, hus, hvs, hun, hvn);
-        } else {
-            hun = R(0);
-            hvn = R(0);
-        }
-        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
+        hun = R(0);
+        hvn = R(0);
     }
+    dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
 }
 
 // Where a workgroup's cells live when several meshes (scenarios) are stepped together: tile t
@@ -760,7 +767,7 @@ __global__ __launch_bounds__(TB, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a,
         }
         // explicit Euler update, positivity clamp, semi-implicit friction
         const R area = a.cell_geo[i], inradius = a.cell_geo[T + i];
-        const R r = div_(dt, area);
+        const R r = kFastForms<R> ? dt * rcp_(area) : div_(dt, area);   // dt / A
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
@@ -1108,7 +1115,7 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
                 acc0 = acc0 + c0; acc1 = acc1 + c1; acc2 = acc2 + c2;
             }
         }
-        const R r = div_(dt, area);
+        const R r = kFastForms<R> ? dt * rcp_(area) : div_(dt, area);   // dt / A
         R hs = h - r * acc0;
         const R hus = hu - r * acc1;
         const R hvs = hv - r * acc2;
