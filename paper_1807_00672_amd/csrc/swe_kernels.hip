@@ -849,9 +849,9 @@ struct TileArgs {
     int32_t n_tiles, max_halo, max_edges, max_nodes;
 };
 
-// LDS of the tiled step: the tile + halo states (h, u, v, z) and five values per edge-list
-// entry (side a's contribution and side b's momentum contribution; side b's mass part is
-// -a's).
+// LDS of the tiled step: the tile + halo states ((h, u, v, z) interleaved per cell) and five
+// values per edge-list entry (side a's contribution and side b's momentum contribution; side
+// b's mass part is -a's).
 // Plain layout: [states | 5 rows of max_edges].  Shared layout (at most 2 TB entries, TB the
 // tile's cells): [5 rows of TB for entries 0..TB-1 | states], the entries from TB on written in
 // 5 rows of TB over the states once every interface of the tile has been evaluated.  An FP64
@@ -939,10 +939,11 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
     const int ebase = alias ? 0 : 4 * ns;
     const int estride = alias ? TB : ta.max_edges;
     const int bshift = alias ? 4 * TB : 0;
-    R *s_h = lds + sbase;
-    R *s_u = s_h + ns;
-    R *s_v = s_u + ns;
-    R *s_z = s_v + ns;
+    // staged cells' (h, u, v, z) interleaved: one cell in two 16-byte LDS accesses (FP64)
+    struct alignas(16) St {
+        R h, u, v, z;
+    };
+    St *const s_st = reinterpret_cast<St *>(lds + sbase);
     // Nodes (FP64 with node lists): the tile's nodes after the layout's other words (an even
     // count, so 16-byte aligned), each entry's edge vector formed from them
     constexpr bool nodes = Nodes;
@@ -999,20 +1000,14 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
         const int32_t c = ld<O32>(ta.halo, j);
         const R hh = ld<O32>(a.h, c);
         const int q = TB + (j - hb);
-        s_h[q] = hh;
         R uu, vv;
         velocities(hh, ld<O32>(a.hu, c), ld<O32>(a.hv, c), hd, uu, vv);
-        s_u[q] = uu;
-        s_v[q] = vv;
-        s_z[q] = ld<O32>(a.z, c);
+        s_st[q] = St{hh, uu, vv, ld<O32>(a.z, c)};
     }
     if (mine) {
-        s_h[tid] = h;
         R uu, vv;
         velocities(h, hu, hv, hd, uu, vv);
-        s_u[tid] = uu;
-        s_v[tid] = vv;
-        s_z[tid] = zc;
+        s_st[tid] = St{h, uu, vv, zc};
     }
     if (node_mine) s_nd[tid] = nd;
     __syncthreads();
@@ -1039,11 +1034,13 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
         const int cb = static_cast<int16_t>(w >> 16);
         R nx, ny, l;
         edge_normal<R>(dx, dy, nx, ny, l);
-        const R ha = s_h[ca], ua = s_u[ca], va = s_v[ca];
+        const St A = s_st[ca];
+        const R ha = A.h, ua = A.u, va = A.v;
         R fh, fx, fy, pa, pb;
         if (cb >= 0) {
-            interface_flux_uv<R>(g, hd, ha, ua, va, s_z[ca], s_h[cb], s_u[cb], s_v[cb], s_z[cb],
-                                 nx, ny, fh, fx, fy, pa, pb);
+            const St B = s_st[cb];
+            interface_flux_uv<R>(g, hd, ha, ua, va, A.z, B.h, B.u, B.v, B.z, nx, ny, fh, fx, fy,
+                                 pa, pb);
             // side b's contributions are l (-f_h) = -(l f_h) and l (-f + p_b (-n)) =
             // -(l (f + p_b n)), exactly; its momentum parts are stored as they are added
             o.b1 = -(l * (fx + pb * nx));
