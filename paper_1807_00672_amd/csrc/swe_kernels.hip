@@ -1,8 +1,9 @@
 // HIP kernels of libswe for gfx950: the tiled and the per-cell step, the dt reductions, the
 // initial-dt pass, the shard helpers and the flux test hook.
 //
-// Cells are in Morton order.  The tiled step (the default) stages a tile of 256 cells and its
-// halo in LDS and evaluates each interface of the tile once; the per-cell step has each cell
+// Cells are in Morton order.  The tiled step (the default) stages a tile of cells (64, 128, 256
+// or 512, the mesh's tile size) and its halo in LDS and evaluates each interface of the tile
+// once; the per-cell step has each cell
 // gather its three neighbours and evaluate its three interface fluxes itself (section 2.2: HLLC
 // with hydrostatic reconstruction).  Both accumulate a cell's contributions in local-edge
 // order, apply the explicit Euler update of eq. 4, clamp negative depths, apply semi-implicit
@@ -34,10 +35,6 @@ namespace {
 
 constexpr double kInf = __builtin_huge_val();
 
-// Division and square root of the step.  FP64: the correctly rounded operations (the same
-// results as the CPU oracle's).  FP32: the hardware reciprocal and square root (about 1 ulp),
-// a fraction of the instructions of the correctly rounded sequences; both are odd in their
-// sign arguments, so interface fluxes stay exact negatives of each other.
 // Minimum waves per SIMD the compiler must allow for (register budget) in the two step
 // kernels; 1 leaves the choice to the compiler.  Six holds the FP64 tiled kernels to 80
 // VGPRs (the correctly rounded one needs 81 unconstrained), which the shared LDS layout
@@ -75,6 +72,11 @@ constexpr double kInf = __builtin_huge_val();
 #ifndef SWE_TILE_ALIAS
 #define SWE_TILE_ALIAS 1
 #endif
+// Division and square root of the step.  FP64: the correctly rounded operations (the same
+// results as the CPU oracle's), or with SWE_F64_FAST their Newton forms.  FP32: the hardware
+// reciprocal and square root (about 1 ulp), a fraction of the instructions of the correctly
+// rounded sequences.  All are odd in their sign arguments, so interface fluxes stay exact
+// negatives of each other.
 template <typename R>
 __device__ __forceinline__ R div_(R a, R b)
 {
@@ -661,7 +663,7 @@ __device__ __forceinline__ void cell_finish(R g, R hd, R dt, R nm, R inradius, R
 // Where a workgroup's cells live when several meshes (scenarios) are stepped together: tile t
 // holds cells [tile_start[t], tile_start[t+1]) of scenario tile_scen[t], whose control block
 // is ctrl + tile_scen[t] * SWE_CTRL_BYTES and inflow discharges q_table[16 s ..].  A single
-// mesh leaves tile_start null: tile t holds cells [256 t, 256 t + 256).
+// mesh leaves tile_start null: tile t holds cells [TB t, TB t + TB) (TB its tile size).
 struct Batch {
     const int32_t *tile_start;
     const int32_t *tile_scen;
