@@ -200,9 +200,16 @@ def test_cell_order_does_not_change_results(gpu):
         assert np.array_equal(x, y) and np.array_equal(x, w)
 
 
-def test_runs_are_bitwise_repeatable_and_stepwise_equal(gpu):
+def _large():
+    """40,000 cells in 157 tiles: the step merges its dt partials into atomic slots that a
+    fold kernel reads and resets (up to 128 tiles the step folds them itself)."""
+    return gen.dam_break(nx=200, ny=100, lx=40.0, ly=20.0)
+
+
+@pytest.mark.parametrize("large", [False, True])
+def test_runs_are_bitwise_repeatable_and_stepwise_equal(gpu, large):
     import paper_1807_00672_amd as swe
-    case = gen.small(3)
+    case = _large() if large else gen.small(3)
     a = run_gpu(case, "f64", steps=60)
     b = run_gpu(case, "f64", steps=60)
     for x, y in zip(a[2:], b[2:]):
@@ -215,8 +222,9 @@ def test_runs_are_bitwise_repeatable_and_stepwise_equal(gpu):
         assert np.array_equal(x, y)
 
 
-def test_t_end_gives_the_oracle_step_count(gpu):
-    case = gen.config(1)
+@pytest.mark.parametrize("large", [False, True])
+def test_t_end_gives_the_oracle_step_count(gpu, large):
+    case = _large() if large else gen.config(1)
     rc_o, *ora, dts, st_o = run_oracle(case, steps=100000, t_end=0.5)
     rc_g, st_g, *g = run_gpu(case, "f64", steps=1000, t_end=0.5)
     assert rc_o == 0 and rc_g == 0
@@ -224,10 +232,11 @@ def test_t_end_gives_the_oracle_step_count(gpu):
     assert max(errors(case, g, ora)) <= TOL_F64
 
 
-def test_replayed_dt_sequence(gpu):
-    case = gen.small(2)
-    seq = np.full(80, 0.05)
-    seq[::7] = 0.08
+@pytest.mark.parametrize("large", [False, True])
+def test_replayed_dt_sequence(gpu, large):
+    case = _large() if large else gen.small(2)
+    seq = np.full(80, 0.005 if large else 0.05)
+    seq[::7] = 0.008 if large else 0.08
     rc_o, *ora, dts, st_o = run_oracle(case, steps=80, dt_seq=seq)
     rc_g, st_g, *g = run_gpu(case, "f64", steps=80, dt_seq=seq)
     assert rc_o == 0 and rc_g == 0 and st_g["steps"] == 80
