@@ -639,8 +639,9 @@ __device__ __forceinline__ R cell_dt(R g, R hd, R h, R hu, R hv, R inradius, con
 
 // The positivity clamp, the semi-implicit friction and the next CFL bound of one cell after its
 // flux update U* = (hs, hus, hvs) (eq. 4 and the source treatments of section 2.2).  Outputs
-// U^{n+1} = (hs, hun, hvn) (hs clamped in place), the cell's CFL bound and whether it clamped.
-template <typename R>
+// U^{n+1} = (hs, hun, hvn) (hs clamped in place), the cell's CFL bound (+inf with Cfl false: a
+// step whose dt is replayed forms none) and whether it clamped.
+template <typename R, bool Cfl = true>
 __device__ __forceinline__ void cell_finish(R g, R hd, R dt, R nm, R inradius, R &hs, R hus,
                                             R hvs, const int32_t *nb, const StepConfig &cfg,
                                             const double *qtab, R &hun, R &hvn, R &dtc,
@@ -657,7 +658,10 @@ __device__ __forceinline__ void cell_finish(R g, R hd, R dt, R nm, R inradius, R
         hun = R(0);
         hvn = R(0);
     }
-    dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
+    if constexpr (Cfl)
+        dtc = cell_dt<R>(g, hd, hs, hun, hvn, inradius, nb, cfg, qtab);
+    else
+        dtc = static_cast<R>(kInf);
 }
 
 // Where a workgroup's cells live when several meshes (scenarios) are stepped together: tile t
@@ -918,7 +922,9 @@ inline size_t tile_lds_bytes(size_t word, int64_t tb, int64_t max_halo, int64_t 
 // round's results wait in registers until every work-item has read the states they replace.
 // Phase 3 sums each cell's three contributions in local-edge order and applies the update of
 // eq. 4, the clamp, the friction and the next CFL bound, as the per-cell kernel does.
-template <typename R, int TB, bool O32, bool Fuse, bool Shared, bool Nodes>
+// Replay: a step whose dt is given (a.dt_direct) forms no CFL bound and reads no inradius; the
+// other instances replay too when a.dt_direct is set, forming the bound and discarding it.
+template <typename R, int TB, bool O32, bool Fuse, bool Shared, bool Nodes, bool Replay = false>
 __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<R> ta, StepConfig cfg,
                                                                        Batch bt)
 {
@@ -974,7 +980,7 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
         h = ld<O32>(a.h, i); hu = ld<O32>(a.hu, i); hv = ld<O32>(a.hv, i);
         zc = ld<O32>(a.z, i); nm = ld<O32>(a.n, i);
         area = ld<O32>(a.cell_geo, i);
-        inradius = ld<O32>(a.cell_geo, T + i);
+        if constexpr (!Replay) inradius = ld<O32>(a.cell_geo, T + i);   // for the CFL bound
     }
     // global loads: the edge-list entries of the first two rounds and their edge vectors (or
     // their node ids, and the tile's nodes, one per work-item)
@@ -1106,7 +1112,7 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
             const R c1 = m[0];
             const R c2 = m[estride];
             nb[k] = 0;
-            if ((cfg.n_inflow > 0 || batched) && !side_b)
+            if (!Replay && (cfg.n_inflow > 0 || batched) && !side_b)   // for the CFL bound
                 nb[k] = static_cast<int16_t>(ld<O32>(ta.edges, eb + q) >> 16);
             if (k == 0) {
                 acc0 = c0; acc1 = c1; acc2 = c2;
@@ -1124,7 +1130,8 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
             st<O32>(a.us_hv, i, hvs);
         }
         R hun, hvn;
-        cell_finish<R>(g, hd, dt, nm, inradius, hs, hus, hvs, nb, cfg, qtab, hun, hvn, dtc, clamp);
+        cell_finish<R, !Replay>(g, hd, dt, nm, inradius, hs, hus, hvs, nb, cfg, qtab, hun, hvn, dtc,
+                                clamp);
         st<O32>(a.ho, i, hs);
         st<O32>(a.huo, i, hun);
         st<O32>(a.hvo, i, hvn);
@@ -1135,7 +1142,7 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
             flag = 0;
         }
     }
-    if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
+    if (Replay || a.dt_direct) return;   // uniform: a replay that needs no dt reduction
     finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv,
                           SWE_GROUP_ATOMIC && !batched);
 }
@@ -1624,13 +1631,19 @@ int launch_init(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
     return static_cast<int>(hipGetLastError());
 }
 
-// The tiled kernel for a launch (FP32 has no shared-layout or node-list instances).
+// The tiled kernel for a launch (FP32 has no shared-layout, node-list or replay instances; an
+// FP32 replay takes the plain instance, which checks a.dt_direct).
 template <typename R>
 using TileKernel = void (*)(TileArgs<R>, StepConfig, Batch);
 
 template <typename R, int TB, bool Shared, bool Nodes>
-TileKernel<R> tile_kernel_of(bool o32, bool fuse)
+TileKernel<R> tile_kernel_of(bool o32, bool fuse, bool replay)
 {
+    if constexpr (sizeof(R) == 8) {
+        if (replay)
+            return o32 ? tile_step_kernel<R, TB, true, false, Shared, Nodes, true>
+                       : tile_step_kernel<R, TB, false, false, Shared, Nodes, true>;
+    }
     return o32 ? (fuse ? tile_step_kernel<R, TB, true, true, Shared, Nodes>
                        : tile_step_kernel<R, TB, true, false, Shared, Nodes>)
                : (fuse ? tile_step_kernel<R, TB, false, true, Shared, Nodes>
@@ -1638,14 +1651,14 @@ TileKernel<R> tile_kernel_of(bool o32, bool fuse)
 }
 
 template <typename R, int TB>
-TileKernel<R> tile_kernel(bool o32, bool fuse, bool shared, bool nodes)
+TileKernel<R> tile_kernel(bool o32, bool fuse, bool shared, bool nodes, bool replay = false)
 {
     if constexpr (sizeof(R) == 8) {
         if (shared)
-            return nodes ? tile_kernel_of<R, TB, true, true>(o32, fuse)
-                         : tile_kernel_of<R, TB, true, false>(o32, fuse);
+            return nodes ? tile_kernel_of<R, TB, true, true>(o32, fuse, replay)
+                         : tile_kernel_of<R, TB, true, false>(o32, fuse, replay);
     }
-    return tile_kernel_of<R, TB, false, false>(o32, fuse);
+    return tile_kernel_of<R, TB, false, false>(o32, fuse, replay);
 }
 
 size_t tile_lds_bytes_for(int dtype, const TileLayout &tl)
@@ -1659,15 +1672,19 @@ int prepare_tile_kernels(size_t max_lds)
     for (int tile = kTileMin; tile <= kTileMax; tile *= 2) {
         const int e = with_tile(tile, [&](auto tb) {
             constexpr int TB = decltype(tb)::value;
-            const void *k[16];
+            const void *k[22];
             int n = 0;
-            for (int o32 = 0; o32 < 2; ++o32)
+            for (int o32 = 0; o32 < 2; ++o32) {
                 for (int fuse = 0; fuse < 2; ++fuse) {
                     k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, fuse, false, false));
                     k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, fuse, true, false));
                     k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, fuse, true, true));
                     k[n++] = reinterpret_cast<const void *>(tile_kernel<float, TB>(o32, fuse, false, false));
                 }
+                k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, false, false, false, true));
+                k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, false, true, false, true));
+                k[n++] = reinterpret_cast<const void *>(tile_kernel<double, TB>(o32, false, true, true, true));
+            }
             for (const void *f : k) {
                 const hipError_t e = hipFuncSetAttribute(
                     f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(max_lds));
@@ -1727,8 +1744,8 @@ int launch_step(int dtype, const swe_dev_mesh &dm, const StepConfig &cfg, const 
                 const bool shared = tile_alias(sizeof(double), TB, tl->max_halo, tl->max_edges,
                                                tl->max_nodes);
                 const bool nodes = shared && ta.edge_nodes != nullptr;
-                tile_kernel<double, TB>(o32, fuse, shared, nodes)<<<dim3(grid), dim3(TB), lds, st>>>(
-                    ta, cfg, bv);
+                tile_kernel<double, TB>(o32, fuse, shared, nodes, dt_direct != nullptr)
+                    <<<dim3(grid), dim3(TB), lds, st>>>(ta, cfg, bv);
             } else {
                 TileArgs<float> ta = make_tile_args<float>(dm, s, cur, *tl);
                 ta.s.part = part;
