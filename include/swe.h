@@ -397,8 +397,9 @@ int32_t swe_adjoint_workspace_bytes(const swe_mesh *mesh, int64_t n_steps, int32
  * misfit J of `loss`, and the hand-written reverse sweep of the step (friction and clamp,
  * then the transposed interface fluxes with hydrostatic reconstruction, every branch frozen
  * to the forward run).  Forward states are checkpointed every ckpt_every steps and recomputed
- * segment by segment in the reverse pass; ckpt_every = 1 stores every state and U* in the
- * forward pass and recomputes nothing (the same gradients, bit for bit).  The caller's state
+ * segment by segment in the reverse pass, except the last segment, whose states the forward
+ * pass keeps; ckpt_every = 1 stores every state and U* in the forward pass and recomputes
+ * nothing (the same gradients, bit for bit).  The caller's state
  * is not modified.  ws: device, swe_adjoint_workspace_bytes bytes, 256-byte aligned.
  * *loss_out (host, may be NULL) receives J; then the stream is synchronised.
  * Errors: SWE_EINVAL, SWE_EUNSUPPORTED (FP32), SWE_EDEVICE.
@@ -409,8 +410,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
                     void *ws, int64_t ws_bytes, void *stream);
 
 /* Device time of this thread's last completed swe_adjoint call, in milliseconds, from HIP
- * events on its stream: the forward pass (checkpoints or every state, with the loss) and the
- * reverse sweep (segment recompute, unless every state was stored, and adjoint steps).
+ * events on its stream: the forward pass (checkpoints or every state) and the reverse sweep
+ * (segment recompute, unless every state was stored, adjoint steps and the loss).
  * Waits for that call's work to finish.
  * Errors: SWE_EINVAL (no completed call on this thread), SWE_EDEVICE. */
 int32_t swe_adjoint_timings(double *forward_ms, double *reverse_ms);

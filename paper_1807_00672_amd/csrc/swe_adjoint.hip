@@ -13,11 +13,13 @@
 // the forward values and its derivative taken as is.  dt is replayed, not differentiated.
 //
 // Forward states are checkpointed every K steps; the reverse pass recomputes each segment
-// (storing U^n and the pre-friction U*) and then runs the adjoint through it backwards.  With
+// (storing U^n and the pre-friction U*) and then runs the adjoint through it backwards; the
+// forward pass stores the last segment so, and it is not recomputed.  With
 // K = 1 the forward pass itself stores every U^n and U* (HBM holds them for the meshes and
 // step counts of a calibration run) and the reverse pass recomputes nothing.  The forward
 // passes replay dt without the control block.  FP64 divisions and square roots of the
-// adjoint use the Newton forms of swe_device_math.h (within an ulp).
+// adjoint use the Newton forms of swe_device_math.h; quotients by one divisor are products
+// with its reciprocal (within about an ulp), as in the default step.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -100,17 +102,21 @@ __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, doubl
         const double rden = rcp_nr(den);
         const double fh = quot_nr((sr * fhl - sl * fhr) + sl * sr * dh, rden, den);
         const double fq = quot_nr((sr * fql - sl * fqr) + sl * sr * dq, rden, den);
-        const double sstar = div_nr(sl * hr * (qr - sr) - sr * hl * (ql - sl),
-                                    hr * (qr - sr) - hl * (ql - sl));
+        // the sign of the contact speed as the step takes it (den2 < 0 here: -num, unless the
+        // quotient could underflow)
+        const double num = sl * hr * (qr - sr) - sr * hl * (ql - sl);
+        const double den2 = hr * (qr - sr) - hl * (ql - sl);
+        const double sstar = fabs(num) < 0x1p-1000 * fabs(den2) ? div_nr(num, den2) : -num;
         const int sel = sstar > 0.0 ? 1 : (sstar < 0.0 ? 2 : 3);
         const double wup = sel == 1 ? wl : (sel == 2 ? wr : (wl + wr) / 2.0);
         const double fhtb = fhb + fwb * wup;
         const double wupb = fwb * fh;
-        if (sel == 1) wlb += wupb;
-        else if (sel == 2) wrb += wupb;
-        else { wlb += 0.5 * wupb; wrb += 0.5 * wupb; }
-        const double nhb = div_nr(fhtb, den), nqb = div_nr(fqb, den);
-        const double denb = -div_nr(fhtb * fh + fqb * fq, den);
+        // both zero before this branch; set by value (a store through a chosen reference
+        // would keep them in memory)
+        wlb = sel == 1 ? wupb : (sel == 3 ? 0.5 * wupb : 0.0);
+        wrb = sel == 2 ? wupb : (sel == 3 ? 0.5 * wupb : 0.0);
+        const double nhb = fhtb * rden, nqb = fqb * rden;
+        const double denb = -((fhtb * fh + fqb * fq) * rden);
         srb += nhb * (fhl + sl * dh) + nqb * (fql + sl * dq) + denb;
         slb += nhb * (-fhr + sr * dh) + nqb * (-fqr + sr * dq) - denb;
         fhlb += nhb * sr;
@@ -149,8 +155,8 @@ __device__ void hllc_normal_vjp(double g, double hl, double ql, double wl, doubl
         qlb += 0.25 * csb;
         qrb -= 0.25 * csb;
     }
-    if (cl > 0.0) hlb += div_nr(clb * g, 2.0 * cl);
-    if (cr > 0.0) hrb += div_nr(crb * g, 2.0 * cr);
+    if (cl > 0.0) hlb += (0.5 * clb * g) * rcp_nr(cl);
+    if (cr > 0.0) hrb += (0.5 * crb * g) * rcp_nr(cr);
 }
 
 // Cotangent of a cell's velocity pair (u, v) = (hu, hv)/h pulled back to (h, hu, hv).
@@ -158,10 +164,11 @@ __device__ __forceinline__ void vel_vjp(double h, double hu, double hv, double h
                                         double vb, Vjp3 &out)
 {
     if (h > hd) {
-        const double u = div_nr(hu, h), v = div_nr(hv, h);
-        out.h -= div_nr(ub * u + vb * v, h);
-        out.hu += div_nr(ub, h);
-        out.hv += div_nr(vb, h);
+        const double ih = rcp_nr(h);
+        const double u = hu * ih, v = hv * ih;
+        out.h -= (ub * u + vb * v) * ih;
+        out.hu += ub * ih;
+        out.hv += vb * ih;
     }
 }
 
@@ -190,19 +197,17 @@ __device__ void interface_vjp(double g, double hd, double ha, double hua, double
     const double fqb = fxb * nx + fyb * ny, fwb = -fxb * ny + fyb * nx;
     double hsab, qab, wab, hsbb, qbb, wbb;
     hllc_normal_vjp(g, hsa, qa, wa, hsb, qb, wb, fhb, fqb, fwb, hsab, qab, wab, hsbb, qbb, wbb);
-    ua_out = {pab * g * ha, 0.0, 0.0};
-    ub_out = {pbb * g * hb, 0.0, 0.0};
     hsab -= pab * g * hsa;
     hsbb -= pbb * g * hsb;
-    double zsb = 0.0;
-    za_out = 0.0;
-    zb_out = 0.0;
-    if (act_a) { ua_out.h += hsab; zsb -= hsab; za_out += hsab; }
-    if (act_b) { ub_out.h += hsbb; zsb -= hsbb; zb_out += hsbb; }
+    // the reconstructed depths' cotangents where h* = h - (z* - z) is active; all by value
+    // selects (a store through a chosen reference would keep the outputs in memory)
+    const double ta = act_a ? hsab : 0.0, tb = act_b ? hsbb : 0.0;
+    ua_out = {pab * g * ha + ta, 0.0, 0.0};
+    ub_out = {pbb * g * hb + tb, 0.0, 0.0};
+    const double zsb = -ta - tb;
     // max(za, zb) at a tie: half to each side (the convention of the tangent model too)
-    if (za > zb) za_out += zsb;
-    else if (zb > za) zb_out += zsb;
-    else { za_out += 0.5 * zsb; zb_out += 0.5 * zsb; }
+    za_out = ta + (za > zb ? zsb : (zb > za ? 0.0 : 0.5 * zsb));
+    zb_out = tb + (zb > za ? zsb : (za > zb ? 0.0 : 0.5 * zsb));
     vel_vjp(ha, hua, hva, hd, qab * nx - wab * ny, qab * ny + wab * nx, ua_out);
     vel_vjp(hb, hub, hvb, hd, qbb * nx - wbb * ny, qbb * ny + wbb * nx, ub_out);
 }
@@ -256,43 +261,55 @@ struct AdjArgs {
     double q[SWE_MAX_INFLOW];
 };
 
-// mu = (dU^{n+1}/dU*)^T lambda^{n+1} of cell i, and the roughness gradient's share
-// (dU^{n+1}/dn_i)^T lambda^{n+1}; returns whether the cell is wet (the share exists).
-__device__ __forceinline__ bool friction_vjp(const AdjArgs &a, int64_t i, double dt, Vjp3 &mu,
-                                             double &gn)
+// What the adjoint step reads of one cell: U^n, bed, U* before the clamp, lambda^{n+1},
+// roughness and area.
+struct CellIn {
+    double h, hu, hv, z, sh, shu, shv, lh, lhu, lhv, n, area;
+};
+
+__device__ __forceinline__ CellIn load_cell(const AdjArgs &a, int64_t c)
 {
-    const double g = a.g;
-    const double hraw = a.sh[i], hus = a.shu[i], hvs = a.shv[i];
+    return {a.h[c],  a.hu[c],  a.hv[c],  a.z[c],  a.sh[c], a.shu[c],
+            a.shv[c], a.lh[c], a.lhu[c], a.lhv[c], a.n[c],  a.area[c]};
+}
+
+// mu = (dU^{n+1}/dU*)^T lambda^{n+1} of a cell, and the roughness gradient's share
+// (dU^{n+1}/dn_i)^T lambda^{n+1}; returns whether the cell is wet (the share exists).
+__device__ __forceinline__ bool friction_vjp(double g, double hd, const CellIn &ci, double dt,
+                                             Vjp3 &mu, double &gn)
+{
+    const double hraw = ci.sh, hus = ci.shu, hvs = ci.shv;
     const bool clamped = hraw < 0.0;
     const double hs = clamped ? 0.0 : hraw;
-    const double lh = a.lh[i], lhu = a.lhu[i], lhv = a.lhv[i];
+    const double lh = ci.lh, lhu = ci.lhu, lhv = ci.lhv;
     double mh = lh, mhu = 0.0, mhv = 0.0;
     gn = 0.0;
-    if (hs > a.hd) {
-        const double nm = a.n[i];
+    if (hs > hd) {
+        const double nm = ci.n;
         const double mag = sqrt_nr(hus * hus + hvs * hvs);
         const double c = cbrt_(hs);
         const double P = hs * hs * c;
         const double K = dt * g * nm * nm;
-        const double D = 1.0 + div_nr(K * mag, P);
-        const double rD = div_nr(1.0, D);
+        const double rP = rcp_nr(P);   // every quotient by P as a product (within 1.5 ulp)
+        const double D = 1.0 + (K * mag) * rP;
+        const double rD = rcp_nr(D);
         const double hun = hus * rD, hvn = hvs * rD;
         const double Db = -(lhu * hun + lhv * hvn) * rD;
         mhu = lhu * rD;
         mhv = lhv * rD;
         if (mag > 0.0) {
-            const double magb = div_nr(Db * K, P);
-            const double rm = div_nr(1.0, mag);
+            const double magb = (Db * K) * rP;
+            const double rm = rcp_nr(mag);
             mhu += magb * hus * rm;
             mhv += magb * hvs * rm;
         }
-        const double Pb = -div_nr(Db * K * mag, P * P);
+        const double Pb = -((Db * K * mag) * rP) * rP;
         mh += Pb * (7.0 / 3.0) * hs * c;
-        gn = div_nr(Db * mag, P) * 2.0 * dt * g * nm;
+        gn = ((Db * mag) * rP) * 2.0 * dt * g * nm;
     }
     if (clamped) mh = 0.0;
     mu = {mh, mhu, mhv};
-    return hs > a.hd;
+    return hs > hd;
 }
 
 // mu of every cell into a.mh (the per-cell flux adjoint reads it); roughness gradient.
@@ -302,7 +319,7 @@ __global__ __launch_bounds__(256) void friction_adjoint_kernel(AdjArgs a)
     if (i >= a.T) return;
     Vjp3 mu;
     double gn;
-    if (friction_vjp(a, i, a.dt_seq[a.step], mu, gn)) a.gn[i] += gn;
+    if (friction_vjp(a.g, a.hd, load_cell(a, i), a.dt_seq[a.step], mu, gn)) a.gn[i] += gn;
     a.mh[i] = mu.h;
     a.mhu[i] = mu.hu;
     a.mhv[i] = mu.hv;
@@ -317,7 +334,7 @@ __global__ __launch_bounds__(256) void flux_adjoint_kernel(AdjArgs a)
     const double dt = a.dt_seq[a.step], g = a.g, hd = a.hd;
     const double2 p[3] = {a.xy[a.c2n[i]], a.xy[a.c2n[T + i]], a.xy[a.c2n[2 * T + i]]};
     const double h = a.h[i], hu = a.hu[i], hv = a.hv[i], z = a.z[i];
-    const double ri = div_nr(dt, a.area[i]);
+    const double ri = dt * rcp_nr(a.area[i]);
     const double ci[3] = {-ri * a.mh[i], -ri * a.mhu[i], -ri * a.mhv[i]};
     double lh = a.mh[i], lhu = a.mhu[i], lhv = a.mhv[i], zb_sum = 0.0;
 #pragma unroll
@@ -329,7 +346,7 @@ __global__ __launch_bounds__(256) void flux_adjoint_kernel(AdjArgs a)
         const int32_t j = a.nbr[k * T + i];
         Vjp3 u{0.0, 0.0, 0.0};
         if (j >= 0) {
-            const double rj = div_nr(dt, a.area[j]);
+            const double rj = dt * rcp_nr(a.area[j]);
             const double cj[3] = {-rj * a.mh[j], -rj * a.mhu[j], -rj * a.mhv[j]};
             Vjp3 uj;
             double zi_b, zj_b;
@@ -409,37 +426,54 @@ __global__ __launch_bounds__(TB, 4) void tile_flux_adjoint_kernel(AdjArgs a, Adj
     // mu and the contribution cotangent -dt/A mu; a tile cell keeps its mu and adds its
     // roughness gradient
     Vjp3 mu_own{0.0, 0.0, 0.0};
-    auto stage = [&](int q, int64_t c, bool own) {
-        s_h[q] = a.h[c];
-        s_hu[q] = a.hu[c];
-        s_hv[q] = a.hv[c];
-        s_z[q] = a.z[c];
+    double gn_own = 0.0;
+    bool wet_own = false;
+    auto stage = [&](int q, const CellIn &ci, bool own) {
+        s_h[q] = ci.h;
+        s_hu[q] = ci.hu;
+        s_hv[q] = ci.hv;
+        s_z[q] = ci.z;
         Vjp3 mu;
         double gn;
-        const bool wet = friction_vjp(a, c, dt, mu, gn);
+        const bool wet = friction_vjp(g, hd, ci, dt, mu, gn);
         if (own) {
             mu_own = mu;
-            if (wet) a.gn[c] += gn;
+            gn_own = gn;
+            wet_own = wet;
         }
-        const double r = div_nr(dt, a.area[c]);
+        const double r = dt * rcp_nr(ci.area);
         s_c0[q] = -r * mu.h;
         s_c1[q] = -r * mu.hu;
         s_c2[q] = -r * mu.hv;
     };
-    if (mine) stage(tid, i, true);
+    // Global loads up front: the work-item's first halo index, then together that halo cell's
+    // inputs, its own cell's and the first round's edge-list entry, so that one wait on the
+    // index precedes one wait on all of them.
     const int hb = t.halo_off[tile], he = t.halo_off[tile + 1];
-    for (int j = hb + ph; j < he; j += TB) stage(TB + (j - hb), t.halo[j], false);
+    const int j0 = hb + ph;
+    const int32_t c0 = j0 < he ? t.halo[j0] : -1;
+    const int eb = t.edge_off[tile], ee = t.edge_off[tile + 1];
+    CellIn own{}, hal{};
+    if (c0 >= 0) hal = load_cell(a, c0);
+    if (mine) own = load_cell(a, i);
+    uint32_t w = 0u;
+    double2 d = {0.0, 0.0};
+    if (eb + pt < ee) {
+        w = t.edges[eb + pt];
+        d = t.edge_vec[eb + pt];
+    }
+    if (mine) stage(tid, own, true);
+    if (c0 >= 0) stage(TB + (j0 - hb), hal, false);
+    for (int j = j0 + TB; j < he; j += TB) stage(TB + (j - hb), load_cell(a, t.halo[j]), false);
     __syncthreads();
 
     // side a's (h, hu, hv) cotangent and bed term, then side b's for interfaces inside the tile
     struct EdgeAdj {
         double v[8];
     };
-    auto diff = [&](int e, EdgeAdj &o) {
-        const uint32_t w = t.edges[e];
+    auto diff = [&](uint32_t w, double2 d, EdgeAdj &o) {
         const int ca = static_cast<int>(w & kEdgeA);
         const int cb = static_cast<int16_t>(w >> 16);
-        const double2 d = t.edge_vec[e];
         const double dx = d.x, dy = d.y;
         double nx, ny, l;
         edge_normal_nr(dx, dy, nx, ny, l);
@@ -478,32 +512,49 @@ __global__ __launch_bounds__(TB, 4) void tile_flux_adjoint_kernel(AdjArgs a, Adj
             for (int r = 4; r < 8; ++r) ed[r * estride] = o.v[r];
         }
     };
-    const int eb = t.edge_off[tile], ee = t.edge_off[tile + 1];
     // one call site of diff: in the shared layout (two rounds at most) the second round's
-    // result waits for the barrier after which the staged cells may be overwritten
+    // result waits for the barrier after which the staged cells may be overwritten; each
+    // round's successor entry is loaded before the round is differentiated
     EdgeAdj o;
     bool inner = false;
     int held = -1;
     for (int q = pt; eb + q < ee; q += TB) {
-        inner = diff(eb + q, o);
+        uint32_t wn = 0u;
+        double2 dn = {0.0, 0.0};
+        if (eb + q + TB < ee) {
+            wn = t.edges[eb + q + TB];
+            dn = t.edge_vec[eb + q + TB];
+        }
+        inner = diff(w, d, o);
         if (Shared && q >= TB) {
             held = q;
             break;
         }
         put(q, o, inner);
+        w = wn;
+        d = dn;
     }
     if constexpr (Shared) {
         __syncthreads();   // every read of the staged cells is done
         if (held >= 0) put(held, o, inner);
+    }
+    // the cell's three edge-list slots, its roughness and bed gradients so far, loaded before
+    // the wait for the other work-items' interfaces
+    uint32_t sl[3] = {0u, 0u, 0u};
+    double gn0 = 0.0, gz0 = 0.0;
+    if (mine) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sl[k] = t.slot[k * T + i];
+        if (wet_own) gn0 = a.gn[i];
+        gz0 = a.gz[i];
     }
     __syncthreads();
     if (!mine) return;
     double lh = mu_own.h, lhu = mu_own.hu, lhv = mu_own.hv, zb_sum = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const uint32_t sl = t.slot[k * T + i];
-        const int q = static_cast<int>(sl & 0x7fffu);
-        const double *ed = lds + ebase + q + (q >= TB ? bshift : 0) + ((sl & 0x8000u) ? 4 * estride : 0);
+        const int q = static_cast<int>(sl[k] & 0x7fffu);
+        const double *ed = lds + ebase + q + (q >= TB ? bshift : 0) + ((sl[k] & 0x8000u) ? 4 * estride : 0);
         lh += ed[0];
         lhu += ed[estride];
         lhv += ed[2 * estride];
@@ -512,7 +563,8 @@ __global__ __launch_bounds__(TB, 4) void tile_flux_adjoint_kernel(AdjArgs a, Adj
     a.lo[i] = lh;
     a.lou[i] = lhu;
     a.lov[i] = lhv;
-    a.gz[i] += zb_sum;
+    if (wet_own) a.gn[i] = gn0 + gn_own;
+    a.gz[i] = gz0 + zb_sum;
 }
 
 // The tiled flux adjoint of a tile size and layout.
@@ -528,17 +580,12 @@ AdjKernel tile_adj_kernel(int tb, bool shared)
     }
 }
 
-// Misfit at an observation: the loss gains sum (h_g - obs_g)^2, summed in gauge order by one
-// work-item from squares the 64 work-items of the (single) workgroup form a chunk at a time;
-// with lam != nullptr the adjoint gains 2 (h_g - obs_g) at the gauges instead.
+// Misfit at an observation (one workgroup of 64 work-items, a chunk of gauges at a time): its
+// share of the loss, sum (h_g - obs_g)^2 in gauge order, into *part, and the adjoint's
+// 2 (h_g - obs_g) added at the gauges (distinct cells) of lam.
 __global__ void misfit_kernel(const double *h, const int32_t *gauges, int ng, const double *obs,
-                              double *loss, double *lam)
+                              double *part, double *lam)
 {
-    if (lam) {
-        const int q = blockIdx.x * blockDim.x + threadIdx.x;
-        if (q < ng) lam[gauges[q]] += 2.0 * (h[gauges[q]] - obs[q]);
-        return;
-    }
     __shared__ double sq[64];
     double acc = 0.0;
     for (int base = 0; base < ng; base += 64) {
@@ -546,13 +593,22 @@ __global__ void misfit_kernel(const double *h, const int32_t *gauges, int ng, co
         if (q < ng) {
             const double r = h[gauges[q]] - obs[q];
             sq[threadIdx.x] = r * r;
+            lam[gauges[q]] += 2.0 * r;
         }
         __syncthreads();
         if (threadIdx.x == 0)
             for (int k = 0; k < 64 && base + k < ng; ++k) acc += sq[k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *loss += acc;
+    if (threadIdx.x == 0) *part = acc;
+}
+
+// The loss: the observations' shares added in observation order.
+__global__ void loss_sum_kernel(const double *part, int64_t n_obs, double *loss)
+{
+    double j = 0.0;
+    for (int64_t m = 0; m < n_obs; ++m) j += part[m];
+    *loss = j;
 }
 
 __global__ void fill_kernel(double *p, int64_t n, double v)
@@ -583,7 +639,7 @@ AdjLayout adj_layout(int64_t T, int64_t n_steps, int64_t K)
     L.lam = off; off += al(st);
     L.lam2 = off; off += al(st);
     L.mu = off; off += al(st);
-    L.loss = off; off += 256;
+    L.loss = off; off += al(8 * (static_cast<size_t>(n_steps) + 1));   // J, then each observation's share
     L.ctrl = off; off += al(SWE_CTRL_BYTES);
     L.work = off; off += al(static_cast<size_t>(workspace_bytes(T)));
     L.total = off;
@@ -695,7 +751,7 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     // lambda^n to the other (neighbouring tiles still read the former)
     double *lamb[2] = {D(L.lam), D(L.lam2)};
     int lcur = 0;
-    double *mu = D(L.mu), *lossd = D(L.loss);
+    double *mu = D(L.mu), *lossd = D(L.loss), *obs_part = lossd + 1;
     const unsigned blocks = static_cast<unsigned>((T + 255) / 256);
 
     StepConfig cfg;
@@ -732,9 +788,8 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         return ahip(hipMemcpyAsync(dhv, shv, bytes3, hipMemcpyDeviceToDevice, st), W);
     };
 
-    fill_kernel<<<1, 256, 0, st>>>(lossd, 1, 0.0);
-
-    // forward pass: checkpoints and the loss (segment slots 0 and 1 serve as ping-pong)
+    // forward pass: checkpoints (the loss is formed in the reverse pass, whose misfit launches
+    // have every observed state at hand)
     if (int32_t rc = copy3(ck(0, 0), ck(0, 1), ck(0, 2), s->h[s->cur], s->hu[s->cur], s->hv[s->cur])) return rc;
     const bool record = K == 1;
     if (record) {
@@ -747,30 +802,39 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
                                                                       n_steps, st, tl, nullptr, remap,
                                                                       ustar, dt_seq + nstep)), W))
                 return rc;
-            if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
-                misfit_kernel<<<1, 64, 0, st>>>(ck(nstep + 1, 0), loss->gauges, loss->n_gauges,
-                                                loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges,
-                                                lossd, nullptr);
         }
     } else {
     if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(0, 0), ck(0, 1), ck(0, 2))) return rc;
-    // the steps replay dt_seq directly: no control block, no dt reduction
+    // the steps replay dt_seq directly: no control block, no dt reduction.  Segment slots 0
+    // and 1 serve as ping-pong until the last segment, whose states and U* the pass stores
+    // as the reverse pass's recompute would (so that segment is not recomputed).
+    const int64_t s_last = ((n_steps + K - 1) / K - 1) * K;
     swe_state fw = view(sg(0, 0), sg(0, 1), sg(0, 2), sg(1, 0), sg(1, 1), sg(1, 2));
     int cur = 0;
     for (int64_t nstep = 0; nstep < n_steps; ++nstep) {
-        if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, fw, cur, dt_seq,
-                                                                  n_steps, st, tl, nullptr, remap,
-                                                                  nullptr, dt_seq + nstep)), W))
-            return rc;
-        cur ^= 1;
-        const double *hc = static_cast<const double *>(fw.h[cur]);
-        if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
-            misfit_kernel<<<1, 64, 0, st>>>(hc, loss->gauges, loss->n_gauges,
-                                            loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges,
-                                            lossd, nullptr);
+        const int64_t q = nstep - s_last;
+        if (q == 0 && cur != 0)   // the last segment starts in slot 0
+            if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), sg(1, 0), sg(1, 1), sg(1, 2))) return rc;
+        double *un[3];
+        if (q < 0) {
+            if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, fw, cur, dt_seq,
+                                                                      n_steps, st, tl, nullptr, remap,
+                                                                      nullptr, dt_seq + nstep)), W))
+                return rc;
+            cur ^= 1;
+            for (int f = 0; f < 3; ++f) un[f] = sg(cur, f);
+        } else {
+            swe_state v = view(sg(q, 0), sg(q, 1), sg(q, 2), sg(q + 1, 0), sg(q + 1, 1), sg(q + 1, 2));
+            double *ustar[3] = {ss(q, 0), ss(q, 1), ss(q, 2)};
+            if (int32_t rc = ahip(static_cast<hipError_t>(launch_step(SWE_F64, *dm, cfg, v, 0, dt_seq,
+                                                                      n_steps, st, tl, nullptr, remap,
+                                                                      ustar, dt_seq + nstep)), W))
+                return rc;
+            for (int f = 0; f < 3; ++f) un[f] = sg(q + 1, f);
+        }
         if ((nstep + 1) % K == 0) {
             const int64_t c = (nstep + 1) / K;
-            if (int32_t rc = copy3(ck(c, 0), ck(c, 1), ck(c, 2), fw.h[cur], fw.hu[cur], fw.hv[cur])) return rc;
+            if (int32_t rc = copy3(ck(c, 0), ck(c, 1), ck(c, 2), un[0], un[1], un[2])) return rc;
         }
     }
     }
@@ -848,10 +912,11 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     auto adjoint_step = [&](int64_t nstep, const double *const *un, const double *const *us1,
                             const double *const *ustar) {
         double *lin = lamb[lcur], *lout = lamb[lcur ^ 1];
-        if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0)
-            misfit_kernel<<<(loss->n_gauges + 63) / 64, 64, 0, st>>>(
-                us1[0], loss->gauges, loss->n_gauges,
-                loss->obs + ((nstep + 1) / loss->every - 1) * loss->n_gauges, nullptr, lin);
+        if ((nstep + 1) % loss->every == 0 && loss->n_gauges > 0) {
+            const int64_t m = (nstep + 1) / loss->every - 1;   // the observation
+            misfit_kernel<<<1, 64, 0, st>>>(us1[0], loss->gauges, loss->n_gauges,
+                                            loss->obs + m * loss->n_gauges, obs_part + m, lin);
+        }
         a.step = nstep;
         a.sh = ustar[0]; a.shu = ustar[1]; a.shv = ustar[2];
         a.lh = lin; a.lhu = lin + S; a.lhv = lin + 2 * S;
@@ -878,8 +943,10 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
     const int64_t n_seg = record ? 0 : (n_steps + K - 1) / K;
     for (int64_t sgi = n_seg - 1; sgi >= 0; --sgi) {
         const int64_t s0 = sgi * K, s1 = std::min(n_steps, s0 + K);
-        if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(sgi, 0), ck(sgi, 1), ck(sgi, 2))) return rc;
-        for (int64_t nstep = s0; nstep < s1; ++nstep) {
+        // the last segment is in the slots already (forward pass)
+        if (sgi < n_seg - 1)
+            if (int32_t rc = copy3(sg(0, 0), sg(0, 1), sg(0, 2), ck(sgi, 0), ck(sgi, 1), ck(sgi, 2))) return rc;
+        for (int64_t nstep = sgi < n_seg - 1 ? s0 : s1; nstep < s1; ++nstep) {
             const int64_t q = nstep - s0;
             swe_state v = view(sg(q, 0), sg(q, 1), sg(q, 2), sg(q + 1, 0), sg(q + 1, 1), sg(q + 1, 2));
             double *ustar[3] = {ss(q, 0), ss(q, 1), ss(q, 2)};
@@ -897,6 +964,10 @@ int32_t swe_adjoint(const swe_mesh *mesh, const swe_dev_mesh *dm, const swe_para
         }
         if (int32_t rc = ahip(hipGetLastError(), W)) return rc;
     }
+    if (loss->n_gauges > 0)
+        loss_sum_kernel<<<1, 1, 0, st>>>(obs_part, n_steps / loss->every, lossd);
+    else
+        fill_kernel<<<1, 256, 0, st>>>(lossd, 1, 0.0);
     double *lam = lamb[lcur];   // lambda^0
     if (int32_t rc = copy3(out->dh, out->dhu, out->dhv, lam, lam + S, lam + 2 * S)) return rc;
     if (int32_t rc = ahip(hipEventRecord(tm.ev[2], st), W)) return rc;
