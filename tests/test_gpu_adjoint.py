@@ -34,6 +34,31 @@ def test_loss_matches_oracle(setup):
     assert j > 0
 
 
+def test_loss_has_the_bits_of_a_plain_run(setup, gpu):
+    """The adjoint's forward and recompute passes step with the replay instance of the step
+    kernel (dt given, no CFL bound formed); a plain run with the same dt sequence must pass
+    through the same states, so the misfit of its gauge depths, summed on the host in the
+    kernels' order (squares in gauge order per observation, then the observations in order),
+    has the loss's bits."""
+    import torch
+    case, om, dts, obs, calib, j, grads = setup
+    mesh = gpu.Mesh(case.xy, case.tri)
+    sv = gpu.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype="f64")
+    dt = torch.as_tensor(np.asarray(dts, np.float64), device=mesh.device)
+    gauges = np.asarray(case.extra["gauges"])
+    jj = 0.0
+    for m in range(STEPS // 10):
+        rc, _ = sv.run(10, dt_seq=dt[10 * m:10 * m + 10])
+        assert rc == 0
+        h = sv.numpy_state()[0]
+        acc = 0.0
+        for g, o in zip(gauges, obs[m]):
+            r = float(h[g]) - float(o)
+            acc += r * r
+        jj += acc
+    assert jj == j
+
+
 @pytest.mark.parametrize("which", ["n", "z", "h", "hu", "hv"])
 def test_dot_product_with_oracle_tangent(setup, which):
     case, om, dts, obs, calib, j, grads = setup
