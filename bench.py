@@ -244,23 +244,37 @@ def bench_shards(mesh, case, stream, parts: int = 8, steps: int = 100) -> dict:
             "exchange_us_per_step": us_x, "halo_cells_total": int(sum(halos))}
 
 
-def bench_configs(stream, dtypes) -> dict:
+def bench_configs(stream, dtypes, tiles) -> dict:
     """Configs 1 (10,000-cell dam break, 200 steps) and 2 (1,000,000-cell wet/dry bumps, 1,000
-    steps) in full on the GPU."""
+    steps) in full on the GPU, each precision on the tile size the autotuner picks among
+    `tiles` for its size class."""
+    import torch
+
     import gen
     import paper_1807_00672_amd as swe
     out = {}
     for k in (1, 2):
         case = gen.config(k)
-        mesh = swe.Mesh(case.xy, case.tri)
         r = {"n_cells": case.n_cells, "steps": case.steps}
         for dt in dtypes:
+            by_tile = None
+            tile = tiles[0]
+            if len(tiles) > 1:
+                tile, per_tile = swe.tune.tune_tiles(case.xy, case.tri, case.z, case.n, case.h,
+                                                     case.hu, case.hv, case.edge_tag, dtype=dt,
+                                                     steps=20, tiles=tiles, order="morton")
+                by_tile = {str(t): min(v for v in q["ms_per_step"].values() if v > 0)
+                           for t, q in per_tile.items()}
+            mesh = swe.Mesh(case.xy, case.tri, case.edge_tag, tile=tile)
             solver = swe.Solver(mesh, case.z, case.n, case.h, case.hu, case.hv, dtype=dt)
             ms, rc, st, warm, _ = time_gpu(solver, case.steps, 0, stream)
             if rc != swe.SWE_OK or st["steps"] != warm + 5 * case.steps:
                 raise RuntimeError(f"config {k} {dt}: rc={rc} stats={st}")
             r[dt] = {"cell_updates_per_s": case.n_cells * case.steps / (ms * 1e-3),
-                     "ms_per_step": ms / case.steps}
+                     "ms_per_step": ms / case.steps, "tile": tile,
+                     "tuner_ms_per_step_by_tile": by_tile}
+            del solver, mesh
+            torch.cuda.empty_cache()
         out[f"config{k}"] = r
     return out
 
@@ -604,10 +618,10 @@ def main():
 
     configs = {}
     if args.size == "full" and not args.no_configs:
-        configs = bench_configs(stream, args.dtypes.split(","))
+        configs = bench_configs(stream, args.dtypes.split(","), tiles)
         for k, v in configs.items():
             print(f"# {k}: {v['n_cells']} cells x {v['steps']} steps: " +
-                  ", ".join(f"{dt} {v[dt]['cell_updates_per_s'] / 1e9:.2f} G/s"
+                  ", ".join(f"{dt} {v[dt]['cell_updates_per_s'] / 1e9:.2f} G/s (tile {v[dt]['tile']})"
                             for dt in args.dtypes.split(",")), file=sys.stderr, flush=True)
 
     adjoint = {}
