@@ -410,6 +410,51 @@ __device__ __forceinline__ double wave_min(double v)
     return fmin(fmin(r[0], r[1]), fmin(r[2], r[3]));
 }
 
+// Minimum over the wave of unsigned words, on every lane and with every lane active: DPP
+// steps within each row of 16 lanes (as wave_min), then the four rows' minima read from one
+// lane each.
+template <int Ctrl>
+__device__ __forceinline__ unsigned dpp_min_u32(unsigned v)
+{
+    // all lanes active and in range: the old value (the min's identity) is never taken
+    const unsigned o = static_cast<unsigned>(__builtin_amdgcn_update_dpp(
+        static_cast<int>(0xffffffffu), static_cast<int>(v), Ctrl, 0xF, 0xF, false));
+    return min(v, o);
+}
+
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v)
+{
+    v = dpp_min_u32<0xB1>(v);
+    v = dpp_min_u32<0x4E>(v);
+    v = dpp_min_u32<0x141>(v);
+    v = dpp_min_u32<0x140>(v);
+    const unsigned r0 = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 0));
+    const unsigned r1 = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 16));
+    const unsigned r2 = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 32));
+    const unsigned r3 = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 48));
+    return min(min(r0, r1), min(r2, r3));
+}
+
+// Minimum over the wave of CFL bounds, as a double on every lane.  A bound is positive or
+// +inf (never negative, -0 or NaN: cell_dt divides a positive length by a positive speed, or
+// gives +inf), and such numbers order as their bit patterns read as unsigned integers; so the
+// minimum is an unsigned one: of the 32-bit patterns in FP32 (then widened, exactly), of the
+// high words in FP64 and then of the low words of the lanes that hold the high minimum.
+__device__ __forceinline__ double wave_min_bound(float v)
+{
+    return static_cast<double>(__uint_as_float(wave_min_u32(__float_as_uint(v))));
+}
+
+__device__ __forceinline__ double wave_min_bound(double v)
+{
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned hi = static_cast<unsigned>(b >> 32), lo = static_cast<unsigned>(b);
+    const unsigned mh = wave_min_u32(hi);
+    const unsigned ml = wave_min_u32(hi == mh ? lo : 0xffffffffu);
+    return __longlong_as_double(
+        static_cast<long long>((static_cast<unsigned long long>(mh) << 32) | ml));
+}
+
 __device__ __forceinline__ int wave_sum(int v)
 {
 #pragma unroll
@@ -424,17 +469,18 @@ __device__ __forceinline__ int wave_or(int v)
     return v;
 }
 
-// Block-wide (TB work-items) min of the CFL bounds, count of clamps and status of a step, on
-// thread 0.  A work-item's flag is 0 or kStatusNonFinite and its clamp 0 or 1: a wave counts
-// its clamps and flags from ballots, and one integer sum across the waves carries both, clamps
-// in the low 16 bits, flagged waves above them.
-template <int TB>
-__device__ __forceinline__ void block_reduce(double &dtc, int clamp, int flag, int &cf)
+// Block-wide (TB work-items) min of the CFL bounds (bound: a work-item's, in the step's
+// precision), count of clamps and status of a step, on thread 0 (dtc).  A work-item's flag is
+// 0 or kStatusNonFinite and its clamp 0 or 1: a wave counts its clamps and flags from ballots,
+// and one integer sum across the waves carries both, clamps in the low 16 bits, flagged waves
+// above them.
+template <int TB, typename R>
+__device__ __forceinline__ void block_reduce(R bound, double &dtc, int clamp, int flag, int &cf)
 {
     static_assert(TB < (1 << 16), "clamp count must fit 16 bits");
     __shared__ double s_dt[TB / 64];
     __shared__ int s_cf[TB / 64];
-    dtc = wave_min(dtc);
+    dtc = wave_min_bound(bound);
     cf = __popcll(__ballot(clamp != 0)) + (__ballot(flag != 0) ? (1 << 16) : 0);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
@@ -451,12 +497,13 @@ __device__ __forceinline__ void block_reduce(double &dtc, int clamp, int flag, i
 }
 
 // The block's partials written as partials[slot] (thread 0).
-template <int TB>
-__device__ __forceinline__ void block_partials_at(double dtc, int clamp, int flag,
+template <int TB, typename R>
+__device__ __forceinline__ void block_partials_at(R bound, int clamp, int flag,
                                                   const Partials &part, int slot)
 {
     int cf;
-    block_reduce<TB>(dtc, clamp, flag, cf);
+    double dtc;
+    block_reduce<TB>(bound, dtc, clamp, flag, cf);
     if (threadIdx.x == 0) {
         part.dt[slot] = dtc;
         part.clamps[slot] = cf & 0xffff;
@@ -469,12 +516,13 @@ __device__ __forceinline__ void block_partials_at(double dtc, int clamp, int fla
 // number, as fmin ignores a NaN), the clamps by an add and the status by an or (both only when
 // non-zero); relaxed device-scope atomics, read after the step by dt_group_fold_kernel.  A
 // slot takes few workgroups' atomics: one address taking hundreds per step serialises them.
-template <int TB>
-__device__ __forceinline__ void block_partials_group(double dtc, int clamp, int flag,
+template <int TB, typename R>
+__device__ __forceinline__ void block_partials_group(R bound, int clamp, int flag,
                                                      const Partials &part, int slot)
 {
     int cf;
-    block_reduce<TB>(dtc, clamp, flag, cf);
+    double dtc;
+    block_reduce<TB>(bound, dtc, clamp, flag, cf);
     if (threadIdx.x == 0) {
         const int q = slot / kSlotTiles;
         __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(part.dt) + q,
@@ -489,11 +537,10 @@ __device__ __forceinline__ void block_partials_group(double dtc, int clamp, int 
     }
 }
 
-template <int TB>
-__device__ __forceinline__ void block_partials(double dtc, int clamp, int flag,
-                                               const Partials &part)
+template <int TB, typename R>
+__device__ __forceinline__ void block_partials(R bound, int clamp, int flag, const Partials &part)
 {
-    block_partials_at<TB>(dtc, clamp, flag, part, blockIdx.x);
+    block_partials_at<TB>(bound, clamp, flag, part, blockIdx.x);
 }
 
 // Account for the step just taken (m: min CFL bound over the cells, cl: clamps, fl: status
@@ -557,15 +604,15 @@ struct Advance {
 // read the control block before it arrived.
 // Fuse selects this at compile time: the kernels without it run measurably faster on large
 // grids even though the branch is never taken there.
-template <int TB, bool Fuse>
-__device__ __forceinline__ void finish_step(double dtc, int clamp, int flag, const Partials &part,
+template <int TB, bool Fuse, typename R>
+__device__ __forceinline__ void finish_step(R bound, int clamp, int flag, const Partials &part,
                                             int slot, int n_tiles, const Advance &adv, bool group)
 {
     if (!Fuse && group) {
-        block_partials_group<TB>(dtc, clamp, flag, part, slot);
+        block_partials_group<TB>(bound, clamp, flag, part, slot);
         return;
     }
-    block_partials_at<TB>(dtc, clamp, flag, part, slot);
+    block_partials_at<TB>(bound, clamp, flag, part, slot);
     if constexpr (Fuse) {
     if (!adv.ctrl || threadIdx.x >= 64) return;
     // wave 0 only; work-item 0 wrote the partial
@@ -796,7 +843,7 @@ __global__ __launch_bounds__(TB, SWE_CELL_WAVES) void step_kernel(StepArgs<R> a,
         }
     }
     if (a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, bt.n_tiles, a.adv,
+    finish_step<TB, Fuse>(dtc, clamp, flag, a.part, tile, bt.n_tiles, a.adv,
                           SWE_GROUP_ATOMIC && !batched);
 }
 
@@ -1143,7 +1190,7 @@ __global__ __launch_bounds__(TB, SWE_TILE_WAVES) void tile_step_kernel(TileArgs<
         }
     }
     if (Replay || a.dt_direct) return;   // uniform: a replay that needs no dt reduction
-    finish_step<TB, Fuse>(static_cast<double>(dtc), clamp, flag, a.part, tile, ta.n_tiles, a.adv,
+    finish_step<TB, Fuse>(dtc, clamp, flag, a.part, tile, ta.n_tiles, a.adv,
                           SWE_GROUP_ATOMIC && !batched);
 }
 
@@ -1170,7 +1217,7 @@ __global__ __launch_bounds__(TB) void init_kernel(StepArgs<R> a, StepConfig cfg,
             flag = 0;
         }
     }
-    block_partials<TB>(static_cast<double>(dtc), 0, flag, a.part);
+    block_partials<TB>(dtc, 0, flag, a.part);
 }
 
 constexpr int kPassThreads = 1024;
