@@ -385,9 +385,10 @@ typedef struct swe_grads {
     double *dh, *dhu, *dhv;  /* dJ/d(initial state) */
 } swe_grads;
 
-/* Workspace bytes of swe_adjoint: checkpoints, a recompute segment and the adjoint state;
- * with ckpt_every = 1, every state and every step's U* instead (6 T doubles per step) and no
- * segment.  Errors: SWE_EINVAL. */
+/* Workspace bytes of swe_adjoint: checkpoints, a recompute segment, the adjoint state and
+ * the loss with each observation's share (n_steps + 1 doubles); with ckpt_every = 1, every
+ * state and every step's U* instead (6 T doubles per step) and no segment.
+ * Errors: SWE_EINVAL. */
 int32_t swe_adjoint_workspace_bytes(const swe_mesh *mesh, int64_t n_steps, int32_t ckpt_every,
                                     int64_t *bytes);
 
