@@ -477,3 +477,27 @@ def test_tile_size_is_a_mesh_property():
     assert "tile sizes" in swe.swe_last_error()
     # workspace: room for the partials of the smallest tiles
     assert swe.swe_workspace_bytes(c.n_cells) >= 16 * (-(-c.n_cells // 64))
+
+
+def test_adjoint_workspace_holds_checkpoints_segment_and_loss_shares():
+    """swe_adjoint's workspace: the checkpoints, one recompute segment (states and U*), the
+    adjoint state and the loss with a share per step; with ckpt_every = 1 every state and U*
+    instead of the segment.  Bad step counts and intervals are rejected."""
+    c = gen.small(1)
+    m = swe.Mesh(c.xy, c.tri, device=None)
+    st = 3 * m.n_cells * 8   # one state (h, hu, hv) in doubles
+
+    def ws(n, k):
+        return swe.swe_adjoint_workspace_bytes(m.handle, n, k)
+
+    n, k = 200, 50
+    n_ckpt = -(-n // k) + 1
+    assert ws(n, k) >= st * n_ckpt + st * (k + 1) + st * k + 3 * st + 8 * (n + 1)
+    assert ws(n, 1) >= st * (n + 1) + st * n + 3 * st + 8 * (n + 1)
+    # an interval beyond both step counts keeps the checkpoints and the segment: what a
+    # thousand more steps add is the loss shares, a double each (256-byte aligned)
+    grow = ws(2000, 5000) - ws(1000, 5000)
+    assert 8 * 1000 - 256 <= grow <= 8 * 1000 + 256
+    for bad in ((0, 50), (200, 0), (-1, 1)):
+        with pytest.raises(swe.SweError):
+            ws(*bad)
